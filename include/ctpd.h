@@ -1,0 +1,234 @@
+/*
+ * ctpd: preconditioned primal-dual TV/metal CT reconstruction on AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * Method: C. Schiffer, "TV-regularized CT reconstruction and metal artifact
+ * reduction using inequality constraints with preconditioning" (2018,
+ * arXiv:1810.03275).  Problem (C_h) of §3.2:
+ *
+ *   min_u  1/2 ||R_h u - u0||^2 on D\D0  +  lambda ||nabla_h u||_1
+ *          subject to (R_h u)(l,k) >= C(l,k) for (l,k) in the metal trace D0,
+ *
+ * solved by Algorithm PDRQS1 (§4.4) with the inverse-norm + periodic-Laplacian
+ * Fourier preconditioner (§4.3.1) on the normalized operator A = R_h/beta (§5.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are float32 [n][n], row-major, u[j][i] with j the y index and i the
+ *   x index (§3.1 grid: pixel centres x_i = h (i - (n-1)/2), same for y_j).
+ * - Sinograms are float32 [N][M], one contiguous row of M bins per angle.
+ *   Bin k (0-based) has centre s_k = ds (k - (M-1)/2) (§3.1 detector).
+ * - Gradient fields are float32 planar [2][n][n]: plane 0 the x difference,
+ *   plane 1 the y difference (§3.1 nabla_h).
+ * - Metal-trace masks are uint32 bitmasks [N][ceil(M/32)], bit (k & 31) of word
+ *   k >> 5 set when bin k of angle l is in D0.
+ * - Every array pointer is a DEVICE pointer owned by the caller (contiguous).
+ *   The library never frees caller memory.  Opaque objects (plans,
+ *   preconditioners, solvers) are created and destroyed by explicit calls and
+ *   own their internal device memory.
+ * - Work is enqueued on the given stream (a hipStream_t; NULL is the default
+ *   stream).  Only calls that return host scalars synchronize that stream.
+ * - Return value: CT_OK (0) or a negative CT_E_* code; ct_last_error() gives a
+ *   message for the calling thread.  No exception crosses the ABI.
+ */
+#ifndef CTPD_H
+#define CTPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ct_stream; /* hipStream_t */
+
+enum {
+  CT_OK = 0,
+  CT_E_INVALID = -1,     /* null pointer, non-positive size, bad parameter */
+  CT_E_UNSUPPORTED = -2, /* n not of the form 2^a 3^b, n > 8192, ds/h outside [0.75, 1.4] */
+  CT_E_DEVICE = -3,      /* a HIP runtime error (message in ct_last_error) */
+  CT_E_NONFINITE = -4,   /* validation found NaN/Inf in an input */
+  CT_E_DIVERGED = -5,    /* the gap record became non-finite */
+  CT_E_STATE = -6        /* call out of order (e.g. gap before any step) */
+};
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ct_version(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *ct_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Geometry and projector plan (§3.1 "Discretization")                       */
+
+typedef struct ct_geom {
+  int32_t n;        /* image side; n >= 2, n <= 8192 */
+  int32_t n_angles; /* N >= 1 */
+  int32_t n_bins;   /* M >= 2 */
+  double h;         /* pixel spacing > 0 */
+  double ds;        /* detector bin width > 0, 0.75 <= ds/h <= 1.4 */
+} ct_geom;
+
+typedef struct ct_plan ct_plan;
+
+/* Build the projector plan: per-angle bin-coordinate tables and work lists.
+ * angles: HOST array of N radians, or NULL for theta_l = pi l / N.
+ * The bin coordinate of pixel (i,j) at angle l is
+ *   t = (x_i cos theta_l + y_j sin theta_l)/ds + (M-1)/2,
+ * held in 64-bit fixed point with 30 fractional bits (|error| <= (1+i+j) 2^-31),
+ * so that R_h and R_h^* use bit-identical interpolation weights.
+ * Errors: CT_E_INVALID, CT_E_UNSUPPORTED, CT_E_DEVICE. */
+int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
+int ct_plan_destroy(ct_plan *p);
+
+/* sino = R_h img (§3.1: R_h is the transpose of R_h^*; each pixel's value is
+ * split between bins floor(t) and floor(t)+1 with weights 1-alpha and alpha,
+ * alpha = t - floor(t); bins outside [0, M) receive nothing).
+ * img: [n][n], sino: [N][M] (overwritten).  Ray-driven gather: no atomics,
+ * deterministic.  Errors: CT_E_INVALID, CT_E_DEVICE. */
+int ct_radon_fwd(const ct_plan *p, const float *img, float *sino, ct_stream s);
+
+/* img = R_h^* sino (§3.1 linear backprojection: per angle the detector row is
+ * interpolated linearly at t, values summed over angles; bins outside [0, M)
+ * read as zero).  sino: [N][M], img: [n][n] (overwritten).  Pixel-driven
+ * gather, deterministic.  Errors: CT_E_INVALID, CT_E_DEVICE. */
+int ct_radon_adj(const ct_plan *p, const float *sino, float *img, ct_stream s);
+
+/* p = nabla_h u: forward differences divided by h, zero in the last column
+ * (plane 0) and last row (plane 1) (§3.1, Neumann boundary).
+ * u: [n][n]; p: [2][n][n] (overwritten). */
+int ct_grad(int32_t n, double h, const float *u, float *p, ct_stream s);
+
+/* d = div_h p = -nabla_h^T p: backward differences with Dirichlet boundary
+ * (§3.1).  p: [2][n][n]; d: [n][n] (overwritten). */
+int ct_div(int32_t n, double h, const float *p, float *d, ct_stream s);
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioner (§4.3 periodic Laplacian, §4.3.1 inverse norm, §4.4)       */
+
+typedef struct ct_precond ct_precond;
+
+/* M^{-1} y = F^{-1}( F(y) rho / (sigma^2 c + (sigma tau)^2 lambda_Delta rho) ),
+ * rho = sqrt(f1^2 + f2^2 + eps^2) with (f1, f2) the centred integer DFT
+ * frequency, lambda_Delta = 4 sin^2(pi k1/n) + 4 sin^2(pi k2/n).
+ * n must be 2^a 3^b (mixed-radix FFT in LDS).  sigma, tau, c, eps > 0.
+ * Errors: CT_E_INVALID, CT_E_UNSUPPORTED, CT_E_DEVICE. */
+int ct_precond_create(int32_t n, double sigma, double tau, double c, double eps,
+                      ct_precond **out);
+/* x = M^{-1} y; y, x: [n][n] (x may equal y). */
+int ct_precond_apply(const ct_precond *m, const float *y, float *x, ct_stream s);
+int ct_precond_destroy(ct_precond *m);
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise resolvents (§3.3, §4.4), exposed for testing                    */
+
+/* y = (q - s u0)/(1 + s) off D0,  y = min(q - s C, 0) on D0  (count = N*M,
+ * row length M for the mask lookup).  mask may be NULL (D0 empty). */
+int ct_prox_sino(int32_t n_angles, int32_t n_bins, const float *q, double step,
+                 const float *u0, const float *bound, const uint32_t *mask,
+                 float *y, ct_stream s);
+
+/* w = q / max(1, |q|/radius) per pixel for a planar field q: [2][n][n]
+ * (radius 0 projects onto 0). */
+int ct_tv_project(int32_t n, const float *q, double radius, float *w, ct_stream s);
+
+/* ------------------------------------------------------------------------ */
+/* Power iteration (§4.3, §5.1)                                             */
+
+/* *out = sqrt(lambda_max(R_h^* R_h)) by `iters` steps x <- R^*R x/||R^*R x||
+ * from x0 (device [n][n]; NULL: a fixed deterministic start), the estimate
+ * being ||R^*R x|| at the last step.  Norms reduced in FP64.  Synchronizes s. */
+int ct_power_norm(const ct_plan *p, int32_t iters, const float *x0, double *out,
+                  ct_stream s);
+
+/* ------------------------------------------------------------------------ */
+/* Solver: problem setup and Algorithm PDRQS1                               */
+
+typedef struct ct_problem {
+  const float *sino;     /* u0: [N][M] measured sinogram (device) */
+  const uint32_t *mask;  /* D0 bitmask [N][ceil(M/32)] (device) or NULL (D0 empty) */
+  const float *bound;    /* C: [N][M] (device) or NULL to use bound_scalar */
+  float bound_scalar;    /* C when bound is NULL */
+  float pad_;
+  double lambda;         /* lambda of (C_h) (unnormalized), >= 0 */
+} ct_problem;
+
+enum {
+  CT_FLAG_VALIDATE = 1u  /* scan sino/bound for NaN/Inf at setup (CT_E_NONFINITE) */
+};
+
+typedef struct ct_params {
+  double sigma;          /* PDRQ step sigma > 0 (default 1) */
+  double tau;            /* gradient scaling tau > 0 (default 1/sqrt(8)) */
+  double eps;            /* inverse-norm regularization eps > 0 (default 0.3) */
+  double c;              /* preconditioner constant; <= 0: c_safety * power-iteration estimate */
+  double c_safety;       /* default 1.1 */
+  double beta;           /* normalization ||R_h||; <= 0: power-iteration estimate */
+  int32_t k_max;         /* iterations for ct_reconstruct, >= 0 */
+  int32_t gap_every;     /* gap record period for ct_reconstruct (0: none) */
+  int32_t power_iters;   /* power-iteration steps (default 30) */
+  uint32_t flags;        /* CT_FLAG_* */
+  const float *start_norm;    /* device [n][n] start of the ||R_h|| iteration or NULL */
+  const float *start_precond; /* device [n][n] start of the c iteration or NULL */
+} ct_params;
+
+/* Fill *p with the defaults above (k_max = 0, gap_every = 0). */
+void ct_params_default(ct_params *p);
+
+typedef struct ct_solver ct_solver;
+
+/* Setup (§5.1, §4.3.1): beta (power iteration unless given), data b = u0/beta,
+ * bounds C/beta, lambda~ = lambda/beta^2, c (power iteration on
+ * tilde M^{-1/2} A^*A tilde M^{-1/2} unless given), the Fourier multiplier,
+ * and a zero state u = bar v1 = bar v2 = 0.  The solver keeps pointers to
+ * problem->sino/mask/bound only during this call (it copies what it needs).
+ * Synchronizes s.  Errors: CT_E_INVALID, CT_E_UNSUPPORTED, CT_E_NONFINITE,
+ * CT_E_DEVICE. */
+int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
+                     ct_stream s, ct_solver **out);
+int ct_solver_destroy(ct_solver *sv);
+
+/* out[0] = beta, out[1] = c, out[2] = lambda~, out[3] = iterations done. */
+int ct_solver_info(const ct_solver *sv, double out[4]);
+
+/* Run k iterations of PDRQS1 (§4.4) on the solver's state:
+ *   u_tmp = -sigma (A^*(vb1 + sigma A u) - tau div(vb2 + sigma tau nabla u))
+ *   u     = u + M^{-1} u_tmp
+ *   v1 = vb1 + sigma A u,  v2 = vb2 + sigma tau nabla u
+ *   y1 = prox_sino(2 v1 - vb1, sigma),   vb1 += y1 - v1
+ *   w  = tv_project(2 v2 - vb2, lambda~/tau),  vb2 += w - v2
+ * A u and nabla u are cached across iterations (one R_h and one R_h^* per
+ * iteration).  Asynchronous; k >= 0. */
+int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s);
+
+/* Copy the state out: u [n][n], vb1 [N][M], vb2 [2][n][n] (any may be NULL). */
+int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_stream s);
+/* Replace the state (all three required); caches A u, nabla u are recomputed. */
+int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float *vb2,
+                    ct_stream s);
+
+/* FP64 record of the current state, in normalized units, with y = (y1, w)
+ * the resolvent outputs of the last iteration:
+ *   out[0] P  = 1/2 sum_{D\D0} (A u - b)^2 + lambda~ sum |nabla u|
+ *   out[1] G* = sum_{D\D0} (y1^2/2 + y1 b) + sum_{D0} y1 C~
+ *   out[2] gap = P + G*
+ *   out[3] ||A^* y1 - tau div w||
+ *   out[4] max_{D0} (C~ - A u)_+
+ *   out[5] ||u_k - u_{k-1}||
+ * Requires at least one ct_pd_step since creation/import (CT_E_STATE).
+ * Synchronizes s. */
+int ct_gap(ct_solver *sv, double out[6], ct_stream s);
+
+/* One-shot solve: setup, k_max iterations, u_out [n][n].  With gap_every > 0
+ * and report non-NULL, writes 6 doubles per record into report (capacity
+ * report_len doubles, records after iterations gap_every, 2 gap_every, ...).
+ * Returns CT_E_DIVERGED if a record is non-finite.  Synchronizes s. */
+int ct_reconstruct(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
+                   float *u_out, double *report, int32_t report_len, ct_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTPD_H */

@@ -5,7 +5,8 @@ Readings taken here (the thesis text is 1-based and partly garbled):
   x_i = h (i - (n-1)/2) and y_j = h (j - (n-1)/2), the same points as the
   thesis' h (i - (n+1)/2) for 1-based i.  Images are stored u[j, i]
   (row j = y index, column i = x index).  The grid is square (n = m).
-* Angles: theta_l = pi l / N, l in [0, N), uniform on [0, pi).
+* Angles: theta_l = pi l / N, l in [0, N), uniform on [0, pi), unless explicit
+  angles are given (§3.1 allows arbitrary theta_1, ..., theta_N).
 * Detector bins (§3.1, bin spacing Delta s, rotation centre between the two
   middle bins for even M): 0-based bin k has centre s_k = ds (k - (M-1)/2).
 * Bin coordinate (§3.1, definition of R_h^*): a pixel at (x, y) projects to
@@ -31,9 +32,15 @@ class Geometry:
     n_bins: int
     h: float = 1.0
     ds: float = 1.0
+    thetas: tuple | None = None   # explicit angles theta_1..theta_N (the thesis allows any)
+
+    def theta(self, l: int) -> float:
+        return float(self.thetas[l]) if self.thetas is not None else math.pi * l / self.n_angles
 
     def angles(self) -> np.ndarray:
-        """theta_l = pi * l / N for l in [0, N)."""
+        """theta_l = pi * l / N for l in [0, N), or the explicit angles."""
+        if self.thetas is not None:
+            return np.asarray(self.thetas, dtype=np.float64)
         return math.pi * np.arange(self.n_angles, dtype=np.float64) / self.n_angles
 
     def pixel_centres(self) -> np.ndarray:
@@ -46,14 +53,14 @@ class Geometry:
 
     def bin_coordinate(self, l: int) -> np.ndarray:
         """t[j, i] = (x_i cos theta_l + y_j sin theta_l)/ds + (M-1)/2 for angle l."""
-        th = math.pi * l / self.n_angles
+        th = self.theta(l)
         x = self.pixel_centres()
         s = x[None, :] * math.cos(th) + x[:, None] * math.sin(th)
         return s / self.ds + (self.n_bins - 1) / 2.0
 
     def bin_coordinate_scalar(self, i: int, j: int, l: int) -> float:
         """The same quantity for one pixel, with scalar math only."""
-        th = math.pi * l / self.n_angles
+        th = self.theta(l)
         x = self.h * (i - (self.n - 1) / 2.0)
         y = self.h * (j - (self.n - 1) / 2.0)
         return (x * math.cos(th) + y * math.sin(th)) / self.ds + (self.n_bins - 1) / 2.0

@@ -110,3 +110,39 @@ def radon_matrix(g: Geometry) -> np.ndarray:
                 if 0 <= k + 1 < M:
                     A[l * M + k + 1, col] += a
     return A
+
+
+def radon_adj_at(g: Geometry, v: np.ndarray, pixels) -> np.ndarray:
+    """(R_h^* v)[j, i] for a list of (j, i) pixels only, with scalar geometry
+    (for spot checks of full-size backprojections)."""
+    v = np.asarray(v, dtype=np.float64)
+    out = np.zeros(len(pixels))
+    for q, (j, i) in enumerate(pixels):
+        acc = 0.0
+        for l in range(g.n_angles):
+            t = g.bin_coordinate_scalar(i, j, l)
+            k = math.floor(t)
+            a = t - k
+            if 0 <= k < g.n_bins:
+                acc += (1.0 - a) * v[l, k]
+            if 0 <= k + 1 < g.n_bins:
+                acc += a * v[l, k + 1]
+        out[q] = acc
+    return out
+
+
+def radon_fwd_at(g: Geometry, u: np.ndarray, bins) -> np.ndarray:
+    """(R_h u)[l, k] for a list of (l, k) bins only: the pixels with
+    floor(t) = k contribute (1 - alpha) u, those with floor(t) = k - 1
+    contribute alpha u (for spot checks of full-size projections)."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros(len(bins))
+    cache = {}
+    for q, (l, k) in enumerate(bins):
+        if l not in cache:
+            t = g.bin_coordinate(l)
+            kk = np.floor(t)
+            cache = {l: (kk.astype(np.int64), t - kk)}
+        kk, a = cache[l]
+        out[q] = np.sum(((1.0 - a) * u)[kk == k]) + np.sum((a * u)[kk == k - 1])
+    return out

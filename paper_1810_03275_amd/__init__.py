@@ -1,0 +1,348 @@
+"""MI355X-native preconditioned primal-dual TV/metal CT reconstruction.
+
+Python binding of libctpd.so (include/ctpd.h).  Every step of the method runs
+in the library's HIP kernels; this module only marshals arguments.  PyTorch
+provides device memory (contiguous float32 CUDA/HIP tensors) and the current
+stream.  There is no CPU fallback: without the built library, importing this
+package raises ImportError, and a call on tensors that are not on the GPU
+raises ValueError.
+
+Method: C. Schiffer, "TV-regularized CT reconstruction and metal artifact
+reduction using inequality constraints with preconditioning" (2018,
+arXiv:1810.03275), Algorithm PDRQS1 (§4.4) with the inverse-norm
+preconditioner (§4.3.1) and the normalization of §5.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_L = _lib.load()
+
+__all__ = [
+    "CtpdError", "Plan", "Precond", "Solver", "radon_fwd", "radon_adj", "grad", "div",
+    "prox_sino", "tv_project", "power_norm", "reconstruct", "pack_mask", "RadonFn",
+    "RadonAdjFn", "lib",
+]
+
+lib = _L
+
+
+class CtpdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _L.ct_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != _lib.CT_OK:
+        raise CtpdError(code, where)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, shape, name: str, dtype=torch.float32) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU (no CPU path exists)")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def pack_mask(mask) -> torch.Tensor:
+    """Bool (N, M) metal-trace mask -> uint32 bitmask (N, ceil(M/32)) on the GPU
+    (bit k & 31 of word k >> 5)."""
+    m = mask.detach().cpu().numpy() if isinstance(mask, torch.Tensor) else np.asarray(mask)
+    m = m.astype(bool)
+    N, M = m.shape
+    MW = (M + 31) // 32
+    pad = np.zeros((N, MW * 32), dtype=bool)
+    pad[:, :M] = m
+    bits = np.packbits(pad, axis=1, bitorder="little").view(np.uint32)
+    return torch.from_numpy(bits.astype(np.int32).copy()).cuda()
+
+
+class Plan:
+    """Projector plan for an n x n image, N angles, M bins (§3.1)."""
+
+    def __init__(self, n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1.0,
+                 angles: Optional[np.ndarray] = None):
+        self.n, self.n_angles, self.n_bins, self.h, self.ds = n, n_angles, n_bins, h, ds
+        g = _lib.CtGeom(n, n_angles, n_bins, h, ds)
+        handle = ctypes.c_void_p()
+        if angles is not None:
+            a = np.ascontiguousarray(angles, dtype=np.float64)
+            if a.shape != (n_angles,):
+                raise ValueError("angles must have shape (n_angles,)")
+            _check(_L.ct_plan_create(ctypes.byref(g), a.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(handle)), "ct_plan_create")
+        else:
+            _check(_L.ct_plan_create(ctypes.byref(g), None, ctypes.byref(handle)),
+                   "ct_plan_create")
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _L.ct_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def radon_fwd(self, img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        p = _dev(img, (self.n, self.n), "img")
+        if out is None:
+            out = torch.empty((self.n_angles, self.n_bins), device=img.device, dtype=torch.float32)
+        q = _dev(out, (self.n_angles, self.n_bins), "out")
+        _check(_L.ct_radon_fwd(self._h, p, q, _stream()), "ct_radon_fwd")
+        return out
+
+    def radon_adj(self, sino: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        p = _dev(sino, (self.n_angles, self.n_bins), "sino")
+        if out is None:
+            out = torch.empty((self.n, self.n), device=sino.device, dtype=torch.float32)
+        q = _dev(out, (self.n, self.n), "out")
+        _check(_L.ct_radon_adj(self._h, p, q, _stream()), "ct_radon_adj")
+        return out
+
+
+def radon_fwd(plan: Plan, img: torch.Tensor, out=None) -> torch.Tensor:
+    """sino = R_h img (§3.1)."""
+    return plan.radon_fwd(img, out)
+
+
+def radon_adj(plan: Plan, sino: torch.Tensor, out=None) -> torch.Tensor:
+    """img = R_h^* sino (§3.1)."""
+    return plan.radon_adj(sino, out)
+
+
+def grad(u: torch.Tensor, h: float = 1.0, out=None) -> torch.Tensor:
+    """Forward-difference gradient, planar (2, n, n) (§3.1)."""
+    n = u.shape[0]
+    p = _dev(u, (n, n), "u")
+    if out is None:
+        out = torch.empty((2, n, n), device=u.device, dtype=torch.float32)
+    _check(_L.ct_grad(n, h, p, _dev(out, (2, n, n), "out"), _stream()), "ct_grad")
+    return out
+
+
+def div(pf: torch.Tensor, h: float = 1.0, out=None) -> torch.Tensor:
+    """div_h = -nabla_h^T (§3.1)."""
+    n = pf.shape[1]
+    p = _dev(pf, (2, n, n), "p")
+    if out is None:
+        out = torch.empty((n, n), device=pf.device, dtype=torch.float32)
+    _check(_L.ct_div(n, h, p, _dev(out, (n, n), "out"), _stream()), "ct_div")
+    return out
+
+
+def prox_sino(q: torch.Tensor, step: float, u0: torch.Tensor, bound: Optional[torch.Tensor],
+              mask_bits: Optional[torch.Tensor], out=None) -> torch.Tensor:
+    """Sinogram resolvent of §3.3/§4.4 (mask_bits from pack_mask, or None)."""
+    N, M = q.shape
+    if out is None:
+        out = torch.empty_like(q)
+    mb = _dev(mask_bits, (N, (M + 31) // 32), "mask", torch.int32) if mask_bits is not None else None
+    bd = _dev(bound, (N, M), "bound") if bound is not None else None
+    _check(_L.ct_prox_sino(N, M, _dev(q, (N, M), "q"), step, _dev(u0, (N, M), "u0"), bd, mb,
+                           _dev(out, (N, M), "out"), _stream()), "ct_prox_sino")
+    return out
+
+
+def tv_project(q: torch.Tensor, radius: float, out=None) -> torch.Tensor:
+    """Pointwise projection onto the Euclidean ball (§3.3)."""
+    n = q.shape[1]
+    if out is None:
+        out = torch.empty_like(q)
+    _check(_L.ct_tv_project(n, _dev(q, (2, n, n), "q"), radius, _dev(out, (2, n, n), "out"),
+                            _stream()), "ct_tv_project")
+    return out
+
+
+class Precond:
+    """M^{-1} of §4.4: F^{-1}( F(y) rho / (sigma^2 c + (sigma tau)^2 lambda_Delta rho) )."""
+
+    def __init__(self, n: int, sigma: float, tau: float, c: float, eps: float):
+        self.n = n
+        h = ctypes.c_void_p()
+        _check(_L.ct_precond_create(n, sigma, tau, c, eps, ctypes.byref(h)), "ct_precond_create")
+        self._h = h
+
+    def apply(self, y: torch.Tensor, out=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(y)
+        _check(_L.ct_precond_apply(self._h, _dev(y, (self.n, self.n), "y"),
+                                   _dev(out, (self.n, self.n), "out"), _stream()),
+               "ct_precond_apply")
+        return out
+
+    def __del__(self):
+        try:
+            if self._h:
+                _L.ct_precond_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def power_norm(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -> float:
+    """sqrt(lambda_max(R^* R)) by power iteration (§5.1); synchronizes."""
+    out = ctypes.c_double()
+    xp = _dev(x0, (plan.n, plan.n), "x0") if x0 is not None else None
+    _check(_L.ct_power_norm(plan.handle, iters, xp, ctypes.byref(out), _stream()),
+           "ct_power_norm")
+    return out.value
+
+
+def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
+            start_norm, start_precond, n):
+    p = _lib.CtParams()
+    _L.ct_params_default(ctypes.byref(p))
+    p.sigma, p.tau, p.eps = sigma, tau, eps
+    p.c = c if c is not None else 0.0
+    p.c_safety = c_safety
+    p.beta = beta if beta is not None else 0.0
+    p.k_max, p.gap_every, p.power_iters = k_max, gap_every, power_iters
+    p.flags = _lib.CT_FLAG_VALIDATE if validate else 0
+    p.start_norm = _dev(start_norm, (n, n), "start_norm") if start_norm is not None else None
+    p.start_precond = (_dev(start_precond, (n, n), "start_precond")
+                       if start_precond is not None else None)
+    return p
+
+
+def _problem(plan: Plan, sino, mask_bits, bound, lam, bound_scalar=0.0):
+    N, M = plan.n_angles, plan.n_bins
+    pr = _lib.CtProblem()
+    pr.sino = _dev(sino, (N, M), "sino")
+    pr.mask = _dev(mask_bits, (N, (M + 31) // 32), "mask", torch.int32) if mask_bits is not None else None
+    pr.bound = _dev(bound, (N, M), "bound") if bound is not None else None
+    pr.bound_scalar = bound_scalar
+    pr.lambda_ = lam
+    return pr
+
+
+class Solver:
+    """PDRQS1 solver state on the GPU (§4.4).  Keeps references to its inputs."""
+
+    def __init__(self, plan: Plan, sino: torch.Tensor, lam: float,
+                 mask_bits: Optional[torch.Tensor] = None, bound: Optional[torch.Tensor] = None,
+                 *, sigma: float = 1.0, tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3,
+                 c: Optional[float] = None, c_safety: float = 1.1, beta: Optional[float] = None,
+                 power_iters: int = 30, validate: bool = False,
+                 start_norm: Optional[torch.Tensor] = None,
+                 start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0):
+        self.plan = plan
+        self._keep = (sino, mask_bits, bound, start_norm, start_precond)
+        prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
+        prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
+                      start_norm, start_precond, plan.n)
+        h = ctypes.c_void_p()
+        _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
+                                   ctypes.byref(h)), "ct_solver_create")
+        self._h = h
+
+    def info(self) -> dict:
+        o = (ctypes.c_double * 4)()
+        _check(_L.ct_solver_info(self._h, o), "ct_solver_info")
+        return {"beta": o[0], "c": o[1], "lam_t": o[2], "iters": int(o[3])}
+
+    def step(self, k: int = 1) -> None:
+        _check(_L.ct_pd_step(self._h, k, _stream()), "ct_pd_step")
+
+    def export(self):
+        n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins
+        dev = torch.device("cuda")
+        u = torch.empty((n, n), device=dev)
+        vb1 = torch.empty((N, M), device=dev)
+        vb2 = torch.empty((2, n, n), device=dev)
+        _check(_L.ct_state_export(self._h, u.data_ptr(), vb1.data_ptr(), vb2.data_ptr(),
+                                  _stream()), "ct_state_export")
+        return u, vb1, vb2
+
+    def import_state(self, u, vb1, vb2) -> None:
+        n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins
+        _check(_L.ct_state_import(self._h, _dev(u, (n, n), "u"), _dev(vb1, (N, M), "vb1"),
+                                  _dev(vb2, (2, n, n), "vb2"), _stream()), "ct_state_import")
+
+    def gap(self) -> np.ndarray:
+        o = (ctypes.c_double * 6)()
+        _check(_L.ct_gap(self._h, o, _stream()), "ct_gap")
+        return np.array(list(o), dtype=np.float64)
+
+    def close(self):
+        if self._h:
+            _L.ct_solver_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, bound=None, *,
+                k_max: int = 100, gap_every: int = 0, sigma: float = 1.0,
+                tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3, c: Optional[float] = None,
+                c_safety: float = 1.1, beta: Optional[float] = None, power_iters: int = 30,
+                validate: bool = False, start_norm=None, start_precond=None,
+                bound_scalar: float = 0.0):
+    """One-shot PDRQS1 solve; returns (u, report (records x 6) or None)."""
+    prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
+    prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
+                  start_norm, start_precond, plan.n)
+    u = torch.empty((plan.n, plan.n), device=sino.device, dtype=torch.float32)
+    nrec = k_max // gap_every if gap_every > 0 else 0
+    rep = (ctypes.c_double * max(1, 6 * nrec))()
+    _check(_L.ct_reconstruct(plan.handle, ctypes.byref(prob), ctypes.byref(prm), u.data_ptr(),
+                             rep if nrec else None, 6 * nrec, _stream()), "ct_reconstruct")
+    report = np.array(list(rep), dtype=np.float64).reshape(-1, 6)[:nrec] if nrec else None
+    return u, report
+
+
+class RadonFn(torch.autograd.Function):
+    """sino = R_h img; the backward pass is R_h^* (the exact transpose, §3.1)."""
+
+    @staticmethod
+    def forward(ctx, img, plan):
+        ctx.plan = plan
+        return plan.radon_fwd(img.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.radon_adj(g.contiguous()), None
+
+
+class RadonAdjFn(torch.autograd.Function):
+    """img = R_h^* sino; the backward pass is R_h."""
+
+    @staticmethod
+    def forward(ctx, sino, plan):
+        ctx.plan = plan
+        return plan.radon_adj(sino.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.radon_fwd(g.contiguous()), None

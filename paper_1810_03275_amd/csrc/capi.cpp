@@ -1,0 +1,706 @@
+// C ABI of ctpd: argument validation, object lifetimes and the PDRQS1 driver
+// (thesis Algorithm PDRQS1 in §4.4, setup of §5.1 and §4.3.1).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ctpd {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+int build_plan(const ct_geom *g, const double *angles, ct_plan *p);
+void free_plan(ct_plan *p);
+
+static bool fft_size_ok(int n) {
+  if (n < 2 || n > 4096 || (n & 1)) return false;
+  int m = n;
+  while (m % 2 == 0) m /= 2;
+  while (m % 3 == 0) m /= 3;
+  return m == 1;
+}
+
+static hipStream_t S(ct_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Preconditioner tables (§4.3, §4.3.1, §4.4), computed in FP64 on the host.
+static double freq(int k, int n) { return (k <= n / 2) ? (double)k : (double)(k - n); }
+
+static std::vector<float> multiplier_table(int n, double sigma, double tau, double c, double eps,
+                                           bool sqrt_rho_only) {
+  const int half = n / 2 + 1;
+  std::vector<float> m((size_t)half * n);
+  const double inv_nn = 1.0 / ((double)n * (double)n);
+  for (int k1 = 0; k1 < half; ++k1) {
+    const double s1 = std::sin(M_PI * k1 / n);
+    const double f1 = freq(k1, n);
+    for (int k2 = 0; k2 < n; ++k2) {
+      const double s2 = std::sin(M_PI * k2 / n);
+      const double f2 = freq(k2, n);
+      const double rho = std::sqrt(f1 * f1 + f2 * f2 + eps * eps);
+      double v;
+      if (sqrt_rho_only) {
+        v = std::sqrt(rho);
+      } else {
+        const double lap = 4.0 * s1 * s1 + 4.0 * s2 * s2;
+        v = rho / (sigma * sigma * c + (sigma * tau) * (sigma * tau) * lap * rho);
+      }
+      m[(size_t)k1 * n + k2] = (float)(v * inv_nn);
+    }
+  }
+  return m;
+}
+
+static int precond_init(ct_precond *pc, int n, double sigma, double tau, double c, double eps) {
+  pc->n = n;
+  pc->sigma = sigma;
+  pc->tau = tau;
+  pc->c = c;
+  pc->eps = eps;
+  if (!fft_factor(n, &pc->fp)) {
+    set_error("FFT size must be 2^a 3^b");
+    return CT_E_UNSUPPORTED;
+  }
+  std::vector<float2> tw(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  const int half = n / 2 + 1;
+  CT_TRY_HIP(hipMalloc(&pc->d_tw, sizeof(float2) * n));
+  CT_TRY_HIP(hipMemcpy(pc->d_tw, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMalloc(&pc->d_spec, sizeof(float2) * (size_t)half * n));
+  CT_TRY_HIP(hipMalloc(&pc->d_mult, sizeof(float) * (size_t)half * n));
+  if (c > 0) {
+    auto m = multiplier_table(n, sigma, tau, c, eps, false);
+    CT_TRY_HIP(hipMemcpy(pc->d_mult, m.data(), sizeof(float) * m.size(), hipMemcpyHostToDevice));
+  }
+  return CT_OK;
+}
+
+static void precond_free(ct_precond *pc) {
+  (void)hipFree(pc->d_tw);
+  (void)hipFree(pc->d_spec);
+  (void)hipFree(pc->d_mult);
+  pc->d_tw = nullptr;
+  pc->d_spec = nullptr;
+  pc->d_mult = nullptr;
+}
+
+// Scratch owned by a plan for standalone calls (allocated on first use).
+static int plan_scratch(ct_plan *p) {
+  const size_t nn = (size_t)p->g.n * p->g.n, NM = (size_t)p->g.n_angles * p->g.n_bins;
+  if (!p->d_scratch_img) CT_TRY_HIP(hipMalloc(&p->d_scratch_img, sizeof(float) * nn * 2));
+  if (!p->d_scratch_sino) CT_TRY_HIP(hipMalloc(&p->d_scratch_sino, sizeof(float) * NM));
+  if (!p->d_red) {
+    p->red_cap = reduction_partials_needed() + 16;
+    CT_TRY_HIP(hipMalloc(&p->d_red, sizeof(double) * p->red_cap));
+  }
+  return CT_OK;
+}
+
+static std::vector<float> default_start(int n) {
+  // smooth, non-symmetric, non-zero-mean start image
+  std::vector<float> x((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i)
+      x[(size_t)j * n + i] = (float)(1.0 + 0.5 * std::sin(0.37 * i + 1.13 * j) +
+                                     0.25 * std::cos(0.071 * i * j + 0.3));
+  return x;
+}
+
+// lambda_max of op by `iters` power steps; x is a work image holding the start.
+// op(x, y) computes y = op(x).  Norms in FP64 on the device.
+template <class Op>
+static int power_iterate(int n, int iters, float *x, float *y, double *d_red, int red_cap,
+                         double *d_norm, Op op, hipStream_t s, double *lam_out) {
+  const int64_t nn = (int64_t)n * n;
+  CT_TRY(launch_norm2(x, nn, d_red, red_cap, d_norm, s));
+  CT_TRY(launch_scale_by_inv(x, nn, d_norm, x, s));
+  for (int it = 0; it < iters; ++it) {
+    CT_TRY(op(x, y));
+    CT_TRY(launch_norm2(y, nn, d_red, red_cap, d_norm, s));
+    CT_TRY(launch_scale_by_inv(y, nn, d_norm, x, s));
+  }
+  double lam = 0.0;
+  CT_TRY_HIP(hipMemcpyAsync(&lam, d_norm, sizeof(double), hipMemcpyDeviceToHost, s));
+  CT_TRY_HIP(hipStreamSynchronize(s));
+  *lam_out = lam;
+  return CT_OK;
+}
+
+}  // namespace ctpd
+
+using namespace ctpd;
+
+struct ct_solver {
+  ct_plan *plan = nullptr;
+  ct_precond pc{};
+  int n = 0, N = 0, M = 0;
+  double beta = 0, c = 0, lam_t = 0, sigma = 0, tau = 0, eps = 0;
+  float *u = nullptr, *u_next = nullptr, *vb1 = nullptr, *s1 = nullptr, *vb2 = nullptr,
+        *s2 = nullptr, *target = nullptr, *rraw = nullptr, *utmp = nullptr;
+  float *y1 = nullptr, *r = nullptr, *w = nullptr;
+  uint32_t *mask = nullptr;
+  double *d_red = nullptr, *d_out = nullptr;
+  int red_cap = 0;
+  int64_t iters = 0;
+  bool have_dual = false;
+};
+
+static void solver_free(ct_solver *sv) {
+  if (!sv) return;
+  float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
+                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w};
+  for (float *b : bufs) (void)hipFree(b);
+  (void)hipFree(sv->mask);
+  (void)hipFree(sv->d_red);
+  (void)hipFree(sv->d_out);
+  precond_free(&sv->pc);
+}
+
+extern "C" {
+
+int ct_version(void) { return 10000; }
+
+const char *ct_last_error(void) { return g_err.c_str(); }
+
+void ct_params_default(ct_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->sigma = 1.0;
+  p->tau = 1.0 / std::sqrt(8.0);
+  p->eps = 0.3;
+  p->c = 0.0;
+  p->c_safety = 1.1;
+  p->beta = 0.0;
+  p->k_max = 0;
+  p->gap_every = 0;
+  p->power_iters = 30;
+  p->flags = 0;
+}
+
+int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
+  clear_error();
+  if (!g || !out) {
+    set_error("ct_plan_create: null argument");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  if (g->n < 2 || g->n_angles < 1 || g->n_bins < 2 || !(g->h > 0) || !(g->ds > 0)) {
+    set_error("ct_plan_create: need n >= 2, N >= 1, M >= 2, h > 0, ds > 0");
+    return CT_E_INVALID;
+  }
+  if (g->n > 8192 || g->n_bins > (1 << 20) || g->n_angles > (1 << 20)) {
+    set_error("ct_plan_create: size too large (n <= 8192)");
+    return CT_E_UNSUPPORTED;
+  }
+  const double ratio = g->ds / g->h;
+  if (ratio < 0.75 || ratio > 1.4) {
+    set_error("ct_plan_create: ds/h must lie in [0.75, 1.4]");
+    return CT_E_UNSUPPORTED;
+  }
+  if (angles) {
+    for (int l = 0; l < g->n_angles; ++l)
+      if (!std::isfinite(angles[l])) {
+        set_error("ct_plan_create: non-finite angle");
+        return CT_E_INVALID;
+      }
+  }
+  ct_plan *p = new (std::nothrow) ct_plan();
+  if (!p) return CT_E_DEVICE;
+  p->g = *g;
+  (void)hipGetDevice(&p->device);
+  int rc = build_plan(g, angles, p);
+  if (rc != CT_OK) {
+    free_plan(p);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return CT_OK;
+}
+
+int ct_plan_destroy(ct_plan *p) {
+  clear_error();
+  if (!p) return CT_OK;
+  free_plan(p);
+  delete p;
+  return CT_OK;
+}
+
+int ct_radon_fwd(const ct_plan *p, const float *img, float *sino, ct_stream s) {
+  clear_error();
+  if (!p || !img || !sino) {
+    set_error("ct_radon_fwd: null argument");
+    return CT_E_INVALID;
+  }
+  return launch_radon_fwd(p, img, sino, S(s));
+}
+
+int ct_radon_adj(const ct_plan *p, const float *sino, float *img, ct_stream s) {
+  clear_error();
+  if (!p || !img || !sino) {
+    set_error("ct_radon_adj: null argument");
+    return CT_E_INVALID;
+  }
+  return launch_radon_adj(p, sino, nullptr, 1.0f, 0.0f, img, S(s));
+}
+
+int ct_grad(int32_t n, double h, const float *u, float *p, ct_stream s) {
+  clear_error();
+  if (n < 1 || !(h > 0) || !u || !p) {
+    set_error("ct_grad: invalid argument");
+    return CT_E_INVALID;
+  }
+  return launch_grad(n, (float)(1.0 / h), u, p, S(s));
+}
+
+int ct_div(int32_t n, double h, const float *p, float *d, ct_stream s) {
+  clear_error();
+  if (n < 2 || !(h > 0) || !p || !d) {
+    set_error("ct_div: invalid argument");
+    return CT_E_INVALID;
+  }
+  return launch_div(n, (float)(1.0 / h), p, d, S(s));
+}
+
+int ct_precond_create(int32_t n, double sigma, double tau, double c, double eps,
+                      ct_precond **out) {
+  clear_error();
+  if (!out || !(sigma > 0) || !(tau > 0) || !(c > 0) || !(eps > 0)) {
+    set_error("ct_precond_create: need sigma, tau, c, eps > 0");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  if (!fft_size_ok(n)) {
+    set_error("ct_precond_create: n must be even, 2^a 3^b and <= 4096");
+    return CT_E_UNSUPPORTED;
+  }
+  ct_precond *pc = new (std::nothrow) ct_precond();
+  if (!pc) return CT_E_DEVICE;
+  int rc = precond_init(pc, n, sigma, tau, c, eps);
+  if (rc != CT_OK) {
+    precond_free(pc);
+    delete pc;
+    return rc;
+  }
+  *out = pc;
+  return CT_OK;
+}
+
+int ct_precond_apply(const ct_precond *m, const float *y, float *x, ct_stream s) {
+  clear_error();
+  if (!m || !y || !x) {
+    set_error("ct_precond_apply: null argument");
+    return CT_E_INVALID;
+  }
+  return launch_apply_mult(m, m->d_mult, y, nullptr, x, S(s));
+}
+
+int ct_precond_destroy(ct_precond *m) {
+  clear_error();
+  if (!m) return CT_OK;
+  precond_free(m);
+  delete m;
+  return CT_OK;
+}
+
+int ct_prox_sino(int32_t n_angles, int32_t n_bins, const float *q, double step, const float *u0,
+                 const float *bound, const uint32_t *mask, float *y, ct_stream s) {
+  clear_error();
+  if (n_angles < 1 || n_bins < 1 || !q || !u0 || !y || !(step > 0) || (mask && !bound)) {
+    set_error("ct_prox_sino: invalid argument");
+    return CT_E_INVALID;
+  }
+  return launch_prox_sino(n_angles, n_bins, q, (float)step, u0, bound, mask, y, S(s));
+}
+
+int ct_tv_project(int32_t n, const float *q, double radius, float *w, ct_stream s) {
+  clear_error();
+  if (n < 1 || !q || !w || !(radius >= 0)) {
+    set_error("ct_tv_project: invalid argument");
+    return CT_E_INVALID;
+  }
+  return launch_tv_project(n, q, (float)radius, w, S(s));
+}
+
+int ct_power_norm(const ct_plan *pc, int32_t iters, const float *x0, double *out, ct_stream s) {
+  clear_error();
+  if (!pc || !out || iters < 1) {
+    set_error("ct_power_norm: invalid argument");
+    return CT_E_INVALID;
+  }
+  ct_plan *p = const_cast<ct_plan *>(pc);
+  CT_TRY(plan_scratch(p));
+  const int n = p->g.n;
+  const size_t nn = (size_t)n * n;
+  float *x = p->d_scratch_img, *y = p->d_scratch_img + nn;
+  hipStream_t st = S(s);
+  if (x0) {
+    CT_TRY_HIP(hipMemcpyAsync(x, x0, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+  } else {
+    auto h0 = default_start(n);
+    CT_TRY_HIP(hipMemcpyAsync(x, h0.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+    CT_TRY_HIP(hipStreamSynchronize(st));
+  }
+  double *d_norm = p->d_red + reduction_partials_needed();
+  double lam = 0;
+  auto op = [&](float *xin, float *yout) -> int {
+    CT_TRY(launch_radon_fwd(p, xin, p->d_scratch_sino, st));
+    return launch_radon_adj(p, p->d_scratch_sino, nullptr, 1.0f, 0.0f, yout, st);
+  };
+  CT_TRY(power_iterate(n, iters, x, y, p->d_red, p->red_cap, d_norm, op, st, &lam));
+  *out = std::sqrt(lam);
+  return CT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+
+static int solver_alloc(ct_solver *sv) {
+  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  CT_TRY_HIP(hipMalloc(&sv->u, sizeof(float) * nn));
+  CT_TRY_HIP(hipMalloc(&sv->u_next, sizeof(float) * nn));
+  CT_TRY_HIP(hipMalloc(&sv->utmp, sizeof(float) * nn));
+  CT_TRY_HIP(hipMalloc(&sv->vb2, sizeof(float) * nn * 2));
+  CT_TRY_HIP(hipMalloc(&sv->s2, sizeof(float) * nn * 2));
+  CT_TRY_HIP(hipMalloc(&sv->w, sizeof(float) * nn * 2));
+  CT_TRY_HIP(hipMalloc(&sv->vb1, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->s1, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->target, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->rraw, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->y1, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->r, sizeof(float) * NM));
+  sv->red_cap = reduction_partials_needed() + 16;
+  CT_TRY_HIP(hipMalloc(&sv->d_red, sizeof(double) * sv->red_cap));
+  CT_TRY_HIP(hipMalloc(&sv->d_out, sizeof(double) * 16));
+  return CT_OK;
+}
+
+static int solver_zero_state(ct_solver *sv, hipStream_t s) {
+  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  CT_TRY_HIP(hipMemsetAsync(sv->u, 0, sizeof(float) * nn, s));
+  CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, s));
+  CT_TRY_HIP(hipMemsetAsync(sv->vb2, 0, sizeof(float) * nn * 2, s));
+  CT_TRY_HIP(hipMemsetAsync(sv->s2, 0, sizeof(float) * nn * 2, s));
+  CT_TRY_HIP(hipMemsetAsync(sv->vb1, 0, sizeof(float) * NM, s));
+  CT_TRY_HIP(hipMemsetAsync(sv->s1, 0, sizeof(float) * NM, s));
+  sv->iters = 0;
+  sv->have_dual = false;
+  return CT_OK;
+}
+
+static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *prm,
+                        hipStream_t st) {
+  ct_plan *p = sv->plan;
+  const int n = sv->n, N = sv->N, M = sv->M;
+  const size_t nn = (size_t)n * n, NM = (size_t)N * M;
+  CT_TRY(solver_alloc(sv));
+  if (prob->mask) {
+    const size_t MW = (size_t)(M + 31) / 32;
+    CT_TRY_HIP(hipMalloc(&sv->mask, sizeof(uint32_t) * N * MW));
+    CT_TRY_HIP(hipMemcpyAsync(sv->mask, prob->mask, sizeof(uint32_t) * N * MW,
+                              hipMemcpyDeviceToDevice, st));
+  }
+  if (prm->flags & CT_FLAG_VALIDATE) {
+    int *flag = reinterpret_cast<int *>(sv->d_out);
+    CT_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    CT_TRY(launch_nonfinite(prob->sino, (int64_t)NM, flag, st));
+    if (prob->bound) CT_TRY(launch_nonfinite(prob->bound, (int64_t)NM, flag, st));
+    int hflag = 0;
+    CT_TRY_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    CT_TRY_HIP(hipStreamSynchronize(st));
+    if (hflag || !std::isfinite(prob->bound_scalar)) {
+      set_error("ct_solver_create: non-finite value in sinogram or bound");
+      return CT_E_NONFINITE;
+    }
+  }
+  CT_TRY(precond_init(&sv->pc, n, prm->sigma, prm->tau, -1.0, prm->eps));
+  double *d_norm = sv->d_out;
+  // beta = ||R_h|| (§5.1 normalization; power iteration unless given)
+  if (prm->beta > 0) {
+    sv->beta = prm->beta;
+  } else {
+    if (prm->start_norm)
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, prm->start_norm, sizeof(float) * nn,
+                                hipMemcpyDeviceToDevice, st));
+    else {
+      auto h0 = default_start(n);
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, h0.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+      CT_TRY_HIP(hipStreamSynchronize(st));
+    }
+    auto op = [&](float *xin, float *yout) -> int {
+      CT_TRY(launch_radon_fwd(p, xin, sv->rraw, st));
+      return launch_radon_adj(p, sv->rraw, nullptr, 1.0f, 0.0f, yout, st);
+    };
+    double lam = 0;
+    CT_TRY(power_iterate(n, prm->power_iters, sv->u, sv->utmp, sv->d_red, sv->red_cap, d_norm,
+                         op, st, &lam));
+    sv->beta = std::sqrt(lam);
+  }
+  if (!(sv->beta > 0) || !std::isfinite(sv->beta)) {
+    set_error("ct_solver_create: operator norm estimate is zero or non-finite");
+    return CT_E_INVALID;
+  }
+  // c > lambda_max(tilde M^{-1} A^* A) (§4.3.1), by power iteration on
+  // tilde M^{-1/2} A^* A tilde M^{-1/2} unless given
+  if (prm->c > 0) {
+    sv->c = prm->c;
+  } else {
+    auto tab = multiplier_table(n, prm->sigma, prm->tau, 1.0, prm->eps, true);
+    CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, tab.data(), sizeof(float) * tab.size(),
+                              hipMemcpyHostToDevice, st));
+    CT_TRY_HIP(hipStreamSynchronize(st));
+    if (prm->start_precond)
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, prm->start_precond, sizeof(float) * nn,
+                                hipMemcpyDeviceToDevice, st));
+    else {
+      auto h0 = default_start(n);
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, h0.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+      CT_TRY_HIP(hipStreamSynchronize(st));
+    }
+    const float inv_b2 = (float)(1.0 / (sv->beta * sv->beta));
+    auto op = [&](float *xin, float *yout) -> int {
+      CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, xin, nullptr, sv->u_next, st));
+      CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st));
+      CT_TRY(launch_radon_adj(p, sv->rraw, nullptr, inv_b2, 0.0f, sv->u_next, st));
+      return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->u_next, nullptr, yout, st);
+    };
+    double lam = 0;
+    CT_TRY(power_iterate(n, prm->power_iters, sv->u, sv->utmp, sv->d_red, sv->red_cap, d_norm,
+                         op, st, &lam));
+    sv->c = prm->c_safety * lam;
+  }
+  if (!(sv->c > 0) || !std::isfinite(sv->c)) {
+    set_error("ct_solver_create: preconditioner constant is zero or non-finite");
+    return CT_E_INVALID;
+  }
+  sv->pc.c = sv->c;
+  {
+    auto m = multiplier_table(n, sv->sigma, sv->tau, sv->c, sv->eps, false);
+    CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, m.data(), sizeof(float) * m.size(),
+                              hipMemcpyHostToDevice, st));
+    CT_TRY_HIP(hipStreamSynchronize(st));
+  }
+  CT_TRY(launch_build_target(N, M, prob->sino, prob->bound, prob->bound_scalar, sv->mask,
+                             (float)(1.0 / sv->beta), sv->target, st));
+  sv->lam_t = prob->lambda / (sv->beta * sv->beta);
+  CT_TRY(solver_zero_state(sv, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  return CT_OK;
+}
+
+// One PDRQS1 iteration (§4.4) from the cached s1 = vb1 + sigma A u,
+// s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and A u for the record.
+static int solver_iter(ct_solver *sv, int mode, hipStream_t st) {
+  ct_plan *p = sv->plan;
+  const float sig = (float)sv->sigma, tau = (float)sv->tau;
+  const float inv_h = (float)(1.0 / p->g.h);
+  CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
+                          (float)(sv->sigma * sv->tau), sv->utmp, st));
+  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st));
+  CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st));
+  CT_TRY(launch_sino_update(sv->N, sv->M, sv->rraw, (float)(1.0 / sv->beta), sig, sv->target,
+                            sv->mask, sv->vb1, sv->s1, sv->y1, sv->r, mode, st));
+  CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
+                          sv->vb2, sv->s2, sv->w, mode, st));
+  std::swap(sv->u, sv->u_next);
+  sv->iters += 1;
+  return CT_OK;
+}
+
+extern "C" {
+
+int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
+                     ct_stream s, ct_solver **out) {
+  clear_error();
+  if (!p || !prob || !prm || !out || !prob->sino) {
+    set_error("ct_solver_create: null argument");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  if (!(prm->sigma > 0) || !(prm->tau > 0) || !(prm->eps > 0) || !(prob->lambda >= 0) ||
+      !std::isfinite(prob->lambda) || prm->k_max < 0 || prm->gap_every < 0 ||
+      (prm->c <= 0 && !(prm->c_safety > 0)) ||
+      ((prm->c <= 0 || prm->beta <= 0) && prm->power_iters < 1)) {
+    set_error("ct_solver_create: need sigma, tau, eps > 0, lambda >= 0, k_max >= 0, "
+              "power_iters >= 1 when beta or c is estimated");
+    return CT_E_INVALID;
+  }
+  if (prob->mask && !prob->bound && !std::isfinite(prob->bound_scalar)) {
+    set_error("ct_solver_create: non-finite bound");
+    return CT_E_INVALID;
+  }
+  if (!fft_size_ok(p->g.n)) {
+    set_error("ct_solver_create: n must be even, 2^a 3^b and <= 4096");
+    return CT_E_UNSUPPORTED;
+  }
+  ct_solver *sv = new (std::nothrow) ct_solver();
+  if (!sv) return CT_E_DEVICE;
+  sv->plan = const_cast<ct_plan *>(p);
+  sv->n = p->g.n;
+  sv->N = p->g.n_angles;
+  sv->M = p->g.n_bins;
+  sv->sigma = prm->sigma;
+  sv->tau = prm->tau;
+  sv->eps = prm->eps;
+  int rc = solver_setup(sv, prob, prm, S(s));
+  if (rc != CT_OK) {
+    (void)hipStreamSynchronize(S(s));
+    solver_free(sv);
+    delete sv;
+    return rc;
+  }
+  *out = sv;
+  return CT_OK;
+}
+
+int ct_solver_destroy(ct_solver *sv) {
+  clear_error();
+  if (!sv) return CT_OK;
+  solver_free(sv);
+  delete sv;
+  return CT_OK;
+}
+
+int ct_solver_info(const ct_solver *sv, double out[4]) {
+  clear_error();
+  if (!sv || !out) {
+    set_error("ct_solver_info: null argument");
+    return CT_E_INVALID;
+  }
+  out[0] = sv->beta;
+  out[1] = sv->c;
+  out[2] = sv->lam_t;
+  out[3] = (double)sv->iters;
+  return CT_OK;
+}
+
+int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
+  clear_error();
+  if (!sv || k < 0) {
+    set_error("ct_pd_step: invalid argument");
+    return CT_E_INVALID;
+  }
+  for (int it = 0; it < k; ++it) CT_TRY(solver_iter(sv, it == k - 1 ? 2 : 0, S(s)));
+  if (k > 0) sv->have_dual = true;
+  return CT_OK;
+}
+
+int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_stream s) {
+  clear_error();
+  if (!sv) {
+    set_error("ct_state_export: null solver");
+    return CT_E_INVALID;
+  }
+  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  hipStream_t st = S(s);
+  if (u) CT_TRY_HIP(hipMemcpyAsync(u, sv->u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+  if (vb1)
+    CT_TRY_HIP(hipMemcpyAsync(vb1, sv->vb1, sizeof(float) * NM, hipMemcpyDeviceToDevice, st));
+  if (vb2)
+    CT_TRY_HIP(hipMemcpyAsync(vb2, sv->vb2, sizeof(float) * nn * 2, hipMemcpyDeviceToDevice, st));
+  return CT_OK;
+}
+
+int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float *vb2,
+                    ct_stream s) {
+  clear_error();
+  if (!sv || !u || !vb1 || !vb2) {
+    set_error("ct_state_import: null argument");
+    return CT_E_INVALID;
+  }
+  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  hipStream_t st = S(s);
+  CT_TRY_HIP(hipMemcpyAsync(sv->u, u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+  CT_TRY_HIP(hipMemcpyAsync(sv->vb1, vb1, sizeof(float) * NM, hipMemcpyDeviceToDevice, st));
+  CT_TRY_HIP(hipMemcpyAsync(sv->vb2, vb2, sizeof(float) * nn * 2, hipMemcpyDeviceToDevice, st));
+  // caches: s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u
+  CT_TRY(launch_radon_fwd(sv->plan, sv->u, sv->rraw, st));
+  CT_TRY(launch_sino_update(sv->N, sv->M, sv->rraw, (float)(1.0 / sv->beta), (float)sv->sigma,
+                            sv->target, sv->mask, sv->vb1, sv->s1, nullptr, nullptr, 1, st));
+  CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
+                          (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st));
+  sv->have_dual = false;
+  return CT_OK;
+}
+
+int ct_gap(ct_solver *sv, double out[6], ct_stream s) {
+  clear_error();
+  if (!sv || !out) {
+    set_error("ct_gap: null argument");
+    return CT_E_INVALID;
+  }
+  if (!sv->have_dual) {
+    set_error("ct_gap: no iteration since creation or import");
+    return CT_E_STATE;
+  }
+  hipStream_t st = S(s);
+  double *o = sv->d_out;
+  CT_TRY(launch_sino_gap(sv->N, sv->M, sv->r, sv->y1, sv->target, sv->mask, sv->d_red,
+                         sv->red_cap, o, st));
+  // z = A^* y1 - tau div w  (= K^* y)
+  CT_TRY(launch_radon_adj(sv->plan, sv->y1, sv->w, (float)(1.0 / sv->beta), (float)(-sv->tau),
+                          sv->utmp, st));
+  CT_TRY(launch_img_gap(sv->n, (float)(1.0 / sv->plan->g.h), sv->u, sv->u_next, sv->utmp,
+                        sv->d_red, sv->red_cap, o + 3, st));
+  double h[6];
+  CT_TRY_HIP(hipMemcpyAsync(h, o, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  const double P = h[0] + sv->lam_t * h[3];
+  out[0] = P;
+  out[1] = h[1];
+  out[2] = P + h[1];
+  out[3] = std::sqrt(h[5]);
+  out[4] = h[2];
+  out[5] = std::sqrt(h[4]);
+  return CT_OK;
+}
+
+int ct_reconstruct(const ct_plan *p, const ct_problem *prob, const ct_params *prm, float *u_out,
+                   double *report, int32_t report_len, ct_stream s) {
+  clear_error();
+  if (!u_out) {
+    set_error("ct_reconstruct: null output");
+    return CT_E_INVALID;
+  }
+  ct_solver *sv = nullptr;
+  CT_TRY(ct_solver_create(p, prob, prm, s, &sv));
+  std::unique_ptr<ct_solver, int (*)(ct_solver *)> guard(sv, ct_solver_destroy);
+  int done = 0, rec = 0;
+  if (prm->gap_every > 0 && report) {
+    while (done < prm->k_max) {
+      const int k = std::min(prm->gap_every, prm->k_max - done);
+      CT_TRY(ct_pd_step(sv, k, s));
+      done += k;
+      if (k == prm->gap_every && (rec + 1) * 6 <= report_len) {
+        double r6[6];
+        CT_TRY(ct_gap(sv, r6, s));
+        for (int q = 0; q < 6; ++q) {
+          report[rec * 6 + q] = r6[q];
+          if (!std::isfinite(r6[q])) {
+            set_error("ct_reconstruct: gap record is not finite");
+            return CT_E_DIVERGED;
+          }
+        }
+        ++rec;
+      }
+    }
+  } else {
+    CT_TRY(ct_pd_step(sv, prm->k_max, s));
+  }
+  CT_TRY(ct_state_export(sv, u_out, nullptr, nullptr, s));
+  CT_TRY_HIP(hipStreamSynchronize(S(s)));
+  return CT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Internal declarations shared by the ctpd HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ctpd.h"
+
+namespace ctpd {
+
+// ---------------------------------------------------------------------------
+// Error reporting: every ABI call returns a code and leaves a thread-local
+// message.
+void set_error(const std::string &msg);
+void clear_error();
+
+#define CT_TRY_HIP(expr)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::ctpd::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));    \
+      return CT_E_DEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+#define CT_TRY(expr)                                                            \
+  do {                                                                          \
+    int r_ = (expr);                                                            \
+    if (r_ != CT_OK) return r_;                                                 \
+  } while (0)
+
+// Fixed-point bin coordinate: t * 2^30 as a 64-bit integer (§3.1 bin
+// coordinate t = (x cos + y sin)/ds + (M-1)/2, quantized so that every
+// kernel evaluates the same exact value for a pixel/angle pair).
+constexpr int kFixBits = 30;
+constexpr double kFixOne = 1073741824.0;  // 2^30
+
+// Backprojection (R_h^*) per-angle constants: t(i, j) = t0 + i a + j b, each
+// an exact multiple of 2^-30, so that the FP64 evaluation is exact.
+struct BpAngle {
+  double t0, a, b;
+  int32_t l;  // sinogram row
+  int32_t pad;
+};
+
+// Forward projection (R_h) per-angle constants in the walk frame: with the
+// image re-indexed by (p, q) (transposed and/or mirrored), the fixed-point
+// coordinate is T + p A + q B with A > 0 and 0 <= B <= A.
+struct FpAngle {
+  int64_t T;
+  uint32_t A;
+  uint32_t B;
+  int32_t l;   // sinogram row
+  int32_t pad;
+};
+
+// A group of up to kFpGroup angles of the same walk class, processed by one
+// workgroup (one wave per kFpPerThread angles, 64 bins per workgroup).
+constexpr int kFpWaves = 4;
+constexpr int kFpPerThread = 2;
+constexpr int kFpGroup = kFpWaves * kFpPerThread;  // 8 angles
+constexpr int kFpStrips = 64;                       // strips per workgroup (63 outputs)
+constexpr int kFpRows = 16;                         // image rows staged per chunk
+
+struct FpGroup {
+  int32_t first;  // index into the FpAngle array
+  int32_t count;  // angles in the group (<= kFpGroup)
+  int32_t cls;    // bit0 transpose (walk columns), bit1 mirror inner, bit2 mirror outer
+  int32_t kmin;   // first bin that can receive a nonzero value
+  int32_t kmax;   // last such bin
+  int32_t nblk;   // workgroups needed along the bins
+  int32_t region; // offset of this group's (block, chunk) region table
+  int32_t pad;
+};
+
+// Backprojection tiling.
+constexpr int kBpTile = 16;     // 16 x 16 pixels per workgroup
+constexpr int kBpChunk = 32;    // angles staged per chunk
+
+// FFT plan (mixed radix 2/3/4, Stockham in LDS).
+struct FftPlan {
+  int32_t L;
+  int32_t npass;
+  int32_t radix[24];
+};
+
+}  // namespace ctpd
+
+// Opaque ABI objects.
+struct ct_plan {
+  ct_geom g;
+  int device;
+  // backprojection
+  ctpd::BpAngle *d_bp = nullptr;
+  int seg = 0;  // staged bins per angle per tile
+  // forward projection
+  ctpd::FpAngle *d_fp = nullptr;
+  ctpd::FpGroup *d_groups = nullptr;
+  int2 *d_regions = nullptr;  // (p_lo, width) per (group, block, chunk)
+  int n_groups = 0;
+  int max_blk = 0;
+  int n_chunks = 0;
+  int wmax = 0;     // widest staged region (columns)
+  bool check_first = false;  // strips may hold no pixel of a row (|a| > 1)
+  // scratch for standalone calls
+  float *d_scratch_sino = nullptr;
+  float *d_scratch_img = nullptr;
+  double *d_red = nullptr;   // reduction partials
+  int red_cap = 0;
+};
+
+struct ct_precond {
+  int n;
+  double sigma, tau, c, eps;
+  float *d_mult = nullptr;   // [n/2+1][n] multiplier incl. 1/n^2
+  float2 *d_tw = nullptr;    // twiddles exp(-2 pi i m / n)
+  float2 *d_spec = nullptr;  // spectrum workspace [n/2+1][n]
+  ctpd::FftPlan fp;
+};
+
+namespace ctpd {
+
+// ---- launchers (kernels live in the .hip files) ---------------------------
+// out = c1 * R^*(v) + c2 * div_h(p)  (p may be null)
+int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
+                     float c2, float *out, hipStream_t s);
+// out = R(u) (raw)
+int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s);
+
+int launch_grad(int n, float inv_h, const float *u, float *p, hipStream_t s);
+int launch_div(int n, float inv_h, const float *p, float *d, hipStream_t s);
+int launch_tv_project(int n, const float *q, float radius, float *w, hipStream_t s);
+int launch_prox_sino(int N, int M, const float *q, float step, const float *u0,
+                     const float *bound, const uint32_t *mask, float *y, hipStream_t s);
+
+// Fused dual updates of PDRQS1.
+// mode 0: full step; mode 1: cache only (s1 = vb1 + sigma r); mode 2: full step and
+// write y1 and r for the gap record.
+int launch_sino_update(int N, int M, const float *rraw, float inv_beta, float sigma,
+                       const float *target, const uint32_t *mask, float *vb1, float *s1,
+                       float *y1, float *rout, int mode, hipStream_t s);
+int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius,
+                     float *vb2, float *s2, float *wout, int mode, hipStream_t s);
+int launch_build_target(int N, int M, const float *u0, const float *bound, float bscalar,
+                        const uint32_t *mask, float inv_beta, float *target, hipStream_t s);
+
+// FFT-based multiplier application: out = (base ? base : 0) + F^{-1}(mult F(y)).
+int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
+                      const float *base, float *out, hipStream_t s);
+
+// Reductions (FP64, deterministic two-level).
+int launch_norm2(const float *x, int64_t count, double *partials, int cap, double *out,
+                 hipStream_t s);
+int launch_scale_by_inv(const float *x, int64_t count, const double *norm, float *y,
+                        hipStream_t s);
+int launch_nonfinite(const float *x, int64_t count, int *flag, hipStream_t s);
+// Gap terms: out[0] = 1/2 sum_off (r - b)^2, out[1] = sum_off (y1^2/2 + y1 b) + sum_on y1 C,
+// out[2] = max_on (C - r)_+
+int launch_sino_gap(int N, int M, const float *r, const float *y1, const float *target,
+                    const uint32_t *mask, double *partials, int cap, double *out,
+                    hipStream_t s);
+// out[0] = sum |nabla u| (with 1/h), out[1] = sum (u - uprev)^2, out[2] = sum z^2
+int launch_img_gap(int n, float inv_h, const float *u, const float *uprev, const float *z,
+                   double *partials, int cap, double *out, hipStream_t s);
+
+int reduction_partials_needed();
+
+// FFT plan helpers
+bool fft_factor(int L, FftPlan *fp);
+
+}  // namespace ctpd

@@ -1,0 +1,265 @@
+"""GPU (HIP, gfx950) vs FP64 oracle parity, through the C ABI.
+
+Inputs are drawn once (seeded), rounded to FP32 and handed to both sides; the
+oracle computes in FP64 on the same FP32 values.  Tolerances (relative L2):
+1e-5 for R_h, R_h^*, M^{-1} and one PDRQS1 step (the spec per-step
+bound), 1e-6 for the pointwise kernels (a few FP32 roundings per element),
+1e-4 for the image after a fixed number of iterations.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gap as ogap
+from oracle import geometry, pdrq, power, precond, prox, radon, tv
+
+from oracle_inputs import build, f32
+
+pytestmark = pytest.mark.gpu
+
+ct = pytest.importorskip("paper_1810_03275_amd")
+
+DEV = torch.device("cuda")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# n, N, M, h, ds -- several tiles and a ragged tail, odd M, N = 1, detector
+# narrower than the image diagonal, ds < h (strips without a pixel), h != 1
+GEOMS = [
+    (64, 90, 96, 1.0, 1.0),
+    (54, 37, 81, 1.0, 1.0),
+    (48, 61, 50, 1.0, 1.3),
+    (40, 33, 64, 1.0, 0.8),
+    (96, 1, 140, 1.0, 1.0),
+    (2, 3, 4, 1.0, 1.0),
+    (128, 180, 192, 0.7, 0.7),
+    (100, 45, 150, 1.0, 1.0),
+]
+
+
+@pytest.mark.parametrize("geo", GEOMS, ids=lambda g: "x".join(map(str, g)))
+def test_radon_pair_parity(geo):
+    n, N, M, h, ds = geo
+    print("radon parity", geo, flush=True)
+    g = geometry.Geometry(n, N, M, h, ds)
+    rng = np.random.default_rng(n * 1000 + N)
+    x = f32(rng.uniform(-1, 1, (n, n)))
+    y = f32(rng.uniform(-1, 1, (N, M)))
+    plan = ct.Plan(n, N, M, h, ds)
+    fx = host(plan.radon_fwd(gpu(x)))
+    by = host(plan.radon_adj(gpu(y)))
+    assert rel(fx, radon.radon_fwd(g, x)) <= 1e-5
+    assert rel(by, radon.radon_adj(g, y)) <= 1e-5
+    # the GPU pair is adjoint to FP32 summation accuracy
+    lhs, rhs = np.sum(fx * y), np.sum(x * by)
+    assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(fx) * np.linalg.norm(y)
+
+
+def test_radon_deterministic_and_arbitrary_angles():
+    """Angles need not be uniform or sorted (§3.1 allows any theta_l); results
+    are bitwise reproducible (no atomics)."""
+    n, N, M = 64, 50, 96
+    rng = np.random.default_rng(7)
+    ang = rng.uniform(0, 2 * math.pi, N)
+    plan = ct.Plan(n, N, M, angles=ang)
+    g = geometry.Geometry(n, N, M, thetas=tuple(ang))
+    x = f32(rng.uniform(0, 1, (n, n)))
+    y = f32(rng.uniform(-1, 1, (N, M)))
+    a = host(plan.radon_fwd(gpu(x)))
+    b = host(plan.radon_fwd(gpu(x)))
+    assert np.array_equal(a, b)
+    assert rel(a, radon.radon_fwd(g, x)) <= 1e-5
+    c = host(plan.radon_adj(gpu(y)))
+    assert np.array_equal(c, host(plan.radon_adj(gpu(y))))
+    assert rel(c, radon.radon_adj(g, y)) <= 1e-5
+
+
+def test_grad_div_prox_parity():
+    rng = np.random.default_rng(3)
+    for n, h in ((64, 1.0), (45, 0.5)):
+        u = f32(rng.standard_normal((n, n)))
+        p = f32(rng.standard_normal((2, n, n)))
+        assert rel(host(ct.grad(gpu(u), h)), tv.grad(u, h)) <= 1e-6
+        assert rel(host(ct.div(gpu(p), h)), tv.div(p, h)) <= 1e-6
+        q = f32(rng.standard_normal((2, n, n)))
+        for r in (0.0, 0.3, 10.0):
+            assert rel(host(ct.tv_project(gpu(q), r)) + 1e-30, prox.tv_project(q, r) + 1e-30) <= 1e-6
+    N, M = 37, 70
+    q = f32(rng.standard_normal((N, M)))
+    u0 = f32(rng.standard_normal((N, M)))
+    bd = f32(rng.standard_normal((N, M)))
+    mask = rng.uniform(size=(N, M)) < 0.3
+    for s in (0.5, 1.0, 2.0):
+        got = host(ct.prox_sino(gpu(q), s, gpu(u0), gpu(bd), ct.pack_mask(mask)))
+        assert rel(got, prox.prox_sino(q, s, u0, bd, mask)) <= 1e-6
+        got = host(ct.prox_sino(gpu(q), s, gpu(u0), None, None))
+        assert rel(got, prox.prox_sino(q, s, u0, bd, np.zeros_like(mask))) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [2, 6, 48, 64, 96, 384, 512])
+def test_precond_parity(n):
+    print("precond parity", n, flush=True)
+    rng = np.random.default_rng(n)
+    y = f32(rng.standard_normal((n, n)))
+    sig, tau, c, eps = 1.0, 1 / math.sqrt(8), 0.7, 0.3
+    pc = ct.Precond(n, sig, tau, c, eps)
+    got = host(pc.apply(gpu(y)))
+    assert rel(got, precond.precond_inverse(y, sig, tau, c, eps)) <= 1e-5
+
+
+def test_power_norm_parity():
+    w = synth.workload("C1")
+    g = geometry.Geometry(w.n, w.n_angles, w.n_bins)
+    x0 = f32(w.start_norm)
+    plan = ct.Plan(w.n, w.n_angles, w.n_bins)
+    b_gpu = ct.power_norm(plan, 30, gpu(x0))
+    b_ref = power.radon_norm(lambda u: radon.radon_fwd(g, u), lambda v: radon.radon_adj(g, v), x0, 30)
+    assert abs(b_gpu - b_ref) <= 1e-5 * b_ref
+
+
+def _small_metal_problem(n=64, N=90, M=96):
+    w = synth.workload("C2", n=n, n_angles=N, n_bins=M)
+    g, u0, mask, bound = build(w)
+    return w, g, u0, mask, bound
+
+
+def test_setup_constants_parity():
+    """beta (||R_h||) and c from the GPU's FP32 operators with FP64 norms match
+    the FP64 oracle's power iterations from the same start images."""
+    w, g, u0, mask, bound = _small_metal_problem()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound),
+                   start_norm=gpu(f32(w.start_norm)), start_precond=gpu(f32(w.start_precond)))
+    info = sv.info()
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    assert abs(info["beta"] - s.beta) <= 1e-5 * s.beta
+    assert abs(info["c"] - s.c) <= 1e-5 * s.c
+    assert abs(info["lam_t"] - s.lam_t) <= 1e-5 * s.lam_t
+
+
+@pytest.mark.parametrize("size", [(64, 90, 96), (54, 41, 80)])
+def test_pd_step_parity(size):
+    """One PDRQS1 step from the same (random) state, with the same beta and c."""
+    n, N, M = size
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    rng = np.random.default_rng(11)
+    u = f32(rng.uniform(0, 1, (n, n)))
+    vb1 = f32(0.01 * rng.standard_normal((N, M)))
+    vb2 = f32(s.lam_t / s.params.tau * rng.standard_normal((2, n, n)))
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(1)
+    gu, g1, g2 = (host(t) for t in sv.export())
+    st = pdrq.step(s, pdrq.state_from(s, u, vb1, vb2))
+    assert rel(gu, st.u) <= 1e-5
+    assert rel(g1, st.vb1) <= 1e-5
+    assert rel(g2, st.vb2) <= 1e-5
+    # a second step continues from the GPU-kept caches
+    sv.step(1)
+    gu2 = host(sv.export()[0])
+    st2 = pdrq.step(s, st)
+    assert rel(gu2, st2.u) <= 2e-5
+
+
+def test_end_to_end_c1():
+    """C1 (64^2, 90 x 96, alpha = 0.01, 200 iterations, no metal): the final
+    image matches the oracle to 1e-4; the gap records agree."""
+    w = synth.workload("C1")
+    g, u0, mask, bound = build(w)
+    assert not mask.any()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    u_gpu, rep = ct.reconstruct(plan, gpu(u0), w.alpha, None, None, k_max=w.iters, gap_every=50,
+                                start_norm=gpu(f32(w.start_norm)),
+                                start_precond=gpu(f32(w.start_precond)))
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    st, recs = pdrq.run(s, w.iters, record_every=50)
+    assert rel(host(u_gpu), st.u) <= 1e-4
+    recs = np.array(recs)
+    assert rep.shape == recs.shape
+    assert np.allclose(rep[:, 0], recs[:, 0], rtol=1e-4)          # P
+    assert np.allclose(rep[:, 1], recs[:, 1], rtol=1e-4)          # G*
+    assert np.all(np.abs(rep[:, 2] - recs[:, 2]) <= 1e-4 * np.abs(recs[:, 0]))
+    assert np.allclose(rep[:, 3], recs[:, 3], rtol=2e-2, atol=1e-6)
+    assert np.allclose(rep[:, 5], recs[:, 5], rtol=2e-2, atol=1e-7)
+
+
+def test_end_to_end_metal_small():
+    """C2 recipe on a 64^2 slice (2 scaled metal discs, inequality constraints
+    active on the metal trace): 100 iterations match the oracle to 1e-4."""
+    w, g, u0, mask, bound = _small_metal_problem()
+    assert mask.any()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    u_gpu, rep = ct.reconstruct(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound),
+                                k_max=100, gap_every=100, start_norm=gpu(f32(w.start_norm)),
+                                start_precond=gpu(f32(w.start_precond)))
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    st, recs = pdrq.run(s, 100, record_every=100)
+    assert rel(host(u_gpu), st.u) <= 1e-4
+    assert rep[0, 4] == pytest.approx(recs[0][4], rel=1e-2, abs=1e-6)   # violation
+
+
+def test_full_size_c2_sampled():
+    """512^2, 720 x 768 in the benchmark's launch configuration: R_h and R_h^*
+    spot-checked against the oracle at sampled outputs, and adjointness."""
+    n, N, M = 512, 720, 768
+    g = geometry.Geometry(n, N, M)
+    rng = np.random.default_rng(5)
+    x = f32(rng.uniform(0, 1, (n, n)))
+    y = f32(rng.uniform(-1, 1, (N, M)))
+    plan = ct.Plan(n, N, M)
+    fx = host(plan.radon_fwd(gpu(x)))
+    by = host(plan.radon_adj(gpu(y)))
+    pix = [(int(j), int(i)) for j, i in rng.integers(0, n, (24, 2))] + [(0, 0), (n - 1, n - 1), (0, n - 1)]
+    ref = radon.radon_adj_at(g, y, pix)
+    got = np.array([by[j, i] for j, i in pix])
+    assert rel(got, ref) <= 1e-5
+    bins = [(int(l), int(k)) for l, k in zip(rng.integers(0, N, 40), rng.integers(100, 668, 40))]
+    bins += [(0, 0), (N - 1, M - 1), (N // 4, M // 2), (N // 2, 30)]
+    ref = radon.radon_fwd_at(g, x, bins)
+    got = np.array([fx[l, k] for l, k in bins])
+    assert rel(got, ref) <= 1e-5
+    lhs, rhs = np.sum(fx * y), np.sum(x * by)
+    assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(fx) * np.linalg.norm(y)
+    # mass conservation per angle (every pixel projects inside: 512 sqrt 2 < 768)
+    assert np.allclose(fx.sum(axis=1), x.sum(), rtol=2e-6)
+
+
+def test_errors_from_gpu_side():
+    plan = ct.Plan(64, 10, 96)
+    with pytest.raises(ValueError):
+        plan.radon_fwd(torch.zeros((64, 64)))            # CPU tensor: no CPU path
+    with pytest.raises(ValueError):
+        plan.radon_fwd(torch.zeros((63, 64), device=DEV))
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(ct.Plan(50, 10, 80), torch.zeros((10, 80), device=DEV), 0.1)  # n = 50: not 2^a 3^b
+    sv = ct.Solver(plan, torch.ones((10, 96), device=DEV), 0.1)
+    with pytest.raises(ct.CtpdError):
+        sv.gap()                                          # no iteration yet
+    bad = torch.ones((10, 96), device=DEV)
+    bad[3, 4] = float("nan")
+    with pytest.raises(ct.CtpdError) as e:
+        ct.Solver(plan, bad, 0.1, validate=True)
+    assert e.value.code == -4
