@@ -1,0 +1,206 @@
+"""Benchmark: PDRQS1 iterations/s on one MI355X at 512^2 x 720 angles x 768 bins.
+
+Workload (synthetic, seeded): a 512 x 512 FP32 random-ellipse phantom with two
+metal discs (radius U[8, 20] px, density 20x the tissue maximum), 720 angles on
+[0, pi), 768 bins; bins whose rays touch metal are inequality constraints
+with lower bound 0.95 x the tissue-only projection, L2 fit elsewhere with 0.5 %
+Gaussian noise; alpha = 0.005.  The sinogram, trace and bounds are built with
+the library's own projector.
+
+A step is one PDRQS1 iteration (R_h^* with the u_tmp epilogue, preconditioner
+FFT pair, R_h, sinogram and gradient-side resolvents), run on inputs resident
+in HBM.  Setup (normalization and c power iterations, 30 steps each) is timed
+separately.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PD iterations/s and R+R* pairs/s (Gvox·angles/s) at 512²×720, % HBM roofline"
+N_IMG, N_ANG, N_BIN = 512, 720, 768
+# Published MI355X peaks used for the roofline fields.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FP32 work of one pixel-angle pair in R_h or R_h^*: the weight
+# application (1 - alpha) v_k + alpha v_{k+1} as v_k + alpha (v_{k+1} - v_k)
+# (subtract, multiply-add) and the accumulation (add): 4 flops.
+FLOPS_PER_PAIR = 4.0
+# Algorithmic HBM bytes of one R_h launch: read the image once, write the sinogram once.
+def radon_fwd_bytes(n, N, M):
+    return 4.0 * (n * n + N * M)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("radon.hip", "common.hpp", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_1810_03275_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM traffic per R_h launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "radon_fwd_512x720x768_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def build_inputs(ct, torch, w):
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(a.astype("float32")).to(dev)
+    plan = ct.Plan(w.n, w.n_angles, w.n_bins)
+    tissue_proj = plan.radon_fwd(t(w.tissue))
+    clean = plan.radon_fwd(t(w.phantom))
+    metal_proj = plan.radon_fwd(t(w.metal.astype("float32")))
+    sigma_n = w.noise_level * float(tissue_proj.max())
+    u0 = (clean + sigma_n * t(w.noise)).contiguous()
+    mask = metal_proj > 0
+    bound = torch.where(mask, 0.95 * tissue_proj, torch.zeros_like(tissue_proj)).contiguous()
+    return plan, u0, ct.pack_mask(mask), bound, t(w.start_norm), t(w.start_precond)
+
+
+def time_kernel(torch, fn, reps):
+    """Average duration of fn() over reps launches, HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def cpu_baseline(w, budget_s: float):
+    """The FP64 oracle timed on this host on a bounded sample of the same
+    workload: setup with beta and c given, then PDRQS1 iterations until about
+    budget_s seconds have passed (at least one)."""
+    import numpy as np
+    from oracle import geometry, pdrq, radon
+    g = geometry.Geometry(w.n, w.n_angles, w.n_bins)
+    tissue = radon.radon_fwd(g, w.tissue)
+    u0 = radon.radon_fwd(g, w.phantom) + w.noise_level * tissue.max() * w.noise
+    mask = radon.radon_fwd(g, w.metal.astype(float)) > 0
+    bound = np.where(mask, 0.95 * tissue, 0.0)
+    prob = pdrq.Problem(g, u0, mask, bound, w.alpha)
+    s = pdrq.setup(prob, pdrq.Params(), beta=1.0e3, c=1.0)
+    st = pdrq.zero_state(s)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        st = pdrq.step(s, st)
+        k += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "it/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} PDRQS1 iteration(s) of the 512^2 x 720 x 768 workload in FP64 "
+                      f"NumPy ({dt:.1f} s, single-threaded NumPy/pocketfft; setup with "
+                      f"beta and c given, not timed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding of the path is described in DESIGN.md, not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1810_03275_amd as ct
+    import synth
+
+    w = synth.workload("C2")
+    plan, u0, mask, bound, x0, x1 = build_inputs(ct, torch, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = sv.info()
+
+    sv.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it_s = args.steps / dt
+    rec = sv.gap()
+
+    # dominant kernels, timed alone on the current stream
+    u = sv.export()[0]
+    sino = torch.empty((N_ANG, N_BIN), device="cuda")
+    img = torch.empty((N_IMG, N_IMG), device="cuda")
+    t_fwd = time_kernel(torch, lambda: plan.radon_fwd(u, sino), args.kernel_reps)
+    t_adj = time_kernel(torch, lambda: plan.radon_adj(sino, img), args.kernel_reps)
+    pairs = float(N_IMG * N_IMG * N_ANG)
+    dom_t = max(t_fwd, t_adj)
+    dom_name = "k_radon_fwd" if t_fwd >= t_adj else "k_radon_adj"
+    achieved = FLOPS_PER_PAIR * pairs / dom_t / 1e12
+    traffic = measured_traffic() if dom_name == "k_radon_fwd" else None
+
+    out = {
+        "metric": METRIC,
+        "value": round(it_s, 2),
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512 random-ellipse phantom + 2 metal discs, 720 angles, "
+                               "768 bins, alpha=0.005, inequality constraints on the metal trace",
+                   "image": N_IMG, "angles": N_ANG, "bins": N_BIN, "alpha": w.alpha,
+                   "iterations_per_solve": w.iters},
+        "radon_pairs_per_s": round(2 * pairs / (t_fwd + t_adj) / 1e9, 2),
+        "radon_pairs_unit": "Gvox*angles/s (R+R*)",
+        "t_radon_fwd_us": round(t_fwd * 1e6, 2),
+        "t_radon_adj_us": round(t_adj * 1e6, 2),
+        "setup_ms": round(setup_s * 1e3, 2),
+        "beta": info["beta"], "c": info["c"],
+        "gap_record": [float(x) for x in rec],
+        "roofline": {"kernel": dom_name, "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic,
+                     "hbm_gbs_algorithmic": round(radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
+                                                  / t_fwd / 1e9, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

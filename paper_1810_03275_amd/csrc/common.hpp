@@ -42,7 +42,8 @@ constexpr double kFixOne = 1073741824.0;  // 2^30
 // an exact multiple of 2^-30, so that the FP64 evaluation is exact.
 struct BpAngle {
   double t0, a, b;
-  int32_t l;  // sinogram row
+  int64_t b8_fix;  // 8 b 2^32 (exact: b is a multiple of 2^-30)
+  int32_t l;       // sinogram row
   int32_t pad;
 };
 
@@ -76,9 +77,13 @@ struct FpGroup {
   int32_t pad;
 };
 
-// Backprojection tiling.
-constexpr int kBpTile = 16;     // 16 x 16 pixels per workgroup
-constexpr int kBpChunk = 32;    // angles staged per chunk
+// Backprojection tiling: 256 threads, 32 x 64 pixels, 8 pixels per thread
+// (rows ty, ty + 8, ..., ty + 56).
+constexpr int kBpTileI = 32;
+constexpr int kBpTileJ = 64;
+constexpr int kBpPix = 8;
+constexpr int kBpRowStep = 8;
+constexpr int kBpChunk = 16;    // angles staged per chunk
 
 // FFT plan (mixed radix 2/3/4, Stockham in LDS).
 struct FftPlan {
@@ -96,6 +101,8 @@ struct ct_plan {
   // backprojection
   ctpd::BpAngle *d_bp = nullptr;
   int seg = 0;  // staged bins per angle per tile
+  int bp_slices = 1;           // angle slices of the backprojection grid
+  float *d_bp_part = nullptr;  // [bp_slices][n][n] partial images (bp_slices > 1)
   // forward projection
   ctpd::FpAngle *d_fp = nullptr;
   ctpd::FpGroup *d_groups = nullptr;

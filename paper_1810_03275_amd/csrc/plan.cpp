@@ -45,6 +45,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     bp[l].t0 = (double)T30 / kFixOne;
     bp[l].a = (double)A30 / kFixOne;
     bp[l].b = (double)B30 / kFixOne;
+    bp[l].b8_fix = B30 * 4 * 8;
     bp[l].l = l;
     bp[l].pad = 0;
     max_span = std::max(max_span, std::fabs(bp[l].a) + std::fabs(bp[l].b));
@@ -62,7 +63,18 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     fp[l].pad = 0;
     cls[l] = (tr ? 1 : 0) | (fi ? 2 : 0) | (fo ? 4 : 0);
   }
-  p->seg = (int)std::ceil(15.0 * max_span) + 2;
+  double max_extent = 0.0;  // largest detector span of a tile, in bins
+  for (int l = 0; l < N; ++l)
+    max_extent = std::max(max_extent, (kBpTileI - 1) * std::fabs(bp[l].a) +
+                                          (kBpTileJ - 1) * std::fabs(bp[l].b));
+  p->seg = (int)std::ceil(max_extent) + 2;
+  {
+    const int tiles = ((n + kBpTileI - 1) / kBpTileI) * ((n + kBpTileJ - 1) / kBpTileJ);
+    int S = (1024 + tiles - 1) / tiles;
+    S = std::min(S, 8);
+    S = std::min(S, std::max(1, N / (2 * kBpChunk)));
+    p->bp_slices = std::max(S, 1);
+  }
   p->check_first = check_first;
 
   // group angles by class, kFpGroup at a time (angle order kept within a class)
@@ -140,6 +152,8 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   }
   if (regions.empty()) regions.push_back(make_int2(0, 4));
   CT_TRY_HIP(hipMalloc(&p->d_bp, sizeof(BpAngle) * N));
+  if (p->bp_slices > 1)
+    CT_TRY_HIP(hipMalloc(&p->d_bp_part, sizeof(float) * (size_t)p->bp_slices * n * n));
   CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * N));
   CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * groups.size()));
   CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * regions.size()));
@@ -155,6 +169,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
 void free_plan(ct_plan *p) {
   if (!p) return;
   (void)hipFree(p->d_bp);
+  (void)hipFree(p->d_bp_part);
   (void)hipFree(p->d_fp);
   (void)hipFree(p->d_groups);
   (void)hipFree(p->d_regions);

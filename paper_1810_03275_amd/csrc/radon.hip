@@ -11,34 +11,55 @@
 
 namespace ctpd {
 
+// clamp x to [lo, hi] in one instruction
+__device__ inline int med3i(int x, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
+
 // ---------------------------------------------------------------------------
-// R_h^*: pixel-driven gather.  One workgroup per 16x16 pixel tile, one pixel
-// per thread.  Angles are processed in chunks; for every angle of a chunk the
-// detector segment the tile projects onto is staged in LDS as pairs
-// (v[k], v[k+1] - v[k]) so that one 8-byte LDS read and one FMA interpolate.
-// Epilogue: out = c1 * R^*(v) + c2 * div_h(p) (p optional; §3.1 divergence).
+// R_h^*: pixel-driven gather.
+//
+// One workgroup per kBpTileI x kBpTileJ pixel tile and per angle slice (the
+// angles are split over gridDim.z slices whose partial images are summed by
+// k_bp_combine when there is more than one).  Thread (tx, ty) owns the
+// kBpPix pixels (i0 + tx, j0 + ty + 8 p).  For every chunk of kBpChunk angles
+// the detector segment the tile projects onto is staged in LDS as pairs
+// (v[k], v[k+1] - v[k]).  Per angle a thread evaluates its first pixel's
+// bin coordinate exactly in FP64, splits it into a local bin index (hi) and a
+// 32-bit fraction (lo), then steps to its other pixels with exact 64-bit
+// integer additions of 8 b 2^32.  alpha = lo 2^-32 is rounded once to FP32,
+// the same rounding as the forward projector's.
 __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
-    int seg, const float *__restrict__ pfield, float c1, float c2, float inv_h,
+    int seg, int slice_len, const float *__restrict__ pfield, float c1, float c2, float inv_h,
     float *__restrict__ out) {
   extern __shared__ float2 vd[];  // kBpChunk * seg
-  __shared__ int kmin_s[kBpChunk];
   __shared__ int row_s[kBpChunk];
-  const int tx = threadIdx.x & (kBpTile - 1);
-  const int ty = threadIdx.x / kBpTile;
-  const int i0 = blockIdx.x * kBpTile, j0 = blockIdx.y * kBpTile;
-  const int i = i0 + tx, j = j0 + ty;
-  const bool inside = (i < n) && (j < n);
-  const double di = (double)i, dj = (double)j;
-  float acc_v = 0.f, acc_d = 0.f;
+  __shared__ int kmin_s[kBpChunk];
+  const int tx = threadIdx.x & (kBpTileI - 1);
+  const int ty = threadIdx.x / kBpTileI;  // 0..7
+  const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBpTileJ;
+  const int i = i0 + tx;
+  const int jb = j0 + ty;
+  const double di = (double)i, dj = (double)jb;
+  const int a_begin = blockIdx.z * slice_len;
+  const int a_end = min(N, a_begin + slice_len);
+  float accv[kBpPix], accd[kBpPix];
+#pragma unroll
+  for (int p = 0; p < kBpPix; ++p) {
+    accv[p] = 0.f;
+    accd[p] = 0.f;
+  }
 
-  for (int c0 = 0; c0 < N; c0 += kBpChunk) {
-    const int nc = min(kBpChunk, N - c0);
+  for (int c0 = a_begin; c0 < a_end; c0 += kBpChunk) {
+    const int nc = min(kBpChunk, a_end - c0);
     __syncthreads();
     if ((int)threadIdx.x < nc) {
       const BpAngle A = ang[c0 + threadIdx.x];
-      const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTile - 1);
-      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBpTile - 1);
+      const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
+      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBpTileJ - 1);
       const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
       kmin_s[threadIdx.x] = (int)floor(tmin);
       row_s[threadIdx.x] = A.l;
@@ -54,41 +75,92 @@ __global__ __launch_bounds__(256) void k_radon_adj(
       vd[idx] = make_float2(v0, v1 - v0);
     }
     __syncthreads();
-    if (inside) {
-      for (int c = 0; c < nc; ++c) {
-        const BpAngle A = ang[c0 + c];
-        const double t = fma(dj, A.b, fma(di, A.a, A.t0));  // exact
-        const double fl = floor(t);
-        const int kk = min(max((int)fl - kmin_s[c], 0), seg - 1);
-        const float al = (float)(t - fl);                     // one rounding
-        const float2 p = vd[c * seg + kk];
-        acc_v += p.x;
-        acc_d = fmaf(al, p.y, acc_d);
+    for (int c = 0; c < nc; ++c) {
+      const BpAngle A = ang[c0 + c];
+      // first pixel: exact FP64 coordinate relative to the staged segment
+      const double t = fma(dj, A.b, fma(di, A.a, A.t0 - (double)kmin_s[c]));
+      const double fl = floor(t);
+      int hi = (int)fl;
+      uint32_t lo = (uint32_t)((t - fl) * 4294967296.0);  // exact: t is a multiple of 2^-30
+      const uint64_t step = (uint64_t)A.b8_fix;            // 8 b 2^32, exact
+      const uint32_t slo = (uint32_t)step, shi = (uint32_t)(step >> 32);
+      const float2 *seg_c = vd + c * seg;
+#pragma unroll
+      for (int p = 0; p < kBpPix; ++p) {
+        if (p > 0) {
+          const uint32_t nlo = lo + slo;
+          hi += (int)(shi + (nlo < lo ? 1u : 0u));
+          lo = nlo;
+        }
+        const int kk = min(max(hi, 0), seg - 1);
+        const float2 q = seg_c[kk];
+        accv[p] += q.x;
+        accd[p] = fmaf((float)lo, q.y, accd[p]);
       }
     }
   }
-  if (!inside) return;
-  float res = c1 * (acc_v + acc_d);
+  const float inv32 = 2.3283064365386963e-10f;  // 2^-32
+  const bool final_out = (gridDim.z == 1);
+#pragma unroll
+  for (int p = 0; p < kBpPix; ++p) {
+    const int j = jb + kBpRowStep * p;
+    if (i >= n || j >= n) continue;
+    const size_t o = (size_t)j * n + i;
+    const float r = fmaf(accd[p], inv32, accv[p]);
+    if (!final_out) {
+      out[(size_t)blockIdx.z * n * n + o] = r;
+      continue;
+    }
+    float res = c1 * r;
+    if (pfield != nullptr) {
+      const float *p1 = pfield;
+      const float *p2 = pfield + (size_t)n * n;
+      const float d1 = (i < n - 1 ? p1[o] : 0.f) - (i > 0 ? p1[o - 1] : 0.f);
+      const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
+      res = fmaf(c2 * inv_h, d1 + d2, res);
+    }
+    out[o] = res;
+  }
+}
+
+// out = c1 * sum_s part[s] + c2 * div_h(p): the angle slices' partial
+// backprojections summed in slice order, with the same epilogue.
+__global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
+                             const float *__restrict__ pfield, float c1, float c2, float inv_h,
+                             float *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  const size_t o = (size_t)j * n + i, nn = (size_t)n * n;
+  float r = part[o];
+  for (int s = 1; s < S; ++s) r += part[s * nn + o];
+  float res = c1 * r;
   if (pfield != nullptr) {
     const float *p1 = pfield;
-    const float *p2 = pfield + (size_t)n * n;
-    const size_t o = (size_t)j * n + i;
+    const float *p2 = pfield + nn;
     const float d1 = (i < n - 1 ? p1[o] : 0.f) - (i > 0 ? p1[o - 1] : 0.f);
     const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
     res = fmaf(c2 * inv_h, d1 + d2, res);
   }
-  out[(size_t)j * n + i] = res;
+  out[o] = res;
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s) {
   const int n = p->g.n;
-  dim3 grid((n + kBpTile - 1) / kBpTile, (n + kBpTile - 1) / kBpTile);
+  const int S = p->bp_slices;
+  const int slice_len = (p->g.n_angles + S - 1) / S;
+  dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S);
   const size_t lds = sizeof(float2) * kBpChunk * p->seg;
-  hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles,
-                     p->g.n_bins, p->d_bp, p->seg, pfield, c1, c2, (float)(1.0 / p->g.h),
-                     out);
+  float *dst = (S == 1) ? out : p->d_bp_part;
+  hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
+                     p->d_bp, p->seg, slice_len, pfield, c1, c2, (float)(1.0 / p->g.h), dst);
   CT_TRY_HIP(hipGetLastError());
+  if (S > 1) {
+    hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n), dim3(256), 0, s, p->d_bp_part, S,
+                       n, pfield, c1, c2, (float)(1.0 / p->g.h), out);
+    CT_TRY_HIP(hipGetLastError());
+  }
   return CT_OK;
 }
 
@@ -108,10 +180,11 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
 // kFpStrips consecutive strips; image rows are staged in LDS kFpRows at a
 // time over the column range precomputed on the host for that
 // (group, block, chunk).  Lane 0's strip only supplies Q_{k-1} to lane 1.
+template <bool CHECK_FIRST>
 __global__ __launch_bounds__(256) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions, int n_chunks,
-    int ldw, int check_first, float *__restrict__ sino) {
+    int ldw, float *__restrict__ sino) {
   extern __shared__ float tile[];  // kFpRows * ldw
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
@@ -138,28 +211,26 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 
   const int kb = grp.kmin + blk * (kFpStrips - 1);  // first output bin
   const int k = kb - 1 + lane;                      // this lane's strip
+  const uint32_t one = 1u << kFixBits;
 
+  // Walk state per angle slot.  Inactive slots (beyond the group's count)
+  // walk a harmless empty strip: their results are never stored.
   uint32_t e[kFpPerThread], A[kFpPerThread], B[kFpPerThread];
   int ps[kFpPerThread];
   float P[kFpPerThread], Q[kFpPerThread];
-  int lrow[kFpPerThread];
-  bool act[kFpPerThread];
 #pragma unroll
   for (int g = 0; g < kFpPerThread; ++g) {
     const int slot = wave * kFpPerThread + g;
-    act[g] = slot < grp.count;
     P[g] = 0.f;
     Q[g] = 0.f;
     e[g] = 0u;
-    ps[g] = 0;
-    A[g] = 1u;
+    ps[g] = -(1 << 29);
+    A[g] = one;
     B[g] = 0u;
-    lrow[g] = 0;
-    if (act[g]) {
+    if (slot < grp.count) {
       const FpAngle fa = angs[grp.first + slot];
       A[g] = fa.A;
       B[g] = fa.B;
-      lrow[g] = fa.l;
       const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T;
       int64_t pp = (int64_t)ceil((double)num / (double)fa.A);
       int64_t ee = pp * (int64_t)fa.A - num;
@@ -180,7 +251,7 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   const bool tr = (grp.cls & 1) != 0;
   const bool fi = (grp.cls & 2) != 0;
   const bool fo = (grp.cls & 4) != 0;
-  const uint32_t one = 1u << kFixBits;
+  constexpr int RB = 8;  // rows whose LDS reads are issued together
 
   for (int ch = 0; ch < n_chunks; ++ch) {
     const int q0 = ch * kFpRows;
@@ -216,23 +287,69 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
       }
     }
     __syncthreads();
-    const int wmax2 = W - 2;
-    for (int r = 0; r < rows; ++r) {
-      const float *trow = tile + r * ldw;
+    // The strip's first pixel ps, clamped to [-2, n] (zero-staged columns
+    // outside the image), addresses the staged row at byte offset
+    // 4 (r ldw + ps - plo).
+    const int cneg = -2, cpos = n;
+    int r0 = 0;
+    for (; r0 + RB <= rows; r0 += RB) {
+      uint32_t off[RB][kFpPerThread], ev[RB][kFpPerThread];
+      // 1. the walk: positions and fractions of RB rows (independent of the data)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int rowbase = ((r0 + r) * ldw - plo) * 4;
+#pragma unroll
+        for (int g = 0; g < kFpPerThread; ++g) {
+          off[r][g] = (uint32_t)(med3i(ps[g], cneg, cpos) * 4 + rowbase);
+          ev[r][g] = e[g];
+          const uint32_t en = e[g] + B[g];
+          const bool m = en >= A[g];
+          e[g] = m ? en - A[g] : en;
+          ps[g] -= m ? 1 : 0;
+        }
+      }
+      // 2. all LDS reads of the batch
+      float u1[RB][kFpPerThread], u2[RB][kFpPerThread];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+#pragma unroll
+        for (int g = 0; g < kFpPerThread; ++g) {
+          const float *pt = reinterpret_cast<const float *>(
+              reinterpret_cast<const char *>(tile) + off[r][g]);
+          u1[r][g] = pt[0];
+          u2[r][g] = pt[1];
+        }
+      }
+      // 3. accumulate: strip pixels ps (fraction e) and ps+1 (fraction e + A)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+#pragma unroll
+        for (int g = 0; g < kFpPerThread; ++g) {
+          const uint32_t e1 = ev[r][g];
+          const uint32_t e2 = e1 + A[g];
+          float a1 = u1[r][g];
+          if (CHECK_FIRST) a1 = (e1 < one) ? a1 : 0.f;
+          const float a2 = (e2 < one) ? u2[r][g] : 0.f;
+          P[g] += a1 + a2;
+          Q[g] = fmaf((float)e1, a1, Q[g]);
+          Q[g] = fmaf((float)e2, a2, Q[g]);
+        }
+      }
+    }
+    for (int r = r0; r < rows; ++r) {  // ragged last chunk
 #pragma unroll
       for (int g = 0; g < kFpPerThread; ++g) {
-        if (!act[g]) continue;
-        int c = min(max(ps[g], -2), n) - plo;
-        c = min(max(c, 0), wmax2);
-        float u1 = trow[c];
-        float u2 = trow[c + 1];
-        const uint32_t e2 = e[g] + A[g];
-        if (check_first) u1 = (e[g] < one) ? u1 : 0.f;
-        u2 = (e2 < one) ? u2 : 0.f;
-        P[g] += u1 + u2;
-        Q[g] = fmaf((float)e[g], u1, Q[g]);
-        Q[g] = fmaf((float)e2, u2, Q[g]);
-        const uint32_t en = e[g] + B[g];
+        const int c = med3i(ps[g], cneg, cpos) - plo;
+        const float *trow = tile + r * ldw;
+        const uint32_t e1 = e[g];
+        const uint32_t e2 = e1 + A[g];
+        float a1 = trow[c];
+        if (CHECK_FIRST) a1 = (e1 < one) ? a1 : 0.f;
+        const float a2 = (e2 < one) ? trow[c + 1] : 0.f;
+        P[g] += a1 + a2;
+        Q[g] = fmaf((float)e1, a1, Q[g]);
+        Q[g] = fmaf((float)e2, a2, Q[g]);
+        const uint32_t en = e1 + B[g];
         const bool m = en >= A[g];
         e[g] = m ? en - A[g] : en;
         ps[g] -= m ? 1 : 0;
@@ -243,10 +360,11 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   const float inv = 1.0f / (float)one;
 #pragma unroll
   for (int g = 0; g < kFpPerThread; ++g) {
-    if (!act[g]) continue;
+    const int slot = wave * kFpPerThread + g;
     const float qprev = __shfl_up(Q[g], 1, 64);
-    if (lane >= 1 && k <= grp.kmax && k < M) {
-      sino[(size_t)lrow[g] * M + k] = fmaf(qprev - Q[g], inv, P[g]);
+    if (slot < grp.count && lane >= 1 && k <= grp.kmax && k < M) {
+      const int l = angs[grp.first + slot].l;
+      sino[(size_t)l * M + k] = fmaf(qprev - Q[g], inv, P[g]);
     }
   }
 }
@@ -255,8 +373,12 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1);
   const int ldw = (p->wmax % 2 == 0) ? p->wmax + 1 : p->wmax;
   const size_t lds = sizeof(float) * kFpRows * ldw;
-  hipLaunchKernelGGL(k_radon_fwd, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins, p->d_fp,
-                     p->d_groups, p->d_regions, p->n_chunks, ldw, p->check_first ? 1 : 0, out);
+  if (p->check_first)
+    hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
+                       p->d_fp, p->d_groups, p->d_regions, p->n_chunks, ldw, out);
+  else
+    hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
+                       p->d_fp, p->d_groups, p->d_regions, p->n_chunks, ldw, out);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }
