@@ -65,6 +65,8 @@ constexpr int kFpPerThread = 2;
 constexpr int kFpGroup = kFpWaves * kFpPerThread;  // 8 angles
 constexpr int kFpStrips = 64;                       // strips per workgroup (63 outputs)
 constexpr int kFpRows = 16;                         // image rows staged per chunk
+constexpr int kFpPrefetch = 12;                     // staged pixels per thread (width <= 192)
+constexpr int kFpMaxWidth = 192;
 
 struct FpGroup {
   int32_t first;  // index into the FpAngle array
@@ -84,6 +86,7 @@ constexpr int kBpTileJ = 64;
 constexpr int kBpPix = 8;
 constexpr int kBpRowStep = 8;
 constexpr int kBpChunk = 16;    // angles staged per chunk
+constexpr int kBpPrefetch = 8;  // staged pairs per thread: kBpChunk * seg <= 2048
 
 // FFT plan (mixed radix 2/3/4, Stockham in LDS).
 struct FftPlan {

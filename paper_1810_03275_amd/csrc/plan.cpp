@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
 
 #include "common.hpp"
 
@@ -68,6 +69,10 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     max_extent = std::max(max_extent, (kBpTileI - 1) * std::fabs(bp[l].a) +
                                           (kBpTileJ - 1) * std::fabs(bp[l].b));
   p->seg = (int)std::ceil(max_extent) + 2;
+  if (kBpChunk * p->seg > 256 * kBpPrefetch) {
+    set_error("projector plan: backprojection segment too long (ds/h too small)");
+    return CT_E_UNSUPPORTED;
+  }
   {
     const int tiles = ((n + kBpTileI - 1) / kBpTileI) * ((n + kBpTileJ - 1) / kBpTileJ);
     int S = (1024 + tiles - 1) / tiles;
@@ -83,22 +88,12 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls[x] < cls[y]; });
   std::vector<FpAngle> fps(N);
   for (int i = 0; i < N; ++i) fps[i] = fp[order[i]];
-  std::vector<FpGroup> groups;
-  for (int i = 0; i < N;) {
-    int j = i;
-    while (j < N && j - i < kFpGroup && cls[order[j]] == cls[order[i]]) ++j;
-    FpGroup G{};
-    G.first = i;
-    G.count = j - i;
-    G.cls = cls[order[i]];
-    groups.push_back(G);
-    i = j;
-  }
   const int n_chunks = (n + kFpRows - 1) / kFpRows;
   const int64_t one = (int64_t)1 << kFixBits;
-  std::vector<int2> regions;
-  int wmax = 4, max_blk = 1;
-  for (auto &G : groups) {
+
+  // Bins a group can reach and the staged column range of every
+  // (block, chunk); returns the widest range.
+  auto layout = [&](FpGroup &G, std::vector<int2> *out) -> int {
     int64_t tmin = INT64_MAX, tmax = INT64_MIN;
     for (int a = 0; a < G.count; ++a) {
       const FpAngle &f = fps[G.first + a];
@@ -118,8 +113,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
       G.kmax = (int)kmax;
       G.nblk = (int)((kmax - kmin + 1 + (kFpStrips - 2)) / (kFpStrips - 1));
     }
-    G.region = (int)regions.size();
-    max_blk = std::max(max_blk, G.nblk);
+    int wmax_g = 0;
     for (int b = 0; b < G.nblk; ++b) {
       const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
       const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
@@ -137,17 +131,39 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
         lo -= 1;
         hi += 1;
         const int W = (int)(hi - lo + 1);
-        regions.push_back(make_int2((int)lo, W));
-        wmax = std::max(wmax, W);
+        if (out) out->push_back(make_int2((int)lo, W));
+        wmax_g = std::max(wmax_g, W);
       }
     }
+    return wmax_g;
+  };
+
+  std::vector<FpGroup> groups;
+  std::vector<int2> regions;
+  int wmax = 4, max_blk = 1;
+  for (int i = 0; i < N;) {
+    int j = i;
+    while (j < N && j - i < kFpGroup && cls[order[j]] == cls[order[i]]) ++j;
+    FpGroup G{};
+    G.first = i;
+    G.cls = cls[order[i]];
+    G.count = j - i;
+    // fewer angles per group when their strips spread too far apart
+    while (G.count > 1 && layout(G, nullptr) > kFpMaxWidth) G.count = (G.count + 1) / 2;
+    G.region = (int)regions.size();
+    const int w = layout(G, &regions);
+    wmax = std::max(wmax, w);
+    max_blk = std::max(max_blk, G.nblk);
+    groups.push_back(G);
+    i += G.count;
   }
   p->n_groups = (int)groups.size();
   p->max_blk = max_blk;
   p->n_chunks = n_chunks;
   p->wmax = wmax;
-  if ((size_t)kFpRows * (wmax + 1) * sizeof(float) > 96 * 1024) {
-    set_error("projector plan: staged region too wide for LDS");
+  if (wmax > kFpMaxWidth) {
+    set_error("projector plan: staged region wider than " + std::to_string(kFpMaxWidth) +
+              " columns (too few angles for the group size)");
     return CT_E_UNSUPPORTED;
   }
   if (regions.empty()) regions.push_back(make_int2(0, 4));

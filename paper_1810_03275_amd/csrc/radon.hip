@@ -31,13 +31,54 @@ __device__ inline int med3i(int x, int lo, int hi) {
 // 32-bit fraction (lo), then steps to its other pixels with exact 64-bit
 // integer additions of 8 b 2^32.  alpha = lo 2^-32 is rounded once to FP32,
 // the same rounding as the forward projector's.
+__device__ inline void bp_chunk_meta(const BpAngle *__restrict__ ang, int c0, int nc, int i0, int j0,
+                                     int *kmin_s, int *row_s) {
+  if ((int)threadIdx.x < nc) {
+    const BpAngle A = ang[c0 + threadIdx.x];
+    const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
+    const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBpTileJ - 1);
+    const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
+    kmin_s[threadIdx.x] = (int)floor(tmin);
+    row_s[threadIdx.x] = A.l;
+  }
+}
+
+// Segment values of one chunk into registers: entry idx = tid + 256 m holds
+// (v[k], v[k+1]) for angle idx / seg, bin kmin + idx % seg (zero off the detector).
+__device__ inline void bp_stage_load(float2 (&v)[kBpPrefetch], const float *__restrict__ sino,
+                                     int M, int seg, int nc, const int *kmin_s,
+                                     const int *row_s) {
+#pragma unroll
+  for (int m = 0; m < kBpPrefetch; ++m) {
+    const int idx = threadIdx.x + 256 * m;
+    float v0 = 0.f, v1 = 0.f;
+    if (idx < nc * seg) {
+      const int c = idx / seg;
+      const int k = kmin_s[c] + (idx - c * seg);
+      const float *row = sino + (size_t)row_s[c] * M;
+      if (k >= 0 && k < M) v0 = row[k];
+      if (k + 1 >= 0 && k + 1 < M) v1 = row[k + 1];
+    }
+    v[m] = make_float2(v0, v1);
+  }
+}
+
+__device__ inline void bp_stage_store(const float2 (&v)[kBpPrefetch], float2 *vd, int seg,
+                                      int nc) {
+#pragma unroll
+  for (int m = 0; m < kBpPrefetch; ++m) {
+    const int idx = threadIdx.x + 256 * m;
+    if (idx < nc * seg) vd[idx] = make_float2(v[m].x, v[m].y - v[m].x);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
     int seg, int slice_len, const float *__restrict__ pfield, float c1, float c2, float inv_h,
     float *__restrict__ out) {
-  extern __shared__ float2 vd[];  // kBpChunk * seg
-  __shared__ int row_s[kBpChunk];
-  __shared__ int kmin_s[kBpChunk];
+  extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
+  __shared__ int row_s[3][kBpChunk];
+  __shared__ int kmin_s[3][kBpChunk];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
   const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBpTileJ;
@@ -46,6 +87,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   const double di = (double)i, dj = (double)jb;
   const int a_begin = blockIdx.z * slice_len;
   const int a_end = min(N, a_begin + slice_len);
+  const int nchunks = a_end > a_begin ? (a_end - a_begin + kBpChunk - 1) / kBpChunk : 0;
   float accv[kBpPix], accd[kBpPix];
 #pragma unroll
   for (int p = 0; p < kBpPix; ++p) {
@@ -53,32 +95,31 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     accd[p] = 0.f;
   }
 
-  for (int c0 = a_begin; c0 < a_end; c0 += kBpChunk) {
+  // Chunk it's detector segments are double-buffered in LDS (the chunk
+  // metadata triple-buffered); chunk it+1 is loaded into registers while
+  // chunk it is interpolated.
+  float2 pf[kBpPrefetch];
+  if (nchunks > 0) {
+    bp_chunk_meta(ang, a_begin, min(kBpChunk, a_end - a_begin), i0, j0, kmin_s[0], row_s[0]);
+    __syncthreads();
+    bp_stage_load(pf, sino, M, seg, min(kBpChunk, a_end - a_begin), kmin_s[0], row_s[0]);
+  }
+  for (int it = 0; it < nchunks; ++it) {
+    const int c0 = a_begin + it * kBpChunk;
     const int nc = min(kBpChunk, a_end - c0);
+    const int slot = it % 3;
+    float2 *vd = vd_all + (it & 1) * (kBpChunk * seg);
+    bp_stage_store(pf, vd, seg, nc);
+    const int c1n = c0 + kBpChunk;
+    const int ncn = min(kBpChunk, a_end - c1n);
+    if (it + 1 < nchunks) bp_chunk_meta(ang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
     __syncthreads();
-    if ((int)threadIdx.x < nc) {
-      const BpAngle A = ang[c0 + threadIdx.x];
-      const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
-      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBpTileJ - 1);
-      const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
-      kmin_s[threadIdx.x] = (int)floor(tmin);
-      row_s[threadIdx.x] = A.l;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nc * seg; idx += blockDim.x) {
-      const int c = idx / seg;
-      const int e = idx - c * seg;
-      const int k = kmin_s[c] + e;
-      const float *row = sino + (size_t)row_s[c] * M;
-      const float v0 = (k >= 0 && k < M) ? row[k] : 0.f;
-      const float v1 = (k + 1 >= 0 && k + 1 < M) ? row[k + 1] : 0.f;
-      vd[idx] = make_float2(v0, v1 - v0);
-    }
-    __syncthreads();
+    if (it + 1 < nchunks)
+      bp_stage_load(pf, sino, M, seg, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
     for (int c = 0; c < nc; ++c) {
       const BpAngle A = ang[c0 + c];
       // first pixel: exact FP64 coordinate relative to the staged segment
-      const double t = fma(dj, A.b, fma(di, A.a, A.t0 - (double)kmin_s[c]));
+      const double t = fma(dj, A.b, fma(di, A.a, A.t0 - (double)kmin_s[slot][c]));
       const double fl = floor(t);
       int hi = (int)fl;
       uint32_t lo = (uint32_t)((t - fl) * 4294967296.0);  // exact: t is a multiple of 2^-30
@@ -151,7 +192,7 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   const int S = p->bp_slices;
   const int slice_len = (p->g.n_angles + S - 1) / S;
   dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S);
-  const size_t lds = sizeof(float2) * kBpChunk * p->seg;
+  const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;
   float *dst = (S == 1) ? out : p->d_bp_part;
   hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
                      p->d_bp, p->seg, slice_len, pfield, c1, c2, (float)(1.0 / p->g.h), dst);
@@ -180,6 +221,68 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
 // kFpStrips consecutive strips; image rows are staged in LDS kFpRows at a
 // time over the column range precomputed on the host for that
 // (group, block, chunk).  Lane 0's strip only supplies Q_{k-1} to lane 1.
+
+// Staging of one chunk of kFpRows walk rows x W columns (W <= 192) for the
+// forward projector: each thread loads kFpPrefetch pixels (zero outside the
+// image).  Walk rows are image rows (tr = false: lanes run along the row) or
+// image columns (tr = true: lanes run along q, contiguous in memory).
+__device__ inline void fp_stage_load(float (&v)[kFpPrefetch], const float *__restrict__ u, int n,
+                                     bool tr, bool fi, bool fo, int q0, int rows, int plo,
+                                     int W) {
+  const int t = threadIdx.x;
+  if (!tr) {
+#pragma unroll
+    for (int mr = 0; mr < 4; ++mr) {
+      const int r = (t >> 6) + 4 * mr;
+      const int q = q0 + r;
+      const int jj = fo ? n - 1 - q : q;
+#pragma unroll
+      for (int mc = 0; mc < 3; ++mc) {
+        const int c = (t & 63) + 64 * mc;
+        const int p = plo + c;
+        float x = 0.f;
+        if (r < rows && c < W && p >= 0 && p < n) x = u[(size_t)jj * n + (fi ? n - 1 - p : p)];
+        v[mr * 3 + mc] = x;
+      }
+    }
+  } else {
+    const int r = t & (kFpRows - 1);
+    const int q = q0 + r;
+    const int ii = fo ? n - 1 - q : q;
+#pragma unroll
+    for (int m = 0; m < kFpPrefetch; ++m) {
+      const int c = (t >> 4) + 16 * m;
+      const int p = plo + c;
+      float x = 0.f;
+      if (r < rows && c < W && p >= 0 && p < n) x = u[(size_t)(fi ? n - 1 - p : p) * n + ii];
+      v[m] = x;
+    }
+  }
+}
+
+__device__ inline void fp_stage_store(const float (&v)[kFpPrefetch], float *tile, int ldw, bool tr,
+                                      int rows, int W) {
+  const int t = threadIdx.x;
+  if (!tr) {
+#pragma unroll
+    for (int mr = 0; mr < 4; ++mr) {
+      const int r = (t >> 6) + 4 * mr;
+#pragma unroll
+      for (int mc = 0; mc < 3; ++mc) {
+        const int c = (t & 63) + 64 * mc;
+        if (r < rows && c < W) tile[r * ldw + c] = v[mr * 3 + mc];
+      }
+    }
+  } else {
+    const int r = t & (kFpRows - 1);
+#pragma unroll
+    for (int m = 0; m < kFpPrefetch; ++m) {
+      const int c = (t >> 4) + 16 * m;
+      if (r < rows && c < W) tile[r * ldw + c] = v[m];
+    }
+  }
+}
+
 template <bool CHECK_FIRST>
 __global__ __launch_bounds__(256) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
@@ -253,40 +356,25 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   const bool fo = (grp.cls & 4) != 0;
   constexpr int RB = 8;  // rows whose LDS reads are issued together
 
+  // Staged image rows are double-buffered; the next chunk's pixels are
+  // loaded into registers while the current chunk is walked.
+  float pf[kFpPrefetch];
+  int2 rg_next = reg[0];
+  fp_stage_load(pf, u, n, tr, fi, fo, 0, min(kFpRows, n), rg_next.x, rg_next.y);
   for (int ch = 0; ch < n_chunks; ++ch) {
     const int q0 = ch * kFpRows;
     const int rows = min(kFpRows, n - q0);
-    const int2 rg = reg[ch];
+    const int2 rg = rg_next;
     const int plo = rg.x, W = rg.y;
+    float *buf = tile + (ch & 1) * (kFpRows * ldw);
+    fp_stage_store(pf, buf, ldw, tr, rows, W);
     __syncthreads();
-    if (!tr) {
-      // walk rows are image rows: consecutive lanes read consecutive pixels
-      for (int r = wave; r < rows; r += kFpWaves) {
-        const int q = q0 + r;
-        const int jj = fo ? n - 1 - q : q;
-        const float *urow = u + (size_t)jj * n;
-        for (int c = lane; c < W; c += 64) {
-          const int p = plo + c;
-          float v = 0.f;
-          if (p >= 0 && p < n) v = urow[fi ? n - 1 - p : p];
-          tile[r * ldw + c] = v;
-        }
-      }
-    } else {
-      // walk rows are image columns: lanes run along q (contiguous in memory)
-      const int r = threadIdx.x & (kFpRows - 1);
-      if (r < rows) {
-        const int q = q0 + r;
-        const int ii = fo ? n - 1 - q : q;
-        for (int c = threadIdx.x / kFpRows; c < W; c += blockDim.x / kFpRows) {
-          const int p = plo + c;
-          float v = 0.f;
-          if (p >= 0 && p < n) v = u[(size_t)(fi ? n - 1 - p : p) * n + ii];
-          tile[r * ldw + c] = v;
-        }
-      }
+    if (ch + 1 < n_chunks) {
+      rg_next = reg[ch + 1];
+      const int q1 = q0 + kFpRows;
+      fp_stage_load(pf, u, n, tr, fi, fo, q1, min(kFpRows, n - q1), rg_next.x, rg_next.y);
     }
-    __syncthreads();
+    const float *tile_c = buf;
     // The strip's first pixel ps, clamped to [-2, n] (zero-staged columns
     // outside the image), addresses the staged row at byte offset
     // 4 (r ldw + ps - plo).
@@ -315,7 +403,7 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 #pragma unroll
         for (int g = 0; g < kFpPerThread; ++g) {
           const float *pt = reinterpret_cast<const float *>(
-              reinterpret_cast<const char *>(tile) + off[r][g]);
+              reinterpret_cast<const char *>(tile_c) + off[r][g]);
           u1[r][g] = pt[0];
           u2[r][g] = pt[1];
         }
@@ -340,7 +428,7 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 #pragma unroll
       for (int g = 0; g < kFpPerThread; ++g) {
         const int c = med3i(ps[g], cneg, cpos) - plo;
-        const float *trow = tile + r * ldw;
+        const float *trow = tile_c + r * ldw;
         const uint32_t e1 = e[g];
         const uint32_t e2 = e1 + A[g];
         float a1 = trow[c];
@@ -372,7 +460,7 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s) {
   dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1);
   const int ldw = (p->wmax % 2 == 0) ? p->wmax + 1 : p->wmax;
-  const size_t lds = sizeof(float) * kFpRows * ldw;
+  const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)
     hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->n_chunks, ldw, out);
