@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 64 MiB device copy (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -197,6 +199,12 @@ def main():
                      "hbm_gbs_algorithmic": round(radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
                                                   / t_fwd / 1e9, 1)},
     }
+    if args.copy_calibration:
+        x = torch.ones(16 * 1024 * 1024, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

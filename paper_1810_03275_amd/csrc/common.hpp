@@ -76,7 +76,7 @@ struct FpGroup {
   int32_t kmax;   // last such bin
   int32_t nblk;   // workgroups needed along the bins
   int32_t region; // offset of this group's (block, chunk) region table
-  int32_t pad;
+  int32_t range;  // offset of this group's per-block active chunk ranges
 };
 
 // Backprojection tiling: 256 threads, 32 x 64 pixels, 8 pixels per thread
@@ -110,6 +110,7 @@ struct ct_plan {
   ctpd::FpAngle *d_fp = nullptr;
   ctpd::FpGroup *d_groups = nullptr;
   int2 *d_regions = nullptr;  // (p_lo, width) per (group, block, chunk)
+  int2 *d_chunk_range = nullptr;  // first/last chunk per (group, block) meeting the image
   int n_groups = 0;
   int max_blk = 0;
   int n_chunks = 0;

@@ -93,7 +93,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
 
   // Bins a group can reach and the staged column range of every
   // (block, chunk); returns the widest range.
-  auto layout = [&](FpGroup &G, std::vector<int2> *out) -> int {
+  auto layout = [&](FpGroup &G, std::vector<int2> *out, std::vector<int2> *ranges) -> int {
     int64_t tmin = INT64_MAX, tmax = INT64_MIN;
     for (int a = 0; a < G.count; ++a) {
       const FpAngle &f = fps[G.first + a];
@@ -117,6 +117,27 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     for (int b = 0; b < G.nblk; ++b) {
       const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
       const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
+      // Chunks where some strip of the block meets the image: strip k meets row
+      // q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q, so a
+      // chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or ps(klo, q1) >= n
+      // for every angle of the group.
+      int cf = n_chunks, cl = -1;
+      for (int ch = 0; ch < n_chunks; ++ch) {
+        const int64_t q0 = (int64_t)ch * kFpRows;
+        const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
+        bool meets = false;
+        for (int a = 0; a < G.count && !meets; ++a) {
+          const FpAngle &f = fps[G.first + a];
+          const int64_t right = ceil_div((khi + 1) * one - f.T - q0 * (int64_t)f.B, f.A);
+          const int64_t left = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
+          meets = right > 0 && left < n;
+        }
+        if (meets) {
+          cf = std::min(cf, ch);
+          cl = std::max(cl, ch);
+        }
+      }
+      if (ranges) ranges->push_back(make_int2(cf, cl));
       for (int ch = 0; ch < n_chunks; ++ch) {
         const int64_t q0 = (int64_t)ch * kFpRows;
         const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
@@ -139,7 +160,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   };
 
   std::vector<FpGroup> groups;
-  std::vector<int2> regions;
+  std::vector<int2> regions, ranges;
   int wmax = 4, max_blk = 1;
   for (int i = 0; i < N;) {
     int j = i;
@@ -149,9 +170,10 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     G.cls = cls[order[i]];
     G.count = j - i;
     // fewer angles per group when their strips spread too far apart
-    while (G.count > 1 && layout(G, nullptr) > kFpMaxWidth) G.count = (G.count + 1) / 2;
+    while (G.count > 1 && layout(G, nullptr, nullptr) > kFpMaxWidth) G.count = (G.count + 1) / 2;
     G.region = (int)regions.size();
-    const int w = layout(G, &regions);
+    G.range = (int)ranges.size();
+    const int w = layout(G, &regions, &ranges);
     wmax = std::max(wmax, w);
     max_blk = std::max(max_blk, G.nblk);
     groups.push_back(G);
@@ -167,12 +189,16 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
     return CT_E_UNSUPPORTED;
   }
   if (regions.empty()) regions.push_back(make_int2(0, 4));
+  if (ranges.empty()) ranges.push_back(make_int2(0, -1));
   CT_TRY_HIP(hipMalloc(&p->d_bp, sizeof(BpAngle) * N));
   if (p->bp_slices > 1)
     CT_TRY_HIP(hipMalloc(&p->d_bp_part, sizeof(float) * (size_t)p->bp_slices * n * n));
   CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * N));
   CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * groups.size()));
   CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * regions.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * ranges.size()));
+  CT_TRY_HIP(hipMemcpy(p->d_chunk_range, ranges.data(), sizeof(int2) * ranges.size(),
+                       hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_bp, bp.data(), sizeof(BpAngle) * N, hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_fp, fps.data(), sizeof(FpAngle) * N, hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_groups, groups.data(), sizeof(FpGroup) * groups.size(),
@@ -189,6 +215,7 @@ void free_plan(ct_plan *p) {
   (void)hipFree(p->d_fp);
   (void)hipFree(p->d_groups);
   (void)hipFree(p->d_regions);
+  (void)hipFree(p->d_chunk_range);
   (void)hipFree(p->d_scratch_sino);
   (void)hipFree(p->d_scratch_img);
   (void)hipFree(p->d_red);

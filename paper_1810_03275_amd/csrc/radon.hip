@@ -121,22 +121,30 @@ __global__ __launch_bounds__(256) void k_radon_adj(
       // first pixel: exact FP64 coordinate relative to the staged segment
       const double t = fma(dj, A.b, fma(di, A.a, A.t0 - (double)kmin_s[slot][c]));
       const double fl = floor(t);
-      int hi = (int)fl;
-      uint32_t lo = (uint32_t)((t - fl) * 4294967296.0);  // exact: t is a multiple of 2^-30
-      const uint64_t step = (uint64_t)A.b8_fix;            // 8 b 2^32, exact
-      const uint32_t slo = (uint32_t)step, shi = (uint32_t)(step >> 32);
+      // 64-bit fixed point, 32 fractional bits: high word = local bin index
+      uint64_t tf = ((uint64_t)(uint32_t)(int)fl << 32) |
+                    (uint64_t)(uint32_t)((t - fl) * 4294967296.0);  // exact
+      const uint64_t step = (uint64_t)A.b8_fix;                    // 8 b 2^32, exact
       const float2 *seg_c = vd + c * seg;
+      // floor(t) - floor(t_min of the tile) lies in [0, seg - 2] by construction
+      int hh[kBpPix];
+      uint32_t ll[kBpPix];
 #pragma unroll
       for (int p = 0; p < kBpPix; ++p) {
         if (p > 0) {
-          const uint32_t nlo = lo + slo;
-          hi += (int)(shi + (nlo < lo ? 1u : 0u));
-          lo = nlo;
+          tf += step;                    // one 64-bit add per pixel
+          asm volatile("" : "+v"(tf));   // keep the chain (no rewrite into multiplies)
         }
-        const int kk = min(max(hi, 0), seg - 1);
-        const float2 q = seg_c[kk];
-        accv[p] += q.x;
-        accd[p] = fmaf((float)lo, q.y, accd[p]);
+        hh[p] = (int)(uint32_t)(tf >> 32);
+        ll[p] = (uint32_t)tf;
+      }
+      float2 q[kBpPix];
+#pragma unroll
+      for (int p = 0; p < kBpPix; ++p) q[p] = seg_c[hh[p]];
+#pragma unroll
+      for (int p = 0; p < kBpPix; ++p) {
+        accv[p] += q[p].x;
+        accd[p] = fmaf((float)ll[p], q[p].y, accd[p]);
       }
     }
   }
@@ -286,8 +294,8 @@ __device__ inline void fp_stage_store(const float (&v)[kFpPrefetch], float *tile
 template <bool CHECK_FIRST>
 __global__ __launch_bounds__(256) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
-    const FpGroup *__restrict__ groups, const int2 *__restrict__ regions, int n_chunks,
-    int ldw, float *__restrict__ sino) {
+    const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
+    const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino) {
   extern __shared__ float tile[];  // kFpRows * ldw
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
@@ -315,6 +323,10 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   const int kb = grp.kmin + blk * (kFpStrips - 1);  // first output bin
   const int k = kb - 1 + lane;                      // this lane's strip
   const uint32_t one = 1u << kFixBits;
+  // chunks in which some strip of this block meets the image (host-computed)
+  const int2 crange = chunk_range[grp.range + blk];
+  const int ch_first = crange.x, ch_last = crange.y;
+  const int q_first = ch_first * kFpRows;
 
   // Walk state per angle slot.  Inactive slots (beyond the group's count)
   // walk a harmless empty strip: their results are never stored.
@@ -334,7 +346,8 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
       const FpAngle fa = angs[grp.first + slot];
       A[g] = fa.A;
       B[g] = fa.B;
-      const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T;
+      const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T -
+                          (int64_t)q_first * (int64_t)fa.B;
       int64_t pp = (int64_t)ceil((double)num / (double)fa.A);
       int64_t ee = pp * (int64_t)fa.A - num;
       if (ee < 0) {
@@ -359,17 +372,20 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   // Staged image rows are double-buffered; the next chunk's pixels are
   // loaded into registers while the current chunk is walked.
   float pf[kFpPrefetch];
-  int2 rg_next = reg[0];
-  fp_stage_load(pf, u, n, tr, fi, fo, 0, min(kFpRows, n), rg_next.x, rg_next.y);
-  for (int ch = 0; ch < n_chunks; ++ch) {
+  int2 rg_next = make_int2(0, 4);
+  if (ch_first <= ch_last) {
+    rg_next = reg[ch_first];
+    fp_stage_load(pf, u, n, tr, fi, fo, q_first, min(kFpRows, n - q_first), rg_next.x, rg_next.y);
+  }
+  for (int ch = ch_first; ch <= ch_last; ++ch) {
     const int q0 = ch * kFpRows;
     const int rows = min(kFpRows, n - q0);
     const int2 rg = rg_next;
     const int plo = rg.x, W = rg.y;
-    float *buf = tile + (ch & 1) * (kFpRows * ldw);
+    float *buf = tile + ((ch - ch_first) & 1) * (kFpRows * ldw);
     fp_stage_store(pf, buf, ldw, tr, rows, W);
     __syncthreads();
-    if (ch + 1 < n_chunks) {
+    if (ch + 1 <= ch_last) {
       rg_next = reg[ch + 1];
       const int q1 = q0 + kFpRows;
       fp_stage_load(pf, u, n, tr, fi, fo, q1, min(kFpRows, n - q1), rg_next.x, rg_next.y);
@@ -463,10 +479,12 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)
     hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
-                       p->d_fp, p->d_groups, p->d_regions, p->n_chunks, ldw, out);
+                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
+                       out);
   else
     hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
-                       p->d_fp, p->d_groups, p->d_regions, p->n_chunks, ldw, out);
+                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
+                       out);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }
