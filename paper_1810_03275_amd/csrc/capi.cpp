@@ -2,6 +2,7 @@
 // (thesis Algorithm PDRQS1 in §4.4, setup of §5.1 and §4.3.1).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -153,6 +154,12 @@ struct ct_solver {
   int red_cap = 0;
   int64_t iters = 0;
   bool have_dual = false;
+  // Two PDRQS1 iterations captured as a HIP graph, one per ping-pong parity of
+  // (u, u_next); captured on a private stream, replayed on the caller's stream.
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  float *gexec_u[2] = {nullptr, nullptr};
+  bool use_graph = true;
 };
 
 static void solver_free(ct_solver *sv) {
@@ -163,6 +170,9 @@ static void solver_free(ct_solver *sv) {
   (void)hipFree(sv->mask);
   (void)hipFree(sv->d_red);
   (void)hipFree(sv->d_out);
+  for (auto &g : sv->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (sv->cap_stream) (void)hipStreamDestroy(sv->cap_stream);
   precond_free(&sv->pc);
 }
 
@@ -508,13 +518,37 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st) {
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
                           (float)(sv->sigma * sv->tau), sv->utmp, st));
   CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st));
-  CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st));
-  CT_TRY(launch_sino_update(sv->N, sv->M, sv->rraw, (float)(1.0 / sv->beta), sig, sv->target,
-                            sv->mask, sv->vb1, sv->s1, sv->y1, sv->r, mode, st));
+  // R_h u_new with the sinogram-side update fused into its output stage
+  const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
+                   sv->y1, sv->r, mode};
+  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
                           sv->vb2, sv->s2, sv->w, mode, st));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
+  return CT_OK;
+}
+
+// Capture two mode-0 iterations starting from the current (u, u_next)
+// assignment; the pointers are back in place after them.
+static int solver_capture(ct_solver *sv, int parity) {
+  if (!sv->cap_stream) CT_TRY_HIP(hipStreamCreateWithFlags(&sv->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  CT_TRY_HIP(hipStreamBeginCapture(sv->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int64_t it0 = sv->iters;
+  int rc = solver_iter(sv, 0, sv->cap_stream);
+  if (rc == CT_OK) rc = solver_iter(sv, 0, sv->cap_stream);
+  sv->iters = it0;  // nothing ran
+  hipError_t e = hipStreamEndCapture(sv->cap_stream, &graph);
+  if (rc != CT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  CT_TRY_HIP(e);
+  hipError_t ei = hipGraphInstantiate(&sv->gexec[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  CT_TRY_HIP(ei);
+  sv->gexec_u[parity] = sv->u;
   return CT_OK;
 }
 
@@ -553,6 +587,10 @@ int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *
   sv->sigma = prm->sigma;
   sv->tau = prm->tau;
   sv->eps = prm->eps;
+  {
+    const char *ng = std::getenv("CTPD_NO_GRAPH");
+    sv->use_graph = !(ng && ng[0] == '1');
+  }
   int rc = solver_setup(sv, prob, prm, S(s));
   if (rc != CT_OK) {
     (void)hipStreamSynchronize(S(s));
@@ -591,7 +629,22 @@ int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
     set_error("ct_pd_step: invalid argument");
     return CT_E_INVALID;
   }
-  for (int it = 0; it < k; ++it) CT_TRY(solver_iter(sv, it == k - 1 ? 2 : 0, S(s)));
+  hipStream_t st = S(s);
+  int left = k;
+  // all but the last iteration in pairs from the graph (identical kernels and order)
+  if (sv->use_graph && left >= 3) {
+    const int parity = (sv->u < sv->u_next) ? 0 : 1;
+    if (!sv->gexec[parity]) CT_TRY(solver_capture(sv, parity));
+    if (sv->gexec_u[parity] != sv->u) {
+      set_error("ct_pd_step: graph parity mismatch");
+      return CT_E_STATE;
+    }
+    const int pairs = (left - 1) / 2;
+    for (int q = 0; q < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(sv->gexec[parity], st));
+    sv->iters += 2 * pairs;
+    left -= 2 * pairs;
+  }
+  for (int it = 0; it < left; ++it) CT_TRY(solver_iter(sv, it == left - 1 ? 2 : 0, st));
   if (k > 0) sv->have_dual = true;
   return CT_OK;
 }
@@ -625,9 +678,9 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
   CT_TRY_HIP(hipMemcpyAsync(sv->vb1, vb1, sizeof(float) * NM, hipMemcpyDeviceToDevice, st));
   CT_TRY_HIP(hipMemcpyAsync(sv->vb2, vb2, sizeof(float) * nn * 2, hipMemcpyDeviceToDevice, st));
   // caches: s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u
-  CT_TRY(launch_radon_fwd(sv->plan, sv->u, sv->rraw, st));
-  CT_TRY(launch_sino_update(sv->N, sv->M, sv->rraw, (float)(1.0 / sv->beta), (float)sv->sigma,
-                            sv->target, sv->mask, sv->vb1, sv->s1, nullptr, nullptr, 1, st));
+  const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
+                   sv->s1, nullptr, nullptr, 1};
+  CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
                           (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st));
   sv->have_dual = false;

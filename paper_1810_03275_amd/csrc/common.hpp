@@ -138,8 +138,22 @@ namespace ctpd {
 // out = c1 * R^*(v) + c2 * div_h(p)  (p may be null)
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s);
-// out = R(u) (raw)
-int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s);
+// Optional epilogue of the forward projector: the PDRQS1 sinogram-side update
+// applied to r = R(u)/beta per bin (see k_sino_update), instead of storing R(u).
+struct SinoEpi {
+  float inv_beta;
+  float sigma;
+  const float *target;
+  const uint32_t *mask;
+  float *vb1;
+  float *s1;
+  float *y1;
+  float *r;
+  int mode;
+};
+// out = R(u) (raw), or the epilogue when epi != nullptr
+int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
+                     const SinoEpi *epi = nullptr);
 
 int launch_grad(int n, float inv_h, const float *u, float *p, hipStream_t s);
 int launch_div(int n, float inv_h, const float *p, float *d, hipStream_t s);

@@ -27,12 +27,15 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
   const int nbf = L / R;
   const int step = L / (Ns * R);
   const float sgn = INV ? 1.f : -1.f;  // forward kernel exp(-i ...)
+  // exact small-integer quotients via a float reciprocal (operands < 2^13)
+  const float inv_nbf = 1.0f / (float)nbf, inv_ns = 1.0f / (float)Ns;
   for (int t = threadIdx.x; t < nrows * nbf; t += blockDim.x) {
-    const int row = t / nbf;
+    const int row = (int)(((float)t + 0.5f) * inv_nbf);
     const int jj = t - row * nbf;
     const float2 *in = a + row * L;
     float2 *out = b + row * L;
-    const int k = jj % Ns;
+    const int jq = (int)(((float)jj + 0.5f) * inv_ns);  // jj / Ns
+    const int k = jj - jq * Ns;
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[jj + r * nbf];
@@ -68,7 +71,7 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
       v[1] = make_float2(m.x + rd.x, m.y + rd.y);
       v[2 % R] = make_float2(m.x - rd.x, m.y - rd.y);
     }
-    const int base = (jj / Ns) * Ns * R + k;
+    const int base = jq * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
   }
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(const float *__restrict__ 
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
   for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
-    const int pr = t / n, i = t - pr * n;
+    const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
     const int j = 2 * (pair0 + pr);
     a[t] = make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
   }
@@ -196,11 +199,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(const float2 *__restrict__
   }
 }
 
+// Rows (pairs) per workgroup: at least ~256 workgroups, at most 64 KB of LDS.
 static int rows_per_block(int n) {
   int rp = 4096 / n;  // keep 2 * RP * n * 8 bytes <= 64 KB
   if (rp < 1) rp = 1;
   if (rp > 4) rp = 4;
-  while (rp > 1 && (n / 2) / rp < 64) rp /= 2;
+  while (rp > 1 && (n / 2) / rp < 256) rp /= 2;
   return rp;
 }
 

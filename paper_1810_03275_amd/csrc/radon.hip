@@ -230,6 +230,39 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
 // time over the column range precomputed on the host for that
 // (group, block, chunk).  Lane 0's strip only supplies Q_{k-1} to lane 1.
 
+// Output of one projected bin: either the raw value R(u)[l][k], or the PDRQS1
+// sinogram-side update (§4.4) with r = R(u)[l][k] / beta:
+//   v1 = vb1 + sigma r, y1 = prox(2 v1 - vb1, sigma), vb1 <- vb1 + y1 - v1,
+//   s1 = vb1 + sigma r  (mode 1: only s1 = vb1 + sigma r; mode 2: also y1, r).
+__device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, int M, int l, int k,
+                                 float raw) {
+  const size_t o = (size_t)l * M + k;
+  if (ep.vb1 == nullptr) {
+    sino[o] = raw;
+    return;
+  }
+  const float r = raw * ep.inv_beta;
+  const float vb = ep.vb1[o];
+  if (ep.mode == 1) {
+    ep.s1[o] = fmaf(ep.sigma, r, vb);
+    return;
+  }
+  const int MW = (M + 31) >> 5;
+  const bool on_d0 =
+      ep.mask != nullptr && ((ep.mask[(size_t)l * MW + (k >> 5)] >> (k & 31)) & 1u);
+  const float v1 = fmaf(ep.sigma, r, vb);
+  const float q = 2.f * v1 - vb;
+  const float tg = ep.target[o];
+  const float y = on_d0 ? fminf(q - ep.sigma * tg, 0.f) : (q - ep.sigma * tg) / (1.f + ep.sigma);
+  const float nb = vb + y - v1;
+  ep.vb1[o] = nb;
+  ep.s1[o] = fmaf(ep.sigma, r, nb);
+  if (ep.mode == 2) {
+    ep.y1[o] = y;
+    ep.r[o] = r;
+  }
+}
+
 // Staging of one chunk of kFpRows walk rows x W columns (W <= 192) for the
 // forward projector: each thread loads kFpPrefetch pixels (zero outside the
 // image).  Walk rows are image rows (tr = false: lanes run along the row) or
@@ -295,7 +328,8 @@ template <bool CHECK_FIRST>
 __global__ __launch_bounds__(256) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
-    const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino) {
+    const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino,
+    SinoEpi ep) {
   extern __shared__ float tile[];  // kFpRows * ldw
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
@@ -303,19 +337,20 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
   const int blk = blockIdx.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
 
-  // Bins no pixel reaches are written as zero (block 0 below kmin, last block above kmax).
+  // Bins no pixel reaches hold zero (block 0 below kmin, last block above kmax).
   if (blk == 0) {
     const int lim = min(grp.kmin, M);
     for (int a = 0; a < grp.count; ++a) {
-      float *row = sino + (size_t)angs[grp.first + a].l * M;
-      for (int k = threadIdx.x; k < lim; k += blockDim.x) row[k] = 0.f;
+      const int l = angs[grp.first + a].l;
+      for (int k = threadIdx.x; k < lim; k += blockDim.x) fp_output(sino, ep, M, l, k, 0.f);
     }
   }
   if (blk == nblk_eff - 1) {
     const int from = max(grp.kmax + 1, grp.kmin);
     for (int a = 0; a < grp.count; ++a) {
-      float *row = sino + (size_t)angs[grp.first + a].l * M;
-      for (int k = max(from, 0) + threadIdx.x; k < M; k += blockDim.x) row[k] = 0.f;
+      const int l = angs[grp.first + a].l;
+      for (int k = max(from, 0) + threadIdx.x; k < M; k += blockDim.x)
+        fp_output(sino, ep, M, l, k, 0.f);
     }
   }
   if (blk >= grp.nblk) return;
@@ -468,23 +503,26 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
     const float qprev = __shfl_up(Q[g], 1, 64);
     if (slot < grp.count && lane >= 1 && k <= grp.kmax && k < M) {
       const int l = angs[grp.first + slot].l;
-      sino[(size_t)l * M + k] = fmaf(qprev - Q[g], inv, P[g]);
+      fp_output(sino, ep, M, l, k, fmaf(qprev - Q[g], inv, P[g]));
     }
   }
 }
 
-int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s) {
+int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
+                     const SinoEpi *epi) {
+  SinoEpi ep{};
+  if (epi) ep = *epi;
   dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1);
   const int ldw = (p->wmax % 2 == 0) ? p->wmax + 1 : p->wmax;
   const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)
     hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
-                       out);
+                       out, ep);
   else
     hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
-                       out);
+                       out, ep);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }
