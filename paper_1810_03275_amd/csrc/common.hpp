@@ -60,13 +60,14 @@ struct FpAngle {
 
 // A group of up to kFpGroup angles of the same walk class, processed by one
 // workgroup (one wave per kFpPerThread angles, 64 bins per workgroup).
-constexpr int kFpWaves = 4;
+constexpr int kFpWaves = 8;
+constexpr int kFpThreads = 64 * kFpWaves;
 constexpr int kFpPerThread = 2;
-constexpr int kFpGroup = kFpWaves * kFpPerThread;  // 8 angles
+constexpr int kFpGroup = kFpWaves * kFpPerThread;  // 16 angles
 constexpr int kFpStrips = 64;                       // strips per workgroup (63 outputs)
 constexpr int kFpRows = 16;                         // image rows staged per chunk
-constexpr int kFpPrefetch = 12;                     // staged pixels per thread (width <= 192)
-constexpr int kFpMaxWidth = 192;
+constexpr int kFpMaxWidth = 192;                    // staged columns per chunk
+constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixels per thread
 
 struct FpGroup {
   int32_t first;  // index into the FpAngle array

@@ -263,39 +263,42 @@ __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, in
   }
 }
 
-// Staging of one chunk of kFpRows walk rows x W columns (W <= 192) for the
-// forward projector: each thread loads kFpPrefetch pixels (zero outside the
-// image).  Walk rows are image rows (tr = false: lanes run along the row) or
-// image columns (tr = true: lanes run along q, contiguous in memory).
+// Staging of one chunk of kFpRows walk rows x W columns (W <= kFpMaxWidth)
+// for the forward projector: each of the kFpThreads threads loads
+// kFpPrefetch pixels (zero outside the image).  Walk rows are image rows
+// (tr = false: lanes run along the row) or image columns (tr = true: lanes run
+// along q, which is contiguous in memory).
 __device__ inline void fp_stage_load(float (&v)[kFpPrefetch], const float *__restrict__ u, int n,
                                      bool tr, bool fi, bool fo, int q0, int rows, int plo,
                                      int W) {
   const int t = threadIdx.x;
   if (!tr) {
 #pragma unroll
-    for (int mr = 0; mr < 4; ++mr) {
-      const int r = (t >> 6) + 4 * mr;
+    for (int mr = 0; mr < kFpRows / (kFpThreads / 64); ++mr) {
+      const int r = (t >> 6) + (kFpThreads / 64) * mr;
       const int q = q0 + r;
-      const int jj = fo ? n - 1 - q : q;
+      const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
+      const bool rok = r < rows;
 #pragma unroll
-      for (int mc = 0; mc < 3; ++mc) {
+      for (int mc = 0; mc < kFpMaxWidth / 64; ++mc) {
         const int c = (t & 63) + 64 * mc;
         const int p = plo + c;
         float x = 0.f;
-        if (r < rows && c < W && p >= 0 && p < n) x = u[(size_t)jj * n + (fi ? n - 1 - p : p)];
-        v[mr * 3 + mc] = x;
+        if (rok && c < W && (unsigned)p < (unsigned)n) x = urow[fi ? n - 1 - p : p];
+        v[mr * (kFpMaxWidth / 64) + mc] = x;
       }
     }
   } else {
     const int r = t & (kFpRows - 1);
     const int q = q0 + r;
-    const int ii = fo ? n - 1 - q : q;
+    const float *ucol = u + (fo ? n - 1 - q : q);
+    const bool rok = r < rows;
 #pragma unroll
     for (int m = 0; m < kFpPrefetch; ++m) {
-      const int c = (t >> 4) + 16 * m;
+      const int c = (t / kFpRows) + (kFpThreads / kFpRows) * m;
       const int p = plo + c;
       float x = 0.f;
-      if (r < rows && c < W && p >= 0 && p < n) x = u[(size_t)(fi ? n - 1 - p : p) * n + ii];
+      if (rok && c < W && (unsigned)p < (unsigned)n) x = ucol[(size_t)(fi ? n - 1 - p : p) * n];
       v[m] = x;
     }
   }
@@ -306,31 +309,41 @@ __device__ inline void fp_stage_store(const float (&v)[kFpPrefetch], float *tile
   const int t = threadIdx.x;
   if (!tr) {
 #pragma unroll
-    for (int mr = 0; mr < 4; ++mr) {
-      const int r = (t >> 6) + 4 * mr;
+    for (int mr = 0; mr < kFpRows / (kFpThreads / 64); ++mr) {
+      const int r = (t >> 6) + (kFpThreads / 64) * mr;
 #pragma unroll
-      for (int mc = 0; mc < 3; ++mc) {
+      for (int mc = 0; mc < kFpMaxWidth / 64; ++mc) {
         const int c = (t & 63) + 64 * mc;
-        if (r < rows && c < W) tile[r * ldw + c] = v[mr * 3 + mc];
+        if (r < rows && c < W) tile[r * ldw + c] = v[mr * (kFpMaxWidth / 64) + mc];
       }
     }
   } else {
     const int r = t & (kFpRows - 1);
 #pragma unroll
     for (int m = 0; m < kFpPrefetch; ++m) {
-      const int c = (t >> 4) + 16 * m;
+      const int c = (t / kFpRows) + (kFpThreads / kFpRows) * m;
       if (r < rows && c < W) tile[r * ldw + c] = v[m];
     }
   }
 }
 
+// One row of the walk for a strip: e = t(ps) - k 2^30 in [0, A); one row
+// down, e += B, and when that reaches A the strip starts one pixel earlier.
+__device__ inline void walk_row(uint32_t &e, int &ps, uint32_t A, uint32_t B) {
+  const uint32_t en = e + B;
+  uint32_t d;
+  const bool below = __builtin_sub_overflow(en, A, &d);  // en < A
+  e = below ? en : d;
+  ps = ps - 1 + (below ? 1 : 0);
+}
+
 template <bool CHECK_FIRST>
-__global__ __launch_bounds__(256) void k_radon_fwd(
+__global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
     const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino,
     SinoEpi ep) {
-  extern __shared__ float tile[];  // kFpRows * ldw
+  extern __shared__ float tile[];  // 2 x kFpRows * ldw
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -365,14 +378,18 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 
   // Walk state per angle slot.  Inactive slots (beyond the group's count)
   // walk a harmless empty strip: their results are never stored.
-  uint32_t e[kFpPerThread], A[kFpPerThread], B[kFpPerThread];
+  // P = sum u, Q = sum (e1 2^-30 ... in units of 2^-30) over the strip's first
+  // pixels and second pixels' shared part, Q2 = sum of second pixels (whose
+  // fraction is e1 + A).
+  uint32_t e[kFpPerThread], A[kFpPerThread], B[kFpPerThread], lim2[kFpPerThread];
   int ps[kFpPerThread];
-  float P[kFpPerThread], Q[kFpPerThread];
+  float P[kFpPerThread], Q[kFpPerThread], Q2[kFpPerThread];
 #pragma unroll
   for (int g = 0; g < kFpPerThread; ++g) {
     const int slot = wave * kFpPerThread + g;
     P[g] = 0.f;
     Q[g] = 0.f;
+    Q2[g] = 0.f;
     e[g] = 0u;
     ps[g] = -(1 << 29);
     A[g] = one;
@@ -396,6 +413,8 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
       ps[g] = (int)pp;
       e[g] = (uint32_t)ee;
     }
+    // the second pixel (fraction e + A) is in the strip iff e < 2^30 - A
+    lim2[g] = A[g] < one ? one - A[g] : 0u;
   }
 
   const int2 *reg = regions + grp.region + blk * n_chunks;
@@ -441,10 +460,7 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
         for (int g = 0; g < kFpPerThread; ++g) {
           off[r][g] = (uint32_t)(med3i(ps[g], cneg, cpos) * 4 + rowbase);
           ev[r][g] = e[g];
-          const uint32_t en = e[g] + B[g];
-          const bool m = en >= A[g];
-          e[g] = m ? en - A[g] : en;
-          ps[g] -= m ? 1 : 0;
+          walk_row(e[g], ps[g], A[g], B[g]);
         }
       }
       // 2. all LDS reads of the batch
@@ -459,19 +475,19 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
           u2[r][g] = pt[1];
         }
       }
-      // 3. accumulate: strip pixels ps (fraction e) and ps+1 (fraction e + A)
+      // 3. accumulate: first pixel (fraction e), second pixel (e + A) if in the strip
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
 #pragma unroll
         for (int g = 0; g < kFpPerThread; ++g) {
           const uint32_t e1 = ev[r][g];
-          const uint32_t e2 = e1 + A[g];
           float a1 = u1[r][g];
           if (CHECK_FIRST) a1 = (e1 < one) ? a1 : 0.f;
-          const float a2 = (e2 < one) ? u2[r][g] : 0.f;
-          P[g] += a1 + a2;
-          Q[g] = fmaf((float)e1, a1, Q[g]);
-          Q[g] = fmaf((float)e2, a2, Q[g]);
+          const float a2 = (e1 < lim2[g]) ? u2[r][g] : 0.f;
+          const float sum = a1 + a2;
+          P[g] += sum;
+          Q[g] = fmaf((float)e1, sum, Q[g]);
+          Q2[g] += a2;
         }
       }
     }
@@ -481,17 +497,14 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
         const int c = med3i(ps[g], cneg, cpos) - plo;
         const float *trow = tile_c + r * ldw;
         const uint32_t e1 = e[g];
-        const uint32_t e2 = e1 + A[g];
         float a1 = trow[c];
         if (CHECK_FIRST) a1 = (e1 < one) ? a1 : 0.f;
-        const float a2 = (e2 < one) ? trow[c + 1] : 0.f;
-        P[g] += a1 + a2;
-        Q[g] = fmaf((float)e1, a1, Q[g]);
-        Q[g] = fmaf((float)e2, a2, Q[g]);
-        const uint32_t en = e1 + B[g];
-        const bool m = en >= A[g];
-        e[g] = m ? en - A[g] : en;
-        ps[g] -= m ? 1 : 0;
+        const float a2 = (e1 < lim2[g]) ? trow[c + 1] : 0.f;
+        const float sum = a1 + a2;
+        P[g] += sum;
+        Q[g] = fmaf((float)e1, sum, Q[g]);
+        Q2[g] += a2;
+        walk_row(e[g], ps[g], A[g], B[g]);
       }
     }
   }
@@ -500,10 +513,11 @@ __global__ __launch_bounds__(256) void k_radon_fwd(
 #pragma unroll
   for (int g = 0; g < kFpPerThread; ++g) {
     const int slot = wave * kFpPerThread + g;
-    const float qprev = __shfl_up(Q[g], 1, 64);
+    const float qt = fmaf((float)A[g], Q2[g], Q[g]);  // sum of fraction * u, in 2^-30 units
+    const float qprev = __shfl_up(qt, 1, 64);
     if (slot < grp.count && lane >= 1 && k <= grp.kmax && k < M) {
       const int l = angs[grp.first + slot].l;
-      fp_output(sino, ep, M, l, k, fmaf(qprev - Q[g], inv, P[g]));
+      fp_output(sino, ep, M, l, k, fmaf(qprev - qt, inv, P[g]));
     }
   }
 }
@@ -516,11 +530,11 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   const int ldw = (p->wmax % 2 == 0) ? p->wmax + 1 : p->wmax;
   const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)
-    hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
+    hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
                        out, ep);
   else
-    hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(256), lds, s, u, p->g.n, p->g.n_bins,
+    hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
                        out, ep);
   CT_TRY_HIP(hipGetLastError());
