@@ -15,7 +15,6 @@ separately.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,17 +32,11 @@ PEAK_HBM_GBS = 8000.0
 # application (1 - alpha) v_k + alpha v_{k+1} as v_k + alpha (v_{k+1} - v_k)
 # (subtract, multiply-add) and the accumulation (add): 4 flops.
 FLOPS_PER_PAIR = 4.0
-# Algorithmic HBM bytes of one R_h launch: read the image once, write the sinogram once.
+# Algorithmic HBM bytes of one R_h launch inside the iteration: read the image
+# once; read the target and vb1 and write vb1 and s1 once per bin (the fused
+# sinogram-side update), plus the packed trace mask.
 def radon_fwd_bytes(n, N, M):
-    return 4.0 * (n * n + N * M)
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("radon.hip", "common.hpp", "plan.cpp"):
-        with open(os.path.join(ROOT, "paper_1810_03275_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return 4.0 * (n * n + 4 * N * M) + N * ((M + 31) // 32) * 4.0
 
 
 def measured_traffic():
@@ -55,6 +48,7 @@ def measured_traffic():
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
+    from paper_1810_03275_amd.profiling import kernel_source_hash
     if rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
@@ -72,21 +66,6 @@ def build_inputs(ct, torch, w):
     mask = metal_proj > 0
     bound = torch.where(mask, 0.95 * tissue_proj, torch.zeros_like(tissue_proj)).contiguous()
     return plan, u0, ct.pack_mask(mask), bound, t(w.start_norm), t(w.start_precond)
-
-
-def time_kernel(torch, fn, reps):
-    """Average duration of fn() over reps launches, HIP events on the current stream."""
-    s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    fn()
-    torch.cuda.synchronize()
-    e0.record(s)
-    for _ in range(reps):
-        fn()
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
 
 
 def cpu_baseline(w, budget_s: float):
@@ -156,17 +135,14 @@ def main():
     it_s = args.steps / dt
     rec = sv.gap()
 
-    # dominant kernels, timed alone on the current stream
-    u = sv.export()[0]
-    sino = torch.empty((N_ANG, N_BIN), device="cuda")
-    img = torch.empty((N_IMG, N_IMG), device="cuda")
-    t_fwd = time_kernel(torch, lambda: plan.radon_fwd(u, sino), args.kernel_reps)
-    t_adj = time_kernel(torch, lambda: plan.radon_adj(sino, img), args.kernel_reps)
+    # per-phase kernel durations of the same iterations, HIP events on the
+    # solver's stream (the current stream)
+    ph = sv.step_timed(args.kernel_reps)
+    t_fwd = ph["radon_fwd"] * 1e-3
+    t_adj = ph["radon_adj"] * 1e-3
     pairs = float(N_IMG * N_IMG * N_ANG)
-    dom_t = max(t_fwd, t_adj)
-    dom_name = "k_radon_fwd" if t_fwd >= t_adj else "k_radon_adj"
-    achieved = FLOPS_PER_PAIR * pairs / dom_t / 1e12
-    traffic = measured_traffic() if dom_name == "k_radon_fwd" else None
+    achieved = FLOPS_PER_PAIR * pairs / t_fwd / 1e12
+    traffic = measured_traffic()
 
     out = {
         "metric": METRIC,
@@ -187,17 +163,17 @@ def main():
                    "iterations_per_solve": w.iters},
         "radon_pairs_per_s": round(2 * pairs / (t_fwd + t_adj) / 1e9, 2),
         "radon_pairs_unit": "Gvox*angles/s (R+R*)",
-        "t_radon_fwd_us": round(t_fwd * 1e6, 2),
-        "t_radon_adj_us": round(t_adj * 1e6, 2),
+        "phase_us": {k: round(v * 1e3, 2) for k, v in ph.items()},
         "setup_ms": round(setup_s * 1e3, 2),
         "beta": info["beta"], "c": info["c"],
         "gap_record": [float(x) for x in rec],
-        "roofline": {"kernel": dom_name, "bound": "alu", "achieved": round(achieved, 3),
+        "roofline": {"kernel": "k_radon_fwd", "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": traffic,
                      "hbm_gbs_algorithmic": round(radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
-                                                  / t_fwd / 1e9, 1)},
+                                                  / t_fwd / 1e9, 1),
+                     "duration_us": round(t_fwd * 1e6, 2)},
     }
     if args.copy_calibration:
         x = torch.ones(16 * 1024 * 1024, device="cuda")

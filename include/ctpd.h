@@ -80,6 +80,14 @@ typedef struct ct_plan ct_plan;
  * so that R_h and R_h^* use bit-identical interpolation weights.
  * Errors: CT_E_INVALID, CT_E_UNSUPPORTED, CT_E_DEVICE. */
 int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
+
+/* Host-only self-check of the plan that ct_plan_create would build (no device
+ * call): replays the forward projector's fixed-point walk for every strip and
+ * staged row and verifies that each LDS read lies in the staged window and
+ * that every skipped row holds no pixel of the strip.  *steps (may be NULL)
+ * receives the number of (strip, row) steps checked.  CT_E_INVALID with a
+ * message naming the strip and row if a check fails. */
+int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps);
 int ct_plan_destroy(ct_plan *p);
 
 /* sino = R_h img (§3.1: R_h is the transpose of R_h^*; each pixel's value is
@@ -201,6 +209,15 @@ int ct_solver_info(const ct_solver *sv, double out[4]);
  * A u and nabla u are cached across iterations (one R_h and one R_h^* per
  * iteration).  Asynchronous; k >= 0. */
 int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s);
+
+/* Same iterations as ct_pd_step (k >= 1), launched one by one with HIP events
+ * on s around each phase; ms_out receives the average duration per iteration
+ * in milliseconds of [0] R_h^* with the u_tmp epilogue, [1] the preconditioner
+ * update u + M^{-1} u_tmp (§4.3.1), [2] R_h with the sinogram-side update,
+ * [3] the gradient-side update, [4] their sum.  Synchronizes s after every
+ * iteration, so it measures kernels, not throughput.  The state advances as
+ * with ct_pd_step. */
+int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s);
 
 /* Copy the state out: u [n][n], vb1 [N][M], vb2 [2][n][n] (any may be NULL). */
 int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_stream s);

@@ -77,6 +77,23 @@ def pack_mask(mask) -> torch.Tensor:
     return torch.from_numpy(bits.astype(np.int32).copy()).cuda()
 
 
+def plan_check(n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1.0,
+               angles: Optional[np.ndarray] = None) -> int:
+    """Host-only replay of the forward projector's walk over the plan that
+    Plan(...) would build; returns the number of (strip, row) steps checked and
+    raises CtpdError if a staged window or a skipped row is wrong."""
+    g = _lib.CtGeom(n, n_angles, n_bins, h, ds)
+    steps = ctypes.c_int64(0)
+    ptr = None
+    if angles is not None:
+        a = np.ascontiguousarray(angles, dtype=np.float64)
+        if a.shape != (n_angles,):
+            raise ValueError("angles must have shape (n_angles,)")
+        ptr = a.ctypes.data_as(ctypes.c_void_p)
+    _check(_L.ct_plan_check(ctypes.byref(g), ptr, ctypes.byref(steps)), "ct_plan_check")
+    return int(steps.value)
+
+
 class Plan:
     """Projector plan for an n x n image, N angles, M bins (§3.1)."""
 
@@ -270,6 +287,12 @@ class Solver:
 
     def step(self, k: int = 1) -> None:
         _check(_L.ct_pd_step(self._h, k, _stream()), "ct_pd_step")
+
+    def step_timed(self, k: int) -> dict:
+        """k iterations launched one by one; average ms per iteration of each phase."""
+        o = (ctypes.c_double * 5)()
+        _check(_L.ct_pd_step_timed(self._h, k, o, _stream()), "ct_pd_step_timed")
+        return dict(zip(("radon_adj", "precond", "radon_fwd", "tv_update", "total"), list(o)))
 
     def export(self):
         n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins

@@ -56,7 +56,9 @@ SIGNATURES = {
                                    POINTER(c_void_p)]),
     "ct_solver_destroy": (c_int32, [c_void_p]),
     "ct_solver_info": (c_int32, [c_void_p, POINTER(c_double)]),
+    "ct_plan_check": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(ctypes.c_int64)]),
     "ct_pd_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "ct_pd_step_timed": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "ct_state_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_state_import": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_gap": (c_int32, [c_void_p, POINTER(c_double), c_void_p]),
@@ -70,7 +72,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
             f"{path} not found: the HIP library is not built (run "
-            "`python -m paper_1810_03275_amd.build` or __graft_entry__.build())")
+            "`python paper_1810_03275_amd/build.py` or __graft_entry__.build())")
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

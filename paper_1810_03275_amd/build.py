@@ -1,6 +1,6 @@
 """Build libctpd.so (HIP for gfx950) in place, next to this file.
 
-Usage: python -m paper_1810_03275_amd.build  (or build() from Python).
+Usage: python paper_1810_03275_amd/build.py  (or __graft_entry__.build()).
 Every .hip/.cpp under csrc/ is compiled with hipcc into objects under
 _build/ at the repository root, then linked into paper_1810_03275_amd/libctpd.so.
 """

@@ -18,6 +18,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
 int build_plan(const ct_geom *g, const double *angles, ct_plan *p);
+int check_plan(const ct_geom *g, const double *angles, int64_t *steps);
 void free_plan(ct_plan *p);
 
 static bool fft_size_ok(int n) {
@@ -197,13 +198,7 @@ void ct_params_default(ct_params *p) {
   p->flags = 0;
 }
 
-int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
-  clear_error();
-  if (!g || !out) {
-    set_error("ct_plan_create: null argument");
-    return CT_E_INVALID;
-  }
-  *out = nullptr;
+static int check_geom(const ct_geom *g, const double *angles) {
   if (g->n < 2 || g->n_angles < 1 || g->n_bins < 2 || !(g->h > 0) || !(g->ds > 0)) {
     set_error("ct_plan_create: need n >= 2, N >= 1, M >= 2, h > 0, ds > 0");
     return CT_E_INVALID;
@@ -224,6 +219,17 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
         return CT_E_INVALID;
       }
   }
+  return CT_OK;
+}
+
+int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
+  clear_error();
+  if (!g || !out) {
+    set_error("ct_plan_create: null argument");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  CT_TRY(check_geom(g, angles));
   ct_plan *p = new (std::nothrow) ct_plan();
   if (!p) return CT_E_DEVICE;
   p->g = *g;
@@ -236,6 +242,16 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
   }
   *out = p;
   return CT_OK;
+}
+
+int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps) {
+  clear_error();
+  if (!g) {
+    set_error("ct_plan_check: null argument");
+    return CT_E_INVALID;
+  }
+  CT_TRY(check_geom(g, angles));
+  return check_plan(g, angles, steps);
 }
 
 int ct_plan_destroy(ct_plan *p) {
@@ -511,19 +527,25 @@ static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *
 
 // One PDRQS1 iteration (§4.4) from the cached s1 = vb1 + sigma A u,
 // s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and A u for the record.
-static int solver_iter(ct_solver *sv, int mode, hipStream_t st) {
+// With ev (5 events) the phase boundaries are recorded on st.
+static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr) {
   ct_plan *p = sv->plan;
   const float sig = (float)sv->sigma, tau = (float)sv->tau;
   const float inv_h = (float)(1.0 / p->g.h);
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
                           (float)(sv->sigma * sv->tau), sv->utmp, st));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
   CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
   // R_h u_new with the sinogram-side update fused into its output stage
   const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
                    sv->y1, sv->r, mode};
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
                           sv->vb2, sv->s2, sv->w, mode, st));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
   return CT_OK;
@@ -647,6 +669,38 @@ int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
   for (int it = 0; it < left; ++it) CT_TRY(solver_iter(sv, it == left - 1 ? 2 : 0, st));
   if (k > 0) sv->have_dual = true;
   return CT_OK;
+}
+
+int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s) {
+  clear_error();
+  if (!sv || k < 1 || !ms_out) {
+    set_error("ct_pd_step_timed: invalid argument");
+    return CT_E_INVALID;
+  }
+  hipStream_t st = S(s);
+  hipEvent_t ev[5] = {};
+  int rc = CT_OK;
+  for (int i = 0; i < 5 && rc == CT_OK; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) rc = CT_E_DEVICE;
+  for (int i = 0; i < 5; ++i) ms_out[i] = 0.0;
+  for (int it = 0; it < k && rc == CT_OK; ++it) {
+    rc = solver_iter(sv, it == k - 1 ? 2 : 0, st, ev);
+    if (rc == CT_OK && hipEventSynchronize(ev[4]) != hipSuccess) rc = CT_E_DEVICE;
+    for (int i = 0; i < 4 && rc == CT_OK; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) rc = CT_E_DEVICE;
+      ms_out[i] += ms;
+      ms_out[4] += ms;
+    }
+  }
+  for (int i = 0; i < 5; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  if (rc == CT_E_DEVICE) set_error("ct_pd_step_timed: HIP event failure");
+  if (rc == CT_OK) {
+    sv->have_dual = true;
+    for (int i = 0; i < 5; ++i) ms_out[i] /= k;
+  }
+  return rc;
 }
 
 int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_stream s) {

@@ -2,7 +2,10 @@
 // work list (thesis §3.1 geometry), built on the host in FP64/int64.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <numeric>
 #include <string>
 
@@ -26,40 +29,80 @@ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > h
 
 }  // namespace
 
-int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
+// Everything a plan holds, computed on the host.
+struct HostPlan {
+  std::vector<BpAngle> bp;
+  std::vector<FpAngle> dev;
+  std::vector<FpGroup> groups;
+  std::vector<int2> regions, ranges;
+  int seg = 0, bp_slices = 1, n_groups = 0, max_blk = 0, n_chunks = 0, wmax = 0;
+  bool check_first = false, paired = false;
+};
+
+static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   const int n = g->n, N = g->n_angles, M = g->n_bins;
   const double h = g->h, ds = g->ds;
-  std::vector<BpAngle> bp(N);
+  std::vector<BpAngle> &bp = p->bp;
+  bp.assign(N, BpAngle{});
   std::vector<FpAngle> fp(N);
   std::vector<int> cls(N);
-  double max_span = 0.0;
   bool check_first = false;
-  const double x0 = -h * (n - 1) / 2.0;
+  // cos and sin of the default angles theta_l = pi l / N come from one
+  // octant, so that angles related by pi/2 - theta or 3pi/2 - theta get
+  // exactly swapped / negated values (their walks then coincide exactly).
+  auto trig = [&](int l, double &c, double &s) {
+    if (angles || N % 2 != 0) {
+      const double th = angles ? angles[l] : M_PI * (double)l / (double)N;
+      c = std::cos(th);
+      s = std::sin(th);
+      return;
+    }
+    if (4 * l <= N) {
+      c = std::cos(M_PI * l / N);
+      s = std::sin(M_PI * l / N);
+    } else if (2 * l <= N) {
+      const int m = N / 2 - l;
+      c = std::sin(M_PI * m / N);
+      s = std::cos(M_PI * m / N);
+    } else if (4 * l < 3 * N) {
+      const int m = l - N / 2;
+      c = -std::sin(M_PI * m / N);
+      s = std::cos(M_PI * m / N);
+    } else {
+      const int m = N - l;
+      c = -std::cos(M_PI * m / N);
+      s = std::sin(M_PI * m / N);
+    }
+  };
   for (int l = 0; l < N; ++l) {
-    const double th = angles ? angles[l] : M_PI * (double)l / (double)N;
-    const double c = std::cos(th), s = std::sin(th);
+    double c, s;
+    trig(l, c, s);
     const double a = h * c / ds, b = h * s / ds;
-    const double t00 = (x0 * c + x0 * s) / ds + (M - 1) / 2.0;
     const int64_t A30 = std::llround(a * kFixOne);
     const int64_t B30 = std::llround(b * kFixOne);
-    const int64_t T30 = std::llround(t00 * kFixOne);
+    // walk frame: the inner coefficient is the larger one, both made >= 0
+    // by mirroring; (p, q) = (0, 0) is image pixel (i0, j0)
+    const bool tr = std::llabs(A30) < std::llabs(B30);
+    const int64_t Ci = tr ? B30 : A30, Co = tr ? A30 : B30;
+    const bool fi = Ci < 0, fo = Co < 0;
+    const int i0 = tr ? (fo ? n - 1 : 0) : (fi ? n - 1 : 0);
+    const int j0 = tr ? (fi ? n - 1 : 0) : (fo ? n - 1 : 0);
+    const double x = h * (i0 - (n - 1) / 2.0), y = h * (j0 - (n - 1) / 2.0);
+    const double t_origin = (x * c + y * s) / ds + (M - 1) / 2.0;
+    const int64_t Tw = std::llround(t_origin * kFixOne);
+    // image frame: t(i, j) = T30 + i A30 + j B30 (same integers as the walk)
+    const int64_t T30 = Tw - (int64_t)i0 * A30 - (int64_t)j0 * B30;
     bp[l].t0 = (double)T30 / kFixOne;
     bp[l].a = (double)A30 / kFixOne;
     bp[l].b = (double)B30 / kFixOne;
     bp[l].b8_fix = B30 * 4 * 8;
     bp[l].l = l;
     bp[l].pad = 0;
-    max_span = std::max(max_span, std::fabs(bp[l].a) + std::fabs(bp[l].b));
-    // walk frame
-    const bool tr = std::llabs(A30) < std::llabs(B30);
-    int64_t Ci = tr ? B30 : A30, Co = tr ? A30 : B30, T = T30;
-    bool fi = false, fo = false;
-    if (Ci < 0) { T += (int64_t)(n - 1) * Ci; Ci = -Ci; fi = true; }
-    if (Co < 0) { T += (int64_t)(n - 1) * Co; Co = -Co; fo = true; }
-    if (Ci > (int64_t)1 << kFixBits) check_first = true;
-    fp[l].T = T;
-    fp[l].A = (uint32_t)Ci;
-    fp[l].B = (uint32_t)Co;
+    const int64_t Ai = fi ? -Ci : Ci, Bo = fo ? -Co : Co;
+    if (Ai > (int64_t)1 << kFixBits) check_first = true;
+    fp[l].T = Tw;
+    fp[l].A = (uint32_t)Ai;
+    fp[l].B = (uint32_t)Bo;
     fp[l].l = l;
     fp[l].pad = 0;
     cls[l] = (tr ? 1 : 0) | (fi ? 2 : 0) | (fo ? 4 : 0);
@@ -82,129 +125,297 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   }
   p->check_first = check_first;
 
-  // group angles by class, kFpGroup at a time (angle order kept within a class)
-  std::vector<int> order(N);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls[x] < cls[y]; });
-  std::vector<FpAngle> fps(N);
-  for (int i = 0; i < N; ++i) fps[i] = fp[order[i]];
   const int n_chunks = (n + kFpRows - 1) / kFpRows;
   const int64_t one = (int64_t)1 << kFixBits;
 
-  // Bins a group can reach and the staged column range of every
-  // (block, chunk); returns the widest range.
-  auto layout = [&](FpGroup &G, std::vector<int2> *out, std::vector<int2> *ranges) -> int {
-    int64_t tmin = INT64_MAX, tmax = INT64_MIN;
-    for (int a = 0; a < G.count; ++a) {
-      const FpAngle &f = fps[G.first + a];
-      tmin = std::min(tmin, f.T);
-      tmax = std::max(tmax, f.T + (int64_t)(n - 1) * ((int64_t)f.A + (int64_t)f.B));
+  // Angles with identical walk constants can share one walk (paired kernel).
+  // Used when at least half of the angles pair up; the others then run as
+  // pairs of an angle with itself (second result discarded).
+  std::vector<std::pair<int, int>> pairs;  // (l0, l1), l1 = -1: alone
+  {
+    std::map<std::tuple<int64_t, uint32_t, uint32_t>, std::vector<int>> by_key;
+    for (int l = 0; l < N; ++l) by_key[std::make_tuple(fp[l].T, fp[l].A, fp[l].B)].push_back(l);
+    for (auto &kv : by_key) {
+      const std::vector<int> &v = kv.second;
+      size_t i = 0;
+      for (; i + 1 < v.size(); i += 2) pairs.emplace_back(v[i], v[i + 1]);
+      if (i < v.size()) pairs.emplace_back(v[i], -1);
     }
-    int64_t kmin = floor_div(tmin, one);
-    int64_t kmax = floor_div(tmax, one) + 1;
-    kmin = std::max<int64_t>(kmin, 0);
-    kmax = std::min<int64_t>(kmax, M - 1);
-    if (kmin > kmax) {
-      G.kmin = M;
-      G.kmax = M - 1;
-      G.nblk = 0;
-    } else {
-      G.kmin = (int)kmin;
-      G.kmax = (int)kmax;
-      G.nblk = (int)((kmax - kmin + 1 + (kFpStrips - 2)) / (kFpStrips - 1));
-    }
-    int wmax_g = 0;
-    for (int b = 0; b < G.nblk; ++b) {
-      const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
-      const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
-      // Chunks where some strip of the block meets the image: strip k meets row
-      // q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q, so a
-      // chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or ps(klo, q1) >= n
-      // for every angle of the group.
-      int cf = n_chunks, cl = -1;
-      for (int ch = 0; ch < n_chunks; ++ch) {
-        const int64_t q0 = (int64_t)ch * kFpRows;
-        const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
-        bool meets = false;
-        for (int a = 0; a < G.count && !meets; ++a) {
-          const FpAngle &f = fps[G.first + a];
-          const int64_t right = ceil_div((khi + 1) * one - f.T - q0 * (int64_t)f.B, f.A);
-          const int64_t left = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
-          meets = right > 0 && left < n;
-        }
-        if (meets) {
-          cf = std::min(cf, ch);
-          cl = std::max(cl, ch);
-        }
-      }
-      if (ranges) ranges->push_back(make_int2(cf, cl));
-      for (int ch = 0; ch < n_chunks; ++ch) {
-        const int64_t q0 = (int64_t)ch * kFpRows;
-        const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
-        int64_t lo = INT64_MAX, hi = INT64_MIN;
-        for (int a = 0; a < G.count; ++a) {
-          const FpAngle &f = fps[G.first + a];
-          const int64_t ps_lo = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
-          const int64_t ps_hi = ceil_div(khi * one - f.T - q0 * (int64_t)f.B, f.A);
-          lo = std::min(lo, clamp64(ps_lo, -2, n));
-          hi = std::max(hi, clamp64(ps_hi, -2, n) + 1);
-        }
-        lo -= 1;
-        hi += 1;
-        const int W = (int)(hi - lo + 1);
-        if (out) out->push_back(make_int2((int)lo, W));
-        wmax_g = std::max(wmax_g, W);
-      }
-    }
-    return wmax_g;
-  };
+  }
+  int n_paired = 0;
+  for (auto &pr : pairs) n_paired += pr.second >= 0 ? 2 : 0;
+  // The paired kernel stages at most kPrMaxWidth columns; geometries whose
+  // blocks need more (large ds/h) fall back to the unpaired kernel.
+  bool want_paired = N >= 2 && 2 * n_paired >= N;
+  {
+    const char *env = std::getenv("CTPD_FWD_UNPAIRED");
+    if (env && env[0] == '1') want_paired = false;
+  }
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool paired = want_paired && attempt == 0;
+    if (attempt == 1 && !want_paired) break;
+    const int max_width = paired ? kPrMaxWidth : kFpMaxWidth;
+    const int per_group = paired ? kPrPairs : kFpGroup;
 
-  std::vector<FpGroup> groups;
-  std::vector<int2> regions, ranges;
-  int wmax = 4, max_blk = 1;
-  for (int i = 0; i < N;) {
-    int j = i;
-    while (j < N && j - i < kFpGroup && cls[order[j]] == cls[order[i]]) ++j;
-    FpGroup G{};
-    G.first = i;
-    G.cls = cls[order[i]];
-    G.count = j - i;
-    // fewer angles per group when their strips spread too far apart
-    while (G.count > 1 && layout(G, nullptr, nullptr) > kFpMaxWidth) G.count = (G.count + 1) / 2;
-    G.region = (int)regions.size();
-    G.range = (int)ranges.size();
-    const int w = layout(G, &regions, &ranges);
-    wmax = std::max(wmax, w);
-    max_blk = std::max(max_blk, G.nblk);
-    groups.push_back(G);
-    i += G.count;
+    // Work items (angles, or pairs) in class order; rep[i] holds the walk
+    // constants of item i, icls[i] its class (pairs: the two classes).
+    std::vector<FpAngle> rep;
+    std::vector<FpAngle> &dev = p->dev;  // the device table (2 entries per pair)
+    dev.clear();
+    std::vector<std::pair<int, int>> icls;
+    if (paired) {
+      for (auto &pr : pairs) {
+        if (pr.second >= 0 && cls[pr.second] < cls[pr.first]) std::swap(pr.first, pr.second);
+      }
+      std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int, int> &x,
+                                                       const std::pair<int, int> &y) {
+        const int cx1 = x.second >= 0 ? cls[x.second] : cls[x.first];
+        const int cy1 = y.second >= 0 ? cls[y.second] : cls[y.first];
+        if (cls[x.first] != cls[y.first]) return cls[x.first] < cls[y.first];
+        if (cx1 != cy1) return cx1 < cy1;
+        return x.first < y.first;
+      });
+      for (auto &pr : pairs) {
+        rep.push_back(fp[pr.first]);
+        dev.push_back(fp[pr.first]);
+        FpAngle second = fp[pr.second >= 0 ? pr.second : pr.first];
+        if (pr.second < 0) second.l = -1;
+        dev.push_back(second);
+        icls.emplace_back(cls[pr.first], pr.second >= 0 ? cls[pr.second] : cls[pr.first]);
+      }
+    } else {
+      std::vector<int> order(N);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls[x] < cls[y]; });
+      for (int i = 0; i < N; ++i) {
+        rep.push_back(fp[order[i]]);
+        icls.emplace_back(cls[order[i]], cls[order[i]]);
+      }
+      dev = rep;
+    }
+    const int n_items = (int)rep.size();
+
+    // Bins a group can reach and the staged column range of every
+    // (block, chunk); returns the widest range.  The paired kernel does not
+    // clamp strip positions, so its ranges cover every position a lane reaches;
+    // the unpaired kernel clamps positions to [-2, n].
+    auto layout = [&](FpGroup &G, std::vector<int2> *out, std::vector<int2> *ranges) -> int {
+      int64_t tmin = INT64_MAX, tmax = INT64_MIN;
+      for (int a = 0; a < G.count; ++a) {
+        const FpAngle &f = rep[G.first + a];
+        tmin = std::min(tmin, f.T);
+        tmax = std::max(tmax, f.T + (int64_t)(n - 1) * ((int64_t)f.A + (int64_t)f.B));
+      }
+      int64_t kmin = floor_div(tmin, one);
+      int64_t kmax = floor_div(tmax, one) + 1;
+      kmin = std::max<int64_t>(kmin, 0);
+      kmax = std::min<int64_t>(kmax, M - 1);
+      if (kmin > kmax) {
+        G.kmin = M;
+        G.kmax = M - 1;
+        G.nblk = 0;
+      } else {
+        G.kmin = (int)kmin;
+        G.kmax = (int)kmax;
+        G.nblk = (int)((kmax - kmin + 1 + (kFpStrips - 2)) / (kFpStrips - 1));
+      }
+      int wmax_g = 0;
+      for (int b = 0; b < G.nblk; ++b) {
+        const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
+        const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
+        // Chunks where some strip of the block meets the image: strip k meets row
+        // q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q, so a
+        // chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or ps(klo, q1) >= n
+        // for every angle of the group.
+        int cf = n_chunks, cl = -1;
+        for (int ch = 0; ch < n_chunks; ++ch) {
+          const int64_t q0 = (int64_t)ch * kFpRows;
+          const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
+          bool meets = false;
+          for (int a = 0; a < G.count && !meets; ++a) {
+            const FpAngle &f = rep[G.first + a];
+            const int64_t right = ceil_div((khi + 1) * one - f.T - q0 * (int64_t)f.B, f.A);
+            const int64_t left = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
+            meets = right > 0 && left < n;
+          }
+          if (meets) {
+            cf = std::min(cf, ch);
+            cl = std::max(cl, ch);
+          }
+        }
+        if (ranges) ranges->push_back(make_int2(cf, cl));
+        for (int ch = 0; ch < n_chunks; ++ch) {
+          const int64_t q0 = (int64_t)ch * kFpRows;
+          const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
+          int64_t lo = INT64_MAX, hi = INT64_MIN;
+          for (int a = 0; a < G.count; ++a) {
+            const FpAngle &f = rep[G.first + a];
+            const int64_t ps_lo = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
+            const int64_t ps_hi = ceil_div(khi * one - f.T - q0 * (int64_t)f.B, f.A);
+            lo = std::min(lo, paired ? ps_lo : clamp64(ps_lo, -2, n));
+            hi = std::max(hi, (paired ? ps_hi : clamp64(ps_hi, -2, n)) + 1);
+          }
+          lo -= 1;
+          hi += 1;
+          const int64_t W = hi - lo + 1;
+          const bool active = ch >= cf && ch <= cl;
+          // inactive chunks are never staged; keep their entry small
+          if (out) out->push_back(active ? make_int2((int)lo, (int)W) : make_int2(0, 4));
+          if (active) wmax_g = (int)std::max<int64_t>(wmax_g, W);
+        }
+      }
+      return wmax_g;
+    };
+
+    std::vector<FpGroup> &groups = p->groups;
+    std::vector<int2> &regions = p->regions, &ranges = p->ranges;
+    groups.clear();
+    regions.clear();
+    ranges.clear();
+    int wmax = 4, max_blk = 1;
+    for (int i = 0; i < n_items;) {
+      int j = i;
+      while (j < n_items && j - i < per_group && icls[j] == icls[i]) ++j;
+      FpGroup G{};
+      G.first = i;
+      G.cls = icls[i].first;
+      G.cls1 = icls[i].second;
+      G.count = j - i;
+      // fewer angles per group when their strips spread too far apart
+      while (G.count > 1 && layout(G, nullptr, nullptr) > max_width) G.count = (G.count + 1) / 2;
+      G.region = (int)regions.size();
+      G.range = (int)ranges.size();
+      const int w = layout(G, &regions, &ranges);
+      wmax = std::max(wmax, w);
+      max_blk = std::max(max_blk, G.nblk);
+      groups.push_back(G);
+      i += G.count;
+    }
+    p->n_groups = (int)groups.size();
+    p->max_blk = max_blk;
+    p->n_chunks = n_chunks;
+    p->wmax = wmax;
+    p->paired = paired;
+    if (wmax <= max_width) break;
+    if (!paired) {
+      set_error("projector plan: staged region wider than " + std::to_string(max_width) +
+                " columns (too few angles for the group size)");
+      return CT_E_UNSUPPORTED;
+    }
   }
-  p->n_groups = (int)groups.size();
-  p->max_blk = max_blk;
-  p->n_chunks = n_chunks;
-  p->wmax = wmax;
-  if (wmax > kFpMaxWidth) {
-    set_error("projector plan: staged region wider than " + std::to_string(kFpMaxWidth) +
-              " columns (too few angles for the group size)");
-    return CT_E_UNSUPPORTED;
-  }
-  if (regions.empty()) regions.push_back(make_int2(0, 4));
-  if (ranges.empty()) ranges.push_back(make_int2(0, -1));
+  if (p->regions.empty()) p->regions.push_back(make_int2(0, 4));
+  if (p->ranges.empty()) p->ranges.push_back(make_int2(0, -1));
+  return CT_OK;
+}
+
+int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
+  HostPlan hp;
+  CT_TRY(plan_host(g, angles, &hp));
+  const int n = g->n, N = g->n_angles;
+  p->seg = hp.seg;
+  p->bp_slices = hp.bp_slices;
+  p->check_first = hp.check_first;
+  p->paired = hp.paired;
+  p->n_groups = hp.n_groups;
+  p->max_blk = hp.max_blk;
+  p->n_chunks = hp.n_chunks;
+  p->wmax = hp.wmax;
   CT_TRY_HIP(hipMalloc(&p->d_bp, sizeof(BpAngle) * N));
   if (p->bp_slices > 1)
     CT_TRY_HIP(hipMalloc(&p->d_bp_part, sizeof(float) * (size_t)p->bp_slices * n * n));
-  CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * N));
-  CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * groups.size()));
-  CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * regions.size()));
-  CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * ranges.size()));
-  CT_TRY_HIP(hipMemcpy(p->d_chunk_range, ranges.data(), sizeof(int2) * ranges.size(),
+  CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * hp.dev.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * hp.groups.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * hp.regions.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * hp.ranges.size()));
+  CT_TRY_HIP(hipMemcpy(p->d_chunk_range, hp.ranges.data(), sizeof(int2) * hp.ranges.size(),
                        hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_bp, bp.data(), sizeof(BpAngle) * N, hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_fp, fps.data(), sizeof(FpAngle) * N, hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_groups, groups.data(), sizeof(FpGroup) * groups.size(),
+  CT_TRY_HIP(hipMemcpy(p->d_bp, hp.bp.data(), sizeof(BpAngle) * N, hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_fp, hp.dev.data(), sizeof(FpAngle) * hp.dev.size(),
                        hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_regions, regions.data(), sizeof(int2) * regions.size(),
+  CT_TRY_HIP(hipMemcpy(p->d_groups, hp.groups.data(), sizeof(FpGroup) * hp.groups.size(),
                        hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_regions, hp.regions.data(), sizeof(int2) * hp.regions.size(),
+                       hipMemcpyHostToDevice));
+  return CT_OK;
+}
+
+// Host replay of the forward projector's walk over every (group, block, wave,
+// lane, staged row) of a plan: each LDS read must fall inside the staged
+// window of its chunk, and every row that the kernel skips must hold no pixel
+// of any strip of the block.  Exact integer arithmetic, as on the device.
+int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
+  HostPlan hp;
+  CT_TRY(plan_host(g, angles, &hp));
+  const int n = g->n;
+  const int64_t one = (int64_t)1 << kFixBits;
+  int64_t count = 0;
+  for (const FpGroup &G : hp.groups) {
+    const int slots = G.count;
+    for (int b = 0; b < G.nblk; ++b) {
+      const int2 cr = hp.ranges[G.range + b];
+      const int2 *reg = hp.regions.data() + G.region + (size_t)b * hp.n_chunks;
+      for (int w = 0; w < slots; ++w) {
+        const FpAngle fa = hp.paired ? hp.dev[2 * (G.first + w)] : hp.dev[G.first + w];
+        for (int lane = 0; lane < kFpStrips; ++lane) {
+          const int64_t k = G.kmin + (int64_t)b * (kFpStrips - 1) - 1 + lane;
+          // rows of skipped chunks: no pixel of the strip inside the image
+          for (int64_t q = 0; q < n; ++q) {
+            const int64_t ch = q / kFpRows;
+            if (ch >= cr.x && ch <= cr.y) continue;
+            const int64_t ps = ceil_div(k * one - fa.T - q * (int64_t)fa.B, fa.A);
+            const int64_t pe = ceil_div((k + 1) * one - fa.T - q * (int64_t)fa.B, fa.A);
+            if (pe > ps && ps < n && pe > 0) {
+              set_error("plan check: a skipped row holds pixels of strip " + std::to_string(k));
+              return CT_E_INVALID;
+            }
+          }
+          if (cr.x > cr.y) continue;
+          const int64_t q_first = (int64_t)cr.x * kFpRows;
+          const int64_t num = k * one - fa.T - q_first * (int64_t)fa.B;
+          int64_t pp = (int64_t)std::ceil((double)num / (double)fa.A);
+          int64_t ee = pp * (int64_t)fa.A - num;
+          if (ee < 0) {
+            pp += 1;
+            ee += fa.A;
+          } else if (ee >= (int64_t)fa.A) {
+            pp -= 1;
+            ee -= fa.A;
+          }
+          if (ee < 0 || ee >= (int64_t)fa.A ||
+              pp != ceil_div(num, fa.A)) {
+            set_error("plan check: initial walk state is not exact");
+            return CT_E_INVALID;
+          }
+          if (!hp.paired) pp = clamp64(pp, -(1 << 29), 1 << 29);
+          int64_t ps = pp;
+          uint32_t e = (uint32_t)ee;
+          for (int ch = cr.x; ch <= cr.y; ++ch) {
+            const int rows = std::min(kFpRows, n - ch * kFpRows);
+            const int2 rg = reg[ch];
+            if (rg.y > hp.wmax) {
+              set_error("plan check: window wider than the plan's width");
+              return CT_E_INVALID;
+            }
+            for (int r = 0; r < rows; ++r) {
+              const int64_t pos = hp.paired ? ps : clamp64(ps, -2, n);
+              const int64_t c = pos - rg.x;
+              if (c < 0 || c + 1 > rg.y - 1) {
+                set_error("plan check: staged window misses strip " + std::to_string(k) +
+                          " at row " + std::to_string(ch * kFpRows + r));
+                return CT_E_INVALID;
+              }
+              ++count;
+              const uint32_t en = e + fa.B;
+              const bool below = en < fa.A;
+              e = below ? en : en - fa.A;
+              ps = ps - 1 + (below ? 1 : 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (steps) *steps = count;
   return CT_OK;
 }
 

@@ -522,11 +522,280 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
   }
 }
 
+// ---------------------------------------------------------------------------
+// R_h for angle pairs that share one walk.  The strips, the walk and the
+// output are those of k_radon_fwd; a wave owns one pair (both angles walk the
+// same (e, ps) sequence), a workgroup kPrPairs pairs.  Each chunk stages the
+// same (row, column) window twice -- once per angle, through that angle's
+// transpose/mirror mapping -- as rows of pitch kPrLdw, the two angles' copies
+// of a row adjacent, so both angles' reads at (row, ps) share one address.
+// Strip positions are not clamped: the host-computed windows cover every
+// position the block's lanes reach, with zeros outside the image.
+
+// Buffer loads with range checking (a load whose byte offset is not below
+// the descriptor's record count returns 0, a documented property of buffer
+// addressing) provide the zeros outside the image, so staging has no
+// branches and no masks: in the row case each wave reads one image row
+// through a descriptor covering just that row; in the column case one
+// descriptor covers the image and an offset outside it comes from a column
+// index outside [0, n).  Positions beyond the window or past the chunk's
+// last row are staged too but never read.
+constexpr int kBufWord3 = 0x00020000;  // raw buffer, 32-bit data
+
+__device__ inline void pr_stage_load(float (&v)[kPrPrefetch], const float *__restrict__ u, int n,
+                                     int cls, int q0, int rows, int plo) {
+  const bool tr = (cls & 1) != 0, fi = (cls & 2) != 0, fo = (cls & 4) != 0;
+  const int t = threadIdx.x;
+  if (!tr) {
+#pragma unroll
+    for (int mr = 0; mr < kFpRows / kPrWaves; ++mr) {
+      const int r = (t >> 6) + kPrWaves * mr;  // wave-uniform
+      const int q = min(q0 + r, n - 1);
+      const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)urow, (short)0, r < rows ? n * 4 : 0, kBufWord3);
+      const int p0 = plo + (t & 63);
+#pragma unroll
+      for (int mc = 0; mc < kPrMaxWidth / 64; ++mc) {
+        const int p = p0 + 64 * mc;
+        const int pi = fi ? n - 1 - p : p;
+        v[mr * (kPrMaxWidth / 64) + mc] =
+            __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, pi * 4, 0, 0));
+      }
+    }
+  } else {
+    const int r = t & (kFpRows - 1);
+    const int q = min(q0 + r, n - 1);
+    const int qi = fo ? n - 1 - q : q;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)u, (short)0, n * n * 4, kBufWord3);
+    const int p0 = plo + t / kFpRows;
+#pragma unroll
+    for (int m = 0; m < kPrPrefetch; ++m) {
+      const int p = p0 + (kPrThreads / kFpRows) * m;
+      const int pi = fi ? n - 1 - p : p;
+      v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (pi * n + qi) * 4, 0, 0));
+    }
+  }
+}
+
+// Row r of angle `slot` starts at tile + (2 r + slot) kPrLdw; every staged
+// position is written (zeros beyond the window), so stores need no mask.
+__device__ inline void pr_stage_store(const float (&v)[kPrPrefetch], float *tile, int cls,
+                                      int slot) {
+  const int t = threadIdx.x;
+  if (!(cls & 1)) {
+#pragma unroll
+    for (int mr = 0; mr < kFpRows / kPrWaves; ++mr) {
+      const int r = (t >> 6) + kPrWaves * mr;
+#pragma unroll
+      for (int mc = 0; mc < kPrMaxWidth / 64; ++mc) {
+        const int c = (t & 63) + 64 * mc;
+        tile[(2 * r + slot) * kPrLdw + c] = v[mr * (kPrMaxWidth / 64) + mc];
+      }
+    }
+  } else {
+    const int r = t & (kFpRows - 1);
+#pragma unroll
+    for (int m = 0; m < kPrPrefetch; ++m) {
+      const int c = (t / kFpRows) + (kPrThreads / kFpRows) * m;
+      tile[(2 * r + slot) * kPrLdw + c] = v[m];
+    }
+  }
+}
+
+template <bool CHECK_FIRST>
+__global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
+    const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
+    const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
+    const int2 *__restrict__ chunk_range, int n_chunks, float *__restrict__ sino, SinoEpi ep) {
+  __shared__ float tile[2 * 2 * kFpRows * kPrLdw];  // 2 buffers x kFpRows x 2 angles x kPrLdw
+  const FpGroup grp = groups[blockIdx.x];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int blk = blockIdx.y;
+  const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
+  const FpAngle *pa = angs + 2 * grp.first;
+
+  // Bins no pixel reaches hold zero (block 0 below kmin, last block above kmax).
+  if (blk == 0) {
+    const int lim = min(grp.kmin, M);
+    for (int a = 0; a < 2 * grp.count; ++a) {
+      const int l = pa[a].l;
+      if (l < 0) continue;
+      for (int k = threadIdx.x; k < lim; k += blockDim.x) fp_output(sino, ep, M, l, k, 0.f);
+    }
+  }
+  if (blk == nblk_eff - 1) {
+    const int from = max(max(grp.kmax + 1, grp.kmin), 0);
+    for (int a = 0; a < 2 * grp.count; ++a) {
+      const int l = pa[a].l;
+      if (l < 0) continue;
+      for (int k = from + threadIdx.x; k < M; k += blockDim.x) fp_output(sino, ep, M, l, k, 0.f);
+    }
+  }
+  if (blk >= grp.nblk) return;
+
+  const int kb = grp.kmin + blk * (kFpStrips - 1);  // first output bin
+  const int k = kb - 1 + lane;                      // this lane's strip
+  const uint32_t one = 1u << kFixBits;
+  const int2 crange = chunk_range[grp.range + blk];
+  const int ch_first = crange.x, ch_last = crange.y;
+  const int q_first = ch_first * kFpRows;
+  const bool active = wave < grp.count;  // wave-uniform
+
+  uint32_t e = 0u, A = one, B = 0u;
+  int ps = 0;
+  if (active) {
+    const FpAngle fa = pa[2 * wave];
+    A = fa.A;
+    B = fa.B;
+    const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T -
+                        (int64_t)q_first * (int64_t)fa.B;
+    int64_t pp = (int64_t)ceil((double)num / (double)fa.A);
+    int64_t ee = pp * (int64_t)fa.A - num;
+    if (ee < 0) {
+      pp += 1;
+      ee += fa.A;
+    } else if (ee >= (int64_t)fa.A) {
+      pp -= 1;
+      ee -= fa.A;
+    }
+    ps = (int)pp;
+    e = (uint32_t)ee;
+  }
+  // the second pixel (fraction e + A) is in the strip iff e < 2^30 - A
+  const uint32_t lim2 = A < one ? one - A : 0u;
+  float P0 = 0.f, Q0 = 0.f, S0 = 0.f, P1 = 0.f, Q1 = 0.f, S1 = 0.f;
+
+  const int2 *reg = regions + grp.region + blk * n_chunks;
+  constexpr int RB = 8;  // rows whose LDS reads are issued together
+  float pf0[kPrPrefetch], pf1[kPrPrefetch];
+  int2 rg_next = make_int2(0, 4);
+  if (ch_first <= ch_last) {
+    rg_next = reg[ch_first];
+    const int rows0 = min(kFpRows, n - q_first);
+    pr_stage_load(pf0, u, n, grp.cls, q_first, rows0, rg_next.x);
+    pr_stage_load(pf1, u, n, grp.cls1, q_first, rows0, rg_next.x);
+  }
+  for (int ch = ch_first; ch <= ch_last; ++ch) {
+    const int q0 = ch * kFpRows;
+    const int rows = min(kFpRows, n - q0);
+    const int2 rg = rg_next;
+    const int plo = rg.x, W = rg.y;
+    float *buf = tile + ((ch - ch_first) & 1) * (2 * kFpRows * kPrLdw);
+    pr_stage_store(pf0, buf, grp.cls, 0);
+    pr_stage_store(pf1, buf, grp.cls1, 1);
+    __syncthreads();
+    if (ch + 1 <= ch_last) {
+      rg_next = reg[ch + 1];
+      const int q1 = q0 + kFpRows;
+      const int rows1 = min(kFpRows, n - q1);
+      pr_stage_load(pf0, u, n, grp.cls, q1, rows1, rg_next.x);
+      pr_stage_load(pf1, u, n, grp.cls1, q1, rows1, rg_next.x);
+    }
+    if (active) {
+      // pr = ps - plo >= 0 is the strip start within the staged window
+      const float *base = buf;
+      int pr = ps - plo;
+      int r0 = 0;
+      for (; r0 + RB <= rows; r0 += RB) {
+        int off[RB];
+        uint32_t ev[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          off[r] = pr + (r0 + r) * (2 * kPrLdw);
+          ev[r] = e;
+          walk_row(e, pr, A, B);
+        }
+        float a1[RB], a2r[RB], b1[RB], b2r[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const float *pt = base + off[r];
+          a1[r] = pt[0];
+          a2r[r] = pt[1];
+          b1[r] = pt[kPrLdw];
+          b2r[r] = pt[kPrLdw + 1];
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const uint32_t e1 = ev[r];
+          const bool in2 = e1 < lim2;
+          const float ef = (float)e1;
+          float a0 = a1[r], b0 = b1[r];
+          if (CHECK_FIRST) {
+            const bool in1 = e1 < one;
+            a0 = in1 ? a0 : 0.f;
+            b0 = in1 ? b0 : 0.f;
+          }
+          const float a2 = in2 ? a2r[r] : 0.f;
+          const float b2 = in2 ? b2r[r] : 0.f;
+          const float sa = a0 + a2, sb = b0 + b2;
+          P0 += sa;
+          Q0 = fmaf(ef, sa, Q0);
+          S0 += a2;
+          P1 += sb;
+          Q1 = fmaf(ef, sb, Q1);
+          S1 += b2;
+        }
+      }
+      for (int r = r0; r < rows; ++r) {  // ragged last chunk
+        const float *pt = base + pr + r * (2 * kPrLdw);
+        const uint32_t e1 = e;
+        const bool in2 = e1 < lim2;
+        const float ef = (float)e1;
+        float a0 = pt[0], b0 = pt[kPrLdw];
+        if (CHECK_FIRST) {
+          const bool in1 = e1 < one;
+          a0 = in1 ? a0 : 0.f;
+          b0 = in1 ? b0 : 0.f;
+        }
+        const float a2 = in2 ? pt[1] : 0.f;
+        const float b2 = in2 ? pt[kPrLdw + 1] : 0.f;
+        const float sa = a0 + a2, sb = b0 + b2;
+        P0 += sa;
+        Q0 = fmaf(ef, sa, Q0);
+        S0 += a2;
+        P1 += sb;
+        Q1 = fmaf(ef, sb, Q1);
+        S1 += b2;
+        walk_row(e, pr, A, B);
+      }
+      ps = pr + plo;
+    }
+  }
+
+  if (active) {
+    const float inv = 1.0f / (float)one;
+    const float qt0 = fmaf((float)A, S0, Q0);  // sum of fraction * u, in 2^-30 units
+    const float qt1 = fmaf((float)A, S1, Q1);
+    const float qp0 = __shfl_up(qt0, 1, 64);
+    const float qp1 = __shfl_up(qt1, 1, 64);
+    if (lane >= 1 && k <= grp.kmax && k < M) {
+      const int l0 = pa[2 * wave].l, l1 = pa[2 * wave + 1].l;
+      fp_output(sino, ep, M, l0, k, fmaf(qp0 - qt0, inv, P0));
+      if (l1 >= 0) fp_output(sino, ep, M, l1, k, fmaf(qp1 - qt1, inv, P1));
+    }
+  }
+}
+
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
                      const SinoEpi *epi) {
   SinoEpi ep{};
   if (epi) ep = *epi;
   dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1);
+  if (p->paired) {
+    if (p->check_first)
+      hipLaunchKernelGGL(k_radon_fwd_pair<true>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
+                         p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
+                         p->n_chunks, out, ep);
+    else
+      hipLaunchKernelGGL(k_radon_fwd_pair<false>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
+                         p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
+                         p->n_chunks, out, ep);
+    CT_TRY_HIP(hipGetLastError());
+    return CT_OK;
+  }
   const int ldw = (p->wmax % 2 == 0) ? p->wmax + 1 : p->wmax;
   const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)

@@ -51,6 +51,9 @@ GEOMS = [
     (2, 3, 4, 1.0, 1.0),
     (128, 180, 192, 0.7, 0.7),
     (100, 45, 150, 1.0, 1.0),
+    (90, 180, 128, 1.0, 0.8),   # angle pairs, strips that can miss a row
+    (90, 180, 128, 1.0, 1.4),   # pairs too wide for the paired kernel
+    (66, 4, 100, 1.0, 1.0),     # one pair and two angles alone
 ]
 
 
