@@ -54,10 +54,11 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def build_inputs(ct, torch, w):
+def build_inputs(ct, torch, w, plan=None):
     dev = torch.device("cuda")
     t = lambda a: torch.from_numpy(a.astype("float32")).to(dev)
-    plan = ct.Plan(w.n, w.n_angles, w.n_bins)
+    if plan is None:
+        plan = ct.Plan(w.n, w.n_angles, w.n_bins)
     tissue_proj = plan.radon_fwd(t(w.tissue))
     clean = plan.radon_fwd(t(w.phantom))
     metal_proj = plan.radon_fwd(t(w.metal.astype("float32")))
@@ -66,6 +67,48 @@ def build_inputs(ct, torch, w):
     mask = metal_proj > 0
     bound = torch.where(mask, 0.95 * tissue_proj, torch.zeros_like(tissue_proj)).contiguous()
     return plan, u0, ct.pack_mask(mask), bound, t(w.start_norm), t(w.start_precond)
+
+
+def batched_run(ct, torch, iters: int, count: int = 64):
+    """The uneven batch: 64 slices, n from {256, 384, 512, 768, 1024}, N = 1.4 n,
+    M = 1.5 n, 0-3 metal discs; every batch (one per shape) advances with one
+    launch per kernel and all batches replay as one HIP graph.  Times `iters`
+    iterations after setup and 2 warm-up iterations."""
+    import synth
+    shapes = synth.batched_shapes(count)
+    plans, groups = {}, {}
+    for i, sh in enumerate(shapes):
+        w = synth.batched_workload(i, sh)
+        key = sh[:3]
+        if key not in plans:
+            plans[key] = ct.Plan(*key)
+        plan, u0, mask, bound, _, _ = build_inputs(ct, torch, w, plans[key])
+        groups.setdefault(key, []).append((u0, mask, bound, w.alpha))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solvers = []
+    for key, items in groups.items():
+        solvers.append(ct.SolverBatch(plans[key], [x[0] for x in items], items[0][3],
+                                      [x[1] for x in items], [x[2] for x in items]))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    grp = ct.SolverGroup(solvers)
+    grp.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grp.step(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    grp.close()
+    pairs = sum(n * n * N for (n, N, M, _) in shapes)
+    layout = {f"{k[0]}x{k[1]}x{k[2]}": dict(sv.layout(), problems=len(groups[k]))
+              for k, sv in zip(groups, solvers)}
+    return {"workload": f"{count} slices, n in {{256,384,512,768,1024}}, N=1.4n, M=1.5n, "
+                        "0-3 metal discs, alpha=0.005",
+            "iterations": iters, "ms_per_iteration": round(1e3 * dt / iters, 3),
+            "it_per_s": round(iters / dt, 2),
+            "gvox_angles_per_s": round(2 * pairs * iters / dt / 1e9, 1),
+            "pairs_per_pass": pairs, "setup_s": round(setup_s, 3), "batches": layout}
 
 
 def cpu_baseline(w, budget_s: float):
@@ -104,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--batched-iters", type=int, default=20,
+                    help="timed iterations of the 64-slice uneven batch (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -175,6 +220,10 @@ def main():
                                                   / t_fwd / 1e9, 1),
                      "duration_us": round(t_fwd * 1e6, 2)},
     }
+    if args.batched_iters > 0:
+        del sv
+        torch.cuda.empty_cache()
+        out["batched"] = batched_run(ct, torch, args.batched_iters)
     if args.copy_calibration:
         x = torch.ones(16 * 1024 * 1024, device="cuda")
         y = torch.empty_like(x)

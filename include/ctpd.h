@@ -195,10 +195,25 @@ typedef struct ct_solver ct_solver;
  * CT_E_DEVICE. */
 int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
                      ct_stream s, ct_solver **out);
+
+/* A solver for nb >= 1 problems of the plan's geometry (probs[0..nb-1], all
+ * with the same lambda), advanced together: every kernel of an iteration
+ * covers the nb problems in one launch.  beta and c depend on the geometry
+ * only and are estimated once.  The number of angle slices of R_h^* is tuned
+ * at setup by timing the candidates on the batch (CTPD_NO_TUNE=1 keeps the
+ * plan's choice).  All state arrays of the other calls then hold nb problems
+ * one after the other ([nb][n][n], [nb][N][M], [nb][2][n][n]); ct_gap writes
+ * 6 doubles per problem.  Errors as ct_solver_create. */
+int ct_solver_create_batch(const ct_plan *p, const ct_problem *probs, int32_t nb,
+                           const ct_params *prm, ct_stream s, ct_solver **out);
 int ct_solver_destroy(ct_solver *sv);
 
 /* out[0] = beta, out[1] = c, out[2] = lambda~, out[3] = iterations done. */
 int ct_solver_info(const ct_solver *sv, double out[4]);
+
+/* out[0] = problems in the solver, out[1] = angle slices of R_h^*,
+ * out[2] = 1 if R_h runs angle pairs, out[3] = forward-projector groups. */
+int ct_solver_layout(const ct_solver *sv, int32_t out[4]);
 
 /* Run k iterations of PDRQS1 (§4.4) on the solver's state:
  *   u_tmp = -sigma (A^*(vb1 + sigma A u) - tau div(vb2 + sigma tau nabla u))
@@ -233,9 +248,10 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
  *   out[3] ||A^* y1 - tau div w||
  *   out[4] max_{D0} (C~ - A u)_+
  *   out[5] ||u_k - u_{k-1}||
+ * (6 doubles per problem for a batch solver, in problem order)
  * Requires at least one ct_pd_step since creation/import (CT_E_STATE).
  * Synchronizes s. */
-int ct_gap(ct_solver *sv, double out[6], ct_stream s);
+int ct_gap(ct_solver *sv, double *out, ct_stream s);
 
 /* One-shot solve: setup, k_max iterations, u_out [n][n].  With gap_every > 0
  * and report non-NULL, writes 6 doubles per record into report (capacity
@@ -243,6 +259,27 @@ int ct_gap(ct_solver *sv, double out[6], ct_stream s);
  * Returns CT_E_DIVERGED if a record is non-finite.  Synchronizes s. */
 int ct_reconstruct(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
                    float *u_out, double *report, int32_t report_len, ct_stream s);
+
+typedef struct ct_group ct_group;
+
+/* A group of solvers (any geometries, same number of iterations done) that
+ * ct_group_step advances together: k iterations of every solver, all but the
+ * last replayed from one HIP graph holding two iterations of every solver.
+ * The group does not own the solvers; destroy it before them.  A solver
+ * stepped on its own afterwards makes ct_group_step fail with CT_E_STATE. */
+int ct_group_create(ct_solver *const *svs, int32_t count, ct_group **out);
+int ct_group_step(ct_group *g, int32_t k, ct_stream s);
+int ct_group_destroy(ct_group *g);
+
+/* count problems, problem i on plans[i] (any mix of geometries), output
+ * u_out[i] [n_i][n_i] (device).  Problems with the same plan and lambda are
+ * advanced as one batch (ct_solver_create_batch); the iterations of all
+ * batches are captured together in one HIP graph and replayed.  Report
+ * layout: report[(i * R + r) * 6 + q] for record r < R = k_max / gap_every
+ * (records that do not fit report_len are skipped).  Synchronizes s. */
+int ct_reconstruct_batched(int32_t count, const ct_plan *const *plans, const ct_problem *probs,
+                           const ct_params *prm, float *const *u_out, double *report,
+                           int32_t report_len, ct_stream s);
 
 #ifdef __cplusplus
 }

@@ -294,25 +294,40 @@ class Solver:
         _check(_L.ct_pd_step_timed(self._h, k, o, _stream()), "ct_pd_step_timed")
         return dict(zip(("radon_adj", "precond", "radon_fwd", "tv_update", "total"), list(o)))
 
+    nb = 1
+
+    def _lead(self):
+        return () if self.nb == 1 else (self.nb,)
+
+    def layout(self) -> dict:
+        o = (ctypes.c_int32 * 4)()
+        _check(_L.ct_solver_layout(self._h, o), "ct_solver_layout")
+        return {"problems": o[0], "bp_slices": o[1], "paired": bool(o[2]), "fwd_groups": o[3]}
+
     def export(self):
         n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins
         dev = torch.device("cuda")
-        u = torch.empty((n, n), device=dev)
-        vb1 = torch.empty((N, M), device=dev)
-        vb2 = torch.empty((2, n, n), device=dev)
+        L = self._lead()
+        u = torch.empty(L + (n, n), device=dev)
+        vb1 = torch.empty(L + (N, M), device=dev)
+        vb2 = torch.empty(L + (2, n, n), device=dev)
         _check(_L.ct_state_export(self._h, u.data_ptr(), vb1.data_ptr(), vb2.data_ptr(),
                                   _stream()), "ct_state_export")
         return u, vb1, vb2
 
     def import_state(self, u, vb1, vb2) -> None:
         n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins
-        _check(_L.ct_state_import(self._h, _dev(u, (n, n), "u"), _dev(vb1, (N, M), "vb1"),
-                                  _dev(vb2, (2, n, n), "vb2"), _stream()), "ct_state_import")
+        L = self._lead()
+        _check(_L.ct_state_import(self._h, _dev(u, L + (n, n), "u"),
+                                  _dev(vb1, L + (N, M), "vb1"),
+                                  _dev(vb2, L + (2, n, n), "vb2"), _stream()), "ct_state_import")
 
     def gap(self) -> np.ndarray:
-        o = (ctypes.c_double * 6)()
+        """FP64 record (6 values; (nb, 6) for a batch)."""
+        o = (ctypes.c_double * (6 * self.nb))()
         _check(_L.ct_gap(self._h, o, _stream()), "ct_gap")
-        return np.array(list(o), dtype=np.float64)
+        r = np.array(list(o), dtype=np.float64)
+        return r if self.nb == 1 else r.reshape(self.nb, 6)
 
     def close(self):
         if self._h:
@@ -324,6 +339,99 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class SolverBatch(Solver):
+    """nb problems of one geometry advanced together (one launch per kernel
+    for all of them); state tensors carry a leading batch dimension."""
+
+    def __init__(self, plan: Plan, sinos, lam: float, masks=None, bounds=None, *,
+                 sigma: float = 1.0, tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3,
+                 c: Optional[float] = None, c_safety: float = 1.1, beta: Optional[float] = None,
+                 power_iters: int = 30, validate: bool = False,
+                 start_norm: Optional[torch.Tensor] = None,
+                 start_precond: Optional[torch.Tensor] = None, bound_scalars=None):
+        self.plan = plan
+        nb = len(sinos)
+        masks = masks if masks is not None else [None] * nb
+        bounds = bounds if bounds is not None else [None] * nb
+        bsc = bound_scalars if bound_scalars is not None else [0.0] * nb
+        if not (len(masks) == len(bounds) == len(bsc) == nb) or nb < 1:
+            raise ValueError("sinos, masks, bounds and bound_scalars need one entry per problem")
+        self.nb = nb
+        self._keep = (list(sinos), list(masks), list(bounds), start_norm, start_precond)
+        probs = (_lib.CtProblem * nb)()
+        for b in range(nb):
+            probs[b] = _problem(plan, sinos[b], masks[b], bounds[b], lam, bsc[b])
+        prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
+                      start_norm, start_precond, plan.n)
+        h = ctypes.c_void_p()
+        _check(_L.ct_solver_create_batch(plan.handle, probs, nb, ctypes.byref(prm), _stream(),
+                                         ctypes.byref(h)), "ct_solver_create_batch")
+        self._h = h
+
+
+class SolverGroup:
+    """Solvers (any geometries, same iteration count) stepped together from one
+    HIP graph.  Keeps references to the solvers; close() before they go."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        _check(_L.ct_group_create(arr, len(self.solvers), ctypes.byref(h)), "ct_group_create")
+        self._h = h
+
+    def step(self, k: int = 1) -> None:
+        _check(_L.ct_group_step(self._h, k, _stream()), "ct_group_step")
+
+    def close(self):
+        if self._h:
+            _L.ct_group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma: float = 1.0,
+                        tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3,
+                        c: Optional[float] = None, c_safety: float = 1.1,
+                        beta: Optional[float] = None, power_iters: int = 30,
+                        validate: bool = False):
+    """PDRQS1 solves of many problems, any mix of geometries.  problems: list of
+    dicts with keys plan, sino, lam and optionally mask_bits, bound,
+    bound_scalar.  Problems sharing a plan and lambda run as one batch; all
+    batches' iterations replay as one HIP graph.  beta and c (if not given)
+    are estimated per batch.  Returns ([u_i], report (count, records, 6) or
+    None)."""
+    count = len(problems)
+    if count < 1:
+        raise ValueError("no problems")
+    plans = (ctypes.c_void_p * count)()
+    probs = (_lib.CtProblem * count)()
+    outs = (ctypes.c_void_p * count)()
+    us = []
+    for i, pr in enumerate(problems):
+        plan = pr["plan"]
+        plans[i] = plan.handle.value
+        probs[i] = _problem(plan, pr["sino"], pr.get("mask_bits"), pr.get("bound"), pr["lam"],
+                            pr.get("bound_scalar", 0.0))
+        u = torch.empty((plan.n, plan.n), device=pr["sino"].device, dtype=torch.float32)
+        us.append(u)
+        outs[i] = u.data_ptr()
+    prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
+                  None, None, problems[0]["plan"].n)
+    nrec = k_max // gap_every if gap_every > 0 else 0
+    rep = (ctypes.c_double * max(1, 6 * nrec * count))()
+    _check(_L.ct_reconstruct_batched(count, plans, probs, ctypes.byref(prm), outs,
+                                     rep if nrec else None, 6 * nrec * count, _stream()),
+           "ct_reconstruct_batched")
+    report = (np.array(list(rep), dtype=np.float64).reshape(count, nrec, 6) if nrec else None)
+    return us, report
 
 
 def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, bound=None, *,

@@ -54,7 +54,10 @@ SIGNATURES = {
     "ct_params_default": (None, [POINTER(CtParams)]),
     "ct_solver_create": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                    POINTER(c_void_p)]),
+    "ct_solver_create_batch": (c_int32, [c_void_p, POINTER(CtProblem), c_int32,
+                                         POINTER(CtParams), c_void_p, POINTER(c_void_p)]),
     "ct_solver_destroy": (c_int32, [c_void_p]),
+    "ct_solver_layout": (c_int32, [c_void_p, POINTER(c_int32)]),
     "ct_solver_info": (c_int32, [c_void_p, POINTER(c_double)]),
     "ct_plan_check": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(ctypes.c_int64)]),
     "ct_pd_step": (c_int32, [c_void_p, c_int32, c_void_p]),
@@ -64,6 +67,12 @@ SIGNATURES = {
     "ct_gap": (c_int32, [c_void_p, POINTER(c_double), c_void_p]),
     "ct_reconstruct": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                  POINTER(c_double), c_int32, c_void_p]),
+    "ct_group_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p)]),
+    "ct_group_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "ct_group_destroy": (c_int32, [c_void_p]),
+    "ct_reconstruct_batched": (c_int32, [c_int32, POINTER(c_void_p), POINTER(CtProblem),
+                                         POINTER(CtParams), POINTER(c_void_p),
+                                         POINTER(c_double), c_int32, c_void_p]),
 }
 
 

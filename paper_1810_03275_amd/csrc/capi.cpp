@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -145,12 +146,18 @@ using namespace ctpd;
 struct ct_solver {
   ct_plan *plan = nullptr;
   ct_precond pc{};
+  int nb = 1;  // problems advanced together
   int n = 0, N = 0, M = 0;
   double beta = 0, c = 0, lam_t = 0, sigma = 0, tau = 0, eps = 0;
   float *u = nullptr, *u_next = nullptr, *vb1 = nullptr, *s1 = nullptr, *vb2 = nullptr,
         *s2 = nullptr, *target = nullptr, *rraw = nullptr, *utmp = nullptr;
   float *y1 = nullptr, *r = nullptr, *w = nullptr;
   uint32_t *mask = nullptr;
+  float2 *spec = nullptr;     // nb spectra of the preconditioner FFT
+  float *bp_part = nullptr;   // nb * bp_S partial backprojections
+  size_t bp_cap = 0;
+  int bp_S = 1;               // angle slices of the backprojection (tuned)
+  bool tune = true;
   double *d_red = nullptr, *d_out = nullptr;
   int red_cap = 0;
   int64_t iters = 0;
@@ -166,9 +173,10 @@ struct ct_solver {
 static void solver_free(ct_solver *sv) {
   if (!sv) return;
   float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
-                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w};
+                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part};
   for (float *b : bufs) (void)hipFree(b);
   (void)hipFree(sv->mask);
+  (void)hipFree(sv->spec);
   (void)hipFree(sv->d_red);
   (void)hipFree(sv->d_out);
   for (auto &g : sv->gexec)
@@ -391,9 +399,13 @@ int ct_power_norm(const ct_plan *pc, int32_t iters, const float *x0, double *out
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// Solver: nb >= 1 problems of one geometry advanced together.  Every state
+// array holds the nb problems one after the other ([nb][n][n], [nb][N][M],
+// ...); each kernel of an iteration covers all of them in one launch.
 
 static int solver_alloc(ct_solver *sv) {
-  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  const size_t nb = sv->nb;
+  const size_t nn = (size_t)sv->n * sv->n * nb, NM = (size_t)sv->N * sv->M * nb;
   CT_TRY_HIP(hipMalloc(&sv->u, sizeof(float) * nn));
   CT_TRY_HIP(hipMalloc(&sv->u_next, sizeof(float) * nn));
   CT_TRY_HIP(hipMalloc(&sv->utmp, sizeof(float) * nn));
@@ -403,17 +415,34 @@ static int solver_alloc(ct_solver *sv) {
   CT_TRY_HIP(hipMalloc(&sv->vb1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->s1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->target, sizeof(float) * NM));
-  CT_TRY_HIP(hipMalloc(&sv->rraw, sizeof(float) * NM));
+  CT_TRY_HIP(hipMalloc(&sv->rraw, sizeof(float) * (size_t)sv->N * sv->M));
   CT_TRY_HIP(hipMalloc(&sv->y1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->r, sizeof(float) * NM));
+  const size_t MW = (size_t)(sv->M + 31) / 32;
+  CT_TRY_HIP(hipMalloc(&sv->mask, sizeof(uint32_t) * sv->N * MW * nb));
+  CT_TRY_HIP(hipMalloc(&sv->spec, sizeof(float2) * (size_t)(sv->n / 2 + 1) * sv->n * nb));
   sv->red_cap = reduction_partials_needed() + 16;
   CT_TRY_HIP(hipMalloc(&sv->d_red, sizeof(double) * sv->red_cap));
   CT_TRY_HIP(hipMalloc(&sv->d_out, sizeof(double) * 16));
   return CT_OK;
 }
 
+// Partial images of the sliced backprojection: nb * S images.
+static int solver_set_slices(ct_solver *sv, int S) {
+  const size_t need = (S > 1) ? (size_t)S * sv->nb * sv->n * sv->n : 0;
+  if (need > sv->bp_cap) {
+    (void)hipFree(sv->bp_part);
+    sv->bp_part = nullptr;
+    sv->bp_cap = 0;
+    CT_TRY_HIP(hipMalloc(&sv->bp_part, sizeof(float) * need));
+    sv->bp_cap = need;
+  }
+  sv->bp_S = S;
+  return CT_OK;
+}
+
 static int solver_zero_state(ct_solver *sv, hipStream_t s) {
-  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
   CT_TRY_HIP(hipMemsetAsync(sv->u, 0, sizeof(float) * nn, s));
   CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, s));
   CT_TRY_HIP(hipMemsetAsync(sv->vb2, 0, sizeof(float) * nn * 2, s));
@@ -425,34 +454,109 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   return CT_OK;
 }
 
-static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *prm,
+// One PDRQS1 iteration (§4.4) of all nb problems from the cached
+// s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and
+// A u for the record.  With ev (5 events) the phase boundaries are recorded.
+static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr) {
+  ct_plan *p = sv->plan;
+  const float sig = (float)sv->sigma, tau = (float)sv->tau;
+  const float inv_h = (float)(1.0 / p->g.h);
+  const int nb = sv->nb;
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
+  CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
+                          (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
+  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
+                           sv->spec));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
+  // R_h u_new with the sinogram-side update fused into its output stage
+  const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
+                   sv->y1, sv->r, mode};
+  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
+  CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
+                          sv->vb2, sv->s2, sv->w, mode, st, nb));
+  if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
+  std::swap(sv->u, sv->u_next);
+  sv->iters += 1;
+  return CT_OK;
+}
+
+// Choose the number of angle slices of the backprojection for this batch by
+// timing the candidates on the solver's own data (the caches s1, s2).
+static int solver_tune(ct_solver *sv, hipStream_t st) {
+  const int N = sv->N;
+  int cands[4], nc = 0;
+  for (int S : {1, 2, 4, 8})
+    if (S == 1 || N / S >= 2 * kBpChunk) cands[nc++] = S;
+  if (nc == 1) return solver_set_slices(sv, 1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CT_TRY_HIP(hipEventCreate(&e0));
+  std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g0(
+      e0, hipEventDestroy);
+  CT_TRY_HIP(hipEventCreate(&e1));
+  std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(
+      e1, hipEventDestroy);
+  float best = 0.f;
+  int bestS = cands[0];
+  for (int c = 0; c < nc; ++c) {
+    CT_TRY(solver_set_slices(sv, cands[c]));
+    auto run = [&]() {
+      return launch_radon_adj(sv->plan, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+                              sv->bp_part, sv->bp_S);
+    };
+    CT_TRY(run());  // warm-up
+    CT_TRY_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) CT_TRY(run());
+    CT_TRY_HIP(hipEventRecord(e1, st));
+    CT_TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CT_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (c == 0 || ms < best) {
+      best = ms;
+      bestS = cands[c];
+    }
+  }
+  return solver_set_slices(sv, bestS);
+}
+
+static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params *prm,
                         hipStream_t st) {
   ct_plan *p = sv->plan;
-  const int n = sv->n, N = sv->N, M = sv->M;
+  const int n = sv->n, N = sv->N, M = sv->M, nb = sv->nb;
   const size_t nn = (size_t)n * n, NM = (size_t)N * M;
+  const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
-  if (prob->mask) {
-    const size_t MW = (size_t)(M + 31) / 32;
-    CT_TRY_HIP(hipMalloc(&sv->mask, sizeof(uint32_t) * N * MW));
-    CT_TRY_HIP(hipMemcpyAsync(sv->mask, prob->mask, sizeof(uint32_t) * N * MW,
-                              hipMemcpyDeviceToDevice, st));
+  CT_TRY(solver_set_slices(sv, p->bp_slices));
+  for (int b = 0; b < nb; ++b) {
+    uint32_t *mb = sv->mask + (size_t)b * N * MW;
+    if (probs[b].mask)
+      CT_TRY_HIP(hipMemcpyAsync(mb, probs[b].mask, sizeof(uint32_t) * N * MW,
+                                hipMemcpyDeviceToDevice, st));
+    else
+      CT_TRY_HIP(hipMemsetAsync(mb, 0, sizeof(uint32_t) * N * MW, st));
   }
   if (prm->flags & CT_FLAG_VALIDATE) {
     int *flag = reinterpret_cast<int *>(sv->d_out);
     CT_TRY_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-    CT_TRY(launch_nonfinite(prob->sino, (int64_t)NM, flag, st));
-    if (prob->bound) CT_TRY(launch_nonfinite(prob->bound, (int64_t)NM, flag, st));
+    bool finite = true;
+    for (int b = 0; b < nb; ++b) {
+      CT_TRY(launch_nonfinite(probs[b].sino, (int64_t)NM, flag, st));
+      if (probs[b].bound) CT_TRY(launch_nonfinite(probs[b].bound, (int64_t)NM, flag, st));
+      finite = finite && std::isfinite(probs[b].bound_scalar);
+    }
     int hflag = 0;
     CT_TRY_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
-    if (hflag || !std::isfinite(prob->bound_scalar)) {
+    if (hflag || !finite) {
       set_error("ct_solver_create: non-finite value in sinogram or bound");
       return CT_E_NONFINITE;
     }
   }
   CT_TRY(precond_init(&sv->pc, n, prm->sigma, prm->tau, -1.0, prm->eps));
   double *d_norm = sv->d_out;
-  // beta = ||R_h|| (§5.1 normalization; power iteration unless given)
+  // beta = ||R_h|| (§5.1 normalization; power iteration unless given).  It and
+  // c depend on the geometry only, so one estimate serves the whole batch.
   if (prm->beta > 0) {
     sv->beta = prm->beta;
   } else {
@@ -466,7 +570,8 @@ static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *
     }
     auto op = [&](float *xin, float *yout) -> int {
       CT_TRY(launch_radon_fwd(p, xin, sv->rraw, st));
-      return launch_radon_adj(p, sv->rraw, nullptr, 1.0f, 0.0f, yout, st);
+      return launch_radon_adj(p, sv->rraw, nullptr, 1.0f, 0.0f, yout, st, 1, sv->bp_part,
+                              sv->bp_S);
     };
     double lam = 0;
     CT_TRY(power_iterate(n, prm->power_iters, sv->u, sv->utmp, sv->d_red, sv->red_cap, d_norm,
@@ -498,7 +603,8 @@ static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *
     auto op = [&](float *xin, float *yout) -> int {
       CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, xin, nullptr, sv->u_next, st));
       CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st));
-      CT_TRY(launch_radon_adj(p, sv->rraw, nullptr, inv_b2, 0.0f, sv->u_next, st));
+      CT_TRY(launch_radon_adj(p, sv->rraw, nullptr, inv_b2, 0.0f, sv->u_next, st, 1,
+                              sv->bp_part, sv->bp_S));
       return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->u_next, nullptr, yout, st);
     };
     double lam = 0;
@@ -517,84 +623,111 @@ static int solver_setup(ct_solver *sv, const ct_problem *prob, const ct_params *
                               hipMemcpyHostToDevice, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
   }
-  CT_TRY(launch_build_target(N, M, prob->sino, prob->bound, prob->bound_scalar, sv->mask,
-                             (float)(1.0 / sv->beta), sv->target, st));
-  sv->lam_t = prob->lambda / (sv->beta * sv->beta);
+  for (int b = 0; b < nb; ++b)
+    CT_TRY(launch_build_target(N, M, probs[b].sino, probs[b].bound, probs[b].bound_scalar,
+                               sv->mask + (size_t)b * N * MW, (float)(1.0 / sv->beta),
+                               sv->target + (size_t)b * NM, st));
+  sv->lam_t = probs[0].lambda / (sv->beta * sv->beta);
   CT_TRY(solver_zero_state(sv, st));
+  if (sv->tune) CT_TRY(solver_tune(sv, st));
   CT_TRY_HIP(hipStreamSynchronize(st));
   return CT_OK;
 }
 
-// One PDRQS1 iteration (§4.4) from the cached s1 = vb1 + sigma A u,
-// s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and A u for the record.
-// With ev (5 events) the phase boundaries are recorded on st.
-static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr) {
-  ct_plan *p = sv->plan;
-  const float sig = (float)sv->sigma, tau = (float)sv->tau;
-  const float inv_h = (float)(1.0 / p->g.h);
-  if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
-  CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
-                          (float)(sv->sigma * sv->tau), sv->utmp, st));
-  if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
-  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st));
-  if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
-  // R_h u_new with the sinogram-side update fused into its output stage
-  const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
-                   sv->y1, sv->r, mode};
-  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep));
-  if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
-  CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
-                          sv->vb2, sv->s2, sv->w, mode, st));
-  if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
-  std::swap(sv->u, sv->u_next);
-  sv->iters += 1;
-  return CT_OK;
-}
-
-// Capture two mode-0 iterations starting from the current (u, u_next)
-// assignment; the pointers are back in place after them.
-static int solver_capture(ct_solver *sv, int parity) {
-  if (!sv->cap_stream) CT_TRY_HIP(hipStreamCreateWithFlags(&sv->cap_stream, hipStreamNonBlocking));
+// Capture two mode-0 iterations of every solver in svs (all at the same
+// ping-pong parity) as one HIP graph on a private stream; the pointers are
+// back in place after them.
+static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap,
+                        hipGraphExec_t *out) {
   hipGraph_t graph = nullptr;
-  CT_TRY_HIP(hipStreamBeginCapture(sv->cap_stream, hipStreamCaptureModeThreadLocal));
-  const int64_t it0 = sv->iters;
-  int rc = solver_iter(sv, 0, sv->cap_stream);
-  if (rc == CT_OK) rc = solver_iter(sv, 0, sv->cap_stream);
-  sv->iters = it0;  // nothing ran
-  hipError_t e = hipStreamEndCapture(sv->cap_stream, &graph);
+  CT_TRY_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int rc = CT_OK;
+  for (int it = 0; it < 2 && rc == CT_OK; ++it)
+    for (int q = 0; q < count && rc == CT_OK; ++q) {
+      const int64_t it0 = svs[q]->iters;
+      rc = solver_iter(svs[q], 0, cap);
+      svs[q]->iters = it0;  // nothing ran
+    }
+  hipError_t e = hipStreamEndCapture(cap, &graph);
   if (rc != CT_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return rc;
   }
   CT_TRY_HIP(e);
-  hipError_t ei = hipGraphInstantiate(&sv->gexec[parity], graph, nullptr, nullptr, 0);
+  hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   CT_TRY_HIP(ei);
-  sv->gexec_u[parity] = sv->u;
   return CT_OK;
 }
 
-extern "C" {
+static bool use_graphs() {
+  const char *ng = std::getenv("CTPD_NO_GRAPH");
+  return !(ng && ng[0] == '1');
+}
 
-int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
-                     ct_stream s, ct_solver **out) {
-  clear_error();
-  if (!p || !prob || !prm || !out || !prob->sino) {
-    set_error("ct_solver_create: null argument");
+// k iterations of every solver in svs (same iteration count and parity):
+// all but the last in graph-replayed pairs, the last one eager in mode 2 so
+// that y1, w and A u are there for a record.  graphs[2] and cap are the
+// caller's cache (captured on first use per parity).
+static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, hipStream_t *cap,
+                      hipGraphExec_t graphs[2], float *graph_u[2]) {
+  int left = k;
+  if (use_graphs() && left >= 3) {
+    const int parity = (svs[0]->u < svs[0]->u_next) ? 0 : 1;
+    if (!graphs[parity]) {
+      if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+      CT_TRY(capture_pair(svs, count, *cap, &graphs[parity]));
+      graph_u[parity] = svs[0]->u;
+    }
+    if (graph_u[parity] != svs[0]->u) {
+      set_error("ct_pd_step: graph parity mismatch");
+      return CT_E_STATE;
+    }
+    const int pairs = (left - 1) / 2;
+    for (int q = 0; q < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(graphs[parity], st));
+    for (int q = 0; q < count; ++q) svs[q]->iters += 2 * pairs;
+    left -= 2 * pairs;
+  }
+  for (int it = 0; it < left; ++it)
+    for (int q = 0; q < count; ++q) CT_TRY(solver_iter(svs[q], it == left - 1 ? 2 : 0, st));
+  if (k > 0)
+    for (int q = 0; q < count; ++q) svs[q]->have_dual = true;
+  return CT_OK;
+}
+
+static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, const ct_params *prm,
+                         ct_stream s, ct_solver **out) {
+  if (!p || !probs || !prm || !out || nb < 1) {
+    set_error("ct_solver_create: null argument or empty batch");
     return CT_E_INVALID;
   }
   *out = nullptr;
-  if (!(prm->sigma > 0) || !(prm->tau > 0) || !(prm->eps > 0) || !(prob->lambda >= 0) ||
-      !std::isfinite(prob->lambda) || prm->k_max < 0 || prm->gap_every < 0 ||
-      (prm->c <= 0 && !(prm->c_safety > 0)) ||
+  if (!(prm->sigma > 0) || !(prm->tau > 0) || !(prm->eps > 0) || prm->k_max < 0 ||
+      prm->gap_every < 0 || (prm->c <= 0 && !(prm->c_safety > 0)) ||
       ((prm->c <= 0 || prm->beta <= 0) && prm->power_iters < 1)) {
     set_error("ct_solver_create: need sigma, tau, eps > 0, lambda >= 0, k_max >= 0, "
               "power_iters >= 1 when beta or c is estimated");
     return CT_E_INVALID;
   }
-  if (prob->mask && !prob->bound && !std::isfinite(prob->bound_scalar)) {
-    set_error("ct_solver_create: non-finite bound");
-    return CT_E_INVALID;
+  for (int b = 0; b < nb; ++b) {
+    const ct_problem &pr = probs[b];
+    if (!pr.sino) {
+      set_error("ct_solver_create: null sinogram");
+      return CT_E_INVALID;
+    }
+    if (!(pr.lambda >= 0) || !std::isfinite(pr.lambda)) {
+      set_error("ct_solver_create: need sigma, tau, eps > 0, lambda >= 0, k_max >= 0, "
+                "power_iters >= 1 when beta or c is estimated");
+      return CT_E_INVALID;
+    }
+    if (pr.lambda != probs[0].lambda) {
+      set_error("ct_solver_create: the problems of one batch need the same lambda");
+      return CT_E_INVALID;
+    }
+    if (pr.mask && !pr.bound && !std::isfinite(pr.bound_scalar)) {
+      set_error("ct_solver_create: non-finite bound");
+      return CT_E_INVALID;
+    }
   }
   if (!fft_size_ok(p->g.n)) {
     set_error("ct_solver_create: n must be even, 2^a 3^b and <= 4096");
@@ -603,17 +736,19 @@ int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *
   ct_solver *sv = new (std::nothrow) ct_solver();
   if (!sv) return CT_E_DEVICE;
   sv->plan = const_cast<ct_plan *>(p);
+  sv->nb = nb;
   sv->n = p->g.n;
   sv->N = p->g.n_angles;
   sv->M = p->g.n_bins;
   sv->sigma = prm->sigma;
   sv->tau = prm->tau;
   sv->eps = prm->eps;
+  sv->use_graph = use_graphs();
   {
-    const char *ng = std::getenv("CTPD_NO_GRAPH");
-    sv->use_graph = !(ng && ng[0] == '1');
+    const char *nt = std::getenv("CTPD_NO_TUNE");
+    sv->tune = !(nt && nt[0] == '1');
   }
-  int rc = solver_setup(sv, prob, prm, S(s));
+  int rc = solver_setup(sv, probs, prm, S(s));
   if (rc != CT_OK) {
     (void)hipStreamSynchronize(S(s));
     solver_free(sv);
@@ -622,6 +757,46 @@ int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *
   }
   *out = sv;
   return CT_OK;
+}
+
+// FP64 record of problem b (see ct_gap).
+static int solver_gap(ct_solver *sv, int b, double out[6], hipStream_t st) {
+  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  const size_t MW = (size_t)(sv->M + 31) / 32;
+  double *o = sv->d_out;
+  CT_TRY(launch_sino_gap(sv->N, sv->M, sv->r + b * NM, sv->y1 + b * NM, sv->target + b * NM,
+                         sv->mask + b * (size_t)sv->N * MW, sv->d_red, sv->red_cap, o, st));
+  // z = A^* y1 - tau div w  (= K^* y), into the first u_tmp image
+  CT_TRY(launch_radon_adj(sv->plan, sv->y1 + b * NM, sv->w + b * 2 * nn,
+                          (float)(1.0 / sv->beta), (float)(-sv->tau), sv->utmp, st, 1,
+                          sv->bp_part, sv->bp_S));
+  CT_TRY(launch_img_gap(sv->n, (float)(1.0 / sv->plan->g.h), sv->u + b * nn,
+                        sv->u_next + b * nn, sv->utmp, sv->d_red, sv->red_cap, o + 3, st));
+  double h[6];
+  CT_TRY_HIP(hipMemcpyAsync(h, o, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  const double P = h[0] + sv->lam_t * h[3];
+  out[0] = P;
+  out[1] = h[1];
+  out[2] = P + h[1];
+  out[3] = std::sqrt(h[5]);
+  out[4] = h[2];
+  out[5] = std::sqrt(h[4]);
+  return CT_OK;
+}
+
+extern "C" {
+
+int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *prm,
+                     ct_stream s, ct_solver **out) {
+  clear_error();
+  return solver_create(p, prob, 1, prm, s, out);
+}
+
+int ct_solver_create_batch(const ct_plan *p, const ct_problem *probs, int32_t nb,
+                           const ct_params *prm, ct_stream s, ct_solver **out) {
+  clear_error();
+  return solver_create(p, probs, nb, prm, s, out);
 }
 
 int ct_solver_destroy(ct_solver *sv) {
@@ -645,30 +820,32 @@ int ct_solver_info(const ct_solver *sv, double out[4]) {
   return CT_OK;
 }
 
+int ct_solver_layout(const ct_solver *sv, int32_t out[4]) {
+  clear_error();
+  if (!sv || !out) {
+    set_error("ct_solver_layout: null argument");
+    return CT_E_INVALID;
+  }
+  out[0] = sv->nb;
+  out[1] = sv->bp_S;
+  out[2] = sv->plan->paired ? 1 : 0;
+  out[3] = sv->plan->n_groups;
+  return CT_OK;
+}
+
 int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
   clear_error();
   if (!sv || k < 0) {
     set_error("ct_pd_step: invalid argument");
     return CT_E_INVALID;
   }
-  hipStream_t st = S(s);
-  int left = k;
-  // all but the last iteration in pairs from the graph (identical kernels and order)
-  if (sv->use_graph && left >= 3) {
-    const int parity = (sv->u < sv->u_next) ? 0 : 1;
-    if (!sv->gexec[parity]) CT_TRY(solver_capture(sv, parity));
-    if (sv->gexec_u[parity] != sv->u) {
-      set_error("ct_pd_step: graph parity mismatch");
-      return CT_E_STATE;
-    }
-    const int pairs = (left - 1) / 2;
-    for (int q = 0; q < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(sv->gexec[parity], st));
-    sv->iters += 2 * pairs;
-    left -= 2 * pairs;
+  if (!sv->use_graph) {
+    for (int it = 0; it < k; ++it) CT_TRY(solver_iter(sv, it == k - 1 ? 2 : 0, S(s)));
+    if (k > 0) sv->have_dual = true;
+    return CT_OK;
   }
-  for (int it = 0; it < left; ++it) CT_TRY(solver_iter(sv, it == left - 1 ? 2 : 0, st));
-  if (k > 0) sv->have_dual = true;
-  return CT_OK;
+  ct_solver *one[1] = {sv};
+  return multi_step(one, 1, k, S(s), &sv->cap_stream, sv->gexec, sv->gexec_u);
 }
 
 int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s) {
@@ -709,7 +886,7 @@ int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_st
     set_error("ct_state_export: null solver");
     return CT_E_INVALID;
   }
-  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
   hipStream_t st = S(s);
   if (u) CT_TRY_HIP(hipMemcpyAsync(u, sv->u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
   if (vb1)
@@ -726,7 +903,7 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
     set_error("ct_state_import: null argument");
     return CT_E_INVALID;
   }
-  const size_t nn = (size_t)sv->n * sv->n, NM = (size_t)sv->N * sv->M;
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
   hipStream_t st = S(s);
   CT_TRY_HIP(hipMemcpyAsync(sv->u, u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
   CT_TRY_HIP(hipMemcpyAsync(sv->vb1, vb1, sizeof(float) * NM, hipMemcpyDeviceToDevice, st));
@@ -734,14 +911,15 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
   // caches: s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u
   const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
                    sv->s1, nullptr, nullptr, 1};
-  CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep));
+  CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep, sv->nb));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
-                          (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st));
+                          (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st,
+                          sv->nb));
   sv->have_dual = false;
   return CT_OK;
 }
 
-int ct_gap(ct_solver *sv, double out[6], ct_stream s) {
+int ct_gap(ct_solver *sv, double *out, ct_stream s) {
   clear_error();
   if (!sv || !out) {
     set_error("ct_gap: null argument");
@@ -751,62 +929,160 @@ int ct_gap(ct_solver *sv, double out[6], ct_stream s) {
     set_error("ct_gap: no iteration since creation or import");
     return CT_E_STATE;
   }
-  hipStream_t st = S(s);
-  double *o = sv->d_out;
-  CT_TRY(launch_sino_gap(sv->N, sv->M, sv->r, sv->y1, sv->target, sv->mask, sv->d_red,
-                         sv->red_cap, o, st));
-  // z = A^* y1 - tau div w  (= K^* y)
-  CT_TRY(launch_radon_adj(sv->plan, sv->y1, sv->w, (float)(1.0 / sv->beta), (float)(-sv->tau),
-                          sv->utmp, st));
-  CT_TRY(launch_img_gap(sv->n, (float)(1.0 / sv->plan->g.h), sv->u, sv->u_next, sv->utmp,
-                        sv->d_red, sv->red_cap, o + 3, st));
-  double h[6];
-  CT_TRY_HIP(hipMemcpyAsync(h, o, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
-  CT_TRY_HIP(hipStreamSynchronize(st));
-  const double P = h[0] + sv->lam_t * h[3];
-  out[0] = P;
-  out[1] = h[1];
-  out[2] = P + h[1];
-  out[3] = std::sqrt(h[5]);
-  out[4] = h[2];
-  out[5] = std::sqrt(h[4]);
+  for (int b = 0; b < sv->nb; ++b) CT_TRY(solver_gap(sv, b, out + 6 * b, S(s)));
+  return CT_OK;
+}
+
+}  // extern "C"
+
+struct ct_group {
+  std::vector<ct_solver *> svs;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t graphs[2] = {nullptr, nullptr};
+  float *graph_u[2] = {nullptr, nullptr};
+  ~ct_group() {
+    for (auto g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+extern "C" {
+
+int ct_group_create(ct_solver *const *svs, int32_t count, ct_group **out) {
+  clear_error();
+  if (!svs || count < 1 || !out) {
+    set_error("ct_group_create: null argument or empty group");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  for (int q = 0; q < count; ++q) {
+    if (!svs[q]) {
+      set_error("ct_group_create: null solver");
+      return CT_E_INVALID;
+    }
+    if (svs[q]->iters != svs[0]->iters) {
+      set_error("ct_group_create: solvers must have done the same number of iterations");
+      return CT_E_STATE;
+    }
+    for (int r = 0; r < q; ++r)
+      if (svs[r] == svs[q]) {
+        set_error("ct_group_create: a solver appears twice");
+        return CT_E_INVALID;
+      }
+  }
+  ct_group *g = new (std::nothrow) ct_group();
+  if (!g) return CT_E_DEVICE;
+  g->svs.assign(svs, svs + count);
+  *out = g;
+  return CT_OK;
+}
+
+int ct_group_step(ct_group *g, int32_t k, ct_stream s) {
+  clear_error();
+  if (!g || k < 0) {
+    set_error("ct_group_step: invalid argument");
+    return CT_E_INVALID;
+  }
+  for (ct_solver *sv : g->svs)
+    if (sv->iters != g->svs[0]->iters) {
+      set_error("ct_group_step: a solver of the group was stepped on its own");
+      return CT_E_STATE;
+    }
+  return multi_step(g->svs.data(), (int)g->svs.size(), k, S(s), &g->cap, g->graphs,
+                    g->graph_u);
+}
+
+int ct_group_destroy(ct_group *g) {
+  clear_error();
+  delete g;
   return CT_OK;
 }
 
 int ct_reconstruct(const ct_plan *p, const ct_problem *prob, const ct_params *prm, float *u_out,
                    double *report, int32_t report_len, ct_stream s) {
   clear_error();
-  if (!u_out) {
-    set_error("ct_reconstruct: null output");
+  if (!u_out || !prm) {
+    set_error("ct_reconstruct: null argument");
     return CT_E_INVALID;
   }
-  ct_solver *sv = nullptr;
-  CT_TRY(ct_solver_create(p, prob, prm, s, &sv));
-  std::unique_ptr<ct_solver, int (*)(ct_solver *)> guard(sv, ct_solver_destroy);
+  float *outs[1] = {u_out};
+  return ct_reconstruct_batched(1, &p, prob, prm, outs, report, report_len, s);
+}
+
+int ct_reconstruct_batched(int32_t count, const ct_plan *const *plans, const ct_problem *probs,
+                           const ct_params *prm, float *const *u_out, double *report,
+                           int32_t report_len, ct_stream s) {
+  clear_error();
+  if (count < 1 || !plans || !probs || !prm || !u_out) {
+    set_error("ct_reconstruct_batched: null argument or empty batch");
+    return CT_E_INVALID;
+  }
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !u_out[i]) {
+      set_error("ct_reconstruct_batched: null plan or output");
+      return CT_E_INVALID;
+    }
+  hipStream_t st = S(s);
+  // one solver per (plan, lambda): its problems share every kernel launch
+  std::vector<std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    bool placed = false;
+    for (auto &g : groups)
+      if (plans[g[0]] == plans[i] && probs[g[0]].lambda == probs[i].lambda) {
+        g.push_back(i);
+        placed = true;
+        break;
+      }
+    if (!placed) groups.push_back({i});
+  }
+  struct Owned : ct_group {
+    ~Owned() {
+      for (auto sv : svs) ct_solver_destroy(sv);
+    }
+  } own;
+  for (auto &g : groups) {
+    std::vector<ct_problem> pg;
+    for (int i : g) pg.push_back(probs[i]);
+    ct_solver *sv = nullptr;
+    CT_TRY(solver_create(plans[g[0]], pg.data(), (int)pg.size(), prm, s, &sv));
+    own.svs.push_back(sv);
+  }
+  const int ng = (int)own.svs.size();
+  const int n_rec = prm->gap_every > 0 ? prm->k_max / prm->gap_every : 0;
   int done = 0, rec = 0;
-  if (prm->gap_every > 0 && report) {
-    while (done < prm->k_max) {
-      const int k = std::min(prm->gap_every, prm->k_max - done);
-      CT_TRY(ct_pd_step(sv, k, s));
-      done += k;
-      if (k == prm->gap_every && (rec + 1) * 6 <= report_len) {
-        double r6[6];
-        CT_TRY(ct_gap(sv, r6, s));
-        for (int q = 0; q < 6; ++q) {
-          report[rec * 6 + q] = r6[q];
-          if (!std::isfinite(r6[q])) {
-            set_error("ct_reconstruct: gap record is not finite");
-            return CT_E_DIVERGED;
+  while (done < prm->k_max) {
+    const int k = (n_rec > 0 && report) ? std::min(prm->gap_every, prm->k_max - done)
+                                        : prm->k_max - done;
+    CT_TRY(multi_step(own.svs.data(), ng, k, st, &own.cap, own.graphs, own.graph_u));
+    done += k;
+    if (n_rec > 0 && report && k == prm->gap_every) {
+      for (int gi = 0; gi < ng; ++gi)
+        for (int b = 0; b < (int)groups[gi].size(); ++b) {
+          const int i = groups[gi][b];
+          const int64_t at = ((int64_t)i * n_rec + rec) * 6;
+          if (at + 6 > report_len) continue;
+          double r6[6];
+          CT_TRY(solver_gap(own.svs[gi], b, r6, st));
+          for (int q = 0; q < 6; ++q) {
+            report[at + q] = r6[q];
+            if (!std::isfinite(r6[q])) {
+              set_error("ct_reconstruct: gap record is not finite");
+              return CT_E_DIVERGED;
+            }
           }
         }
-        ++rec;
-      }
+      ++rec;
     }
-  } else {
-    CT_TRY(ct_pd_step(sv, prm->k_max, s));
   }
-  CT_TRY(ct_state_export(sv, u_out, nullptr, nullptr, s));
-  CT_TRY_HIP(hipStreamSynchronize(S(s)));
+  for (int gi = 0; gi < ng; ++gi) {
+    ct_solver *sv = own.svs[gi];
+    const size_t nn = (size_t)sv->n * sv->n;
+    for (int b = 0; b < (int)groups[gi].size(); ++b)
+      CT_TRY_HIP(hipMemcpyAsync(u_out[groups[gi][b]], sv->u + b * nn, sizeof(float) * nn,
+                                hipMemcpyDeviceToDevice, st));
+  }
+  CT_TRY_HIP(hipStreamSynchronize(st));
   return CT_OK;
 }
 

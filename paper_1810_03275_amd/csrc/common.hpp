@@ -152,8 +152,12 @@ namespace ctpd {
 
 // ---- launchers (kernels live in the .hip files) ---------------------------
 // out = c1 * R^*(v) + c2 * div_h(p)  (p may be null)
+// nb problems of one geometry stored contiguously; part: nb * bp_slices
+// partial images (NULL: the plan's own buffer, nb = 1 only).
+// S: angle slices (0: the plan's choice).
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
-                     float c2, float *out, hipStream_t s);
+                     float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
+                     int S = 0);
 // Optional epilogue of the forward projector: the PDRQS1 sinogram-side update
 // applied to r = R(u)/beta per bin (see k_sino_update), instead of storing R(u).
 struct SinoEpi {
@@ -169,7 +173,7 @@ struct SinoEpi {
 };
 // out = R(u) (raw), or the epilogue when epi != nullptr
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
-                     const SinoEpi *epi = nullptr);
+                     const SinoEpi *epi = nullptr, int nb = 1);
 
 int launch_grad(int n, float inv_h, const float *u, float *p, hipStream_t s);
 int launch_div(int n, float inv_h, const float *p, float *d, hipStream_t s);
@@ -184,13 +188,16 @@ int launch_sino_update(int N, int M, const float *rraw, float inv_beta, float si
                        const float *target, const uint32_t *mask, float *vb1, float *s1,
                        float *y1, float *rout, int mode, hipStream_t s);
 int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius,
-                     float *vb2, float *s2, float *wout, int mode, hipStream_t s);
+                     float *vb2, float *s2, float *wout, int mode, hipStream_t s, int nb = 1);
 int launch_build_target(int N, int M, const float *u0, const float *bound, float bscalar,
                         const uint32_t *mask, float inv_beta, float *target, hipStream_t s);
 
 // FFT-based multiplier application: out = (base ? base : 0) + F^{-1}(mult F(y)).
+// nb problems stored contiguously; spec: nb spectra (NULL: the
+// preconditioner's own buffer, nb = 1 only).
 int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
-                      const float *base, float *out, hipStream_t s);
+                      const float *base, float *out, hipStream_t s, int nb = 1,
+                      float2 *spec = nullptr);
 
 // Reductions (FP64, deterministic two-level).
 int launch_norm2(const float *x, int64_t count, double *partials, int cap, double *out,

@@ -112,6 +112,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(const float *__restrict__ 
   float2 *b = sm + RP * n;
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
+  y += (size_t)blockIdx.y * n * n;  // problem blockIdx.y of a batch
+  spec += (size_t)blockIdx.y * (n / 2 + 1) * n;
   for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
     const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
     const int j = 2 * (pair0 + pr);
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(float2 *__restrict__ spec, int
   const int half = n / 2 + 1;
   const int k10 = blockIdx.x * CP;
   const int ncol = min(CP, half - k10);
+  spec += (size_t)blockIdx.y * half * n;
   for (int t = threadIdx.x; t < ncol * n; t += blockDim.x) a[t] = spec[(size_t)k10 * n + t];
   __syncthreads();
   float2 *z = fft_rows<false>(a, b, ncol, pl, tw);
@@ -171,6 +174,9 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(const float2 *__restrict__
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
   const int half = n / 2 + 1;
+  spec += (size_t)blockIdx.y * half * n;
+  if (base != nullptr) base += (size_t)blockIdx.y * n * n;
+  out += (size_t)blockIdx.y * n * n;
   for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
     const int pr = t / n, k = t - pr * n;
     const int j = 2 * (pair0 + pr);
@@ -209,20 +215,27 @@ static int rows_per_block(int n) {
 }
 
 int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
-                      const float *base, float *out, hipStream_t s) {
+                      const float *base, float *out, hipStream_t s, int nb, float2 *spec) {
   const int n = pc->n;
-  const int RP = rows_per_block(n);
+  int RP = rows_per_block(n);
+  // a batch fills the chip with its problems: fewer, larger row blocks
+  while (nb > 1 && RP < 4 && 2 * RP * n * 8 <= 65536 && (n / 2) / (2 * RP) * nb >= 512) RP *= 2;
   const int half = n / 2 + 1;
+  if (nb < 1 || (nb > 1 && spec == nullptr)) {
+    set_error("preconditioner: batch needs its own spectrum buffer");
+    return CT_E_INVALID;
+  }
+  if (spec == nullptr) spec = pc->d_spec;
   const size_t lds = 2 * sizeof(float2) * (size_t)RP * n;
-  hipLaunchKernelGGL(k_fft_rows_fwd, dim3((n / 2 + RP - 1) / RP), dim3(256), lds, s, y, n, RP,
-                     pc->fp, pc->d_tw, pc->d_spec);
+  hipLaunchKernelGGL(k_fft_rows_fwd, dim3((n / 2 + RP - 1) / RP, nb), dim3(256), lds, s, y, n,
+                     RP, pc->fp, pc->d_tw, spec);
   CT_TRY_HIP(hipGetLastError());
   const int CP = RP;
-  hipLaunchKernelGGL(k_fft_cols, dim3((half + CP - 1) / CP), dim3(256), lds, s, pc->d_spec, n,
-                     CP, pc->fp, pc->d_tw, mult);
+  hipLaunchKernelGGL(k_fft_cols, dim3((half + CP - 1) / CP, nb), dim3(256), lds, s, spec, n, CP,
+                     pc->fp, pc->d_tw, mult);
   CT_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_fft_rows_inv, dim3((n / 2 + RP - 1) / RP), dim3(256), lds, s,
-                     pc->d_spec, n, RP, pc->fp, pc->d_tw, base, out);
+  hipLaunchKernelGGL(k_fft_rows_inv, dim3((n / 2 + RP - 1) / RP, nb), dim3(256), lds, s, spec,
+                     n, RP, pc->fp, pc->d_tw, base, out);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

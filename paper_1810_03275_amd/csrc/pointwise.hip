@@ -61,7 +61,13 @@ __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, flo
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
-  const size_t o = (size_t)j * n + i, nn = (size_t)n * n;
+  const size_t nn = (size_t)n * n;
+  const size_t o = (size_t)j * n + i;
+  // problem blockIdx.z of a batch
+  u += blockIdx.z * nn;
+  vb2 += blockIdx.z * 2 * nn;
+  s2 += blockIdx.z * 2 * nn;
+  if (wout != nullptr) wout += blockIdx.z * 2 * nn;
   const float c = u[o];
   const float g1 = (i < n - 1) ? (u[o + 1] - c) * inv_h : 0.f;
   const float g2 = (j < n - 1) ? (u[o + n] - c) * inv_h : 0.f;
@@ -299,9 +305,11 @@ int launch_tv_project(int n, const float *q, float radius, float *w, hipStream_t
 }
 
 int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius, float *vb2,
-                     float *s2, float *wout, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_tv_update, row_grid(n, n), dim3(256), 0, s, n, inv_h, u, sigtau, radius,
-                     vb2, s2, wout, mode);
+                     float *s2, float *wout, int mode, hipStream_t s, int nb) {
+  dim3 grid = row_grid(n, n);
+  grid.z = nb;
+  hipLaunchKernelGGL(k_tv_update, grid, dim3(256), 0, s, n, inv_h, u, sigtau, radius, vb2, s2,
+                     wout, mode);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

@@ -72,10 +72,11 @@ __device__ inline void bp_stage_store(const float2 (&v)[kBpPrefetch], float2 *vd
   }
 }
 
+// gridDim.z = (problems of a batch) x S angle slices: problem b = z / S.
 __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
-    int seg, int slice_len, const float *__restrict__ pfield, float c1, float c2, float inv_h,
-    float *__restrict__ out) {
+    int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
+    float inv_h, float *__restrict__ out) {
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
@@ -85,7 +86,12 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   const int i = i0 + tx;
   const int jb = j0 + ty;
   const double di = (double)i, dj = (double)jb;
-  const int a_begin = blockIdx.z * slice_len;
+  const int bz = blockIdx.z / S, sl = blockIdx.z - bz * S;
+  const size_t nn = (size_t)n * n;
+  sino += (size_t)bz * N * M;
+  if (pfield != nullptr) pfield += (size_t)bz * 2 * nn;
+  out += (size_t)blockIdx.z * nn;  // own image (S == 1) or own partial image
+  const int a_begin = sl * slice_len;
   const int a_end = min(N, a_begin + slice_len);
   const int nchunks = a_end > a_begin ? (a_end - a_begin + kBpChunk - 1) / kBpChunk : 0;
   float accv[kBpPix], accd[kBpPix];
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     }
   }
   const float inv32 = 2.3283064365386963e-10f;  // 2^-32
-  const bool final_out = (gridDim.z == 1);
+  const bool final_out = (S == 1);
 #pragma unroll
   for (int p = 0; p < kBpPix; ++p) {
     const int j = jb + kBpRowStep * p;
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     const size_t o = (size_t)j * n + i;
     const float r = fmaf(accd[p], inv32, accv[p]);
     if (!final_out) {
-      out[(size_t)blockIdx.z * n * n + o] = r;
+      out[o] = r;
       continue;
     }
     float res = c1 * r;
@@ -181,6 +187,9 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
   const int j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i, nn = (size_t)n * n;
+  part += (size_t)blockIdx.z * S * nn;  // problem blockIdx.z of a batch
+  if (pfield != nullptr) pfield += (size_t)blockIdx.z * 2 * nn;
+  out += (size_t)blockIdx.z * nn;
   float r = part[o];
   for (int s = 1; s < S; ++s) r += part[s * nn + o];
   float res = c1 * r;
@@ -195,19 +204,24 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
-                     float c2, float *out, hipStream_t s) {
+                     float c2, float *out, hipStream_t s, int nb, float *part, int S) {
   const int n = p->g.n;
-  const int S = p->bp_slices;
+  if (S <= 0) S = p->bp_slices;
   const int slice_len = (p->g.n_angles + S - 1) / S;
-  dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S);
+  if (nb < 1 || (S > 1 && part == nullptr && (nb > 1 || S > p->bp_slices))) {
+    set_error("backprojection: batch needs its own partial-image buffer");
+    return CT_E_INVALID;
+  }
+  if (part == nullptr) part = p->d_bp_part;
+  dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S * nb);
   const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;
-  float *dst = (S == 1) ? out : p->d_bp_part;
+  float *dst = (S == 1) ? out : part;
   hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
-                     p->d_bp, p->seg, slice_len, pfield, c1, c2, (float)(1.0 / p->g.h), dst);
+                     p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h), dst);
   CT_TRY_HIP(hipGetLastError());
   if (S > 1) {
-    hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n), dim3(256), 0, s, p->d_bp_part, S,
-                       n, pfield, c1, c2, (float)(1.0 / p->g.h), out);
+    hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n, nb), dim3(256), 0, s, part, S, n,
+                       pfield, c1, c2, (float)(1.0 / p->g.h), out);
     CT_TRY_HIP(hipGetLastError());
   }
   return CT_OK;
@@ -229,6 +243,25 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
 // kFpStrips consecutive strips; image rows are staged in LDS kFpRows at a
 // time over the column range precomputed on the host for that
 // (group, block, chunk).  Lane 0's strip only supplies Q_{k-1} to lane 1.
+
+// Problem blockIdx.z of a batch: images [n][n], sinograms [N][M] and masks
+// [N][ceil(M/32)] follow each other contiguously.
+__device__ inline void fp_batch_offsets(const float *__restrict__ &u, float *__restrict__ &sino,
+                                        SinoEpi &ep, int n, int N, int M) {
+  const size_t b = blockIdx.z;
+  if (b == 0) return;
+  const size_t NM = (size_t)N * M;
+  u += b * n * n;
+  if (sino != nullptr) sino += b * NM;
+  if (ep.vb1 != nullptr) {
+    ep.target += b * NM;
+    ep.vb1 += b * NM;
+    ep.s1 += b * NM;
+    if (ep.y1 != nullptr) ep.y1 += b * NM;
+    if (ep.r != nullptr) ep.r += b * NM;
+    if (ep.mask != nullptr) ep.mask += b * (size_t)N * ((M + 31) >> 5);
+  }
+}
 
 // Output of one projected bin: either the raw value R(u)[l][k], or the PDRQS1
 // sinogram-side update (§4.4) with r = R(u)[l][k] / beta:
@@ -342,8 +375,9 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
     const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino,
-    SinoEpi ep) {
+    SinoEpi ep, int N) {
   extern __shared__ float tile[];  // 2 x kFpRows * ldw
+  fp_batch_offsets(u, sino, ep, n, N, M);
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -608,8 +642,10 @@ template <bool CHECK_FIRST>
 __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
-    const int2 *__restrict__ chunk_range, int n_chunks, float *__restrict__ sino, SinoEpi ep) {
+    const int2 *__restrict__ chunk_range, int n_chunks, float *__restrict__ sino, SinoEpi ep,
+    int N) {
   __shared__ float tile[2 * 2 * kFpRows * kPrLdw];  // 2 buffers x kFpRows x 2 angles x kPrLdw
+  fp_batch_offsets(u, sino, ep, n, N, M);
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -780,19 +816,20 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
 }
 
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
-                     const SinoEpi *epi) {
+                     const SinoEpi *epi, int nb) {
   SinoEpi ep{};
   if (epi) ep = *epi;
-  dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1);
+  const int N = p->g.n_angles;
+  dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1, nb);
   if (p->paired) {
     if (p->check_first)
       hipLaunchKernelGGL(k_radon_fwd_pair<true>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->n_chunks, out, ep);
+                         p->n_chunks, out, ep, N);
     else
       hipLaunchKernelGGL(k_radon_fwd_pair<false>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->n_chunks, out, ep);
+                         p->n_chunks, out, ep, N);
     CT_TRY_HIP(hipGetLastError());
     return CT_OK;
   }
@@ -801,11 +838,11 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   if (p->check_first)
     hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
-                       out, ep);
+                       out, ep, N);
   else
     hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
                        p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
-                       out, ep);
+                       out, ep, N);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

@@ -187,14 +187,15 @@ def workload(name: str, slice_index: int = 0, *, n: int | None = None,
     return _make(name, n, N, M, n_ell, n_metal, p, alpha, it, seed)
 
 
-def batched_shapes(count: int = 64, seed: int = 3000) -> list[tuple[int, int, int, int]]:
+def batched_shapes(count: int = 64, seed: int = 3000,
+                   sizes=(256, 384, 512, 768, 1024)) -> list[tuple[int, int, int, int]]:
     """Uneven batched slices: (n, N, M, metal discs) per slice.
 
-    n is drawn from {256, 384, 512, 768, 1024}; N = round(1.4 n); M = 1.5 n;
-    0-3 metal discs.
+    n is drawn from `sizes` ({256, 384, 512, 768, 1024} for the full batch);
+    N = round(1.4 n); M = 1.5 n; 0-3 metal discs.
     """
     rng = np.random.default_rng(seed)
-    sizes = np.array([256, 384, 512, 768, 1024])
+    sizes = np.array(sizes)
     out = []
     for _ in range(count):
         n = int(rng.choice(sizes))
