@@ -111,6 +111,45 @@ def batched_run(ct, torch, iters: int, count: int = 64):
             "pairs_per_pass": pairs, "setup_s": round(setup_s, 3), "batches": layout}
 
 
+def unrolled_run(ct, torch, K: int = 50, every: int = 10, count: int = 8):
+    """Differentiation workload: 8 slices of 1024^2, 1440 angles x 1536 bins
+    (random-ellipse phantoms, 1 % noise, alpha = 0.01) as one batch; K
+    unrolled PDRQS1 iterations forward (checkpoints every `every`) and the
+    reverse sweep for an MSE loss against the clean phantoms."""
+    import synth
+    ws = [synth.workload("C4", i) for i in range(count)]
+    plan = ct.Plan(ws[0].n, ws[0].n_angles, ws[0].n_bins)
+    sinos, truths = [], []
+    for w in ws:
+        _, u0, _, _, _, _ = build_inputs(ct, torch, w, plan)
+        sinos.append(u0)
+        truths.append(torch.from_numpy(w.phantom.astype("float32")).cuda())
+    sinos = torch.stack(sinos).requires_grad_(True)
+    truths = torch.stack(truths)
+    lam = torch.tensor(ws[0].alpha, device="cuda", requires_grad=True)
+    # warm-up (setup, graph capture) on a short unroll
+    u = ct.unrolled_pd(plan, sinos, lam, K=2, every=1)
+    ((u - truths) ** 2).mean().backward()
+    sinos.grad = None
+    lam.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = ct.unrolled_pd(plan, sinos, lam, K=K, every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = ((u - truths) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pairs = count * ws[0].n ** 2 * ws[0].n_angles
+    return {"workload": f"{count} x {ws[0].n}^2, {ws[0].n_angles} x {ws[0].n_bins}, K={K}, "
+                        f"checkpoint every {every}, MSE loss",
+            "forward_ms": round(1e3 * (t1 - t0), 2), "backward_ms": round(1e3 * (t2 - t1), 2),
+            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+            "gvox_angles_per_s_forward": round(2 * pairs * K / (t1 - t0) / 1e9, 1),
+            "dL_dlambda": float(lam.grad), "loss": float(loss.detach())}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: setup with beta and c given, then PDRQS1 iterations until about
@@ -149,6 +188,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--batched-iters", type=int, default=20,
                     help="timed iterations of the 64-slice uneven batch (0: skip)")
+    ap.add_argument("--unrolled-iters", type=int, default=50,
+                    help="unrolled iterations of the differentiation workload (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -224,6 +265,9 @@ def main():
         del sv
         torch.cuda.empty_cache()
         out["batched"] = batched_run(ct, torch, args.batched_iters)
+    if args.unrolled_iters > 0:
+        torch.cuda.empty_cache()
+        out["unrolled"] = unrolled_run(ct, torch, args.unrolled_iters)
     if args.copy_calibration:
         x = torch.ones(16 * 1024 * 1024, device="cuda")
         y = torch.empty_like(x)

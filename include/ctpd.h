@@ -281,6 +281,27 @@ int ct_reconstruct_batched(int32_t count, const ct_plan *const *plans, const ct_
                            const ct_params *prm, float *const *u_out, double *report,
                            int32_t report_len, ct_stream s);
 
+/* Differentiation through K unrolled PDRQS1 iterations (§4.4 applied K
+ * times from the zero state).  ct_unrolled_forward resets the solver's state,
+ * runs K iterations (graph-replayed) and keeps the state every `every`
+ * iterations in the returned tape; u_K is then the solver's state
+ * (ct_state_export).  Synchronizes s.
+ * ct_unrolled_backward takes gbar = dL/du_K (device, the solver's [nb][n][n]
+ * layout) and returns dL/du0 (device [nb][N][M], zero on the metal trace,
+ * may be NULL) and dL/dlambda per problem (host, nb doubles, may be NULL),
+ * by the reverse sweep of the iteration: each segment between checkpoints is
+ * recomputed once, then swept backwards through the transposed linear maps
+ * (A, A^*, nabla, div, M^{-1}) and the Jacobians of the two resolvents.  beta
+ * and c are held fixed (they depend on the geometry only).  It leaves the
+ * solver's state undefined; the tape stays valid for further backward calls
+ * as long as the solver is not stepped.  Synchronizes s.  The tape borrows the
+ * solver: destroy the tape first. */
+typedef struct ct_tape ct_tape;
+int ct_unrolled_forward(ct_solver *sv, int32_t K, int32_t every, ct_tape **out, ct_stream s);
+int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *grad_lambda,
+                         ct_stream s);
+int ct_tape_destroy(ct_tape *t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -453,6 +453,78 @@ def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, boun
     return u, report
 
 
+class Tape:
+    """K unrolled PDRQS1 iterations of a solver (from the zero state), kept for
+    the reverse sweep (checkpoints every `every` iterations)."""
+
+    def __init__(self, solver: Solver, K: int, every: int = 10):
+        self.solver = solver
+        h = ctypes.c_void_p()
+        _check(_L.ct_unrolled_forward(solver._h, K, every, ctypes.byref(h), _stream()),
+               "ct_unrolled_forward")
+        self._h = h
+        self.K = K
+
+    def backward(self, gbar: torch.Tensor):
+        """dL/du0 (solver's sinogram layout) and dL/dlambda per problem."""
+        sv = self.solver
+        n, N, M = sv.plan.n, sv.plan.n_angles, sv.plan.n_bins
+        L = sv._lead()
+        g = gbar.detach().to(torch.float32).contiguous()
+        ptr = _dev(g, L + (n, n), "gbar")
+        du0 = torch.empty(L + (N, M), device=g.device, dtype=torch.float32)
+        dl = (ctypes.c_double * sv.nb)()
+        _check(_L.ct_unrolled_backward(self._h, ptr, du0.data_ptr(), dl, _stream()),
+               "ct_unrolled_backward")
+        return du0, np.array(list(dl), dtype=np.float64)
+
+    def close(self):
+        if self._h:
+            _L.ct_tape_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UnrolledPD(torch.autograd.Function):
+    """u_K of K unrolled PDRQS1 iterations (§4.4) from the zero state, as a
+    differentiable function of the data u0 (nb, N, M) and of lambda (a 0-d
+    tensor).  The backward pass is the reverse sweep of the iteration with
+    checkpoints every `every` iterations (beta and c held fixed: they depend
+    on the geometry only).  Returns (nb, n, n)."""
+
+    @staticmethod
+    def forward(ctx, sinos, lam, plan, masks, bounds, K, every, opts):
+        nb = sinos.shape[0]
+        sv = SolverBatch(plan, [sinos[b].detach() for b in range(nb)], float(lam), masks,
+                         bounds, **(opts or {}))
+        tape = Tape(sv, K, every)
+        u = sv.export()[0]
+        ctx.tape = tape
+        return u.reshape(nb, plan.n, plan.n)
+
+    @staticmethod
+    def backward(ctx, gu):
+        tape = ctx.tape
+        nb = tape.solver.nb
+        sv = tape.solver
+        g = gu.reshape(sv._lead() + (sv.plan.n, sv.plan.n))
+        du0, dl = tape.backward(g)
+        dlam = torch.tensor(float(dl.sum()), dtype=torch.float32, device=gu.device)
+        return (du0.reshape(nb, sv.plan.n_angles, sv.plan.n_bins), dlam, None, None, None, None,
+                None, None)
+
+
+def unrolled_pd(plan: Plan, sinos: torch.Tensor, lam: torch.Tensor, masks=None, bounds=None,
+                K: int = 50, every: int = 10, **opts) -> torch.Tensor:
+    """Differentiable u_K for the batch of sinograms sinos (nb, N, M)."""
+    return UnrolledPD.apply(sinos, lam, plan, masks, bounds, K, every, opts)
+
+
 class RadonFn(torch.autograd.Function):
     """sino = R_h img; the backward pass is R_h^* (the exact transpose, §3.1)."""
 

@@ -67,6 +67,10 @@ SIGNATURES = {
     "ct_gap": (c_int32, [c_void_p, POINTER(c_double), c_void_p]),
     "ct_reconstruct": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                  POINTER(c_double), c_int32, c_void_p]),
+    "ct_unrolled_forward": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_void_p), c_void_p]),
+    "ct_unrolled_backward": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                       c_void_p]),
+    "ct_tape_destroy": (c_int32, [c_void_p]),
     "ct_group_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p)]),
     "ct_group_step": (c_int32, [c_void_p, c_int32, c_void_p]),
     "ct_group_destroy": (c_int32, [c_void_p]),

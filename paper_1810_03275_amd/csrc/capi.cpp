@@ -457,7 +457,8 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
 // One PDRQS1 iteration (§4.4) of all nb problems from the cached
 // s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and
 // A u for the record.  With ev (5 events) the phase boundaries are recorded.
-static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr) {
+static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr,
+                       float *q1out = nullptr, float *q2out = nullptr) {
   ct_plan *p = sv->plan;
   const float sig = (float)sv->sigma, tau = (float)sv->tau;
   const float inv_h = (float)(1.0 / p->g.h);
@@ -470,12 +471,13 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
                            sv->spec));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
   // R_h u_new with the sinogram-side update fused into its output stage
-  const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
-                   sv->y1, sv->r, mode};
+  SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
+             sv->y1, sv->r, mode};
+  ep.q1 = q1out;
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
-                          sv->vb2, sv->s2, sv->w, mode, st, nb));
+                          sv->vb2, sv->s2, sv->w, mode, st, nb, q2out));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
@@ -1083,6 +1085,186 @@ int ct_reconstruct_batched(int32_t count, const ct_plan *const *plans, const ct_
                                 hipMemcpyDeviceToDevice, st));
   }
   CT_TRY_HIP(hipStreamSynchronize(st));
+  return CT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Unrolled PDRQS1 with a reverse sweep (derivatives of u_K with respect to the
+// data u0 and the weight lambda), checkpointing every `every` iterations.
+
+struct ct_tape {
+  ct_solver *sv = nullptr;
+  int K = 0, every = 0, n_ck = 0;
+  int64_t iters_after = 0;
+  std::vector<float *> bufs;  // everything below, freed together
+  std::vector<float *> ck;    // per checkpoint: u, vb1, vb2 (3 entries each)
+  float *q1s = nullptr, *q2s = nullptr;
+  float *U = nullptr, *Utot = nullptr, *X = nullptr, *V1 = nullptr, *P = nullptr,
+        *Q1 = nullptr, *bbar = nullptr, *V2 = nullptr, *Q2 = nullptr, *G = nullptr;
+  double *partials = nullptr, *acc = nullptr, *d_beta = nullptr;
+  ~ct_tape() {
+    for (float *b : bufs) (void)hipFree(b);
+    (void)hipFree(partials);
+    (void)hipFree(acc);
+    (void)hipFree(d_beta);
+  }
+  int alloc(float **p, size_t count) {
+    CT_TRY_HIP(hipMalloc(p, sizeof(float) * count));
+    bufs.push_back(*p);
+    return CT_OK;
+  }
+};
+
+static int tape_alloc(ct_tape *t) {
+  ct_solver *sv = t->sv;
+  const size_t nb = sv->nb;
+  const size_t nn = (size_t)sv->n * sv->n * nb, NM = (size_t)sv->N * sv->M * nb;
+  for (int c = 0; c < t->n_ck; ++c) {
+    float *u, *vb1, *vb2;
+    CT_TRY(t->alloc(&u, nn));
+    CT_TRY(t->alloc(&vb1, NM));
+    CT_TRY(t->alloc(&vb2, 2 * nn));
+    t->ck.push_back(u);
+    t->ck.push_back(vb1);
+    t->ck.push_back(vb2);
+  }
+  CT_TRY(t->alloc(&t->q1s, NM * t->every));
+  CT_TRY(t->alloc(&t->q2s, 2 * nn * t->every));
+  CT_TRY(t->alloc(&t->U, nn));
+  CT_TRY(t->alloc(&t->Utot, nn));
+  CT_TRY(t->alloc(&t->X, nn));
+  CT_TRY(t->alloc(&t->V1, NM));
+  CT_TRY(t->alloc(&t->P, NM));
+  CT_TRY(t->alloc(&t->Q1, NM));
+  CT_TRY(t->alloc(&t->bbar, NM));
+  CT_TRY(t->alloc(&t->V2, 2 * nn));
+  CT_TRY(t->alloc(&t->Q2, 2 * nn));
+  CT_TRY(t->alloc(&t->G, 2 * nn));
+  CT_TRY_HIP(hipMalloc(&t->partials, sizeof(double) * tv_reverse_partials(sv->n, sv->nb)));
+  CT_TRY_HIP(hipMalloc(&t->acc, sizeof(double) * nb));
+  CT_TRY_HIP(hipMalloc(&t->d_beta, sizeof(double)));
+  return CT_OK;
+}
+
+static int copy_state(ct_solver *sv, float *u, float *vb1, float *vb2, bool out,
+                      hipStream_t st) {
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
+  const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+  if (out) {
+    CT_TRY_HIP(hipMemcpyAsync(u, sv->u, sizeof(float) * nn, kd, st));
+    CT_TRY_HIP(hipMemcpyAsync(vb1, sv->vb1, sizeof(float) * NM, kd, st));
+    CT_TRY_HIP(hipMemcpyAsync(vb2, sv->vb2, sizeof(float) * 2 * nn, kd, st));
+  } else {
+    CT_TRY_HIP(hipMemcpyAsync(sv->u, u, sizeof(float) * nn, kd, st));
+    CT_TRY_HIP(hipMemcpyAsync(sv->vb1, vb1, sizeof(float) * NM, kd, st));
+    CT_TRY_HIP(hipMemcpyAsync(sv->vb2, vb2, sizeof(float) * 2 * nn, kd, st));
+  }
+  return CT_OK;
+}
+
+extern "C" {
+
+int ct_unrolled_forward(ct_solver *sv, int32_t K, int32_t every, ct_tape **out, ct_stream s) {
+  clear_error();
+  if (!sv || !out || K < 1 || every < 1) {
+    set_error("ct_unrolled_forward: need a solver, K >= 1 and every >= 1");
+    return CT_E_INVALID;
+  }
+  *out = nullptr;
+  hipStream_t st = S(s);
+  std::unique_ptr<ct_tape> t(new (std::nothrow) ct_tape());
+  if (!t) return CT_E_DEVICE;
+  t->sv = sv;
+  t->K = K;
+  t->every = std::min(every, K);
+  t->n_ck = (K + t->every - 1) / t->every;
+  CT_TRY(tape_alloc(t.get()));
+  CT_TRY(solver_zero_state(sv, st));
+  ct_solver *one[1] = {sv};
+  for (int c = 0; c < t->n_ck; ++c) {
+    CT_TRY(copy_state(sv, t->ck[3 * c], t->ck[3 * c + 1], t->ck[3 * c + 2], true, st));
+    const int k = std::min(t->every, K - c * t->every);
+    CT_TRY(multi_step(one, 1, k, st, &sv->cap_stream, sv->gexec, sv->gexec_u));
+  }
+  t->iters_after = sv->iters;
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  *out = t.release();
+  return CT_OK;
+}
+
+int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *grad_lambda,
+                         ct_stream s) {
+  clear_error();
+  if (!t || !gbar) {
+    set_error("ct_unrolled_backward: null argument");
+    return CT_E_INVALID;
+  }
+  ct_solver *sv = t->sv;
+  if (sv->iters != t->iters_after) {
+    set_error("ct_unrolled_backward: the solver was stepped after the forward pass");
+    return CT_E_STATE;
+  }
+  hipStream_t st = S(s);
+  ct_plan *p = sv->plan;
+  const int n = sv->n, N = sv->N, M = sv->M, nb = sv->nb;
+  const size_t nn = (size_t)n * n * nb, NM = (size_t)N * M * nb;
+  const float sig = (float)sv->sigma, st_ = (float)(sv->sigma * sv->tau);
+  const float inv_h = (float)(1.0 / p->g.h);
+  const float rho = (float)(sv->lam_t / sv->tau);
+  CT_TRY_HIP(hipMemcpyAsync(t->U, gbar, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+  CT_TRY_HIP(hipMemsetAsync(t->P, 0, sizeof(float) * NM, st));
+  CT_TRY_HIP(hipMemsetAsync(t->V1, 0, sizeof(float) * NM, st));
+  CT_TRY_HIP(hipMemsetAsync(t->bbar, 0, sizeof(float) * NM, st));
+  CT_TRY_HIP(hipMemsetAsync(t->V2, 0, sizeof(float) * 2 * nn, st));
+  CT_TRY_HIP(hipMemsetAsync(t->acc, 0, sizeof(double) * nb, st));
+  for (int c = t->n_ck - 1; c >= 0; --c) {
+    const int k0 = c * t->every;
+    const int cnt = std::min(t->every, t->K - k0);
+    // recompute the segment from its checkpoint, keeping the resolvent inputs
+    CT_TRY(copy_state(sv, t->ck[3 * c], t->ck[3 * c + 1], t->ck[3 * c + 2], false, st));
+    {
+      const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
+                       nullptr, nullptr, 1};
+      CT_TRY(launch_radon_fwd(p, sv->u, nullptr, st, &ep, nb));
+      CT_TRY(launch_tv_update(n, inv_h, sv->u, st_, 0.0f, sv->vb2, sv->s2, nullptr, 1, st, nb));
+    }
+    for (int i = 0; i < cnt; ++i)
+      CT_TRY(solver_iter(sv, 0, st, nullptr, t->q1s + i * NM, t->q2s + i * 2 * nn));
+    for (int i = cnt - 1; i >= 0; --i) {
+      CT_TRY(launch_sino_reverse(N, M, nb, sig, t->V1, t->q1s + i * NM, sv->target, sv->mask,
+                                 t->P, t->Q1, t->bbar, st));
+      CT_TRY(launch_tv_reverse(n, nb, st_, rho, t->V2, t->q2s + i * 2 * nn, t->Q2, t->G,
+                               t->partials, t->acc, st));
+      // Utot = U + A^* P - div G
+      CT_TRY(launch_radon_adj(p, t->P, t->G, (float)(1.0 / sv->beta), -1.0f, t->Utot, st, nb,
+                              sv->bp_part, sv->bp_S, t->U));
+      CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, t->Utot, nullptr, t->X, st, nb,
+                               sv->spec));
+      SinoEpi ep{(float)(1.0 / sv->beta), sig, nullptr, nullptr, t->Q1, t->V1, t->P, nullptr,
+                 3};
+      CT_TRY(launch_radon_fwd(p, t->X, nullptr, st, &ep, nb));
+      CT_TRY(launch_img_tail(n, nb, st_, inv_h, t->X, t->Q2, t->Utot, t->U, t->V2, st));
+    }
+  }
+  t->iters_after = sv->iters;
+  if (grad_u0) {
+    const double beta = sv->beta;
+    CT_TRY_HIP(hipMemcpyAsync(t->d_beta, &beta, sizeof(double), hipMemcpyHostToDevice, st));
+    CT_TRY(launch_scale_by_inv(t->bbar, (int64_t)NM, t->d_beta, grad_u0, st));
+  }
+  std::vector<double> acc(nb);
+  CT_TRY_HIP(hipMemcpyAsync(acc.data(), t->acc, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  if (grad_lambda)
+    for (int b = 0; b < nb; ++b) grad_lambda[b] = acc[b] / (sv->beta * sv->beta * sv->tau);
+  return CT_OK;
+}
+
+int ct_tape_destroy(ct_tape *t) {
+  clear_error();
+  delete t;
   return CT_OK;
 }
 

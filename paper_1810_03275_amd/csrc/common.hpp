@@ -155,9 +155,10 @@ namespace ctpd {
 // nb problems of one geometry stored contiguously; part: nb * bp_slices
 // partial images (NULL: the plan's own buffer, nb = 1 only).
 // S: angle slices (0: the plan's choice).
+// base (optional, nb images) is added to the result.
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
-                     int S = 0);
+                     int S = 0, const float *base = nullptr);
 // Optional epilogue of the forward projector: the PDRQS1 sinogram-side update
 // applied to r = R(u)/beta per bin (see k_sino_update), instead of storing R(u).
 struct SinoEpi {
@@ -169,7 +170,8 @@ struct SinoEpi {
   float *s1;
   float *y1;
   float *r;
-  int mode;
+  int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep
+  float *q1 = nullptr;  // optional: the resolvent input 2 v1 - vb1 (modes 0, 2)
 };
 // out = R(u) (raw), or the epilogue when epi != nullptr
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
@@ -187,8 +189,20 @@ int launch_prox_sino(int N, int M, const float *q, float step, const float *u0,
 int launch_sino_update(int N, int M, const float *rraw, float inv_beta, float sigma,
                        const float *target, const uint32_t *mask, float *vb1, float *s1,
                        float *y1, float *rout, int mode, hipStream_t s);
+// q2out (optional): the resolvent input 2 v2 - vb2 (modes 0, 2).
 int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius,
-                     float *vb2, float *s2, float *wout, int mode, hipStream_t s, int nb = 1);
+                     float *vb2, float *s2, float *wout, int mode, hipStream_t s, int nb = 1,
+                     float *q2out = nullptr);
+// Reverse sweep of unrolled PDRQS1 (see unrolled.hip).
+int launch_sino_reverse(int N, int M, int nb, float sigma, const float *V1, const float *q1,
+                        const float *target, const uint32_t *mask, float *P, float *Q1,
+                        float *bbar, hipStream_t s);
+int launch_tv_reverse(int n, int nb, float sigtau, float rho, const float *V2, const float *q2,
+                      float *Q2, float *G, double *partials, double *acc, hipStream_t s);
+int launch_img_tail(int n, int nb, float sigtau, float inv_h, const float *Utmp,
+                    const float *Q2, const float *Utot, float *Uout, float *V2out,
+                    hipStream_t s);
+size_t tv_reverse_partials(int n, int nb);
 int launch_build_target(int N, int M, const float *u0, const float *bound, float bscalar,
                         const uint32_t *mask, float inv_beta, float *target, hipStream_t s);
 

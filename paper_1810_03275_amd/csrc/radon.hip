@@ -76,7 +76,7 @@ __device__ inline void bp_stage_store(const float2 (&v)[kBpPrefetch], float2 *vd
 __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
     int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
-    float inv_h, float *__restrict__ out) {
+    float inv_h, const float *__restrict__ base, float *__restrict__ out) {
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   const size_t nn = (size_t)n * n;
   sino += (size_t)bz * N * M;
   if (pfield != nullptr) pfield += (size_t)bz * 2 * nn;
+  if (base != nullptr) base += (size_t)bz * nn;
   out += (size_t)blockIdx.z * nn;  // own image (S == 1) or own partial image
   const int a_begin = sl * slice_len;
   const int a_end = min(N, a_begin + slice_len);
@@ -174,21 +175,23 @@ __global__ __launch_bounds__(256) void k_radon_adj(
       const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
       res = fmaf(c2 * inv_h, d1 + d2, res);
     }
+    if (base != nullptr) res += base[o];
     out[o] = res;
   }
 }
 
-// out = c1 * sum_s part[s] + c2 * div_h(p): the angle slices' partial
+// out = base + c1 * sum_s part[s] + c2 * div_h(p): the angle slices' partial
 // backprojections summed in slice order, with the same epilogue.
 __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
                              const float *__restrict__ pfield, float c1, float c2, float inv_h,
-                             float *__restrict__ out) {
+                             const float *__restrict__ base, float *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
   const size_t o = (size_t)j * n + i, nn = (size_t)n * n;
   part += (size_t)blockIdx.z * S * nn;  // problem blockIdx.z of a batch
   if (pfield != nullptr) pfield += (size_t)blockIdx.z * 2 * nn;
+  if (base != nullptr) base += (size_t)blockIdx.z * nn;
   out += (size_t)blockIdx.z * nn;
   float r = part[o];
   for (int s = 1; s < S; ++s) r += part[s * nn + o];
@@ -200,11 +203,13 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
     const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
     res = fmaf(c2 * inv_h, d1 + d2, res);
   }
+  if (base != nullptr) res += base[o];
   out[o] = res;
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
-                     float c2, float *out, hipStream_t s, int nb, float *part, int S) {
+                     float c2, float *out, hipStream_t s, int nb, float *part, int S,
+                     const float *base) {
   const int n = p->g.n;
   if (S <= 0) S = p->bp_slices;
   const int slice_len = (p->g.n_angles + S - 1) / S;
@@ -217,11 +222,12 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;
   float *dst = (S == 1) ? out : part;
   hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
-                     p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h), dst);
+                     p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
+                     base, dst);
   CT_TRY_HIP(hipGetLastError());
   if (S > 1) {
     hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n, nb), dim3(256), 0, s, part, S, n,
-                       pfield, c1, c2, (float)(1.0 / p->g.h), out);
+                       pfield, c1, c2, (float)(1.0 / p->g.h), base, out);
     CT_TRY_HIP(hipGetLastError());
   }
   return CT_OK;
@@ -259,6 +265,7 @@ __device__ inline void fp_batch_offsets(const float *__restrict__ &u, float *__r
     ep.s1 += b * NM;
     if (ep.y1 != nullptr) ep.y1 += b * NM;
     if (ep.r != nullptr) ep.r += b * NM;
+    if (ep.q1 != nullptr) ep.q1 += b * NM;
     if (ep.mask != nullptr) ep.mask += b * (size_t)N * ((M + 31) >> 5);
   }
 }
@@ -280,11 +287,21 @@ __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, in
     ep.s1[o] = fmaf(ep.sigma, r, vb);
     return;
   }
+  if (ep.mode == 3) {
+    // reverse sweep of the unrolled iteration: with r = A x for the adjoint x
+    // of u_tmp, S1 = -sigma r; vb1 holds Q1 (in), s1 receives the adjoint of
+    // the previous vb1, Q1 + S1, and y1 the deferred sinogram term sigma S1.
+    const float sb = -ep.sigma * r;
+    ep.s1[o] = vb + sb;
+    ep.y1[o] = ep.sigma * sb;
+    return;
+  }
   const int MW = (M + 31) >> 5;
   const bool on_d0 =
       ep.mask != nullptr && ((ep.mask[(size_t)l * MW + (k >> 5)] >> (k & 31)) & 1u);
   const float v1 = fmaf(ep.sigma, r, vb);
   const float q = 2.f * v1 - vb;
+  if (ep.q1 != nullptr) ep.q1[o] = q;
   const float tg = ep.target[o];
   const float y = on_d0 ? fminf(q - ep.sigma * tg, 0.f) : (q - ep.sigma * tg) / (1.f + ep.sigma);
   const float nb = vb + y - v1;
