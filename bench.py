@@ -150,6 +150,33 @@ def unrolled_run(ct, torch, K: int = 50, every: int = 10, count: int = 8):
             "dL_dlambda": float(lam.grad), "loss": float(loss.detach())}
 
 
+def large_run(ct, torch, iters: int):
+    """The largest single slice: 2048^2, 2880 angles x 3072 bins, 4 metal discs,
+    alpha = 0.005; PDRQS1 iterations/s after setup and 10 warm-up iterations."""
+    import synth
+    w = synth.workload("C5")
+    plan, u0, mask, bound, x0, x1 = build_inputs(ct, torch, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    sv.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.step(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ph = sv.step_timed(5)
+    pairs = w.n * w.n * w.n_angles
+    return {"workload": "2048x2048, 2880 angles, 3072 bins, 4 metal discs, alpha=0.005",
+            "iterations": iters, "it_per_s": round(iters / dt, 2),
+            "ms_per_iteration": round(1e3 * dt / iters, 3), "setup_s": round(setup_s, 3),
+            "gvox_angles_per_s": round(2 * pairs * iters / dt / 1e9, 1),
+            "phase_us": {k: round(v * 1e3, 1) for k, v in ph.items()},
+            "solve_1000_iterations_s": round(1000 * dt / iters + setup_s, 2)}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: setup with beta and c given, then PDRQS1 iterations until about
@@ -190,6 +217,8 @@ def main():
                     help="timed iterations of the 64-slice uneven batch (0: skip)")
     ap.add_argument("--unrolled-iters", type=int, default=50,
                     help="unrolled iterations of the differentiation workload (0: skip)")
+    ap.add_argument("--large-iters", type=int, default=50,
+                    help="timed iterations at 2048^2 x 2880 x 3072 (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -265,6 +294,9 @@ def main():
         del sv
         torch.cuda.empty_cache()
         out["batched"] = batched_run(ct, torch, args.batched_iters)
+    if args.large_iters > 0:
+        torch.cuda.empty_cache()
+        out["large"] = large_run(ct, torch, args.large_iters)
     if args.unrolled_iters > 0:
         torch.cuda.empty_cache()
         out["unrolled"] = unrolled_run(ct, torch, args.unrolled_iters)

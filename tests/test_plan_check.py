@@ -19,7 +19,7 @@ def test_plan_walk_in_bounds(geom):
     assert ct.plan_check(*geom) > 0
 
 
-@pytest.mark.parametrize("shape", [(256, 358, 384), (384, 538, 576)])
+@pytest.mark.parametrize("shape", [(256, 358, 384), (384, 538, 576), (1024, 1440, 1536)])
 def test_plan_walk_batched_shapes(shape):
     assert ct.plan_check(*shape) > 0
 
@@ -33,3 +33,9 @@ def test_plan_walk_arbitrary_angles(seed, N):
 def test_plan_check_rejects_bad_geometry():
     with pytest.raises(ct.CtpdError):
         ct.plan_check(1, 4, 8)
+
+
+def test_plan_walk_largest_geometry():
+    """2048^2, 2880 angles, 3072 bins: every (strip, row) of the plan (5.7e9
+    steps, about 40 s on one core)."""
+    assert ct.plan_check(2048, 2880, 3072) > 5e9
