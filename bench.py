@@ -282,7 +282,8 @@ def main():
         "setup_ms": round(setup_s * 1e3, 2),
         "beta": info["beta"], "c": info["c"],
         "gap_record": [float(x) for x in rec],
-        "roofline": {"kernel": "k_radon_fwd_pair" if sv.layout()["paired"] else "k_radon_fwd",
+        "roofline": {"kernel": ("k_radon_fwd_multi<%d>" % sv.layout()["angles_per_walk"]
+                                if sv.layout()["angles_per_walk"] > 1 else "k_radon_fwd"),
                      "bound": "alu", "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4),

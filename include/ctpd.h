@@ -212,7 +212,8 @@ int ct_solver_destroy(ct_solver *sv);
 int ct_solver_info(const ct_solver *sv, double out[4]);
 
 /* out[0] = problems in the solver, out[1] = angle slices of R_h^*,
- * out[2] = 1 if R_h runs angle pairs, out[3] = forward-projector groups. */
+ * out[2] = angles that share one walk in R_h (1, 2 or 4),
+ * out[3] = forward-projector groups. */
 int ct_solver_layout(const ct_solver *sv, int32_t out[4]);
 
 /* Run k iterations of PDRQS1 (§4.4) on the solver's state:

@@ -830,7 +830,7 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[4]) {
   }
   out[0] = sv->nb;
   out[1] = sv->bp_S;
-  out[2] = sv->plan->paired ? 1 : 0;
+  out[2] = sv->plan->slots;
   out[3] = sv->plan->n_groups;
   return CT_OK;
 }

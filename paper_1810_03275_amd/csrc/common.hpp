@@ -69,17 +69,10 @@ constexpr int kFpRows = 16;                         // image rows staged per chu
 constexpr int kFpMaxWidth = 192;                    // staged columns per chunk
 constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixels per thread
 
-// Paired variant: two angles whose walk constants (T, A, B) are identical --
-// with equispaced angles, theta and pi/2 - theta, or theta and 3pi/2 - theta
-// -- share one walk and differ only in how (p, q) maps to image pixels.  A
-// wave owns one pair (the two angles' staged rows are interleaved in LDS so
-// one 16-byte read serves both), a workgroup kPrPairs pairs.
+// Paired variant: 2 angles whose walk constants (T, A, B) are identical
+// share one walk; a wave owns one pair, a workgroup kPrWaves pairs.
 constexpr int kPrWaves = 8;
-constexpr int kPrThreads = 64 * kPrWaves;
-constexpr int kPrPairs = kPrWaves;
-constexpr int kPrMaxWidth = 128;                                  // staged columns per chunk
-constexpr int kPrLdw = kPrMaxWidth + 1;                           // LDS row pitch (floats)
-constexpr int kPrPrefetch = kFpRows * kPrMaxWidth / kPrThreads;  // per tile per thread
+constexpr int kMultiMaxWidth = 128;  // staged columns per chunk
 
 struct FpGroup {
   int32_t first;  // index into the FpAngle array (pairs: pair index, 2 entries each)
@@ -90,7 +83,7 @@ struct FpGroup {
   int32_t nblk;   // workgroups needed along the bins
   int32_t region; // offset of this group's (block, chunk) region table
   int32_t range;  // offset of this group's per-block active chunk ranges
-  int32_t cls1;   // class of the second angle of each pair (paired plans)
+  int32_t clss;   // multi-angle plans: class of angle s of each set in byte s
   int32_t pad;
 };
 
@@ -131,7 +124,9 @@ struct ct_plan {
   int n_chunks = 0;
   int wmax = 0;     // widest staged region (columns)
   bool check_first = false;  // strips may hold no pixel of a row (|a| > 1)
-  bool paired = false;       // angles run in pairs sharing one walk
+  bool paired = false;       // angles share walks (slots > 1)
+  int slots = 1;             // angles per walk: 1 or 2
+  int chunk_rows = 16;       // image rows staged per chunk by the forward projector
   // scratch for standalone calls
   float *d_scratch_sino = nullptr;
   float *d_scratch_img = nullptr;

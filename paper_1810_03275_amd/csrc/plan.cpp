@@ -37,6 +37,7 @@ struct HostPlan {
   std::vector<int2> regions, ranges;
   int seg = 0, bp_slices = 1, n_groups = 0, max_blk = 0, n_chunks = 0, wmax = 0;
   bool check_first = false, paired = false;
+  int slots = 1, chunk_rows = 16;
 };
 
 static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
@@ -125,63 +126,85 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   }
   p->check_first = check_first;
 
-  const int n_chunks = (n + kFpRows - 1) / kFpRows;
   const int64_t one = (int64_t)1 << kFixBits;
 
-  // Angles with identical walk constants can share one walk (paired kernel).
-  // Used when at least half of the angles pair up; the others then run as
-  // pairs of an angle with itself (second result discarded).
-  std::vector<std::pair<int, int>> pairs;  // (l0, l1), l1 = -1: alone
+  // Angles with identical walk constants can share one walk: for equispaced
+  // angles theta, pi/2 - theta, pi - theta and pi/2 + theta.  Pairs are used
+  // when at least half of the angles pair up, else one angle per walk.  An
+  // angle without a partner is paired with a copy of itself whose results are
+  // discarded (row l = -1).  A plan whose staged windows come out wider than
+  // the paired kernel's limit (large ds/h) falls back to one angle per walk.
+  std::vector<std::vector<int>> keysets;
   {
     std::map<std::tuple<int64_t, uint32_t, uint32_t>, std::vector<int>> by_key;
     for (int l = 0; l < N; ++l) by_key[std::make_tuple(fp[l].T, fp[l].A, fp[l].B)].push_back(l);
-    for (auto &kv : by_key) {
-      const std::vector<int> &v = kv.second;
-      size_t i = 0;
-      for (; i + 1 < v.size(); i += 2) pairs.emplace_back(v[i], v[i + 1]);
-      if (i < v.size()) pairs.emplace_back(v[i], -1);
-    }
+    for (auto &kv : by_key) keysets.push_back(kv.second);
   }
-  int n_paired = 0;
-  for (auto &pr : pairs) n_paired += pr.second >= 0 ? 2 : 0;
-  // The paired kernel stages at most kPrMaxWidth columns; geometries whose
-  // blocks need more (large ds/h) fall back to the unpaired kernel.
-  bool want_paired = N >= 2 && 2 * n_paired >= N;
+  auto complete = [&](int SL) {
+    int c = 0;
+    for (auto &v : keysets) c += (int)(v.size() / SL) * SL;
+    return c;
+  };
+  std::vector<int> modes;
   {
-    const char *env = std::getenv("CTPD_FWD_UNPAIRED");
-    if (env && env[0] == '1') want_paired = false;
+    const char *env = std::getenv("CTPD_FWD_SLOTS");
+    const int forced = env ? std::atoi(env) : 0;
+    if (forced == 1 || forced == 2) {
+      modes.push_back(forced);
+    } else if (N >= 2 && 2 * complete(2) >= N) {
+      modes.push_back(2);
+    }
+    if (modes.empty() || modes.back() != 1) modes.push_back(1);
   }
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    const bool paired = want_paired && attempt == 0;
-    if (attempt == 1 && !want_paired) break;
-    const int max_width = paired ? kPrMaxWidth : kFpMaxWidth;
-    const int per_group = paired ? kPrPairs : kFpGroup;
+  for (size_t attempt = 0; attempt < modes.size(); ++attempt) {
+    const int SL = modes[attempt];
+    const bool multi = SL > 1;
+    const int rows_c = kFpRows;
+    const int n_chunks = (n + rows_c - 1) / rows_c;
+    const int max_width = multi ? kMultiMaxWidth : kFpMaxWidth;
+    const int per_group = (SL == 2) ? kPrWaves : kFpGroup;
 
-    // Work items (angles, or pairs) in class order; rep[i] holds the walk
-    // constants of item i, icls[i] its class (pairs: the two classes).
+    // Work items (angles, or sets of SL angles) in class order; rep[i] holds
+    // the walk constants of item i, icls[i] its classes (one per slot).
     std::vector<FpAngle> rep;
-    std::vector<FpAngle> &dev = p->dev;  // the device table (2 entries per pair)
+    std::vector<FpAngle> &dev = p->dev;  // the device table (SL entries per item)
     dev.clear();
-    std::vector<std::pair<int, int>> icls;
-    if (paired) {
-      for (auto &pr : pairs) {
-        if (pr.second >= 0 && cls[pr.second] < cls[pr.first]) std::swap(pr.first, pr.second);
-      }
-      std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int, int> &x,
-                                                       const std::pair<int, int> &y) {
-        const int cx1 = x.second >= 0 ? cls[x.second] : cls[x.first];
-        const int cy1 = y.second >= 0 ? cls[y.second] : cls[y.first];
-        if (cls[x.first] != cls[y.first]) return cls[x.first] < cls[y.first];
-        if (cx1 != cy1) return cx1 < cy1;
-        return x.first < y.first;
-      });
-      for (auto &pr : pairs) {
-        rep.push_back(fp[pr.first]);
-        dev.push_back(fp[pr.first]);
-        FpAngle second = fp[pr.second >= 0 ? pr.second : pr.first];
-        if (pr.second < 0) second.l = -1;
-        dev.push_back(second);
-        icls.emplace_back(cls[pr.first], pr.second >= 0 ? cls[pr.second] : cls[pr.first]);
+    std::vector<std::vector<int>> icls;
+    if (multi) {
+      std::vector<std::vector<int>> items;  // angles, -1 - l for a discarded copy of l
+      for (auto &v : keysets)
+        for (size_t i = 0; i < v.size(); i += SL) {
+          std::vector<int> it;
+          for (int s = 0; s < SL && i + s < v.size(); ++s) it.push_back(v[i + s]);
+          const size_t real = it.size();
+          for (size_t s = 0; it.size() < (size_t)SL; ++s) it.push_back(-1 - it[s % real]);
+          // order the slots by class so that items of one group align
+          std::stable_sort(it.begin(), it.end(), [&](int x, int y) {
+            const int lx = x >= 0 ? x : -1 - x, ly = y >= 0 ? y : -1 - y;
+            return cls[lx] < cls[ly];
+          });
+          items.push_back(it);
+        }
+      auto key = [&](const std::vector<int> &it) {
+        std::vector<int> kc;
+        for (int x : it) kc.push_back(cls[x >= 0 ? x : -1 - x]);
+        return kc;
+      };
+      std::stable_sort(items.begin(), items.end(),
+                       [&](const std::vector<int> &x, const std::vector<int> &y) {
+                         const auto kx = key(x), ky = key(y);
+                         if (kx != ky) return kx < ky;
+                         return x[0] < y[0];
+                       });
+      for (auto &it : items) {
+        const int l0 = it[0] >= 0 ? it[0] : -1 - it[0];
+        rep.push_back(fp[l0]);
+        for (int x : it) {
+          FpAngle f = fp[x >= 0 ? x : -1 - x];
+          if (x < 0) f.l = -1;
+          dev.push_back(f);
+        }
+        icls.push_back(key(it));
       }
     } else {
       std::vector<int> order(N);
@@ -189,16 +212,16 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls[x] < cls[y]; });
       for (int i = 0; i < N; ++i) {
         rep.push_back(fp[order[i]]);
-        icls.emplace_back(cls[order[i]], cls[order[i]]);
+        icls.push_back({cls[order[i]]});
       }
       dev = rep;
     }
     const int n_items = (int)rep.size();
 
     // Bins a group can reach and the staged column range of every
-    // (block, chunk); returns the widest range.  The paired kernel does not
-    // clamp strip positions, so its ranges cover every position a lane reaches;
-    // the unpaired kernel clamps positions to [-2, n].
+    // (block, chunk); returns the widest range.  The multi-angle kernels do
+    // not clamp strip positions, so their ranges cover every position a lane
+    // reaches; the one-angle kernel clamps positions to [-2, n].
     auto layout = [&](FpGroup &G, std::vector<int2> *out, std::vector<int2> *ranges) -> int {
       int64_t tmin = INT64_MAX, tmax = INT64_MIN;
       for (int a = 0; a < G.count; ++a) {
@@ -223,14 +246,14 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
       for (int b = 0; b < G.nblk; ++b) {
         const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
         const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
-        // Chunks where some strip of the block meets the image: strip k meets row
-        // q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q, so a
-        // chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or ps(klo, q1) >= n
-        // for every angle of the group.
+        // Chunks where some strip of the block meets the image: strip k meets
+        // row q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q,
+        // so a chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or
+        // ps(klo, q1) >= n for every angle of the group.
         int cf = n_chunks, cl = -1;
         for (int ch = 0; ch < n_chunks; ++ch) {
-          const int64_t q0 = (int64_t)ch * kFpRows;
-          const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
+          const int64_t q0 = (int64_t)ch * rows_c;
+          const int64_t q1 = std::min<int64_t>(q0 + rows_c, n) - 1;
           bool meets = false;
           for (int a = 0; a < G.count && !meets; ++a) {
             const FpAngle &f = rep[G.first + a];
@@ -245,15 +268,15 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
         }
         if (ranges) ranges->push_back(make_int2(cf, cl));
         for (int ch = 0; ch < n_chunks; ++ch) {
-          const int64_t q0 = (int64_t)ch * kFpRows;
-          const int64_t q1 = std::min<int64_t>(q0 + kFpRows, n) - 1;
+          const int64_t q0 = (int64_t)ch * rows_c;
+          const int64_t q1 = std::min<int64_t>(q0 + rows_c, n) - 1;
           int64_t lo = INT64_MAX, hi = INT64_MIN;
           for (int a = 0; a < G.count; ++a) {
             const FpAngle &f = rep[G.first + a];
             const int64_t ps_lo = ceil_div(klo * one - f.T - q1 * (int64_t)f.B, f.A);
             const int64_t ps_hi = ceil_div(khi * one - f.T - q0 * (int64_t)f.B, f.A);
-            lo = std::min(lo, paired ? ps_lo : clamp64(ps_lo, -2, n));
-            hi = std::max(hi, (paired ? ps_hi : clamp64(ps_hi, -2, n)) + 1);
+            lo = std::min(lo, multi ? ps_lo : clamp64(ps_lo, -2, n));
+            hi = std::max(hi, (multi ? ps_hi : clamp64(ps_hi, -2, n)) + 1);
           }
           lo -= 1;
           hi += 1;
@@ -278,10 +301,11 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
       while (j < n_items && j - i < per_group && icls[j] == icls[i]) ++j;
       FpGroup G{};
       G.first = i;
-      G.cls = icls[i].first;
-      G.cls1 = icls[i].second;
+      G.cls = icls[i][0];
+      G.clss = 0;
+      for (size_t s = 0; s < icls[i].size() && s < 4; ++s) G.clss |= icls[i][s] << (8 * s);
       G.count = j - i;
-      // fewer angles per group when their strips spread too far apart
+      // fewer items per group when their strips spread too far apart
       while (G.count > 1 && layout(G, nullptr, nullptr) > max_width) G.count = (G.count + 1) / 2;
       G.region = (int)regions.size();
       G.range = (int)ranges.size();
@@ -295,9 +319,11 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
     p->max_blk = max_blk;
     p->n_chunks = n_chunks;
     p->wmax = wmax;
-    p->paired = paired;
+    p->paired = multi;
+    p->slots = SL;
+    p->chunk_rows = rows_c;
     if (wmax <= max_width) break;
-    if (!paired) {
+    if (!multi) {
       set_error("projector plan: staged region wider than " + std::to_string(max_width) +
                 " columns (too few angles for the group size)");
       return CT_E_UNSUPPORTED;
@@ -316,6 +342,8 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   p->bp_slices = hp.bp_slices;
   p->check_first = hp.check_first;
   p->paired = hp.paired;
+  p->slots = hp.slots;
+  p->chunk_rows = hp.chunk_rows;
   p->n_groups = hp.n_groups;
   p->max_blk = hp.max_blk;
   p->n_chunks = hp.n_chunks;
@@ -355,12 +383,12 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
       const int2 cr = hp.ranges[G.range + b];
       const int2 *reg = hp.regions.data() + G.region + (size_t)b * hp.n_chunks;
       for (int w = 0; w < slots; ++w) {
-        const FpAngle fa = hp.paired ? hp.dev[2 * (G.first + w)] : hp.dev[G.first + w];
+        const FpAngle fa = hp.dev[(size_t)hp.slots * (G.first + w)];
         for (int lane = 0; lane < kFpStrips; ++lane) {
           const int64_t k = G.kmin + (int64_t)b * (kFpStrips - 1) - 1 + lane;
           // rows of skipped chunks: no pixel of the strip inside the image
           for (int64_t q = 0; q < n; ++q) {
-            const int64_t ch = q / kFpRows;
+            const int64_t ch = q / hp.chunk_rows;
             if (ch >= cr.x && ch <= cr.y) continue;
             const int64_t ps = ceil_div(k * one - fa.T - q * (int64_t)fa.B, fa.A);
             const int64_t pe = ceil_div((k + 1) * one - fa.T - q * (int64_t)fa.B, fa.A);
@@ -370,7 +398,7 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
             }
           }
           if (cr.x > cr.y) continue;
-          const int64_t q_first = (int64_t)cr.x * kFpRows;
+          const int64_t q_first = (int64_t)cr.x * hp.chunk_rows;
           const int64_t num = k * one - fa.T - q_first * (int64_t)fa.B;
           int64_t pp = (int64_t)std::ceil((double)num / (double)fa.A);
           int64_t ee = pp * (int64_t)fa.A - num;
@@ -390,7 +418,7 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
           int64_t ps = pp;
           uint32_t e = (uint32_t)ee;
           for (int ch = cr.x; ch <= cr.y; ++ch) {
-            const int rows = std::min(kFpRows, n - ch * kFpRows);
+            const int rows = std::min(hp.chunk_rows, n - ch * hp.chunk_rows);
             const int2 rg = reg[ch];
             if (rg.y > hp.wmax) {
               set_error("plan check: window wider than the plan's width");
@@ -401,7 +429,7 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
               const int64_t c = pos - rg.x;
               if (c < 0 || c + 1 > rg.y - 1) {
                 set_error("plan check: staged window misses strip " + std::to_string(k) +
-                          " at row " + std::to_string(ch * kFpRows + r));
+                          " at row " + std::to_string(ch * hp.chunk_rows + r));
                 return CT_E_INVALID;
               }
               ++count;

@@ -574,14 +574,27 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
 }
 
 // ---------------------------------------------------------------------------
-// R_h for angle pairs that share one walk.  The strips, the walk and the
-// output are those of k_radon_fwd; a wave owns one pair (both angles walk the
-// same (e, ps) sequence), a workgroup kPrPairs pairs.  Each chunk stages the
-// same (row, column) window twice -- once per angle, through that angle's
-// transpose/mirror mapping -- as rows of pitch kPrLdw, the two angles' copies
-// of a row adjacent, so both angles' reads at (row, ps) share one address.
+// R_h for SL angles that share one walk (SL = 2: pairs).  With equispaced
+// angles theta, pi/2 - theta, pi - theta and pi/2 + theta have identical walk
+// constants (T, A, B) and differ only in how (p, q) maps to image pixels.
+// (Four angles per walk were measured slower on gfx950: half as many waves
+// to hide LDS latency, and twice the staging per wave.)  The strips, the walk and the output are those of
+// k_radon_fwd; a wave owns SL angles (all walk the same (e, ps) sequence), a
+// workgroup MultiCfg<SL>::kWaves such sets.  Each chunk stages the same
+// (row, column) window SL times -- once per angle, through that angle's
+// transpose/mirror mapping -- as rows of pitch kLdw, the SL copies of a row
+// adjacent, so that the reads of all SL angles at (row, ps) share addresses.
 // Strip positions are not clamped: the host-computed windows cover every
 // position the block's lanes reach, with zeros outside the image.
+template <int SL>
+struct MultiCfg;
+template <>
+struct MultiCfg<2> {
+  static constexpr int kWaves = kPrWaves, kRows = kFpRows;
+};
+
+constexpr int kMultiWidth = 128;              // staged columns per chunk
+constexpr int kLdw = kMultiWidth + 1;         // LDS row pitch (floats)
 
 // Buffer loads with range checking (a load whose byte offset is not below
 // the descriptor's record count returns 0, a documented property of buffer
@@ -593,87 +606,111 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
 // last row are staged too but never read.
 constexpr int kBufWord3 = 0x00020000;  // raw buffer, 32-bit data
 
-__device__ inline void pr_stage_load(float (&v)[kPrPrefetch], const float *__restrict__ u, int n,
-                                     int cls, int q0, int rows, int plo) {
-  const bool tr = (cls & 1) != 0, fi = (cls & 2) != 0, fo = (cls & 4) != 0;
-  const int t = threadIdx.x;
-  if (!tr) {
+template <int SL>
+struct Stage {
+  static constexpr int kWaves = MultiCfg<SL>::kWaves, kRows = MultiCfg<SL>::kRows;
+  static constexpr int kThreads = 64 * kWaves;
+  static constexpr int kPer = kRows * kMultiWidth / kThreads;  // values per thread per tile
+
+  __device__ static void load(float (&v)[kPer], const float *__restrict__ u, int n, int cls,
+                              int q0, int rows, int plo) {
+    const bool tr = (cls & 1) != 0, fi = (cls & 2) != 0, fo = (cls & 4) != 0;
+    const int t = threadIdx.x;
+    if (!tr) {
 #pragma unroll
-    for (int mr = 0; mr < kFpRows / kPrWaves; ++mr) {
-      const int r = (t >> 6) + kPrWaves * mr;  // wave-uniform
+      for (int mr = 0; mr < kRows / kWaves; ++mr) {
+        const int r = (t >> 6) + kWaves * mr;  // wave-uniform
+        const int q = min(q0 + r, n - 1);
+        const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)urow, (short)0, r < rows ? n * 4 : 0, kBufWord3);
+        const int p0 = plo + (t & 63);
+#pragma unroll
+        for (int mc = 0; mc < kMultiWidth / 64; ++mc) {
+          const int p = p0 + 64 * mc;
+          const int pi = fi ? n - 1 - p : p;
+          v[mr * (kMultiWidth / 64) + mc] =
+              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, pi * 4, 0, 0));
+        }
+      }
+    } else {
+      const int r = t & (kRows - 1);
       const int q = min(q0 + r, n - 1);
-      const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          (void *)urow, (short)0, r < rows ? n * 4 : 0, kBufWord3);
-      const int p0 = plo + (t & 63);
+      const int qi = fo ? n - 1 - q : q;
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void *)u, (short)0, n * n * 4, kBufWord3);
+      const int p0 = plo + t / kRows;
 #pragma unroll
-      for (int mc = 0; mc < kPrMaxWidth / 64; ++mc) {
-        const int p = p0 + 64 * mc;
+      for (int m = 0; m < kPer; ++m) {
+        const int p = p0 + (kThreads / kRows) * m;
         const int pi = fi ? n - 1 - p : p;
-        v[mr * (kPrMaxWidth / 64) + mc] =
-            __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, pi * 4, 0, 0));
+        v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (pi * n + qi) * 4, 0, 0));
       }
     }
-  } else {
-    const int r = t & (kFpRows - 1);
-    const int q = min(q0 + r, n - 1);
-    const int qi = fo ? n - 1 - q : q;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)u, (short)0, n * n * 4, kBufWord3);
-    const int p0 = plo + t / kFpRows;
-#pragma unroll
-    for (int m = 0; m < kPrPrefetch; ++m) {
-      const int p = p0 + (kPrThreads / kFpRows) * m;
-      const int pi = fi ? n - 1 - p : p;
-      v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (pi * n + qi) * 4, 0, 0));
-    }
   }
-}
 
-// Row r of angle `slot` starts at tile + (2 r + slot) kPrLdw; every staged
-// position is written (zeros beyond the window), so stores need no mask.
-__device__ inline void pr_stage_store(const float (&v)[kPrPrefetch], float *tile, int cls,
-                                      int slot) {
-  const int t = threadIdx.x;
-  if (!(cls & 1)) {
+  // Row r of angle `slot` starts at tile + (SL r + slot) kLdw; every staged
+  // position is written (window positions beyond W too), so stores need no mask.
+  __device__ static void store(const float (&v)[kPer], float *tile, int cls, int slot) {
+    const int t = threadIdx.x;
+    if (!(cls & 1)) {
 #pragma unroll
-    for (int mr = 0; mr < kFpRows / kPrWaves; ++mr) {
-      const int r = (t >> 6) + kPrWaves * mr;
+      for (int mr = 0; mr < kRows / kWaves; ++mr) {
+        const int r = (t >> 6) + kWaves * mr;
 #pragma unroll
-      for (int mc = 0; mc < kPrMaxWidth / 64; ++mc) {
-        const int c = (t & 63) + 64 * mc;
-        tile[(2 * r + slot) * kPrLdw + c] = v[mr * (kPrMaxWidth / 64) + mc];
+        for (int mc = 0; mc < kMultiWidth / 64; ++mc) {
+          const int c = (t & 63) + 64 * mc;
+          tile[(SL * r + slot) * kLdw + c] = v[mr * (kMultiWidth / 64) + mc];
+        }
+      }
+    } else {
+      const int r = t & (kRows - 1);
+#pragma unroll
+      for (int m = 0; m < kPer; ++m) {
+        const int c = (t / kRows) + (kThreads / kRows) * m;
+        tile[(SL * r + slot) * kLdw + c] = v[m];
       }
     }
-  } else {
-    const int r = t & (kFpRows - 1);
-#pragma unroll
-    for (int m = 0; m < kPrPrefetch; ++m) {
-      const int c = (t / kFpRows) + (kPrThreads / kFpRows) * m;
-      tile[(2 * r + slot) * kPrLdw + c] = v[m];
-    }
   }
-}
+};
 
+// Accumulation of one staged row for one angle: first pixel (fraction e),
+// second pixel (fraction e + A) when it lies in the strip.
 template <bool CHECK_FIRST>
-__global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
+__device__ inline void acc_row(float x1, float x2, bool in1, bool in2, float ef, float &P,
+                               float &Q, float &S) {
+  const float a0 = CHECK_FIRST ? (in1 ? x1 : 0.f) : x1;
+  const float a2 = in2 ? x2 : 0.f;
+  const float sa = a0 + a2;
+  P += sa;
+  Q = fmaf(ef, sa, Q);
+  S += a2;
+}
+
+template <int SL, bool CHECK_FIRST>
+__global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
     const int2 *__restrict__ chunk_range, int n_chunks, float *__restrict__ sino, SinoEpi ep,
     int N) {
-  __shared__ float tile[2 * 2 * kFpRows * kPrLdw];  // 2 buffers x kFpRows x 2 angles x kPrLdw
+  using St = Stage<SL>;
+  constexpr int kRows = St::kRows;
+  __shared__ float tile[2 * kRows * SL * kLdw];  // 2 buffers x kRows x SL angles x kLdw
   fp_batch_offsets(u, sino, ep, n, N, M);
   const FpGroup grp = groups[blockIdx.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int blk = blockIdx.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
-  const FpAngle *pa = angs + 2 * grp.first;
+  const FpAngle *pa = angs + SL * grp.first;
+  int cls[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) cls[s] = (grp.clss >> (8 * s)) & 0xff;
 
   // Bins no pixel reaches hold zero (block 0 below kmin, last block above kmax).
   if (blk == 0) {
     const int lim = min(grp.kmin, M);
-    for (int a = 0; a < 2 * grp.count; ++a) {
+    for (int a = 0; a < SL * grp.count; ++a) {
       const int l = pa[a].l;
       if (l < 0) continue;
       for (int k = threadIdx.x; k < lim; k += blockDim.x) fp_output(sino, ep, M, l, k, 0.f);
@@ -681,7 +718,7 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
   }
   if (blk == nblk_eff - 1) {
     const int from = max(max(grp.kmax + 1, grp.kmin), 0);
-    for (int a = 0; a < 2 * grp.count; ++a) {
+    for (int a = 0; a < SL * grp.count; ++a) {
       const int l = pa[a].l;
       if (l < 0) continue;
       for (int k = from + threadIdx.x; k < M; k += blockDim.x) fp_output(sino, ep, M, l, k, 0.f);
@@ -694,13 +731,13 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
   const uint32_t one = 1u << kFixBits;
   const int2 crange = chunk_range[grp.range + blk];
   const int ch_first = crange.x, ch_last = crange.y;
-  const int q_first = ch_first * kFpRows;
+  const int q_first = ch_first * kRows;
   const bool active = wave < grp.count;  // wave-uniform
 
   uint32_t e = 0u, A = one, B = 0u;
   int ps = 0;
   if (active) {
-    const FpAngle fa = pa[2 * wave];
+    const FpAngle fa = pa[SL * wave];
     A = fa.A;
     B = fa.B;
     const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T -
@@ -719,37 +756,37 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
   }
   // the second pixel (fraction e + A) is in the strip iff e < 2^30 - A
   const uint32_t lim2 = A < one ? one - A : 0u;
-  float P0 = 0.f, Q0 = 0.f, S0 = 0.f, P1 = 0.f, Q1 = 0.f, S1 = 0.f;
+  float P[SL], Q[SL], S[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) P[s] = Q[s] = S[s] = 0.f;
 
   const int2 *reg = regions + grp.region + blk * n_chunks;
   constexpr int RB = 8;  // rows whose LDS reads are issued together
-  float pf0[kPrPrefetch], pf1[kPrPrefetch];
+  float pf[SL][St::kPer];
   int2 rg_next = make_int2(0, 4);
   if (ch_first <= ch_last) {
     rg_next = reg[ch_first];
-    const int rows0 = min(kFpRows, n - q_first);
-    pr_stage_load(pf0, u, n, grp.cls, q_first, rows0, rg_next.x);
-    pr_stage_load(pf1, u, n, grp.cls1, q_first, rows0, rg_next.x);
+    const int rows0 = min(kRows, n - q_first);
+#pragma unroll
+    for (int s = 0; s < SL; ++s) St::load(pf[s], u, n, cls[s], q_first, rows0, rg_next.x);
   }
   for (int ch = ch_first; ch <= ch_last; ++ch) {
-    const int q0 = ch * kFpRows;
-    const int rows = min(kFpRows, n - q0);
-    const int2 rg = rg_next;
-    const int plo = rg.x, W = rg.y;
-    float *buf = tile + ((ch - ch_first) & 1) * (2 * kFpRows * kPrLdw);
-    pr_stage_store(pf0, buf, grp.cls, 0);
-    pr_stage_store(pf1, buf, grp.cls1, 1);
+    const int q0 = ch * kRows;
+    const int rows = min(kRows, n - q0);
+    const int plo = rg_next.x;
+    float *buf = tile + ((ch - ch_first) & 1) * (kRows * SL * kLdw);
+#pragma unroll
+    for (int s = 0; s < SL; ++s) St::store(pf[s], buf, cls[s], s);
     __syncthreads();
     if (ch + 1 <= ch_last) {
       rg_next = reg[ch + 1];
-      const int q1 = q0 + kFpRows;
-      const int rows1 = min(kFpRows, n - q1);
-      pr_stage_load(pf0, u, n, grp.cls, q1, rows1, rg_next.x);
-      pr_stage_load(pf1, u, n, grp.cls1, q1, rows1, rg_next.x);
+      const int q1 = q0 + kRows;
+      const int rows1 = min(kRows, n - q1);
+#pragma unroll
+      for (int s = 0; s < SL; ++s) St::load(pf[s], u, n, cls[s], q1, rows1, rg_next.x);
     }
     if (active) {
       // pr = ps - plo >= 0 is the strip start within the staged window
-      const float *base = buf;
       int pr = ps - plo;
       int r0 = 0;
       for (; r0 + RB <= rows; r0 += RB) {
@@ -757,61 +794,38 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
         uint32_t ev[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          off[r] = pr + (r0 + r) * (2 * kPrLdw);
+          off[r] = pr + (r0 + r) * (SL * kLdw);
           ev[r] = e;
           walk_row(e, pr, A, B);
         }
-        float a1[RB], a2r[RB], b1[RB], b2r[RB];
+        float x1[RB][SL], x2[RB][SL];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const float *pt = base + off[r];
-          a1[r] = pt[0];
-          a2r[r] = pt[1];
-          b1[r] = pt[kPrLdw];
-          b2r[r] = pt[kPrLdw + 1];
+          const float *pt = buf + off[r];
+#pragma unroll
+          for (int s = 0; s < SL; ++s) {
+            x1[r][s] = pt[s * kLdw];
+            x2[r][s] = pt[s * kLdw + 1];
+          }
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           const uint32_t e1 = ev[r];
-          const bool in2 = e1 < lim2;
+          const bool in1 = e1 < one, in2 = e1 < lim2;
           const float ef = (float)e1;
-          float a0 = a1[r], b0 = b1[r];
-          if (CHECK_FIRST) {
-            const bool in1 = e1 < one;
-            a0 = in1 ? a0 : 0.f;
-            b0 = in1 ? b0 : 0.f;
-          }
-          const float a2 = in2 ? a2r[r] : 0.f;
-          const float b2 = in2 ? b2r[r] : 0.f;
-          const float sa = a0 + a2, sb = b0 + b2;
-          P0 += sa;
-          Q0 = fmaf(ef, sa, Q0);
-          S0 += a2;
-          P1 += sb;
-          Q1 = fmaf(ef, sb, Q1);
-          S1 += b2;
+#pragma unroll
+          for (int s = 0; s < SL; ++s)
+            acc_row<CHECK_FIRST>(x1[r][s], x2[r][s], in1, in2, ef, P[s], Q[s], S[s]);
         }
       }
       for (int r = r0; r < rows; ++r) {  // ragged last chunk
-        const float *pt = base + pr + r * (2 * kPrLdw);
+        const float *pt = buf + pr + r * (SL * kLdw);
         const uint32_t e1 = e;
-        const bool in2 = e1 < lim2;
+        const bool in1 = e1 < one, in2 = e1 < lim2;
         const float ef = (float)e1;
-        float a0 = pt[0], b0 = pt[kPrLdw];
-        if (CHECK_FIRST) {
-          const bool in1 = e1 < one;
-          a0 = in1 ? a0 : 0.f;
-          b0 = in1 ? b0 : 0.f;
-        }
-        const float a2 = in2 ? pt[1] : 0.f;
-        const float b2 = in2 ? pt[kPrLdw + 1] : 0.f;
-        const float sa = a0 + a2, sb = b0 + b2;
-        P0 += sa;
-        Q0 = fmaf(ef, sa, Q0);
-        S0 += a2;
-        P1 += sb;
-        Q1 = fmaf(ef, sb, Q1);
-        S1 += b2;
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+          acc_row<CHECK_FIRST>(pt[s * kLdw], pt[s * kLdw + 1], in1, in2, ef, P[s], Q[s], S[s]);
         walk_row(e, pr, A, B);
       }
       ps = pr + plo;
@@ -820,14 +834,18 @@ __global__ __launch_bounds__(kPrThreads) void k_radon_fwd_pair(
 
   if (active) {
     const float inv = 1.0f / (float)one;
-    const float qt0 = fmaf((float)A, S0, Q0);  // sum of fraction * u, in 2^-30 units
-    const float qt1 = fmaf((float)A, S1, Q1);
-    const float qp0 = __shfl_up(qt0, 1, 64);
-    const float qp1 = __shfl_up(qt1, 1, 64);
+    float qt[SL], qp[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      qt[s] = fmaf((float)A, S[s], Q[s]);  // sum of fraction * u, in 2^-30 units
+      qp[s] = __shfl_up(qt[s], 1, 64);
+    }
     if (lane >= 1 && k <= grp.kmax && k < M) {
-      const int l0 = pa[2 * wave].l, l1 = pa[2 * wave + 1].l;
-      fp_output(sino, ep, M, l0, k, fmaf(qp0 - qt0, inv, P0));
-      if (l1 >= 0) fp_output(sino, ep, M, l1, k, fmaf(qp1 - qt1, inv, P1));
+#pragma unroll
+      for (int s = 0; s < SL; ++s) {
+        const int l = pa[SL * wave + s].l;
+        if (l >= 0) fp_output(sino, ep, M, l, k, fmaf(qp[s] - qt[s], inv, P[s]));
+      }
     }
   }
 }
@@ -838,13 +856,14 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   if (epi) ep = *epi;
   const int N = p->g.n_angles;
   dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1, nb);
-  if (p->paired) {
+  if (p->slots == 2) {
+    const dim3 block(64 * kPrWaves);
     if (p->check_first)
-      hipLaunchKernelGGL(k_radon_fwd_pair<true>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
-                         p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->n_chunks, out, ep, N);
+      hipLaunchKernelGGL((k_radon_fwd_multi<2, true>), grid, block, 0, s, u, p->g.n, p->g.n_bins,
+                         p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, out,
+                         ep, N);
     else
-      hipLaunchKernelGGL(k_radon_fwd_pair<false>, grid, dim3(kPrThreads), 0, s, u, p->g.n,
+      hipLaunchKernelGGL((k_radon_fwd_multi<2, false>), grid, block, 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
                          p->n_chunks, out, ep, N);
     CT_TRY_HIP(hipGetLastError());
