@@ -163,7 +163,11 @@ typedef struct ct_problem {
 } ct_problem;
 
 enum {
-  CT_FLAG_VALIDATE = 1u  /* scan sino/bound for NaN/Inf at setup (CT_E_NONFINITE) */
+  CT_FLAG_VALIDATE = 1u, /* scan sino/bound for NaN/Inf at setup (CT_E_NONFINITE) */
+  CT_FLAG_NONNEG = 2u    /* add u >= 0 (§4.5): the iteration gains the state bar u,
+                            u_tmp = bar u - u - sigma (A^* s1 - tau div s2), the
+                            multiplier rho / (rho + sigma^2 c + (sigma tau)^2 lambda_Delta rho),
+                            and bar u += max(2 u_new - bar u, 0) - u_new */
 };
 
 typedef struct ct_params {
@@ -237,6 +241,9 @@ int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s);
 
 /* Copy the state out: u [n][n], vb1 [N][M], vb2 [2][n][n] (any may be NULL). */
 int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_stream s);
+/* bar u of the non-negativity variant ([nb][n][n]); CT_E_STATE without it. */
+int ct_state_export_ubar(const ct_solver *sv, float *ubar, ct_stream s);
+int ct_state_import_ubar(ct_solver *sv, const float *ubar, ct_stream s);
 /* Replace the state (all three required); caches A u, nabla u are recomputed. */
 int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float *vb2,
                     ct_stream s);

@@ -234,7 +234,7 @@ def power_norm(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -
 
 
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-            start_norm, start_precond, n):
+            start_norm, start_precond, n, nonneg=False):
     p = _lib.CtParams()
     _L.ct_params_default(ctypes.byref(p))
     p.sigma, p.tau, p.eps = sigma, tau, eps
@@ -242,7 +242,8 @@ def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, v
     p.c_safety = c_safety
     p.beta = beta if beta is not None else 0.0
     p.k_max, p.gap_every, p.power_iters = k_max, gap_every, power_iters
-    p.flags = _lib.CT_FLAG_VALIDATE if validate else 0
+    p.flags = ((_lib.CT_FLAG_VALIDATE if validate else 0)
+               | (_lib.CT_FLAG_NONNEG if nonneg else 0))
     p.start_norm = _dev(start_norm, (n, n), "start_norm") if start_norm is not None else None
     p.start_precond = (_dev(start_precond, (n, n), "start_precond")
                        if start_precond is not None else None)
@@ -269,12 +270,13 @@ class Solver:
                  c: Optional[float] = None, c_safety: float = 1.1, beta: Optional[float] = None,
                  power_iters: int = 30, validate: bool = False,
                  start_norm: Optional[torch.Tensor] = None,
-                 start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0):
+                 start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0,
+                 nonneg: bool = False):
         self.plan = plan
         self._keep = (sino, mask_bits, bound, start_norm, start_precond)
         prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n)
+                      start_norm, start_precond, plan.n, nonneg)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
                                    ctypes.byref(h)), "ct_solver_create")
@@ -322,6 +324,19 @@ class Solver:
                                   _dev(vb1, L + (N, M), "vb1"),
                                   _dev(vb2, L + (2, n, n), "vb2"), _stream()), "ct_state_import")
 
+    def export_ubar(self) -> torch.Tensor:
+        """bar u of the u >= 0 variant."""
+        n = self.plan.n
+        ub = torch.empty(self._lead() + (n, n), device=torch.device("cuda"))
+        _check(_L.ct_state_export_ubar(self._h, ub.data_ptr(), _stream()),
+               "ct_state_export_ubar")
+        return ub
+
+    def import_ubar(self, ub) -> None:
+        n = self.plan.n
+        _check(_L.ct_state_import_ubar(self._h, _dev(ub, self._lead() + (n, n), "ubar"),
+                                       _stream()), "ct_state_import_ubar")
+
     def gap(self) -> np.ndarray:
         """FP64 record (6 values; (nb, 6) for a batch)."""
         o = (ctypes.c_double * (6 * self.nb))()
@@ -350,7 +365,8 @@ class SolverBatch(Solver):
                  c: Optional[float] = None, c_safety: float = 1.1, beta: Optional[float] = None,
                  power_iters: int = 30, validate: bool = False,
                  start_norm: Optional[torch.Tensor] = None,
-                 start_precond: Optional[torch.Tensor] = None, bound_scalars=None):
+                 start_precond: Optional[torch.Tensor] = None, bound_scalars=None,
+                 nonneg: bool = False):
         self.plan = plan
         nb = len(sinos)
         masks = masks if masks is not None else [None] * nb
@@ -364,7 +380,7 @@ class SolverBatch(Solver):
         for b in range(nb):
             probs[b] = _problem(plan, sinos[b], masks[b], bounds[b], lam, bsc[b])
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n)
+                      start_norm, start_precond, plan.n, nonneg)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create_batch(plan.handle, probs, nb, ctypes.byref(prm), _stream(),
                                          ctypes.byref(h)), "ct_solver_create_batch")
@@ -401,7 +417,7 @@ def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma
                         tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3,
                         c: Optional[float] = None, c_safety: float = 1.1,
                         beta: Optional[float] = None, power_iters: int = 30,
-                        validate: bool = False):
+                        validate: bool = False, nonneg: bool = False):
     """PDRQS1 solves of many problems, any mix of geometries.  problems: list of
     dicts with keys plan, sino, lam and optionally mask_bits, bound,
     bound_scalar.  Problems sharing a plan and lambda run as one batch; all
@@ -424,7 +440,7 @@ def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma
         us.append(u)
         outs[i] = u.data_ptr()
     prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-                  None, None, problems[0]["plan"].n)
+                  None, None, problems[0]["plan"].n, nonneg)
     nrec = k_max // gap_every if gap_every > 0 else 0
     rep = (ctypes.c_double * max(1, 6 * nrec * count))()
     _check(_L.ct_reconstruct_batched(count, plans, probs, ctypes.byref(prm), outs,
@@ -439,11 +455,12 @@ def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, boun
                 tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3, c: Optional[float] = None,
                 c_safety: float = 1.1, beta: Optional[float] = None, power_iters: int = 30,
                 validate: bool = False, start_norm=None, start_precond=None,
-                bound_scalar: float = 0.0):
-    """One-shot PDRQS1 solve; returns (u, report (records x 6) or None)."""
+                bound_scalar: float = 0.0, nonneg: bool = False):
+    """One-shot PDRQS1 solve (nonneg: with u >= 0, §4.5); returns (u, report
+    (records x 6) or None)."""
     prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
     prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-                  start_norm, start_precond, plan.n)
+                  start_norm, start_precond, plan.n, nonneg)
     u = torch.empty((plan.n, plan.n), device=sino.device, dtype=torch.float32)
     nrec = k_max // gap_every if gap_every > 0 else 0
     rep = (ctypes.c_double * max(1, 6 * nrec))()

@@ -14,6 +14,7 @@ CT_OK = 0
 ERRORS = {-1: "CT_E_INVALID", -2: "CT_E_UNSUPPORTED", -3: "CT_E_DEVICE",
           -4: "CT_E_NONFINITE", -5: "CT_E_DIVERGED", -6: "CT_E_STATE"}
 CT_FLAG_VALIDATE = 1
+CT_FLAG_NONNEG = 2
 
 
 class CtGeom(ctypes.Structure):
@@ -64,6 +65,8 @@ SIGNATURES = {
     "ct_pd_step_timed": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "ct_state_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_state_import": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ct_state_export_ubar": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "ct_state_import_ubar": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "ct_gap": (c_int32, [c_void_p, POINTER(c_double), c_void_p]),
     "ct_reconstruct": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                  POINTER(c_double), c_int32, c_void_p]),

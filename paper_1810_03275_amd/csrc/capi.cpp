@@ -36,8 +36,10 @@ static hipStream_t S(ct_stream s) { return reinterpret_cast<hipStream_t>(s); }
 // Preconditioner tables (§4.3, §4.3.1, §4.4), computed in FP64 on the host.
 static double freq(int k, int n) { return (k <= n / 2) ? (double)k : (double)(k - n); }
 
+// sqrt_rho_only: sqrt(rho) (the c estimate); nonneg: the u >= 0 variant's
+// rho / (rho + sigma^2 c + (sigma tau)^2 lambda_Delta rho) (§4.5).
 static std::vector<float> multiplier_table(int n, double sigma, double tau, double c, double eps,
-                                           bool sqrt_rho_only) {
+                                           bool sqrt_rho_only, bool nonneg = false) {
   const int half = n / 2 + 1;
   std::vector<float> m((size_t)half * n);
   const double inv_nn = 1.0 / ((double)n * (double)n);
@@ -53,7 +55,8 @@ static std::vector<float> multiplier_table(int n, double sigma, double tau, doub
         v = std::sqrt(rho);
       } else {
         const double lap = 4.0 * s1 * s1 + 4.0 * s2 * s2;
-        v = rho / (sigma * sigma * c + (sigma * tau) * (sigma * tau) * lap * rho);
+        v = rho / ((nonneg ? rho : 0.0) + sigma * sigma * c +
+                   (sigma * tau) * (sigma * tau) * lap * rho);
       }
       m[(size_t)k1 * n + k2] = (float)(v * inv_nn);
     }
@@ -155,6 +158,7 @@ struct ct_solver {
   uint32_t *mask = nullptr;
   float2 *spec = nullptr;     // nb spectra of the preconditioner FFT
   float *bp_part = nullptr;   // nb * bp_S partial backprojections
+  float *ubar = nullptr;      // bar u of the u >= 0 variant (nb images) or NULL
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -173,7 +177,7 @@ struct ct_solver {
 static void solver_free(ct_solver *sv) {
   if (!sv) return;
   float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
-                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part};
+                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar};
   for (float *b : bufs) (void)hipFree(b);
   (void)hipFree(sv->mask);
   (void)hipFree(sv->spec);
@@ -449,6 +453,7 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   CT_TRY_HIP(hipMemsetAsync(sv->s2, 0, sizeof(float) * nn * 2, s));
   CT_TRY_HIP(hipMemsetAsync(sv->vb1, 0, sizeof(float) * NM, s));
   CT_TRY_HIP(hipMemsetAsync(sv->s1, 0, sizeof(float) * NM, s));
+  if (sv->ubar) CT_TRY_HIP(hipMemsetAsync(sv->ubar, 0, sizeof(float) * nn, s));
   sv->iters = 0;
   sv->have_dual = false;
   return CT_OK;
@@ -464,8 +469,10 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   const float inv_h = (float)(1.0 / p->g.h);
   const int nb = sv->nb;
   if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
+  // u_tmp (u >= 0 variant: plus bar u - u)
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
-                          (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S));
+                          (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S,
+                          sv->ubar, sv->ubar ? sv->u : nullptr));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
   CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
                            sv->spec));
@@ -477,7 +484,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
-                          sv->vb2, sv->s2, sv->w, mode, st, nb, q2out));
+                          sv->vb2, sv->s2, sv->w, mode, st, nb, q2out, sv->ubar));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
@@ -529,6 +536,7 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   const size_t nn = (size_t)n * n, NM = (size_t)N * M;
   const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
+  if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   CT_TRY(solver_set_slices(sv, p->bp_slices));
   for (int b = 0; b < nb; ++b) {
     uint32_t *mb = sv->mask + (size_t)b * N * MW;
@@ -620,7 +628,7 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   }
   sv->pc.c = sv->c;
   {
-    auto m = multiplier_table(n, sv->sigma, sv->tau, sv->c, sv->eps, false);
+    auto m = multiplier_table(n, sv->sigma, sv->tau, sv->c, sv->eps, false, sv->ubar != nullptr);
     CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, m.data(), sizeof(float) * m.size(),
                               hipMemcpyHostToDevice, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
@@ -898,6 +906,36 @@ int ct_state_export(const ct_solver *sv, float *u, float *vb1, float *vb2, ct_st
   return CT_OK;
 }
 
+int ct_state_export_ubar(const ct_solver *sv, float *ubar, ct_stream s) {
+  clear_error();
+  if (!sv || !ubar) {
+    set_error("ct_state_export_ubar: null argument");
+    return CT_E_INVALID;
+  }
+  if (!sv->ubar) {
+    set_error("ct_state_export_ubar: the solver has no u >= 0 constraint");
+    return CT_E_STATE;
+  }
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb;
+  CT_TRY_HIP(hipMemcpyAsync(ubar, sv->ubar, sizeof(float) * nn, hipMemcpyDeviceToDevice, S(s)));
+  return CT_OK;
+}
+
+int ct_state_import_ubar(ct_solver *sv, const float *ubar, ct_stream s) {
+  clear_error();
+  if (!sv || !ubar) {
+    set_error("ct_state_import_ubar: null argument");
+    return CT_E_INVALID;
+  }
+  if (!sv->ubar) {
+    set_error("ct_state_import_ubar: the solver has no u >= 0 constraint");
+    return CT_E_STATE;
+  }
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb;
+  CT_TRY_HIP(hipMemcpyAsync(sv->ubar, ubar, sizeof(float) * nn, hipMemcpyDeviceToDevice, S(s)));
+  return CT_OK;
+}
+
 int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float *vb2,
                     ct_stream s) {
   clear_error();
@@ -1171,6 +1209,10 @@ int ct_unrolled_forward(ct_solver *sv, int32_t K, int32_t every, ct_tape **out, 
   if (!sv || !out || K < 1 || every < 1) {
     set_error("ct_unrolled_forward: need a solver, K >= 1 and every >= 1");
     return CT_E_INVALID;
+  }
+  if (sv->ubar) {
+    set_error("ct_unrolled_forward: the u >= 0 variant has no reverse sweep");
+    return CT_E_UNSUPPORTED;
   }
   *out = nullptr;
   hipStream_t st = S(s);

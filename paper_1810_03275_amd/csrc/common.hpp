@@ -150,10 +150,10 @@ namespace ctpd {
 // nb problems of one geometry stored contiguously; part: nb * bp_slices
 // partial images (NULL: the plan's own buffer, nb = 1 only).
 // S: angle slices (0: the plan's choice).
-// base (optional, nb images) is added to the result.
+// base (optional, nb images) is added to the result, base2 (optional) subtracted.
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
-                     int S = 0, const float *base = nullptr);
+                     int S = 0, const float *base = nullptr, const float *base2 = nullptr);
 // Optional epilogue of the forward projector: the PDRQS1 sinogram-side update
 // applied to r = R(u)/beta per bin (see k_sino_update), instead of storing R(u).
 struct SinoEpi {
@@ -184,10 +184,11 @@ int launch_prox_sino(int N, int M, const float *q, float step, const float *u0,
 int launch_sino_update(int N, int M, const float *rraw, float inv_beta, float sigma,
                        const float *target, const uint32_t *mask, float *vb1, float *s1,
                        float *y1, float *rout, int mode, hipStream_t s);
-// q2out (optional): the resolvent input 2 v2 - vb2 (modes 0, 2).
+// q2out (optional): the resolvent input 2 v2 - vb2 (modes 0, 2).  ubar
+// (optional, modes 0, 2): bar u += max(2 u - bar u, 0) - u (u >= 0 variant).
 int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius,
                      float *vb2, float *s2, float *wout, int mode, hipStream_t s, int nb = 1,
-                     float *q2out = nullptr);
+                     float *q2out = nullptr, float *ubar = nullptr);
 // Reverse sweep of unrolled PDRQS1 (see unrolled.hip).
 int launch_sino_reverse(int N, int M, int nb, float sigma, const float *V1, const float *q1,
                         const float *target, const uint32_t *mask, float *P, float *Q1,

@@ -57,7 +57,8 @@ __global__ void k_tv_project(int64_t count, const float *__restrict__ q, float r
 // mode 1: only s2 = vb2 + sigma tau nabla u.  mode 2: also store w.
 __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, float st,
                             float radius, float *__restrict__ vb2, float *__restrict__ s2,
-                            float *__restrict__ wout, int mode, float *__restrict__ q2out) {
+                            float *__restrict__ wout, int mode, float *__restrict__ q2out,
+                            float *__restrict__ ubar) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
@@ -69,6 +70,7 @@ __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, flo
   s2 += blockIdx.z * 2 * nn;
   if (wout != nullptr) wout += blockIdx.z * 2 * nn;
   if (q2out != nullptr) q2out += blockIdx.z * 2 * nn;
+  if (ubar != nullptr) ubar += blockIdx.z * nn;
   const float c = u[o];
   const float g1 = (i < n - 1) ? (u[o + 1] - c) * inv_h : 0.f;
   const float g2 = (j < n - 1) ? (u[o + n] - c) * inv_h : 0.f;
@@ -84,6 +86,11 @@ __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, flo
   if (q2out != nullptr) {
     q2out[o] = 2.f * v1 - b1;
     q2out[o + nn] = 2.f * v2 - b2;
+  }
+  if (ubar != nullptr) {
+    // resolvent of the indicator of u >= 0 (§4.5): max(., 0)
+    const float ub = ubar[o];
+    ubar[o] = ub + fmaxf(2.f * c - ub, 0.f) - c;
   }
   const float n1 = b1 + w1 - v1, n2 = b2 + w2 - v2;
   vb2[o] = n1;
@@ -310,11 +317,12 @@ int launch_tv_project(int n, const float *q, float radius, float *w, hipStream_t
 }
 
 int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float radius, float *vb2,
-                     float *s2, float *wout, int mode, hipStream_t s, int nb, float *q2out) {
+                     float *s2, float *wout, int mode, hipStream_t s, int nb, float *q2out,
+                     float *ubar) {
   dim3 grid = row_grid(n, n);
   grid.z = nb;
   hipLaunchKernelGGL(k_tv_update, grid, dim3(256), 0, s, n, inv_h, u, sigtau, radius, vb2, s2,
-                     wout, mode, q2out);
+                     wout, mode, q2out, ubar);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

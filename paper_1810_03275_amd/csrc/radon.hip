@@ -76,7 +76,8 @@ __device__ inline void bp_stage_store(const float2 (&v)[kBpPrefetch], float2 *vd
 __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
     int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
-    float inv_h, const float *__restrict__ base, float *__restrict__ out) {
+    float inv_h, const float *__restrict__ base, const float *__restrict__ base2,
+    float *__restrict__ out) {
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
@@ -91,6 +92,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   sino += (size_t)bz * N * M;
   if (pfield != nullptr) pfield += (size_t)bz * 2 * nn;
   if (base != nullptr) base += (size_t)bz * nn;
+  if (base2 != nullptr) base2 += (size_t)bz * nn;
   out += (size_t)blockIdx.z * nn;  // own image (S == 1) or own partial image
   const int a_begin = sl * slice_len;
   const int a_end = min(N, a_begin + slice_len);
@@ -176,15 +178,17 @@ __global__ __launch_bounds__(256) void k_radon_adj(
       res = fmaf(c2 * inv_h, d1 + d2, res);
     }
     if (base != nullptr) res += base[o];
+    if (base2 != nullptr) res -= base2[o];
     out[o] = res;
   }
 }
 
-// out = base + c1 * sum_s part[s] + c2 * div_h(p): the angle slices' partial
+// out = base - base2 + c1 * sum_s part[s] + c2 * div_h(p): the angle slices' partial
 // backprojections summed in slice order, with the same epilogue.
 __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
                              const float *__restrict__ pfield, float c1, float c2, float inv_h,
-                             const float *__restrict__ base, float *__restrict__ out) {
+                             const float *__restrict__ base, const float *__restrict__ base2,
+                             float *__restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
@@ -192,6 +196,7 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
   part += (size_t)blockIdx.z * S * nn;  // problem blockIdx.z of a batch
   if (pfield != nullptr) pfield += (size_t)blockIdx.z * 2 * nn;
   if (base != nullptr) base += (size_t)blockIdx.z * nn;
+  if (base2 != nullptr) base2 += (size_t)blockIdx.z * nn;
   out += (size_t)blockIdx.z * nn;
   float r = part[o];
   for (int s = 1; s < S; ++s) r += part[s * nn + o];
@@ -204,12 +209,13 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
     res = fmaf(c2 * inv_h, d1 + d2, res);
   }
   if (base != nullptr) res += base[o];
+  if (base2 != nullptr) res -= base2[o];
   out[o] = res;
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb, float *part, int S,
-                     const float *base) {
+                     const float *base, const float *base2) {
   const int n = p->g.n;
   if (S <= 0) S = p->bp_slices;
   const int slice_len = (p->g.n_angles + S - 1) / S;
@@ -223,11 +229,11 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   float *dst = (S == 1) ? out : part;
   hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
                      p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
-                     base, dst);
+                     base, base2, dst);
   CT_TRY_HIP(hipGetLastError());
   if (S > 1) {
     hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n, nb), dim3(256), 0, s, part, S, n,
-                       pfield, c1, c2, (float)(1.0 / p->g.h), base, out);
+                       pfield, c1, c2, (float)(1.0 / p->g.h), base, base2, out);
     CT_TRY_HIP(hipGetLastError());
   }
   return CT_OK;
