@@ -164,10 +164,25 @@ typedef struct ct_problem {
 
 enum {
   CT_FLAG_VALIDATE = 1u, /* scan sino/bound for NaN/Inf at setup (CT_E_NONFINITE) */
+  CT_METHOD_SHIFT = 4u,  /* flags bits 4..7 select the iteration (CT_METHOD_*) */
   CT_FLAG_NONNEG = 2u    /* add u >= 0 (§4.5): the iteration gains the state bar u,
                             u_tmp = bar u - u - sigma (A^* s1 - tau div s2), the
                             multiplier rho / (rho + sigma^2 c + (sigma tau)^2 lambda_Delta rho),
                             and bar u += max(2 u_new - bar u, 0) - u_new */
+};
+
+/* Iterations a solver can run (flags |= method << CT_METHOD_SHIFT):
+ *  PDRQS1      Algorithm PDRQS1 (§4.4), inverse-norm + periodic-Laplacian M (default)
+ *  RICHARDSON  PDRQS1 with M = m id, m = 1.1 (sigma^2 + 8 (sigma tau)^2 / h^2) (§4.3)
+ *  CP          Algorithm CP (§3.4), sigma = tau = 0.99 / sqrt(1 + 8/h^2) on the
+ *              normalized problem (the params' sigma, tau are not used)
+ *  PDRQS2      Algorithm PDRQS2 (§4.2, §4.3.1), the unconstrained problem (no D0)
+ * ct_gap is defined for PDRQS1 and RICHARDSON; ct_objective serves all. */
+enum {
+  CT_METHOD_PDRQS1 = 0,
+  CT_METHOD_RICHARDSON = 1,
+  CT_METHOD_CP = 2,
+  CT_METHOD_PDRQS2 = 3
 };
 
 typedef struct ct_params {
@@ -187,6 +202,13 @@ typedef struct ct_params {
 
 /* Fill *p with the defaults above (k_max = 0, gap_every = 0). */
 void ct_params_default(ct_params *p);
+
+/* Objective of (C_h) at u [n][n] (device), in the problem's units (§3.2):
+ * out[0] = 1/2 sum_{D\D0} (R_h u - u0)^2, out[1] = lambda ||nabla_h u||_1,
+ * out[2] = max_{D0} (C - R_h u)_+ (the constraint violation).  FP64 sums.
+ * Uses the plan's scratch; synchronizes s. */
+int ct_objective(const ct_plan *p, const ct_problem *prob, const float *u, double out[3],
+                 ct_stream s);
 
 typedef struct ct_solver ct_solver;
 

@@ -234,7 +234,7 @@ def power_norm(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -
 
 
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-            start_norm, start_precond, n, nonneg=False):
+            start_norm, start_precond, n, nonneg=False, method="pdrqs1"):
     p = _lib.CtParams()
     _L.ct_params_default(ctypes.byref(p))
     p.sigma, p.tau, p.eps = sigma, tau, eps
@@ -242,8 +242,11 @@ def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, v
     p.c_safety = c_safety
     p.beta = beta if beta is not None else 0.0
     p.k_max, p.gap_every, p.power_iters = k_max, gap_every, power_iters
+    if method not in _lib.METHODS:
+        raise ValueError(f"method must be one of {sorted(_lib.METHODS)}")
     p.flags = ((_lib.CT_FLAG_VALIDATE if validate else 0)
-               | (_lib.CT_FLAG_NONNEG if nonneg else 0))
+               | (_lib.CT_FLAG_NONNEG if nonneg else 0)
+               | (_lib.METHODS[method] << _lib.CT_METHOD_SHIFT))
     p.start_norm = _dev(start_norm, (n, n), "start_norm") if start_norm is not None else None
     p.start_precond = (_dev(start_precond, (n, n), "start_precond")
                        if start_precond is not None else None)
@@ -271,12 +274,12 @@ class Solver:
                  power_iters: int = 30, validate: bool = False,
                  start_norm: Optional[torch.Tensor] = None,
                  start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0,
-                 nonneg: bool = False):
+                 nonneg: bool = False, method: str = "pdrqs1"):
         self.plan = plan
         self._keep = (sino, mask_bits, bound, start_norm, start_precond)
         prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n, nonneg)
+                      start_norm, start_precond, plan.n, nonneg, method)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
                                    ctypes.byref(h)), "ct_solver_create")
@@ -450,17 +453,27 @@ def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma
     return us, report
 
 
+def objective(plan: Plan, sino: torch.Tensor, lam: float, u: torch.Tensor, mask_bits=None,
+              bound=None, bound_scalar: float = 0.0) -> np.ndarray:
+    """(1/2 fit off D0, lambda TV, constraint violation) of (C_h) at u, FP64."""
+    prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
+    o = (ctypes.c_double * 3)()
+    _check(_L.ct_objective(plan.handle, ctypes.byref(prob), _dev(u, (plan.n, plan.n), "u"), o,
+                           _stream()), "ct_objective")
+    return np.array(list(o), dtype=np.float64)
+
+
 def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, bound=None, *,
                 k_max: int = 100, gap_every: int = 0, sigma: float = 1.0,
                 tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3, c: Optional[float] = None,
                 c_safety: float = 1.1, beta: Optional[float] = None, power_iters: int = 30,
                 validate: bool = False, start_norm=None, start_precond=None,
-                bound_scalar: float = 0.0, nonneg: bool = False):
-    """One-shot PDRQS1 solve (nonneg: with u >= 0, §4.5); returns (u, report
-    (records x 6) or None)."""
+                bound_scalar: float = 0.0, nonneg: bool = False, method: str = "pdrqs1"):
+    """One-shot solve (PDRQS1 by default; nonneg: with u >= 0, §4.5); returns
+    (u, report (records x 6) or None)."""
     prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
     prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-                  start_norm, start_precond, plan.n, nonneg)
+                  start_norm, start_precond, plan.n, nonneg, method)
     u = torch.empty((plan.n, plan.n), device=sino.device, dtype=torch.float32)
     nrec = k_max // gap_every if gap_every > 0 else 0
     rep = (ctypes.c_double * max(1, 6 * nrec))()

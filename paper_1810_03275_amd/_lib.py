@@ -15,6 +15,8 @@ ERRORS = {-1: "CT_E_INVALID", -2: "CT_E_UNSUPPORTED", -3: "CT_E_DEVICE",
           -4: "CT_E_NONFINITE", -5: "CT_E_DIVERGED", -6: "CT_E_STATE"}
 CT_FLAG_VALIDATE = 1
 CT_FLAG_NONNEG = 2
+CT_METHOD_SHIFT = 4
+METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3}
 
 
 class CtGeom(ctypes.Structure):
@@ -60,6 +62,8 @@ SIGNATURES = {
     "ct_solver_destroy": (c_int32, [c_void_p]),
     "ct_solver_layout": (c_int32, [c_void_p, POINTER(c_int32)]),
     "ct_solver_info": (c_int32, [c_void_p, POINTER(c_double)]),
+    "ct_objective": (c_int32, [c_void_p, POINTER(CtProblem), c_void_p, POINTER(c_double),
+                               c_void_p]),
     "ct_plan_check": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(ctypes.c_int64)]),
     "ct_pd_step": (c_int32, [c_void_p, c_int32, c_void_p]),
     "ct_pd_step_timed": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),

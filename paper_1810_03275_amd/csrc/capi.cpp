@@ -159,6 +159,9 @@ struct ct_solver {
   float2 *spec = nullptr;     // nb spectra of the preconditioner FFT
   float *bp_part = nullptr;   // nb * bp_S partial backprojections
   float *ubar = nullptr;      // bar u of the u >= 0 variant (nb images) or NULL
+  int method = 0;             // CT_METHOD_*
+  float *ucp = nullptr;       // Algorithm CP: the extrapolated iterate (nb images)
+  double rich_m = 0;          // Richardson: M = rich_m id
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -177,7 +180,7 @@ struct ct_solver {
 static void solver_free(ct_solver *sv) {
   if (!sv) return;
   float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
-                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar};
+                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar, sv->ucp};
   for (float *b : bufs) (void)hipFree(b);
   (void)hipFree(sv->mask);
   (void)hipFree(sv->spec);
@@ -264,6 +267,30 @@ int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps) {
   }
   CT_TRY(check_geom(g, angles));
   return check_plan(g, angles, steps);
+}
+
+int ct_objective(const ct_plan *pc, const ct_problem *prob, const float *u, double out[3],
+                 ct_stream s) {
+  clear_error();
+  if (!pc || !prob || !prob->sino || !u || !out) {
+    set_error("ct_objective: null argument");
+    return CT_E_INVALID;
+  }
+  ct_plan *p = const_cast<ct_plan *>(pc);
+  CT_TRY(plan_scratch(p));
+  hipStream_t st = S(s);
+  CT_TRY(launch_radon_fwd(p, u, p->d_scratch_sino, st));
+  double *d = p->d_red + reduction_partials_needed();
+  CT_TRY(launch_objective(p->g.n_angles, p->g.n_bins, p->d_scratch_sino, prob->sino, prob->bound,
+                          prob->bound_scalar, prob->mask, p->g.n, (float)(1.0 / p->g.h), u,
+                          p->d_red, reduction_partials_needed(), d, st));
+  double h[3];
+  CT_TRY_HIP(hipMemcpyAsync(h, d, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  out[0] = h[0];
+  out[1] = prob->lambda * h[2];
+  out[2] = h[1];
+  return CT_OK;
 }
 
 int ct_plan_destroy(ct_plan *p) {
@@ -454,6 +481,10 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   CT_TRY_HIP(hipMemsetAsync(sv->vb1, 0, sizeof(float) * NM, s));
   CT_TRY_HIP(hipMemsetAsync(sv->s1, 0, sizeof(float) * NM, s));
   if (sv->ubar) CT_TRY_HIP(hipMemsetAsync(sv->ubar, 0, sizeof(float) * nn, s));
+  if (sv->ucp) CT_TRY_HIP(hipMemsetAsync(sv->ucp, 0, sizeof(float) * nn, s));
+  // PDRQS2 caches the residual b - A u, which is b at u = 0
+  if (sv->method == CT_METHOD_PDRQS2)
+    CT_TRY_HIP(hipMemcpyAsync(sv->s1, sv->target, sizeof(float) * NM, hipMemcpyDeviceToDevice, s));
   sv->iters = 0;
   sv->have_dual = false;
   return CT_OK;
@@ -462,20 +493,62 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
 // One PDRQS1 iteration (§4.4) of all nb problems from the cached
 // s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u; mode 2 keeps y1, w and
 // A u for the record.  With ev (5 events) the phase boundaries are recorded.
+// Algorithm CP (§3.4) on the normalized problem: dual steps at the
+// extrapolated iterate ucp, then the primal step with its extrapolation.
+// Steps sigma = tau = 0.99 / sqrt(1 + 8/h^2) (sigma tau ||K||^2 < 1 with
+// ||A|| = 1 after the normalization and ||nabla_h||^2 < 8/h^2).
+static int cp_iter(ct_solver *sv, hipStream_t st) {
+  ct_plan *p = sv->plan;
+  const double h = p->g.h;
+  const float step = (float)(0.99 / std::sqrt(1.0 + 8.0 / (h * h)));
+  const int nb = sv->nb;
+  const SinoEpi ep{(float)(1.0 / sv->beta), step, sv->target, sv->mask, sv->vb1, nullptr,
+                   nullptr, nullptr, 4};
+  CT_TRY(launch_radon_fwd(p, sv->ucp, nullptr, st, &ep, nb));
+  CT_TRY(launch_tv_update(sv->n, (float)(1.0 / h), sv->ucp, step, (float)sv->lam_t, sv->vb2,
+                          nullptr, nullptr, 4, st, nb));
+  CT_TRY(launch_radon_adj(p, sv->vb1, sv->vb2, (float)(-step / sv->beta), step, sv->u_next, st,
+                          nb, sv->bp_part, sv->bp_S, sv->u, nullptr, sv->ucp));
+  std::swap(sv->u, sv->u_next);
+  sv->iters += 1;
+  return CT_OK;
+}
+
 static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr,
                        float *q1out = nullptr, float *q2out = nullptr) {
+  if (sv->method == CT_METHOD_CP) return cp_iter(sv, st);
   ct_plan *p = sv->plan;
   const float sig = (float)sv->sigma, tau = (float)sv->tau;
   const float inv_h = (float)(1.0 / p->g.h);
   const int nb = sv->nb;
+  if (sv->method == CT_METHOD_PDRQS2) {
+    // §4.2: u_tmp = sigma A^*(b - A u) + sigma tau div(vb2 + sigma tau nabla u)
+    CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(sv->sigma / sv->beta),
+                            (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part,
+                            sv->bp_S));
+    CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
+                             sv->spec));
+    const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, nullptr, nullptr, sv->s1,
+                     nullptr, nullptr, 5};
+    CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
+    CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
+                            sv->vb2, sv->s2, sv->w, mode == 2 ? 2 : 0, st, nb));
+    std::swap(sv->u, sv->u_next);
+    sv->iters += 1;
+    return CT_OK;
+  }
   if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
   // u_tmp (u >= 0 variant: plus bar u - u)
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
                           (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S,
                           sv->ubar, sv->ubar ? sv->u : nullptr));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
-  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
-                           sv->spec));
+  if (sv->method == CT_METHOD_RICHARDSON)
+    CT_TRY(launch_axpy((int64_t)sv->n * sv->n * nb, sv->u, (float)(1.0 / sv->rich_m), sv->utmp,
+                       sv->u_next, st));
+  else
+    CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
+                             sv->spec));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
   // R_h u_new with the sinogram-side update fused into its output stage
   SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
@@ -537,6 +610,7 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
+  if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
   CT_TRY(solver_set_slices(sv, p->bp_slices));
   for (int b = 0; b < nb; ++b) {
     uint32_t *mb = sv->mask + (size_t)b * N * MW;
@@ -627,8 +701,12 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
     return CT_E_INVALID;
   }
   sv->pc.c = sv->c;
+  sv->rich_m = 1.1 * (sv->sigma * sv->sigma +
+                      8.0 * (sv->sigma * sv->tau) * (sv->sigma * sv->tau) / (p->g.h * p->g.h));
   {
-    auto m = multiplier_table(n, sv->sigma, sv->tau, sv->c, sv->eps, false, sv->ubar != nullptr);
+    // PDRQS2 (§4.3.1 with Q = A^* A): rho / (sigma c + (sigma tau)^2 lambda_Delta rho)
+    const double csig = sv->method == CT_METHOD_PDRQS2 ? sv->c / sv->sigma : sv->c;
+    auto m = multiplier_table(n, sv->sigma, sv->tau, csig, sv->eps, false, sv->ubar != nullptr);
     CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, m.data(), sizeof(float) * m.size(),
                               hipMemcpyHostToDevice, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
@@ -743,10 +821,27 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     set_error("ct_solver_create: n must be even, 2^a 3^b and <= 4096");
     return CT_E_UNSUPPORTED;
   }
+  const int method = (int)((prm->flags >> CT_METHOD_SHIFT) & 15u);
+  if (method > CT_METHOD_PDRQS2) {
+    set_error("ct_solver_create: unknown method");
+    return CT_E_INVALID;
+  }
+  if (method != CT_METHOD_PDRQS1 && method != CT_METHOD_RICHARDSON &&
+      (prm->flags & CT_FLAG_NONNEG)) {
+    set_error("ct_solver_create: u >= 0 is available for PDRQS1 only");
+    return CT_E_UNSUPPORTED;
+  }
+  if (method == CT_METHOD_PDRQS2)
+    for (int b = 0; b < nb; ++b)
+      if (probs[b].mask) {
+        set_error("ct_solver_create: PDRQS2 solves the unconstrained problem (no D0)");
+        return CT_E_UNSUPPORTED;
+      }
   ct_solver *sv = new (std::nothrow) ct_solver();
   if (!sv) return CT_E_DEVICE;
   sv->plan = const_cast<ct_plan *>(p);
   sv->nb = nb;
+  sv->method = method;
   sv->n = p->g.n;
   sv->N = p->g.n_angles;
   sv->M = p->g.n_bins;
@@ -948,9 +1043,15 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
   CT_TRY_HIP(hipMemcpyAsync(sv->u, u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
   CT_TRY_HIP(hipMemcpyAsync(sv->vb1, vb1, sizeof(float) * NM, hipMemcpyDeviceToDevice, st));
   CT_TRY_HIP(hipMemcpyAsync(sv->vb2, vb2, sizeof(float) * nn * 2, hipMemcpyDeviceToDevice, st));
-  // caches: s1 = vb1 + sigma A u, s2 = vb2 + sigma tau nabla u
+  if (sv->method == CT_METHOD_CP) {
+    // restart of Algorithm CP: the extrapolated iterate is u itself
+    CT_TRY_HIP(hipMemcpyAsync(sv->ucp, u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
+    sv->have_dual = false;
+    return CT_OK;
+  }
+  // caches: s1 = vb1 + sigma A u (PDRQS2: b - A u), s2 = vb2 + sigma tau nabla u
   const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
-                   sv->s1, nullptr, nullptr, 1};
+                   sv->s1, nullptr, nullptr, sv->method == CT_METHOD_PDRQS2 ? 5 : 1};
   CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep, sv->nb));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
                           (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st,
@@ -968,6 +1069,10 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
   if (!sv->have_dual) {
     set_error("ct_gap: no iteration since creation or import");
     return CT_E_STATE;
+  }
+  if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2) {
+    set_error("ct_gap: the record is defined for PDRQS1; use ct_objective");
+    return CT_E_UNSUPPORTED;
   }
   for (int b = 0; b < sv->nb; ++b) CT_TRY(solver_gap(sv, b, out + 6 * b, S(s)));
   return CT_OK;
@@ -1210,8 +1315,8 @@ int ct_unrolled_forward(ct_solver *sv, int32_t K, int32_t every, ct_tape **out, 
     set_error("ct_unrolled_forward: need a solver, K >= 1 and every >= 1");
     return CT_E_INVALID;
   }
-  if (sv->ubar) {
-    set_error("ct_unrolled_forward: the u >= 0 variant has no reverse sweep");
+  if (sv->ubar || sv->method != CT_METHOD_PDRQS1) {
+    set_error("ct_unrolled_forward: the reverse sweep is for PDRQS1 without u >= 0");
     return CT_E_UNSUPPORTED;
   }
   *out = nullptr;

@@ -150,10 +150,21 @@ namespace ctpd {
 // nb problems of one geometry stored contiguously; part: nb * bp_slices
 // partial images (NULL: the plan's own buffer, nb = 1 only).
 // S: angle slices (0: the plan's choice).
-// base (optional, nb images) is added to the result, base2 (optional) subtracted.
+// base (optional, nb images) is added to the result, base2 (optional)
+// subtracted; out2 (optional, needs base) receives 2 out - base.
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
-                     int S = 0, const float *base = nullptr, const float *base2 = nullptr);
+                     int S = 0, const float *base = nullptr, const float *base2 = nullptr,
+                     float *out2 = nullptr);
+// out = base + a x over count elements (nb problems contiguous).
+int launch_axpy(int64_t count, const float *base, float a, const float *x, float *out,
+                hipStream_t s);
+// Objective terms of (C_h) in the problem's units, FP64: out[0] = 1/2 sum off
+// D0 of (r - u0)^2, out[1] = max on D0 of (C - r)_+ (r = R_h u, raw), out[2] =
+// sum |nabla_h u|.
+int launch_objective(int N, int M, const float *r, const float *u0, const float *bound,
+                     float bound_scalar, const uint32_t *mask, int n, float inv_h,
+                     const float *u, double *partials, int cap, double *out, hipStream_t s);
 // Optional epilogue of the forward projector: the PDRQS1 sinogram-side update
 // applied to r = R(u)/beta per bin (see k_sino_update), instead of storing R(u).
 struct SinoEpi {
@@ -165,7 +176,8 @@ struct SinoEpi {
   float *s1;
   float *y1;
   float *r;
-  int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep
+  int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep,
+                 // 4 Algorithm CP dual step, 5 PDRQS2 residual
   float *q1 = nullptr;  // optional: the resolvent input 2 v1 - vb1 (modes 0, 2)
 };
 // out = R(u) (raw), or the epilogue when epi != nullptr

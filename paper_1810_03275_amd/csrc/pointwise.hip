@@ -80,6 +80,14 @@ __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, flo
     s2[o + nn] = fmaf(st, g2, b2);
     return;
   }
+  if (mode == 4) {
+    // Algorithm CP dual step: w <- projection of w + st nabla u (u extrapolated)
+    float w1, w2;
+    ball_project(fmaf(st, g1, b1), fmaf(st, g2, b2), radius, w1, w2);
+    vb2[o] = w1;
+    vb2[o + nn] = w2;
+    return;
+  }
   const float v1 = fmaf(st, g1, b1), v2 = fmaf(st, g2, b2);
   float w1, w2;
   ball_project(2.f * v1 - b1, 2.f * v2 - b2, radius, w1, w2);
@@ -323,6 +331,75 @@ int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float rad
   grid.z = nb;
   hipLaunchKernelGGL(k_tv_update, grid, dim3(256), 0, s, n, inv_h, u, sigtau, radius, vb2, s2,
                      wout, mode, q2out, ubar);
+  CT_TRY_HIP(hipGetLastError());
+  return CT_OK;
+}
+
+__global__ void k_axpy(int64_t count, const float *__restrict__ base, float a,
+                       const float *__restrict__ x, float *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = fmaf(a, x[t], base[t]);
+}
+
+// Objective terms of (C_h): sinogram part (fit off D0, violation on D0) and
+// the total variation, in FP64 (one pass each, fixed-order reductions).
+__global__ void k_obj_sino(int N, int M, const float *__restrict__ r, const float *__restrict__ u0,
+                           const float *__restrict__ bound, float bscalar,
+                           const uint32_t *__restrict__ mask, double *partials) {
+  double v[2] = {0.0, 0.0};
+  const int MW = (M + 31) >> 5;
+  const int64_t count = (int64_t)N * M;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(t / M), k = (int)(t - (int64_t)l * M);
+    const double rr = r[t];
+    if (mask_bit(mask, MW, l, k)) {
+      const double cb = bound ? (double)bound[t] : (double)bscalar;
+      v[1] = fmax(v[1], cb - rr);
+    } else {
+      const double d = rr - u0[t];
+      v[0] = fma(0.5 * d, d, v[0]);
+    }
+  }
+  block_reduce_store<2>(v, 2u, partials + (size_t)blockIdx.x * 2);
+}
+
+__global__ void k_obj_tv(int n, float inv_h, const float *__restrict__ u, double *partials) {
+  double v[1] = {0.0};
+  const int64_t count = (int64_t)n * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / n), i = (int)(t - (int64_t)j * n);
+    const double c = u[t];
+    const double g1 = (i < n - 1) ? (u[t + 1] - c) * inv_h : 0.0;
+    const double g2 = (j < n - 1) ? (u[t + n] - c) * inv_h : 0.0;
+    v[0] += sqrt(g1 * g1 + g2 * g2);
+  }
+  block_reduce_store<1>(v, 0u, partials + blockIdx.x);
+}
+
+int launch_axpy(int64_t count, const float *base, float a, const float *x, float *out,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, base,
+                     a, x, out);
+  CT_TRY_HIP(hipGetLastError());
+  return CT_OK;
+}
+
+int launch_objective(int N, int M, const float *r, const float *u0, const float *bound,
+                     float bscalar, const uint32_t *mask, int n, float inv_h, const float *u,
+                     double *partials, int cap, double *out, hipStream_t s) {
+  if (cap < kRedBlocks * 2) {
+    set_error("objective: reduction buffer too small");
+    return CT_E_INVALID;
+  }
+  hipLaunchKernelGGL(k_obj_sino, dim3(kRedBlocks), dim3(kRedThreads), 0, s, N, M, r, u0, bound,
+                     bscalar, mask, partials);
+  hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 2u,
+                     0u, out);
+  hipLaunchKernelGGL(k_obj_tv, dim3(kRedBlocks), dim3(kRedThreads), 0, s, n, inv_h, u, partials);
+  hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kRedThreads), 0, s, partials, kRedBlocks, 0u,
+                     0u, out + 2);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ ang,
     int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
     float inv_h, const float *__restrict__ base, const float *__restrict__ base2,
-    float *__restrict__ out) {
+    float *__restrict__ out, float *__restrict__ out2) {
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   if (pfield != nullptr) pfield += (size_t)bz * 2 * nn;
   if (base != nullptr) base += (size_t)bz * nn;
   if (base2 != nullptr) base2 += (size_t)bz * nn;
+  if (out2 != nullptr) out2 += (size_t)bz * nn;
   out += (size_t)blockIdx.z * nn;  // own image (S == 1) or own partial image
   const int a_begin = sl * slice_len;
   const int a_end = min(N, a_begin + slice_len);
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     if (base != nullptr) res += base[o];
     if (base2 != nullptr) res -= base2[o];
     out[o] = res;
+    if (out2 != nullptr) out2[o] = 2.f * res - base[o];
   }
 }
 
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
 __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
                              const float *__restrict__ pfield, float c1, float c2, float inv_h,
                              const float *__restrict__ base, const float *__restrict__ base2,
-                             float *__restrict__ out) {
+                             float *__restrict__ out, float *__restrict__ out2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= n) return;
@@ -197,6 +199,7 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
   if (pfield != nullptr) pfield += (size_t)blockIdx.z * 2 * nn;
   if (base != nullptr) base += (size_t)blockIdx.z * nn;
   if (base2 != nullptr) base2 += (size_t)blockIdx.z * nn;
+  if (out2 != nullptr) out2 += (size_t)blockIdx.z * nn;
   out += (size_t)blockIdx.z * nn;
   float r = part[o];
   for (int s = 1; s < S; ++s) r += part[s * nn + o];
@@ -211,11 +214,12 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
   if (base != nullptr) res += base[o];
   if (base2 != nullptr) res -= base2[o];
   out[o] = res;
+  if (out2 != nullptr) out2[o] = 2.f * res - base[o];
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb, float *part, int S,
-                     const float *base, const float *base2) {
+                     const float *base, const float *base2, float *out2) {
   const int n = p->g.n;
   if (S <= 0) S = p->bp_slices;
   const int slice_len = (p->g.n_angles + S - 1) / S;
@@ -229,11 +233,11 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   float *dst = (S == 1) ? out : part;
   hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
                      p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
-                     base, base2, dst);
+                     base, base2, dst, S == 1 ? out2 : nullptr);
   CT_TRY_HIP(hipGetLastError());
   if (S > 1) {
     hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n, nb), dim3(256), 0, s, part, S, n,
-                       pfield, c1, c2, (float)(1.0 / p->g.h), base, base2, out);
+                       pfield, c1, c2, (float)(1.0 / p->g.h), base, base2, out, out2);
     CT_TRY_HIP(hipGetLastError());
   }
   return CT_OK;
@@ -265,15 +269,13 @@ __device__ inline void fp_batch_offsets(const float *__restrict__ &u, float *__r
   const size_t NM = (size_t)N * M;
   u += b * n * n;
   if (sino != nullptr) sino += b * NM;
-  if (ep.vb1 != nullptr) {
-    ep.target += b * NM;
-    ep.vb1 += b * NM;
-    ep.s1 += b * NM;
-    if (ep.y1 != nullptr) ep.y1 += b * NM;
-    if (ep.r != nullptr) ep.r += b * NM;
-    if (ep.q1 != nullptr) ep.q1 += b * NM;
-    if (ep.mask != nullptr) ep.mask += b * (size_t)N * ((M + 31) >> 5);
-  }
+  if (ep.target != nullptr) ep.target += b * NM;
+  if (ep.vb1 != nullptr) ep.vb1 += b * NM;
+  if (ep.s1 != nullptr) ep.s1 += b * NM;
+  if (ep.y1 != nullptr) ep.y1 += b * NM;
+  if (ep.r != nullptr) ep.r += b * NM;
+  if (ep.q1 != nullptr) ep.q1 += b * NM;
+  if (ep.mask != nullptr) ep.mask += b * (size_t)N * ((M + 31) >> 5);
 }
 
 // Output of one projected bin: either the raw value R(u)[l][k], or the PDRQS1
@@ -283,12 +285,29 @@ __device__ inline void fp_batch_offsets(const float *__restrict__ &u, float *__r
 __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, int M, int l, int k,
                                  float raw) {
   const size_t o = (size_t)l * M + k;
-  if (ep.vb1 == nullptr) {
+  // every epilogue mode writes vb1 or s1; with neither the raw value is stored
+  if (ep.vb1 == nullptr && ep.s1 == nullptr) {
     sino[o] = raw;
     return;
   }
   const float r = raw * ep.inv_beta;
+  if (ep.mode == 5) {
+    // PDRQS2: the data residual b - A u (D0 empty)
+    ep.s1[o] = ep.target[o] - r;
+    return;
+  }
   const float vb = ep.vb1[o];
+  if (ep.mode == 4) {
+    // Algorithm CP: v <- resolvent of the data term's conjugate, step sigma,
+    // at v + sigma A u (here u is the extrapolated iterate)
+    const int MW4 = (M + 31) >> 5;
+    const bool d0 =
+        ep.mask != nullptr && ((ep.mask[(size_t)l * MW4 + (k >> 5)] >> (k & 31)) & 1u);
+    const float qv = fmaf(ep.sigma, r, vb);
+    const float tg = ep.target[o];
+    ep.vb1[o] = d0 ? fminf(qv - ep.sigma * tg, 0.f) : (qv - ep.sigma * tg) / (1.f + ep.sigma);
+    return;
+  }
   if (ep.mode == 1) {
     ep.s1[o] = fmaf(ep.sigma, r, vb);
     return;

@@ -1,0 +1,134 @@
+"""The comparison methods on the GPU against the FP64 oracle: PDRQS1 with the
+Richardson preconditioner (§4.3), Algorithm CP (§3.4), PDRQS2 (§4.2, §4.3.1),
+and the objective of (C_h)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cp, pdrq, pdrq2
+
+from oracle_inputs import build, f32
+
+pytestmark = pytest.mark.gpu
+
+ct = pytest.importorskip("paper_1810_03275_amd")
+
+DEV = torch.device("cuda")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _metal(n=64, N=90, M=96):
+    w = synth.workload("C2", n=n, n_angles=N, n_bins=M)
+    g, u0, mask, bound = build(w)
+    return w, g, u0, mask, bound
+
+
+def _free(n=64, N=90, M=96):
+    w = synth.workload("C1", n=n, n_angles=N, n_bins=M)
+    g, u0, mask, bound = build(w)
+    assert not mask.any()
+    return w, g, u0, mask, bound
+
+
+def test_objective_matches_oracle():
+    print("objective", flush=True)
+    w, g, u0, mask, bound = _metal()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    u = f32(np.random.default_rng(5).uniform(-0.5, 1.0, (g.n, g.n)))
+    got = ct.objective(plan, gpu(u0), w.alpha, gpu(u), ct.pack_mask(mask), gpu(bound))
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=1.0, c=1.0)
+    fit, reg, viol = pdrq2.objective(s, u)
+    assert got[0] == pytest.approx(fit, rel=1e-5)
+    assert got[1] == pytest.approx(reg, rel=1e-5)
+    assert got[2] == pytest.approx(viol, rel=1e-4, abs=1e-5 * max(1.0, viol))
+
+
+def test_richardson_matches_oracle():
+    print("richardson", flush=True)
+    w, g, u0, mask, bound = _metal()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    mb = ct.pack_mask(mask)
+    probe = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound))
+    inf = probe.info()
+    u, _ = ct.reconstruct(plan, gpu(u0), w.alpha, mb, gpu(bound), k_max=60, beta=inf["beta"],
+                          c=inf["c"], method="richardson")
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    sr = pdrq2.richardson_setup(s)
+    st = pdrq.zero_state(sr)
+    for _ in range(60):
+        st = pdrq.step(sr, st)
+    assert rel(host(u), st.u) <= 1e-4
+
+
+def test_cp_matches_oracle():
+    print("cp", flush=True)
+    w, g, u0, mask, bound = _metal()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    mb = ct.pack_mask(mask)
+    probe = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound))
+    inf = probe.info()
+    u, _ = ct.reconstruct(plan, gpu(u0), w.alpha, mb, gpu(bound), k_max=100, beta=inf["beta"],
+                          c=inf["c"], method="cp")
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    step = 0.99 / 3.0
+    uo, _, _ = cp.run(s.A, s.At, s.b, s.cb, mask, s.lam_t, g.n, 100, step, step)
+    assert rel(host(u), uo) <= 1e-4
+
+
+def test_pdrqs2_matches_oracle():
+    print("pdrqs2", flush=True)
+    w, g, u0, mask, bound = _free()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    probe = ct.Solver(plan, gpu(u0), w.alpha)
+    inf = probe.info()
+    sv = ct.Solver(plan, gpu(u0), w.alpha, beta=inf["beta"], c=inf["c"], method="pdrqs2")
+    sv.step(100)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    st = pdrq2.zero_state2(s)
+    for _ in range(100):
+        st = pdrq2.step2(s, st)
+    assert rel(host(sv.export()[0]), st.u) <= 1e-4
+    # one step from an imported random state
+    rng = np.random.default_rng(8)
+    u = f32(rng.uniform(0, 1, (g.n, g.n)))
+    vb = f32(s.lam_t / s.params.tau * rng.standard_normal((2, g.n, g.n)))
+    sv.import_state(gpu(u), torch.zeros((g.n_angles, g.n_bins), device=DEV), gpu(vb))
+    sv.step(1)
+    nxt = pdrq2.step2(s, pdrq2.State2(u, vb))
+    gu, _, gvb = (host(t) for t in sv.export())
+    assert rel(gu, nxt.u) <= 1e-5
+    assert rel(gvb, nxt.vb) <= 1e-5
+
+
+def test_method_errors():
+    plan = ct.Plan(32, 45, 48)
+    z = torch.zeros((45, 48), device=DEV)
+    m = ct.pack_mask(np.ones((45, 48), dtype=bool))
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, m, method="pdrqs2")     # PDRQS2 has no D0
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, method="cp", nonneg=True)
+    with pytest.raises(ValueError):
+        ct.Solver(plan, z, 0.01, method="admm")
+    sv = ct.Solver(plan, z, 0.01, method="cp")
+    sv.step(2)
+    with pytest.raises(ct.CtpdError):
+        sv.gap()
