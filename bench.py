@@ -177,6 +177,66 @@ def large_run(ct, torch, iters: int):
             "solve_1000_iterations_s": round(1000 * dt / iters + setup_s, 2)}
 
 
+def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 8192):
+    """The preconditioning comparison of the thesis' results (objective value
+    relative to the smallest attained, per iteration): PDRQS1 with the
+    inverse-norm preconditioner, PDRQS1 with Richardson's M = m id, Algorithm
+    CP and PDRQS2, on an unconstrained random-ellipse phantom (n^2, N = 1.4 n,
+    M = 1.5 n, 1 % noise).  Reports the iterations and seconds each method needs
+    to bring (P - P*)/P* below 1, 1e-1 and 1e-2, with P* the smallest
+    objective any method reached (the thesis' measure; P* being an attained
+    value, errors near the end of the fastest method's run are not
+    meaningful, hence no smaller tolerances)."""
+    import synth
+    w = synth.workload("C1", n=n, n_angles=int(round(1.4 * n)), n_bins=int(1.5 * n),
+                       iters=kmax)
+    plan, u0, _, _, x0, x1 = build_inputs(ct, torch, w)
+    probe = ct.Solver(plan, u0, lam, start_norm=x0, start_precond=x1)
+    inf = probe.info()
+    marks = sorted(set([int(round(2 ** (i / 2))) for i in range(0, 60)
+                        if 2 ** (i / 2) <= kmax] + [kmax]))
+    curves, rates = {}, {}
+    for method in ("pdrqs1", "richardson", "cp", "pdrqs2"):
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], method=method)
+        done, vals = 0, []
+        sv.step(10)   # warm-up (graph capture), then restart from zero
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], method=method)
+        torch.cuda.synchronize()
+        t_run = 0.0
+        for m in marks:
+            t0 = time.perf_counter()
+            sv.step(m - done)
+            torch.cuda.synchronize()
+            t_run += time.perf_counter() - t0
+            done = m
+            o = ct.objective(plan, u0, lam, sv.export()[0])
+            vals.append(float(o[0] + o[1]))
+        curves[method] = vals
+        rates[method] = t_run / kmax
+    best = min(min(v) for v in curves.values())
+    out = {"workload": f"{n}x{n}, {w.n_angles} angles, {w.n_bins} bins, random-ellipse phantom, "
+                       f"no metal, 1% noise, lambda={lam}",
+           "P_star": best, "iterations": marks, "ms_per_iteration": {}, "to_tolerance": {}}
+    for method, vals in curves.items():
+        relerr = [(v - best) / best for v in vals]
+        out["ms_per_iteration"][method] = round(1e3 * rates[method], 4)
+        reach = {}
+        for tol in (1.0, 1e-1, 1e-2):
+            k = next((m for m, e in zip(marks, relerr) if e <= tol), None)
+            reach[f"{tol:g}"] = None if k is None else {
+                "iterations": k, "seconds": round(k * rates[method], 4)}
+        out["to_tolerance"][method] = reach
+        out.setdefault("relative_error", {})[method] = [float(f"{e:.2e}") for e in relerr]
+    return out
+
+
+def precond_comparisons(ct, torch, kmax: int):
+    """The comparison at the workload's weight and at lambda = 0.3 (the weight
+    of the thesis' comparison figure)."""
+    return {f"lambda={lam:g}": precond_comparison(ct, torch, lam=lam, kmax=kmax)
+            for lam in (0.005, 0.3)}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: setup with beta and c given, then PDRQS1 iterations until about
@@ -219,6 +279,8 @@ def main():
                     help="unrolled iterations of the differentiation workload (0: skip)")
     ap.add_argument("--large-iters", type=int, default=50,
                     help="timed iterations at 2048^2 x 2880 x 3072 (0: skip)")
+    ap.add_argument("--comparison-iters", type=int, default=8192,
+                    help="iterations of the preconditioning comparison (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -296,6 +358,9 @@ def main():
         del sv
         torch.cuda.empty_cache()
         out["batched"] = batched_run(ct, torch, args.batched_iters)
+    if args.comparison_iters > 0:
+        torch.cuda.empty_cache()
+        out["preconditioning"] = precond_comparisons(ct, torch, args.comparison_iters)
     if args.large_iters > 0:
         torch.cuda.empty_cache()
         out["large"] = large_run(ct, torch, args.large_iters)
