@@ -19,8 +19,9 @@ import numpy as np
 from . import prox, tv
 
 
-def run(A, At, b, cb, mask, lam_t, n, iters, sigma, tau, h=1.0):
-    """Returns (u, v, w) after `iters` CP iterations; A/At act on (n, n) images."""
+def run(A, At, b, cb, mask, lam_t, n, iters, sigma, tau, h=1.0, resolvent=None):
+    """Returns (u, v, w) after `iters` CP iterations; A/At act on (n, n) images.
+    resolvent(q, step) replaces the standard data-term resolvent (variants)."""
     u = np.zeros((n, n))
     ub = np.zeros((n, n))
     v = np.zeros_like(np.asarray(b, dtype=np.float64))
@@ -29,7 +30,8 @@ def run(A, At, b, cb, mask, lam_t, n, iters, sigma, tau, h=1.0):
         wb = w + tau * tv.grad(ub, h)
         vb = v + tau * A(ub)
         w = prox.tv_project(wb, lam_t)
-        v = prox.prox_sino(vb, tau, b, cb, mask)
+        v = (prox.prox_sino(vb, tau, b, cb, mask) if resolvent is None
+             else resolvent(vb, tau))
         u_new = u + sigma * tv.div(w, h) - sigma * At(v)
         ub = 2.0 * u_new - u
         u = u_new

@@ -67,6 +67,8 @@ class Setup:
     mult: np.ndarray
     fwd: object = None      # R_h (defaults to radon.radon_fwd on the geometry)
     adj: object = None      # R_h^* (defaults to radon.radon_adj)
+    fit: str = "standard"   # data term variant of §3.5 (see sino_resolvent)
+    weight: object = None   # per-bin weights of the weighted fit (default 1)
 
     def A(self, u):
         f = self.fwd or (lambda x: radon.radon_fwd(self.problem.geom, x))
@@ -101,6 +103,26 @@ def setup(problem: Problem, params: Params, start_norm: np.ndarray | None = None
                  np.asarray(problem.u0, dtype=np.float64) / beta,
                  np.asarray(problem.bound, dtype=np.float64) / beta,
                  problem.lam / beta ** 2, mult, fwd, adj)
+
+
+def sino_resolvent(s: Setup, q: np.ndarray, step: float) -> np.ndarray:
+    """Resolvent of the data term's conjugate at q, for the variants of §3.5:
+    standard (fit off D0, C~ <= A u on D0), weighted (weights on the fit),
+    ignore (no term on D0), everywhere (fit on all bins plus C~ <= A u on D0),
+    hard (A u = b off D0, C~ <= A u on D0)."""
+    mask = s.problem.mask
+    if s.fit == "standard":
+        return prox.prox_sino(q, step, s.b, s.cb, mask)
+    if s.fit == "weighted":
+        w = np.ones_like(s.b) if s.weight is None else np.asarray(s.weight, dtype=np.float64)
+        return prox.prox_sino_weighted(q, step, s.b, w, s.cb, mask)
+    if s.fit == "ignore":
+        return prox.prox_sino_ignore(q, step, s.b, mask)
+    if s.fit == "everywhere":
+        return prox.prox_sino_fit_everywhere(q, step, s.b, s.cb, mask)
+    if s.fit == "hard":
+        return prox.prox_sino_hard(q, step, s.b, s.cb, mask)
+    raise ValueError(f"unknown data term variant {s.fit!r}")
 
 
 @dataclasses.dataclass
@@ -142,7 +164,7 @@ def step(s: Setup, st: State, return_dual: bool = False):
     g_new = tv.grad(u_new, h)
     v1 = st.vb1 + sig * r_new
     v2 = st.vb2 + sig * tau * g_new
-    y1 = prox.prox_sino(2.0 * v1 - st.vb1, sig, s.b, s.cb, s.problem.mask)
+    y1 = sino_resolvent(s, 2.0 * v1 - st.vb1, sig)
     vb1 = st.vb1 + y1 - v1
     w = prox.tv_project(2.0 * v2 - st.vb2, s.lam_t / tau)
     vb2 = st.vb2 + w - v2
@@ -204,7 +226,7 @@ def step_nonneg(s: Setup, st: StateNonneg) -> StateNonneg:
     g_new = tv.grad(u_new, h)
     v1 = st.vb1 + sig * r_new
     v2 = st.vb2 + sig * tau * g_new
-    y1 = prox.prox_sino(2.0 * v1 - st.vb1, sig, s.b, s.cb, s.problem.mask)
+    y1 = sino_resolvent(s, 2.0 * v1 - st.vb1, sig)
     vb1 = st.vb1 + y1 - v1
     w = prox.tv_project(2.0 * v2 - st.vb2, s.lam_t / tau)
     vb2 = st.vb2 + w - v2

@@ -80,3 +80,59 @@ def test_objective_by_hand():
     # pixel and 1 at its left and upper neighbours
     assert reg == pytest.approx(0.7 * (np.sqrt(2.0) + 2.0))
     assert viol == pytest.approx(np.max(2.0 - r[mask]))
+
+
+@pytest.fixture(scope="module")
+def tiny_metal_clean():
+    """8x8, 12 angles, 16 bins, noise-free data (so that the hard constraint
+    A u = b off D0 is feasible), one metal pixel whose trace is D0."""
+    g = geometry.Geometry(8, 12, 16)
+    R = radon.radon_matrix(g)
+    fwd = lambda u: (R @ u.ravel()).reshape(g.n_angles, g.n_bins)
+    adj = lambda v: (R.T @ v.ravel()).reshape(g.n, g.n)
+    rng = np.random.default_rng(4)
+    ut = np.zeros((8, 8))
+    ut[2:6, 3:7] = 1.0
+    metal = np.zeros((8, 8))
+    metal[4, 4] = 1.0
+    mask = fwd(metal) > 0
+    u0 = np.where(mask, fwd(ut + 3.0 * metal), fwd(ut))
+    prob = pdrq.Problem(g, u0, mask, 0.9 * fwd(ut), lam=0.2)
+    s = pdrq.setup(prob, pdrq.Params(), rng.standard_normal((8, 8)), rng.standard_normal((8, 8)),
+                   fwd=fwd, adj=adj)
+    return s
+
+
+@pytest.mark.parametrize("fit", ["weighted", "ignore", "everywhere", "hard"])
+def test_data_term_variants_reach_the_cp_minimizer(tiny_metal_clean, fit):
+    """Each data-term variant of §3.5 in PDRQS1 reaches the minimizer that
+    Algorithm CP reaches with the same resolvent (two different iterations,
+    one answer; the resolvents themselves are pinned against scipy)."""
+    import dataclasses
+    s = dataclasses.replace(tiny_metal_clean, fit=fit)
+    if fit == "weighted":
+        s = dataclasses.replace(s, weight=np.linspace(0.5, 2.0, s.b.size).reshape(s.b.shape))
+    st = pdrq.zero_state(s)
+    for _ in range(15000):
+        st = pdrq.step(s, st)
+    res = lambda q, step: pdrq.sino_resolvent(s, q, step)
+    u_cp, _, _ = cp.run(s.A, s.At, s.b, s.cb, s.problem.mask, s.lam_t, 8, 30000, 0.32, 0.32,
+                        resolvent=res)
+    assert np.max(np.abs(st.u - u_cp)) < 1e-6
+    if fit == "hard":
+        r = s.A(st.u)
+        assert np.max(np.abs((r - s.b)[~s.problem.mask])) < 1e-6
+
+
+def test_variant_identities(tiny_metal_clean):
+    """Weights of 1 are the standard fit; ignoring D0 is the standard fit with
+    an unreachable bound C~ -> -infinity."""
+    import dataclasses
+    s = tiny_metal_clean
+    q = np.random.default_rng(9).standard_normal(s.b.shape)
+    std = pdrq.sino_resolvent(s, q, 0.7)
+    w1 = pdrq.sino_resolvent(dataclasses.replace(s, fit="weighted"), q, 0.7)
+    assert np.array_equal(std, w1)
+    ign = pdrq.sino_resolvent(dataclasses.replace(s, fit="ignore"), q, 0.7)
+    low = pdrq.sino_resolvent(dataclasses.replace(s, cb=np.full_like(s.cb, -1e30)), q, 0.7)
+    assert np.array_equal(ign, low)
