@@ -242,6 +242,25 @@ int ct_solver_info(const ct_solver *sv, double out[4]);
  * out[3] = forward-projector groups. */
 int ct_solver_layout(const ct_solver *sv, int32_t out[4]);
 
+/* Data-term variants of §3.5 for PDRQS1 (and its Richardson form), set before
+ * the first iteration:
+ *  STANDARD    1/2 (A u - b)^2 off D0, C~ <= A u on D0 (default)
+ *  WEIGHTED    1/2 w (A u - b)^2 off D0; aux = w [nb][N][M] (device, w > 0)
+ *  IGNORE      no term on D0 (the bound is not used)
+ *  EVERYWHERE  1/2 (A u - b)^2 on every bin plus C~ <= A u on D0;
+ *              aux = u0 [nb][N][M] (device, unnormalized) including D0
+ *  HARD        A u = b off D0, C~ <= A u on D0
+ * ct_gap and the reverse sweep are defined for STANDARD only.  Errors:
+ * CT_E_STATE after the first iteration, CT_E_UNSUPPORTED for other methods. */
+enum {
+  CT_FIT_STANDARD = 0,
+  CT_FIT_WEIGHTED = 1,
+  CT_FIT_IGNORE = 2,
+  CT_FIT_EVERYWHERE = 3,
+  CT_FIT_HARD = 4
+};
+int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s);
+
 /* Run k iterations of PDRQS1 (§4.4) on the solver's state:
  *   u_tmp = -sigma (A^*(vb1 + sigma A u) - tau div(vb2 + sigma tau nabla u))
  *   u     = u + M^{-1} u_tmp

@@ -290,6 +290,18 @@ class Solver:
         _check(_L.ct_solver_info(self._h, o), "ct_solver_info")
         return {"beta": o[0], "c": o[1], "lam_t": o[2], "iters": int(o[3])}
 
+    def set_fit(self, fit: str, aux: Optional[torch.Tensor] = None) -> None:
+        """Data-term variant (§3.5): standard, weighted (aux = weights),
+        ignore, everywhere (aux = u0 on every bin), hard.  Before the first
+        iteration."""
+        if fit not in _lib.FITS:
+            raise ValueError(f"fit must be one of {sorted(_lib.FITS)}")
+        N, M = self.plan.n_angles, self.plan.n_bins
+        ptr = _dev(aux, self._lead() + (N, M), "aux") if aux is not None else None
+        self._keep_aux = aux
+        _check(_L.ct_solver_set_fit(self._h, _lib.FITS[fit], ptr, _stream()),
+               "ct_solver_set_fit")
+
     def step(self, k: int = 1) -> None:
         _check(_L.ct_pd_step(self._h, k, _stream()), "ct_pd_step")
 

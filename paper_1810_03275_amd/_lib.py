@@ -17,6 +17,7 @@ CT_FLAG_VALIDATE = 1
 CT_FLAG_NONNEG = 2
 CT_METHOD_SHIFT = 4
 METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3}
+FITS = {"standard": 0, "weighted": 1, "ignore": 2, "everywhere": 3, "hard": 4}
 
 
 class CtGeom(ctypes.Structure):
@@ -66,6 +67,7 @@ SIGNATURES = {
                                c_void_p]),
     "ct_plan_check": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(ctypes.c_int64)]),
     "ct_pd_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "ct_solver_set_fit": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "ct_pd_step_timed": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "ct_state_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_state_import": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -162,6 +162,8 @@ struct ct_solver {
   int method = 0;             // CT_METHOD_*
   float *ucp = nullptr;       // Algorithm CP: the extrapolated iterate (nb images)
   double rich_m = 0;          // Richardson: M = rich_m id
+  int fit = 0;                // data-term variant (CT_FIT_*)
+  float *fit_aux = nullptr;   // its per-bin array (nb sinograms) or NULL
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -180,7 +182,8 @@ struct ct_solver {
 static void solver_free(ct_solver *sv) {
   if (!sv) return;
   float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
-                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar, sv->ucp};
+                   sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar, sv->ucp,
+                   sv->fit_aux};
   for (float *b : bufs) (void)hipFree(b);
   (void)hipFree(sv->mask);
   (void)hipFree(sv->spec);
@@ -554,6 +557,8 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
              sv->y1, sv->r, mode};
   ep.q1 = q1out;
+  ep.fit = sv->fit;
+  ep.aux = sv->fit_aux;
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
@@ -938,6 +943,44 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[4]) {
   return CT_OK;
 }
 
+int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s) {
+  clear_error();
+  if (!sv || fit < CT_FIT_STANDARD || fit > CT_FIT_HARD) {
+    set_error("ct_solver_set_fit: invalid argument");
+    return CT_E_INVALID;
+  }
+  if (sv->method != CT_METHOD_PDRQS1 && sv->method != CT_METHOD_RICHARDSON) {
+    set_error("ct_solver_set_fit: the data-term variants are for PDRQS1");
+    return CT_E_UNSUPPORTED;
+  }
+  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1]) {
+    set_error("ct_solver_set_fit: set the data term before the first iteration");
+    return CT_E_STATE;
+  }
+  const bool needs_aux = fit == CT_FIT_WEIGHTED || fit == CT_FIT_EVERYWHERE;
+  if (needs_aux && !aux) {
+    set_error("ct_solver_set_fit: this data term needs its per-bin array");
+    return CT_E_INVALID;
+  }
+  hipStream_t st = S(s);
+  const size_t NM = (size_t)sv->N * sv->M * sv->nb;
+  if (needs_aux) {
+    if (!sv->fit_aux) CT_TRY_HIP(hipMalloc(&sv->fit_aux, sizeof(float) * NM));
+    if (fit == CT_FIT_EVERYWHERE) {
+      // b = u0 / beta on every bin
+      const double beta = sv->beta;
+      CT_TRY_HIP(hipMemcpyAsync(sv->d_out, &beta, sizeof(double), hipMemcpyHostToDevice, st));
+      CT_TRY(launch_scale_by_inv(aux, (int64_t)NM, sv->d_out, sv->fit_aux, st));
+    } else {
+      CT_TRY_HIP(hipMemcpyAsync(sv->fit_aux, aux, sizeof(float) * NM, hipMemcpyDeviceToDevice,
+                                st));
+    }
+    CT_TRY_HIP(hipStreamSynchronize(st));
+  }
+  sv->fit = fit;
+  return CT_OK;
+}
+
 int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
   clear_error();
   if (!sv || k < 0) {
@@ -1070,8 +1113,8 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
     set_error("ct_gap: no iteration since creation or import");
     return CT_E_STATE;
   }
-  if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2) {
-    set_error("ct_gap: the record is defined for PDRQS1; use ct_objective");
+  if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2 || sv->fit != CT_FIT_STANDARD) {
+    set_error("ct_gap: the record is defined for PDRQS1 with the standard data term");
     return CT_E_UNSUPPORTED;
   }
   for (int b = 0; b < sv->nb; ++b) CT_TRY(solver_gap(sv, b, out + 6 * b, S(s)));
@@ -1315,7 +1358,7 @@ int ct_unrolled_forward(ct_solver *sv, int32_t K, int32_t every, ct_tape **out, 
     set_error("ct_unrolled_forward: need a solver, K >= 1 and every >= 1");
     return CT_E_INVALID;
   }
-  if (sv->ubar || sv->method != CT_METHOD_PDRQS1) {
+  if (sv->ubar || sv->method != CT_METHOD_PDRQS1 || sv->fit != CT_FIT_STANDARD) {
     set_error("ct_unrolled_forward: the reverse sweep is for PDRQS1 without u >= 0");
     return CT_E_UNSUPPORTED;
   }

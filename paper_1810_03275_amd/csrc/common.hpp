@@ -179,6 +179,8 @@ struct SinoEpi {
   int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep,
                  // 4 Algorithm CP dual step, 5 PDRQS2 residual
   float *q1 = nullptr;  // optional: the resolvent input 2 v1 - vb1 (modes 0, 2)
+  int fit = 0;          // data term (modes 0, 2): CT_FIT_* of the C ABI
+  const float *aux = nullptr;  // weights (weighted fit) or b on every bin (fit everywhere)
 };
 // out = R(u) (raw), or the epilogue when epi != nullptr
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,

@@ -276,6 +276,7 @@ __device__ inline void fp_batch_offsets(const float *__restrict__ &u, float *__r
   if (ep.r != nullptr) ep.r += b * NM;
   if (ep.q1 != nullptr) ep.q1 += b * NM;
   if (ep.mask != nullptr) ep.mask += b * (size_t)N * ((M + 31) >> 5);
+  if (ep.aux != nullptr) ep.aux += b * NM;
 }
 
 // Output of one projected bin: either the raw value R(u)[l][k], or the PDRQS1
@@ -328,7 +329,28 @@ __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, in
   const float q = 2.f * v1 - vb;
   if (ep.q1 != nullptr) ep.q1[o] = q;
   const float tg = ep.target[o];
-  const float y = on_d0 ? fminf(q - ep.sigma * tg, 0.f) : (q - ep.sigma * tg) / (1.f + ep.sigma);
+  const float sg = ep.sigma;
+  float y;
+  if (ep.fit == 0) {
+    y = on_d0 ? fminf(q - sg * tg, 0.f) : (q - sg * tg) / (1.f + sg);
+  } else if (on_d0) {
+    // data-term variants of §3.5 on D0: no term (ignore), the fit plus the
+    // bound (everywhere: q - sigma max((q + b)/(1 + sigma), C~)), else the bound
+    if (ep.fit == 2)
+      y = 0.f;
+    else if (ep.fit == 3)
+      y = q - sg * fmaxf((q + ep.aux[o]) / (1.f + sg), tg);
+    else
+      y = fminf(q - sg * tg, 0.f);
+  } else {
+    // off D0: weighted fit (q - sigma b)/(1 + sigma/w), hard constraint q - sigma b
+    if (ep.fit == 1)
+      y = (q - sg * tg) / (1.f + sg / ep.aux[o]);
+    else if (ep.fit == 4)
+      y = q - sg * tg;
+    else
+      y = (q - sg * tg) / (1.f + sg);
+  }
   const float nb = vb + y - v1;
   ep.vb1[o] = nb;
   ep.s1[o] = fmaf(ep.sigma, r, nb);

@@ -95,3 +95,34 @@ def test_nonneg_has_no_reverse_sweep():
     plain = ct.Solver(plan, z, 0.01)
     with pytest.raises(ct.CtpdError):
         plain.export_ubar()
+
+
+@pytest.mark.parametrize("fit", ["weighted", "ignore", "everywhere", "hard"])
+def test_data_term_variants_match_oracle(fit):
+    """60 iterations of PDRQS1 with each data-term variant of §3.5 on a 64^2
+    slice with two metal discs, against the oracle with the same variant."""
+    import dataclasses
+    print("fit", fit, flush=True)
+    w, g, u0, mask, bound, s = _problem()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    weight = None
+    if fit == "weighted":
+        weight = f32(np.random.default_rng(13).uniform(0.5, 2.0, u0.shape))
+        sv.set_fit(fit, gpu(weight))
+    elif fit == "everywhere":
+        sv.set_fit(fit, gpu(u0))
+    else:
+        sv.set_fit(fit)
+    sv.step(60)
+    so = dataclasses.replace(s, fit=fit, weight=weight)
+    st = pdrq.zero_state(so)
+    for _ in range(60):
+        st = pdrq.step(so, st)
+    gu, g1, _ = (host(t) for t in sv.export())
+    assert rel(gu, st.u) <= 1e-4
+    assert rel(g1, st.vb1) <= 1e-4
+    with pytest.raises(ct.CtpdError):
+        sv.set_fit("standard")           # only before the first iteration
+    with pytest.raises(ct.CtpdError):
+        sv.gap()                         # the record is for the standard data term
