@@ -42,7 +42,8 @@ constexpr double kFixOne = 1073741824.0;  // 2^30
 // an exact multiple of 2^-30, so that the FP64 evaluation is exact.
 struct BpAngle {
   double t0, a, b;
-  int64_t b8_fix;  // 8 b 2^32 (exact: b is a multiple of 2^-30)
+  double a32, b32;  // a 2^32 and b 2^32 (integers below 2^33, exact)
+  int64_t b8_fix;   // 8 b 2^32 (exact: b is a multiple of 2^-30)
   int32_t l;       // sinogram row
   int32_t pad;
 };

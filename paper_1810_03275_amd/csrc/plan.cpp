@@ -96,6 +96,8 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
     bp[l].t0 = (double)T30 / kFixOne;
     bp[l].a = (double)A30 / kFixOne;
     bp[l].b = (double)B30 / kFixOne;
+    bp[l].a32 = (double)(A30 * 4);
+    bp[l].b32 = (double)(B30 * 4);
     bp[l].b8_fix = B30 * 4 * 8;
     bp[l].l = l;
     bp[l].pad = 0;

@@ -18,6 +18,12 @@ __device__ inline int med3i(int x, int lo, int hi) {
   return r;
 }
 
+// Word 3 of a raw buffer descriptor (32-bit data).  Buffer loads are range
+// checked: a load whose byte offset is not below the descriptor's record
+// count returns 0, a documented property of buffer addressing; both kernels
+// stage through such loads to get the zeros off the image or detector.
+constexpr int kBufWord3 = 0x00020000;
+
 // ---------------------------------------------------------------------------
 // R_h^*: pixel-driven gather.
 //
@@ -31,44 +37,82 @@ __device__ inline int med3i(int x, int lo, int hi) {
 // 32-bit fraction (lo), then steps to its other pixels with exact 64-bit
 // integer additions of 8 b 2^32.  alpha = lo 2^-32 is rounded once to FP32,
 // the same rounding as the forward projector's.
+//
+// The first pixel's coordinate is formed as the double 2^52 + t 2^32, where
+// t is relative to the staged segment: it is an integer in [2^52, 2^53)
+// (t is a multiple of 2^-30 in [0, seg)), so the FMAs that form it are exact
+// and its bit pattern is the 64-bit fixed-point value itself, offset by the
+// exponent field in the high word (kMagicHi, folded into the LDS base).
+constexpr uint32_t kMagicHi = 0x43300000u;  // high word of the double 2^52
+
 __device__ inline void bp_chunk_meta(const BpAngle *__restrict__ ang, int c0, int nc, int i0, int j0,
-                                     int *kmin_s, int *row_s) {
+                                     int *kmin_s, int *row_s, double *tb_s) {
   if ((int)threadIdx.x < nc) {
     const BpAngle A = ang[c0 + threadIdx.x];
     const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
     const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBpTileJ - 1);
     const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
-    kmin_s[threadIdx.x] = (int)floor(tmin);
+    const int kmin = (int)floor(tmin);
+    kmin_s[threadIdx.x] = kmin;
     row_s[threadIdx.x] = A.l;
+    // 2^52 + (t0 - kmin) 2^32: every term and partial sum is an integer below 2^53
+    tb_s[threadIdx.x] = fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0);
   }
 }
 
-// Segment values of one chunk into registers: entry idx = tid + 256 m holds
-// (v[k], v[k+1]) for angle idx / seg, bin kmin + idx % seg (zero off the detector).
+// Segment values of one chunk into registers.  Wave w stages the angles
+// c = w + 4 r of the chunk, each through a buffer descriptor covering just
+// that angle's sinogram row, so bins off the detector (a negative bin wraps
+// to a huge byte offset) and angles past the chunk's end (record count 0)
+// read as 0 without branches or masks.  Lane t holds the pairs
+// (v[k], v[k+1]) for the local bins k = t and k = t + 64 of each angle.
+constexpr int kBpWaves = 4;                                  // 256 threads
+constexpr int kBpAnglesPerWave = kBpChunk / kBpWaves;        // 4
+constexpr int kBpBinRounds = kBpPrefetch / kBpAnglesPerWave; // 2: seg <= 128
+static_assert(kBpAnglesPerWave * kBpBinRounds == kBpPrefetch, "staging layout");
+static_assert(64 * kBpBinRounds * kBpChunk == 256 * kBpPrefetch, "staging covers seg <= 128");
+
 __device__ inline void bp_stage_load(float2 (&v)[kBpPrefetch], const float *__restrict__ sino,
-                                     int M, int seg, int nc, const int *kmin_s,
-                                     const int *row_s) {
+                                     int M, int nc, const int *kmin_s, const int *row_s) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int m = 0; m < kBpPrefetch; ++m) {
-    const int idx = threadIdx.x + 256 * m;
-    float v0 = 0.f, v1 = 0.f;
-    if (idx < nc * seg) {
-      const int c = idx / seg;
-      const int k = kmin_s[c] + (idx - c * seg);
-      const float *row = sino + (size_t)row_s[c] * M;
-      if (k >= 0 && k < M) v0 = row[k];
-      if (k + 1 >= 0 && k + 1 < M) v1 = row[k + 1];
+  for (int r = 0; r < kBpAnglesPerWave; ++r) {
+    const int c = w + kBpWaves * r;  // wave-uniform
+    const int cc = min(c, nc - 1);
+    const int row = __builtin_amdgcn_readfirstlane(row_s[cc]);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(sino + (size_t)row * M), (short)0, c < nc ? M * 4 : 0, kBufWord3);
+    const int k0 = kmin_s[cc] + lane;
+#pragma unroll
+    for (int m = 0; m < kBpBinRounds; ++m) {
+      const int k = k0 + 64 * m;
+      // a negative bin maps to byte offset 2^31 (out of range) in one unsigned
+      // min, so every load has its own offset register: no folding of the
+      // +4 or +256 into a merged or immediate-offset load, whose range check
+      // would differ at the detector's ends
+      const uint32_t o0 = min((uint32_t)(k * 4), 0x80000000u);
+      const uint32_t o1 = min((uint32_t)(k * 4 + 4), 0x80000000u);
+      const float v0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)o0, 0, 0));
+      const float v1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)o1, 0, 0));
+      v[r * kBpBinRounds + m] = make_float2(v0, v1);
     }
-    v[m] = make_float2(v0, v1);
   }
 }
 
+// LDS entry c seg + k holds (v[k], v[k+1] - v[k]) of angle c, bin kmin_c + k.
 __device__ inline void bp_stage_store(const float2 (&v)[kBpPrefetch], float2 *vd, int seg,
                                       int nc) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int m = 0; m < kBpPrefetch; ++m) {
-    const int idx = threadIdx.x + 256 * m;
-    if (idx < nc * seg) vd[idx] = make_float2(v[m].x, v[m].y - v[m].x);
+  for (int r = 0; r < kBpAnglesPerWave; ++r) {
+    const int c = w + kBpWaves * r;
+#pragma unroll
+    for (int m = 0; m < kBpBinRounds; ++m) {
+      const int k = lane + 64 * m;
+      const float2 q = v[r * kBpBinRounds + m];
+      if (c < nc && k < seg) vd[c * seg + k] = make_float2(q.x, q.y - q.x);
+    }
   }
 }
 
@@ -81,6 +125,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
+  __shared__ double tb_s[3][kBpChunk];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
   const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBpTileJ;
@@ -110,9 +155,10 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   // chunk it is interpolated.
   float2 pf[kBpPrefetch];
   if (nchunks > 0) {
-    bp_chunk_meta(ang, a_begin, min(kBpChunk, a_end - a_begin), i0, j0, kmin_s[0], row_s[0]);
+    bp_chunk_meta(ang, a_begin, min(kBpChunk, a_end - a_begin), i0, j0, kmin_s[0], row_s[0],
+                  tb_s[0]);
     __syncthreads();
-    bp_stage_load(pf, sino, M, seg, min(kBpChunk, a_end - a_begin), kmin_s[0], row_s[0]);
+    bp_stage_load(pf, sino, M, min(kBpChunk, a_end - a_begin), kmin_s[0], row_s[0]);
   }
   for (int it = 0; it < nchunks; ++it) {
     const int c0 = a_begin + it * kBpChunk;
@@ -122,22 +168,21 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     bp_stage_store(pf, vd, seg, nc);
     const int c1n = c0 + kBpChunk;
     const int ncn = min(kBpChunk, a_end - c1n);
-    if (it + 1 < nchunks) bp_chunk_meta(ang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
+    if (it + 1 < nchunks)
+      bp_chunk_meta(ang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3],
+                    tb_s[(it + 1) % 3]);
     __syncthreads();
     if (it + 1 < nchunks)
-      bp_stage_load(pf, sino, M, seg, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
+      bp_stage_load(pf, sino, M, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
     for (int c = 0; c < nc; ++c) {
       const BpAngle A = ang[c0 + c];
-      // first pixel: exact FP64 coordinate relative to the staged segment
-      const double t = fma(dj, A.b, fma(di, A.a, A.t0 - (double)kmin_s[slot][c]));
-      const double fl = floor(t);
-      // 64-bit fixed point, 32 fractional bits: high word = local bin index
-      uint64_t tf = ((uint64_t)(uint32_t)(int)fl << 32) |
-                    (uint64_t)(uint32_t)((t - fl) * 4294967296.0);  // exact
-      const uint64_t step = (uint64_t)A.b8_fix;                    // 8 b 2^32, exact
+      // first pixel: 2^52 + t 2^32 with t relative to the staged segment (exact)
+      const double x = fma(dj, A.b32, fma(di, A.a32, tb_s[slot][c]));
+      uint64_t tf = (uint64_t)__double_as_longlong(x);
+      const uint64_t step = (uint64_t)A.b8_fix;  // 8 b 2^32, exact
       const float2 *seg_c = vd + c * seg;
-      // floor(t) - floor(t_min of the tile) lies in [0, seg - 2] by construction
-      int hh[kBpPix];
+      // the high word is kMagicHi + the local bin index, in [0, seg - 2] by construction
+      uint32_t hh[kBpPix];
       uint32_t ll[kBpPix];
 #pragma unroll
       for (int p = 0; p < kBpPix; ++p) {
@@ -145,12 +190,12 @@ __global__ __launch_bounds__(256) void k_radon_adj(
           tf += step;                    // one 64-bit add per pixel
           asm volatile("" : "+v"(tf));   // keep the chain (no rewrite into multiplies)
         }
-        hh[p] = (int)(uint32_t)(tf >> 32);
+        hh[p] = (uint32_t)(tf >> 32);
         ll[p] = (uint32_t)tf;
       }
       float2 q[kBpPix];
 #pragma unroll
-      for (int p = 0; p < kBpPix; ++p) q[p] = seg_c[hh[p]];
+      for (int p = 0; p < kBpPix; ++p) q[p] = seg_c[(int)(hh[p] - kMagicHi)];
 #pragma unroll
       for (int p = 0; p < kBpPix; ++p) {
         accv[p] += q[p].x;
@@ -651,7 +696,6 @@ constexpr int kLdw = kMultiWidth + 1;         // LDS row pitch (floats)
 // descriptor covers the image and an offset outside it comes from a column
 // index outside [0, n).  Positions beyond the window or past the chunk's
 // last row are staged too but never read.
-constexpr int kBufWord3 = 0x00020000;  // raw buffer, 32-bit data
 
 template <int SL>
 struct Stage {
