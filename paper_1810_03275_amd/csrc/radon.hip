@@ -708,9 +708,11 @@ struct Stage {
     const bool tr = (cls & 1) != 0, fi = (cls & 2) != 0, fo = (cls & 4) != 0;
     const int t = threadIdx.x;
     if (!tr) {
+      // the wave index in a scalar register, so that the descriptor is one too
+      const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
 #pragma unroll
       for (int mr = 0; mr < kRows / kWaves; ++mr) {
-        const int r = (t >> 6) + kWaves * mr;  // wave-uniform
+        const int r = wv + kWaves * mr;  // wave-uniform
         const int q = min(q0 + r, n - 1);
         const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
