@@ -72,7 +72,7 @@ constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixel
 
 // Paired variant: 2 angles whose walk constants (T, A, B) are identical
 // share one walk; a wave owns one pair, a workgroup kPrWaves pairs.
-constexpr int kPrWaves = 8;
+constexpr int kPrWaves = 4;
 constexpr int kMultiMaxWidth = 128;  // staged columns per chunk
 
 struct FpGroup {
@@ -120,6 +120,8 @@ struct ct_plan {
   ctpd::FpGroup *d_groups = nullptr;
   int2 *d_regions = nullptr;  // (p_lo, width) per (group, block, chunk)
   int2 *d_chunk_range = nullptr;  // first/last chunk per (group, block) meeting the image
+  int2 *d_work = nullptr;         // (group, block) of every workgroup, in launch order
+  int n_work = 0;
   int n_groups = 0;
   int max_blk = 0;
   int n_chunks = 0;

@@ -35,10 +35,39 @@ struct HostPlan {
   std::vector<FpAngle> dev;
   std::vector<FpGroup> groups;
   std::vector<int2> regions, ranges;
+  std::vector<int2> work;  // (group, block) per forward workgroup, in launch order
   int seg = 0, bp_slices = 1, n_groups = 0, max_blk = 0, n_chunks = 0, wmax = 0;
   bool check_first = false, paired = false;
   int slots = 1, chunk_rows = 16;
 };
+
+// Launch order of the forward workgroups.  Every (group, block) is one
+// workgroup (a group without blocks still gets block 0, which writes its
+// zero bins); its cost is the number of (wave, staged chunk) pairs it runs.
+// The list is sorted by decreasing cost, so that the workgroups dispatched
+// last, when the device drains, are the short ones.
+static void schedule_work(HostPlan *p) {
+  struct Item {
+    int cost, g, b;
+  };
+  std::vector<Item> items;
+  for (int gi = 0; gi < (int)p->groups.size(); ++gi) {
+    const FpGroup &G = p->groups[gi];
+    const int nb = G.nblk > 0 ? G.nblk : 1;
+    for (int b = 0; b < nb; ++b) {
+      int cost = 0;
+      if (b < G.nblk) {
+        const int2 r = p->ranges[G.range + b];
+        cost = r.y >= r.x ? (r.y - r.x + 1) * G.count : 0;
+      }
+      items.push_back({cost, gi, b});
+    }
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item &x, const Item &y) { return x.cost > y.cost; });
+  p->work.clear();
+  for (const Item &it : items) p->work.push_back(make_int2(it.g, it.b));
+}
 
 static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   const int n = g->n, N = g->n_angles, M = g->n_bins;
@@ -333,6 +362,7 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   }
   if (p->regions.empty()) p->regions.push_back(make_int2(0, 4));
   if (p->ranges.empty()) p->ranges.push_back(make_int2(0, -1));
+  schedule_work(p);
   return CT_OK;
 }
 
@@ -357,6 +387,10 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * hp.groups.size()));
   CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * hp.regions.size()));
   CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * hp.ranges.size()));
+  p->n_work = (int)hp.work.size();
+  CT_TRY_HIP(hipMalloc(&p->d_work, sizeof(int2) * hp.work.size()));
+  CT_TRY_HIP(hipMemcpy(p->d_work, hp.work.data(), sizeof(int2) * hp.work.size(),
+                       hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_chunk_range, hp.ranges.data(), sizeof(int2) * hp.ranges.size(),
                        hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_bp, hp.bp.data(), sizeof(BpAngle) * N, hipMemcpyHostToDevice));
@@ -379,6 +413,24 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
   const int n = g->n;
   const int64_t one = (int64_t)1 << kFixBits;
   int64_t count = 0;
+  {
+    // the launch list holds every (group, block) exactly once
+    std::vector<int> base(hp.groups.size() + 1, 0);
+    for (size_t gi = 0; gi < hp.groups.size(); ++gi)
+      base[gi + 1] = base[gi] + std::max(hp.groups[gi].nblk, 1);
+    std::vector<char> seen(base.back(), 0);
+    bool ok = hp.work.size() == seen.size();
+    for (const int2 &w : hp.work) {
+      if (!ok) break;
+      ok = w.x >= 0 && w.x < (int)hp.groups.size() && w.y >= 0 &&
+           w.y < std::max(hp.groups[w.x].nblk, 1) && !seen[base[w.x] + w.y];
+      if (ok) seen[base[w.x] + w.y] = 1;
+    }
+    if (!ok) {
+      set_error("plan check: the forward launch list is not a permutation of the workgroups");
+      return CT_E_INVALID;
+    }
+  }
   for (const FpGroup &G : hp.groups) {
     const int slots = G.count;
     for (int b = 0; b < G.nblk; ++b) {
@@ -457,6 +509,7 @@ void free_plan(ct_plan *p) {
   (void)hipFree(p->d_groups);
   (void)hipFree(p->d_regions);
   (void)hipFree(p->d_chunk_range);
+  (void)hipFree(p->d_work);
   (void)hipFree(p->d_scratch_sino);
   (void)hipFree(p->d_scratch_img);
   (void)hipFree(p->d_red);

@@ -479,18 +479,29 @@ __device__ inline void walk_row(uint32_t &e, int &ps, uint32_t A, uint32_t B) {
   ps = ps - 1 + (below ? 1 : 0);
 }
 
+// The same step on a pointer into the staged rows (row pitch `stride`).
+__device__ inline void walk_row_ptr(uint32_t &e, const float *&pt, uint32_t A, uint32_t B,
+                                    int stride) {
+  const uint32_t en = e + B;
+  uint32_t d;
+  const bool below = __builtin_sub_overflow(en, A, &d);  // en < A
+  e = below ? en : d;
+  pt += below ? stride : stride - 1;
+}
+
 template <bool CHECK_FIRST>
 __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
-    const int2 *__restrict__ chunk_range, int n_chunks, int ldw, float *__restrict__ sino,
-    SinoEpi ep, int N) {
+    const int2 *__restrict__ chunk_range, const int2 *__restrict__ work, int n_chunks, int ldw,
+    float *__restrict__ sino, SinoEpi ep, int N) {
   extern __shared__ float tile[];  // 2 x kFpRows * ldw
   fp_batch_offsets(u, sino, ep, n, N, M);
-  const FpGroup grp = groups[blockIdx.x];
+  const int2 wk = work[blockIdx.x];  // (group, block along the bins)
+  const FpGroup grp = groups[wk.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int blk = blockIdx.y;
+  const int blk = wk.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
 
   // Bins no pixel reaches hold zero (block 0 below kmin, last block above kmax).
@@ -686,6 +697,10 @@ struct MultiCfg<2> {
 };
 
 constexpr int kMultiWidth = 128;              // staged columns per chunk
+// LDS buffers of staged rows: with 2, chunk c + 1 is stored while chunk c is
+// read (one barrier per chunk); with 1, a second barrier per chunk, half the
+// LDS and so more resident workgroups.
+constexpr int kFpMultiBufs = 1;
 constexpr int kLdw = kMultiWidth + 1;         // LDS row pitch (floats)
 
 // Buffer loads with range checking (a load whose byte offset is not below
@@ -784,16 +799,18 @@ template <int SL, bool CHECK_FIRST>
 __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
-    const int2 *__restrict__ chunk_range, int n_chunks, float *__restrict__ sino, SinoEpi ep,
-    int N) {
+    const int2 *__restrict__ chunk_range, const int2 *__restrict__ work, int n_chunks,
+    float *__restrict__ sino, SinoEpi ep, int N) {
   using St = Stage<SL>;
   constexpr int kRows = St::kRows;
-  __shared__ float tile[2 * kRows * SL * kLdw];  // 2 buffers x kRows x SL angles x kLdw
+  constexpr int kStride = SL * kLdw;  // staged row pitch (floats)
+  __shared__ float tile[kFpMultiBufs * kRows * kStride];  // buffers x kRows x SL angles x kLdw
   fp_batch_offsets(u, sino, ep, n, N, M);
-  const FpGroup grp = groups[blockIdx.x];
+  const int2 wk = work[blockIdx.x];  // (group, block along the bins)
+  const FpGroup grp = groups[wk.x];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int blk = blockIdx.y;
+  const int blk = wk.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
   const FpAngle *pa = angs + SL * grp.first;
   int cls[SL];
@@ -867,7 +884,9 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const int q0 = ch * kRows;
     const int rows = min(kRows, n - q0);
     const int plo = rg_next.x;
-    float *buf = tile + ((ch - ch_first) & 1) * (kRows * SL * kLdw);
+    float *buf = tile + ((ch - ch_first) % kFpMultiBufs) * (kRows * kStride);
+    // one buffer: every wave must be done with the previous chunk first
+    if (kFpMultiBufs == 1 && ch > ch_first) __syncthreads();
 #pragma unroll
     for (int s = 0; s < SL; ++s) St::store(pf[s], buf, cls[s], s);
     __syncthreads();
@@ -879,26 +898,27 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
       for (int s = 0; s < SL; ++s) St::load(pf[s], u, n, cls[s], q1, rows1, rg_next.x);
     }
     if (active) {
-      // pr = ps - plo >= 0 is the strip start within the staged window
-      int pr = ps - plo;
+      // pt walks the strip start through the staged rows: row r of the
+      // window starts at buf + r kStride, and the strip start moves one
+      // position left per row unless the fraction did not wrap.
+      const float *pt = buf + (ps - plo);
       int r0 = 0;
       for (; r0 + RB <= rows; r0 += RB) {
-        int off[RB];
+        const float *pr[RB];
         uint32_t ev[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          off[r] = pr + (r0 + r) * (SL * kLdw);
+          pr[r] = pt;
           ev[r] = e;
-          walk_row(e, pr, A, B);
+          walk_row_ptr(e, pt, A, B, kStride);
         }
         float x1[RB][SL], x2[RB][SL];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const float *pt = buf + off[r];
 #pragma unroll
           for (int s = 0; s < SL; ++s) {
-            x1[r][s] = pt[s * kLdw];
-            x2[r][s] = pt[s * kLdw + 1];
+            x1[r][s] = pr[r][s * kLdw];
+            x2[r][s] = pr[r][s * kLdw + 1];
           }
         }
 #pragma unroll
@@ -912,16 +932,15 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
         }
       }
       for (int r = r0; r < rows; ++r) {  // ragged last chunk
-        const float *pt = buf + pr + r * (SL * kLdw);
         const uint32_t e1 = e;
         const bool in1 = e1 < one, in2 = e1 < lim2;
         const float ef = (float)e1;
 #pragma unroll
         for (int s = 0; s < SL; ++s)
           acc_row<CHECK_FIRST>(pt[s * kLdw], pt[s * kLdw + 1], in1, in2, ef, P[s], Q[s], S[s]);
-        walk_row(e, pr, A, B);
+        walk_row_ptr(e, pt, A, B, kStride);
       }
-      ps = pr + plo;
+      ps = plo + (int)(pt - buf) - rows * kStride;
     }
   }
 
@@ -948,17 +967,17 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   SinoEpi ep{};
   if (epi) ep = *epi;
   const int N = p->g.n_angles;
-  dim3 grid(p->n_groups, p->max_blk > 0 ? p->max_blk : 1, nb);
+  dim3 grid(p->n_work, 1, nb);
   if (p->slots == 2) {
-    const dim3 block(64 * kPrWaves);
+    const dim3 block(64 * MultiCfg<2>::kWaves);
     if (p->check_first)
       hipLaunchKernelGGL((k_radon_fwd_multi<2, true>), grid, block, 0, s, u, p->g.n, p->g.n_bins,
-                         p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, out,
-                         ep, N);
+                         p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->d_work,
+                         p->n_chunks, out, ep, N);
     else
       hipLaunchKernelGGL((k_radon_fwd_multi<2, false>), grid, block, 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->n_chunks, out, ep, N);
+                         p->d_work, p->n_chunks, out, ep, N);
     CT_TRY_HIP(hipGetLastError());
     return CT_OK;
   }
@@ -966,11 +985,11 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   const size_t lds = 2 * sizeof(float) * kFpRows * ldw;
   if (p->check_first)
     hipLaunchKernelGGL(k_radon_fwd<true>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
-                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
+                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->d_work, p->n_chunks, ldw,
                        out, ep, N);
   else
     hipLaunchKernelGGL(k_radon_fwd<false>, grid, dim3(kFpThreads), lds, s, u, p->g.n, p->g.n_bins,
-                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->n_chunks, ldw,
+                       p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->d_work, p->n_chunks, ldw,
                        out, ep, N);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
