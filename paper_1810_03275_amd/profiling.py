@@ -3,9 +3,13 @@
     python -m paper_1810_03275_amd.profiling trace <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1810_03275_amd.profiling traffic <fetch.csv> <write.csv> <kernel> \
         <copy_bytes> <out.json> "<command>"
+    python -m paper_1810_03275_amd.profiling counters <counter_collection.csv> <out.md> \
+        "<title>" "<command>"
 
 trace   : per-kernel calls / average / total duration table from a
           `rocprofv3 --kernel-trace --stats --output-format csv` run.
+counters: per-kernel median over dispatches of every counter of a
+          `rocprofv3 --pmc ... --output-format csv` run.
 traffic : HBM bytes per launch of one kernel from two `--pmc FETCH_SIZE` and
           `--pmc WRITE_SIZE` runs (KiB per dispatch), each scaled by the factor
           that makes the same counter read exactly copy_bytes for the largest
@@ -81,9 +85,35 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: float, out_
     return rec
 
 
+def counters_summary(path: str, out_md: str, title: str, command: str, top: int = 12) -> None:
+    per = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for r in csv.DictReader(open(path)):
+        key = int(r["Dispatch_Id"])
+        per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        names[key] = _short(r["Kernel_Name"])
+    by_kernel = defaultdict(list)
+    for key, vals in per.items():
+        by_kernel[names[key]].append(vals)
+    cols = sorted({c for vals in per.values() for c in vals})
+    rows = []
+    for nm, lst in by_kernel.items():
+        med = {c: sorted(v.get(c, 0.0) for v in lst)[len(lst) // 2] for c in cols}
+        rows.append((nm, len(lst), med))
+    rows.sort(key=lambda x: -x[2].get("SQ_INSTS_VALU", 0.0))
+    lines = [f"# {title}", "", f"Command: `{command}`", "",
+             "| kernel | dispatches | " + " | ".join(c.replace("SQ_", "") for c in cols) + " |",
+             "|---|---|" + "---|" * len(cols)]
+    for nm, cnt, med in rows[:top]:
+        lines.append(f"| {nm} | {cnt} | " + " | ".join(f"{med[c]:.4g}" for c in cols) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6],
                       sys.argv[7]))
+    elif sys.argv[1] == "counters":
+        counters_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
