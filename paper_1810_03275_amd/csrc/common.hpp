@@ -102,6 +102,7 @@ struct FftPlan {
   int32_t L;
   int32_t npass;
   int32_t radix[24];
+  uint64_t code;  // radix of pass i in bits [4 i, 4 i + 4) (a scalar the kernels decode)
 };
 
 }  // namespace ctpd

@@ -9,27 +9,46 @@
 //   inverse rows : rebuild the two Hermitian spectra as one complex row,
 //                  inverse FFT, real/imaginary parts are the two output rows.
 // Twiddles exp(-2 pi i m/n) are precomputed in FP64 and stored as FP32.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
 
 namespace ctpd {
 
+// Threads per workgroup of every FFT kernel (a compile-time constant: the
+// strided loops use it instead of reading the dispatch's workgroup size).
+constexpr int kFftThreads = 256;
+
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Radix-4 DFT in place, kernel exp(sgn 2 pi i jk / 4).
+__device__ inline void dft4(float2 &v0, float2 &v1, float2 &v2, float2 &v3, float sgn) {
+  const float2 s02 = make_float2(v0.x + v2.x, v0.y + v2.y);
+  const float2 d02 = make_float2(v0.x - v2.x, v0.y - v2.y);
+  const float2 s13 = make_float2(v1.x + v3.x, v1.y + v3.y);
+  const float2 d13 = make_float2(v1.x - v3.x, v1.y - v3.y);
+  const float2 rd = make_float2(-sgn * d13.y, sgn * d13.x);  // (sgn i) d13
+  v0 = make_float2(s02.x + s13.x, s02.y + s13.y);
+  v1 = make_float2(d02.x + rd.x, d02.y + rd.y);
+  v2 = make_float2(s02.x - s13.x, s02.y - s13.y);
+  v3 = make_float2(d02.x - rd.x, d02.y - rd.y);
+}
+
 // One radix-R Stockham pass over `nrows` rows of length L (row stride L):
 // reads a, writes b.  Ns is the length of the sub-transforms already done.
+// tw holds exp(-2 pi i m / L), m < L (in LDS or global memory).
 template <int R, bool INV>
 __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, int Ns,
-                                const float2 *__restrict__ tw) {
+                                const float2 *tw) {
   const int nbf = L / R;
   const int step = L / (Ns * R);
   const float sgn = INV ? 1.f : -1.f;  // forward kernel exp(-i ...)
   // exact small-integer quotients via a float reciprocal (operands < 2^13)
   const float inv_nbf = 1.0f / (float)nbf, inv_ns = 1.0f / (float)Ns;
-  for (int t = threadIdx.x; t < nrows * nbf; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nrows * nbf; t += kFftThreads) {
     const int row = (int)(((float)t + 0.5f) * inv_nbf);
     const int jj = t - row * nbf;
     const float2 *in = a + row * L;
@@ -45,23 +64,35 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
       if (INV) w.y = -w.y;
       v[r] = cmul(v[r], w);
     }
-    if (R == 2) {
+    if constexpr (R == 2) {
       const float2 x0 = v[0], x1 = v[1];
       v[0] = make_float2(x0.x + x1.x, x0.y + x1.y);
       v[1] = make_float2(x0.x - x1.x, x0.y - x1.y);
-    } else if (R == 4) {
-      const float2 x0 = v[0], x1 = v[1], x2 = v[2 % R], x3 = v[3 % R];
-      const float2 s02 = make_float2(x0.x + x2.x, x0.y + x2.y);
-      const float2 d02 = make_float2(x0.x - x2.x, x0.y - x2.y);
-      const float2 s13 = make_float2(x1.x + x3.x, x1.y + x3.y);
-      const float2 d13 = make_float2(x1.x - x3.x, x1.y - x3.y);
-      const float2 rd = make_float2(-sgn * d13.y, sgn * d13.x);  // (sgn i) d13
-      v[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
-      v[1] = make_float2(d02.x + rd.x, d02.y + rd.y);
-      v[2 % R] = make_float2(s02.x - s13.x, s02.y - s13.y);
-      v[3 % R] = make_float2(d02.x - rd.x, d02.y - rd.y);
+    } else if constexpr (R == 4) {
+      dft4(v[0], v[1], v[2], v[3], sgn);
+    } else if constexpr (R == 8) {
+      // a_j = x_j + x_{j+4} and b_j = (x_j - x_{j+4}) w8^j (w8 = exp(sgn i pi / 4));
+      // the even outputs are the DFT-4 of a, the odd outputs that of b
+      const float c = 0.70710678118654752440f;  // sqrt(2)/2
+      float2 a4[4], b4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a4[j] = make_float2(v[j].x + v[j + 4].x, v[j].y + v[j + 4].y);
+        b4[j] = make_float2(v[j].x - v[j + 4].x, v[j].y - v[j + 4].y);
+      }
+      b4[1] = make_float2(c * (b4[1].x - sgn * b4[1].y), c * (b4[1].y + sgn * b4[1].x));
+      b4[2] = make_float2(-sgn * b4[2].y, sgn * b4[2].x);
+      b4[3] = make_float2(-c * (b4[3].x + sgn * b4[3].y), c * (sgn * b4[3].x - b4[3].y));
+      dft4(a4[0], a4[1], a4[2], a4[3], sgn);
+      dft4(b4[0], b4[1], b4[2], b4[3], sgn);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] = a4[j];
+        v[2 * j + 1] = b4[j];
+      }
     } else {  // R == 3
-      const float2 x0 = v[0], x1 = v[1], x2 = v[2 % R];
+      static_assert(R == 3, "radix 2, 3, 4 or 8");
+      const float2 x0 = v[0], x1 = v[1], x2 = v[2];
       const float h = 0.86602540378443864676f;  // sqrt(3)/2
       const float2 s = make_float2(x1.x + x2.x, x1.y + x2.y);
       const float2 d = make_float2(x1.x - x2.x, x1.y - x2.y);
@@ -69,7 +100,7 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
       const float2 rd = make_float2(-sgn * h * d.y, sgn * h * d.x);  // (sgn i sqrt(3)/2) d
       v[0] = make_float2(x0.x + s.x, x0.y + s.y);
       v[1] = make_float2(m.x + rd.x, m.y + rd.y);
-      v[2 % R] = make_float2(m.x - rd.x, m.y - rd.y);
+      v[2] = make_float2(m.x - rd.x, m.y - rd.y);
     }
     const int base = jq * Ns * R + k;
 #pragma unroll
@@ -82,12 +113,14 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
 // INV selects the inverse (conjugate) transform, unnormalized.
 template <bool INV>
 __device__ float2 *fft_rows(float2 *a, float2 *b, int nrows, const FftPlan &pl,
-                            const float2 *__restrict__ tw) {
+                            const float2 *tw) {
   const int L = pl.L;
   int Ns = 1;
   for (int ps = 0; ps < pl.npass; ++ps) {
-    const int R = pl.radix[ps];
-    if (R == 4)
+    const int R = (int)((pl.code >> (4 * ps)) & 15u);
+    if (R == 8)
+      fft_pass<8, INV>(a, b, nrows, L, Ns, tw);
+    else if (R == 4)
       fft_pass<4, INV>(a, b, nrows, L, Ns, tw);
     else if (R == 2)
       fft_pass<2, INV>(a, b, nrows, L, Ns, tw);
@@ -102,28 +135,62 @@ __device__ float2 *fft_rows(float2 *a, float2 *b, int nrows, const FftPlan &pl,
   return a;
 }
 
+// A workgroup-strided loop over [0, total) whose loads are issued kIoBatch
+// at a time (all before the first use), so that their latencies overlap.
+constexpr int kIoBatch = 4;
+template <typename Load, typename Use>
+__device__ inline void batched(int total, Load load, Use use) {
+  for (int t0 = threadIdx.x; t0 < total; t0 += kIoBatch * kFftThreads) {
+    decltype(load(0)) r[kIoBatch];
+#pragma unroll
+    for (int u = 0; u < kIoBatch; ++u) {
+      const int t = t0 + u * kFftThreads;
+      if (t < total) r[u] = load(t);
+    }
+#pragma unroll
+    for (int u = 0; u < kIoBatch; ++u) {
+      const int t = t0 + u * kFftThreads;
+      if (t < total) use(t, r[u]);
+    }
+  }
+}
+
+// Twiddle table of a workgroup: copied into LDS behind the two row buffers
+// when it fits (TWL), else read from global memory.
+template <bool TWL>
+__device__ inline const float2 *stage_twiddles(float2 *lds, const float2 *__restrict__ tw, int L) {
+  if (!TWL) return tw;
+  batched(L, [&](int t) { return tw[t]; }, [&](int t, float2 v) { lds[t] = v; });
+  return lds;  // the caller's barrier precedes the first read
+}
+
 // Row pass: rows [2 rp0, 2 rp0 + 2 RP) of y -> spec[k1][j], k1 in [0, n/2].
-__global__ __launch_bounds__(256) void k_fft_rows_fwd(const float *__restrict__ y, int n,
+template <bool TWL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__restrict__ y, int n,
                                                       int RP, FftPlan pl,
                                                       const float2 *__restrict__ tw,
                                                       float2 *__restrict__ spec) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + RP * n;
+  const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
   y += (size_t)blockIdx.y * n * n;  // problem blockIdx.y of a batch
   spec += (size_t)blockIdx.y * (n / 2 + 1) * n;
-  for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
-    const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
-    const int j = 2 * (pair0 + pr);
-    a[t] = make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
-  }
+  batched(
+      npair * n,
+      [&](int t) {
+        const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
+        const int j = 2 * (pair0 + pr);
+        return make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
+      },
+      [&](int t, float2 v) { a[t] = v; });
   __syncthreads();
-  float2 *z = fft_rows<false>(a, b, npair, pl, tw);
+  float2 *z = fft_rows<false>(a, b, npair, pl, twp);
   const int half = n / 2 + 1;
   const int w = 2 * npair;
-  for (int t = threadIdx.x; t < half * w; t += blockDim.x) {
+  for (int t = threadIdx.x; t < half * w; t += kFftThreads) {
     const int k = t / w, c = t - k * w;
     const int pr = c >> 1;
     const float2 Zk = z[pr * n + k];
@@ -139,31 +206,33 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(const float *__restrict__ 
 }
 
 // Column pass: per k1, spec[k1][:] <- IFFT( m[k1][:] * FFT(spec[k1][:]) ).
-__global__ __launch_bounds__(256) void k_fft_cols(float2 *__restrict__ spec, int n, int CP,
+template <bool TWL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ spec, int n, int CP,
                                                   FftPlan pl, const float2 *__restrict__ tw,
                                                   const float *__restrict__ mult) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + CP * n;
+  const float2 *twp = stage_twiddles<TWL>(sm + 2 * CP * n, tw, n);
   const int half = n / 2 + 1;
   const int k10 = blockIdx.x * CP;
   const int ncol = min(CP, half - k10);
   spec += (size_t)blockIdx.y * half * n;
-  for (int t = threadIdx.x; t < ncol * n; t += blockDim.x) a[t] = spec[(size_t)k10 * n + t];
+  batched(ncol * n, [&](int t) { return spec[(size_t)k10 * n + t]; },
+          [&](int t, float2 v) { a[t] = v; });
   __syncthreads();
-  float2 *z = fft_rows<false>(a, b, ncol, pl, tw);
+  float2 *z = fft_rows<false>(a, b, ncol, pl, twp);
   float2 *other = (z == a) ? b : a;
-  for (int t = threadIdx.x; t < ncol * n; t += blockDim.x) {
-    const float m = mult[(size_t)k10 * n + t];
-    z[t] = make_float2(m * z[t].x, m * z[t].y);
-  }
+  batched(ncol * n, [&](int t) { return mult[(size_t)k10 * n + t]; },
+          [&](int t, float m) { z[t] = make_float2(m * z[t].x, m * z[t].y); });
   __syncthreads();
-  z = fft_rows<true>(z, other, ncol, pl, tw);
-  for (int t = threadIdx.x; t < ncol * n; t += blockDim.x) spec[(size_t)k10 * n + t] = z[t];
+  z = fft_rows<true>(z, other, ncol, pl, twp);
+  for (int t = threadIdx.x; t < ncol * n; t += kFftThreads) spec[(size_t)k10 * n + t] = z[t];
 }
 
 // Inverse row pass: out[j][i] = (base ? base[j][i] : 0) + x_j[i].
-__global__ __launch_bounds__(256) void k_fft_rows_inv(const float2 *__restrict__ spec, int n,
+template <bool TWL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const float2 *__restrict__ spec, int n,
                                                       int RP, FftPlan pl,
                                                       const float2 *__restrict__ tw,
                                                       const float *__restrict__ base,
@@ -171,38 +240,47 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(const float2 *__restrict__
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + RP * n;
+  const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
   const int half = n / 2 + 1;
   spec += (size_t)blockIdx.y * half * n;
   if (base != nullptr) base += (size_t)blockIdx.y * n * n;
   out += (size_t)blockIdx.y * n * n;
-  for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
-    const int pr = t / n, k = t - pr * n;
-    const int j = 2 * (pair0 + pr);
-    float2 X, Y;
-    if (k < half) {
-      X = spec[(size_t)k * n + j];
-      Y = spec[(size_t)k * n + j + 1];
-    } else {
-      const int km = n - k;
-      X = spec[(size_t)km * n + j];
-      Y = spec[(size_t)km * n + j + 1];
-      X.y = -X.y;
-      Y.y = -Y.y;
-    }
-    a[t] = make_float2(X.x - Y.y, X.y + Y.x);  // X + i Y
-  }
+  batched(
+      npair * n,
+      [&](int t) {
+        const int pr = t / n, k = t - pr * n;
+        const int j = 2 * (pair0 + pr);
+        const int kk = k < half ? k : n - k;
+        // X and Y of row pair j at frequency kk (contiguous in spec)
+        return *reinterpret_cast<const float4 *>(spec + (size_t)kk * n + j);
+      },
+      [&](int t, float4 xy) {
+        const int k = t - (t / n) * n;
+        float2 X = make_float2(xy.x, xy.y), Y = make_float2(xy.z, xy.w);
+        if (k >= half) {  // Hermitian symmetry: conjugates of frequency n - k
+          X.y = -X.y;
+          Y.y = -Y.y;
+        }
+        a[t] = make_float2(X.x - Y.y, X.y + Y.x);  // X + i Y
+      });
   __syncthreads();
-  float2 *z = fft_rows<true>(a, b, npair, pl, tw);
-  for (int t = threadIdx.x; t < npair * n; t += blockDim.x) {
-    const int pr = t / n, i = t - pr * n;
-    const int j = 2 * (pair0 + pr);
-    const size_t o0 = (size_t)j * n + i, o1 = o0 + n;
-    const float2 v = z[t];
-    out[o0] = (base ? base[o0] : 0.f) + v.x;
-    out[o1] = (base ? base[o1] : 0.f) + v.y;
-  }
+  float2 *z = fft_rows<true>(a, b, npair, pl, twp);
+  batched(
+      npair * n,
+      [&](int t) {
+        const int pr = t / n, i = t - pr * n;
+        const size_t o0 = (size_t)(2 * (pair0 + pr)) * n + i;
+        return base ? make_float2(base[o0], base[o0 + n]) : make_float2(0.f, 0.f);
+      },
+      [&](int t, float2 b0) {
+        const int pr = t / n, i = t - pr * n;
+        const size_t o0 = (size_t)(2 * (pair0 + pr)) * n + i;
+        const float2 v = z[t];
+        out[o0] = b0.x + v.x;
+        out[o0 + n] = b0.y + v.y;
+      });
 }
 
 // Rows (pairs) per workgroup: at least ~256 workgroups, at most 64 KB of LDS.
@@ -226,16 +304,26 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
     return CT_E_INVALID;
   }
   if (spec == nullptr) spec = pc->d_spec;
-  const size_t lds = 2 * sizeof(float2) * (size_t)RP * n;
-  hipLaunchKernelGGL(k_fft_rows_fwd, dim3((n / 2 + RP - 1) / RP, nb), dim3(256), lds, s, y, n,
-                     RP, pc->fp, pc->d_tw, spec);
-  CT_TRY_HIP(hipGetLastError());
+  const size_t rows_lds = 2 * sizeof(float2) * (size_t)RP * n;
+  const bool twl = rows_lds + sizeof(float2) * n <= 65536;
+  const size_t lds = rows_lds + (twl ? sizeof(float2) * n : 0);
+  const dim3 block(kFftThreads);
   const int CP = RP;
-  hipLaunchKernelGGL(k_fft_cols, dim3((half + CP - 1) / CP, nb), dim3(256), lds, s, spec, n, CP,
-                     pc->fp, pc->d_tw, mult);
-  CT_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_fft_rows_inv, dim3((n / 2 + RP - 1) / RP, nb), dim3(256), lds, s, spec,
-                     n, RP, pc->fp, pc->d_tw, base, out);
+  if (twl) {
+    hipLaunchKernelGGL(k_fft_rows_fwd<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s, y,
+                       n, RP, pc->fp, pc->d_tw, spec);
+    hipLaunchKernelGGL(k_fft_cols<true>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec, n,
+                       CP, pc->fp, pc->d_tw, mult);
+    hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
+                       spec, n, RP, pc->fp, pc->d_tw, base, out);
+  } else {
+    hipLaunchKernelGGL(k_fft_rows_fwd<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
+                       y, n, RP, pc->fp, pc->d_tw, spec);
+    hipLaunchKernelGGL(k_fft_cols<false>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec,
+                       n, CP, pc->fp, pc->d_tw, mult);
+    hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
+                       spec, n, RP, pc->fp, pc->d_tw, base, out);
+  }
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }
@@ -243,11 +331,35 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
 bool fft_factor(int L, FftPlan *fp) {
   fp->L = L;
   fp->npass = 0;
-  int m = L;
-  while (m % 4 == 0) { fp->radix[fp->npass++] = 4; m /= 4; }
-  while (m % 2 == 0) { fp->radix[fp->npass++] = 2; m /= 2; }
-  while (m % 3 == 0) { fp->radix[fp->npass++] = 3; m /= 3; }
-  return m == 1 && fp->npass <= 24;
+  int m = L, twos = 0;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++twos;
+  }
+  // powers of two as radix 8 passes, the remainder as one radix-4 or -2 pass
+  // (or, for 2^(3k+1) with k >= 1, two radix-4 passes instead of 8 and 2)
+  int eights = twos / 3, rest = twos % 3;
+  if (rest == 1 && eights > 0) {
+    --eights;
+    rest = 4;  // 2^4 = 4 x 4
+  }
+  for (int i = 0; i < eights; ++i) fp->radix[fp->npass++] = 8;
+  if (rest == 4) {
+    fp->radix[fp->npass++] = 4;
+    fp->radix[fp->npass++] = 4;
+  } else if (rest == 2) {
+    fp->radix[fp->npass++] = 4;
+  } else if (rest == 1) {
+    fp->radix[fp->npass++] = 2;
+  }
+  while (m % 3 == 0) {
+    fp->radix[fp->npass++] = 3;
+    m /= 3;
+    if (fp->npass > 16) return false;
+  }
+  fp->code = 0;
+  for (int i = 0; i < fp->npass; ++i) fp->code |= (uint64_t)fp->radix[i] << (4 * i);
+  return m == 1 && fp->npass <= 16;
 }
 
 }  // namespace ctpd
