@@ -24,6 +24,14 @@ __device__ inline int med3i(int x, int lo, int hi) {
 // stage through such loads to get the zeros off the image or detector.
 constexpr int kBufWord3 = 0x00020000;
 
+// A buffer-load byte offset kept in a register of its own: the range check
+// must see exactly this value, so no constant part of it may be moved into
+// the instruction's immediate offset field.
+__device__ inline int own_offset(int off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+
 // ---------------------------------------------------------------------------
 // R_h^*: pixel-driven gather.
 //
@@ -87,14 +95,14 @@ __device__ inline void bp_stage_load(float2 (&v)[kBpPrefetch], const float *__re
 #pragma unroll
     for (int m = 0; m < kBpBinRounds; ++m) {
       const int k = k0 + 64 * m;
-      // a negative bin maps to byte offset 2^31 (out of range) in one unsigned
-      // min, so every load has its own offset register: no folding of the
-      // +4 or +256 into a merged or immediate-offset load, whose range check
-      // would differ at the detector's ends
-      const uint32_t o0 = min((uint32_t)(k * 4), 0x80000000u);
-      const uint32_t o1 = min((uint32_t)(k * 4 + 4), 0x80000000u);
-      const float v0 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)o0, 0, 0));
-      const float v1 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)o1, 0, 0));
+      // every load keeps its own offset register (a negative bin is a huge
+      // unsigned offset, out of range): no folding of the +4 or +256 into a
+      // merged or immediate-offset load, whose range check would differ at
+      // the detector's ends
+      const float v0 =
+          __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(k * 4), 0, 0));
+      const float v1 =
+          __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(k * 4 + 4), 0, 0));
       v[r * kBpBinRounds + m] = make_float2(v0, v1);
     }
   }
@@ -732,14 +740,15 @@ struct Stage {
         const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)urow, (short)0, r < rows ? n * 4 : 0, kBufWord3);
+        // byte offset of column p0 = plo + lane; position p0 + 64 mc is
+        // 64 columns further along the (possibly mirrored) row
         const int p0 = plo + (t & 63);
+        const int o0 = (fi ? n - 1 - p0 : p0) * 4;
+        const int dstep = fi ? -256 : 256;
 #pragma unroll
-        for (int mc = 0; mc < kMultiWidth / 64; ++mc) {
-          const int p = p0 + 64 * mc;
-          const int pi = fi ? n - 1 - p : p;
+        for (int mc = 0; mc < kMultiWidth / 64; ++mc)
           v[mr * (kMultiWidth / 64) + mc] =
-              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, pi * 4, 0, 0));
-        }
+              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(o0 + mc * dstep), 0, 0));
       }
     } else {
       const int r = t & (kRows - 1);
@@ -747,13 +756,14 @@ struct Stage {
       const int qi = fo ? n - 1 - q : q;
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc((void *)u, (short)0, n * n * 4, kBufWord3);
+      // image row of position p0 = plo + t / kRows; each further value is
+      // kThreads / kRows rows on (up, when mirrored), a fixed byte step
       const int p0 = plo + t / kRows;
+      const int o0 = ((fi ? n - 1 - p0 : p0) * n + qi) * 4;
+      const int dstep = (fi ? -4 : 4) * (kThreads / kRows) * n;
 #pragma unroll
-      for (int m = 0; m < kPer; ++m) {
-        const int p = p0 + (kThreads / kRows) * m;
-        const int pi = fi ? n - 1 - p : p;
-        v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (pi * n + qi) * 4, 0, 0));
-      }
+      for (int m = 0; m < kPer; ++m)
+        v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(o0 + m * dstep), 0, 0));
     }
   }
 
