@@ -210,6 +210,22 @@ void ct_params_default(ct_params *p);
 int ct_objective(const ct_plan *p, const ct_problem *prob, const float *u, double out[3],
                  ct_stream s);
 
+/* Metal-trace estimate from a reconstruction (results chapter, real metal
+ * artifacts): the pixels of u_rec above `threshold` are marked, the marks are
+ * dilated by the disk {a^2 + b^2 <= radius^2} of pixel offsets, the dilated
+ * indicator chi is projected, and D0 holds the bins with (R_h chi) > kappa
+ * (kappa >= 0: the smallest interpolation weight with which a marked pixel
+ * must reach a bin; the two weights of a pixel sum to 1).  When u0 and bound
+ * are given, bound = c0 u0 on D0 and 0 elsewhere (the thesis takes c0 = 0.8).
+ * u_rec: device [n][n]; chi: device [n][n] out (0 or 1); proj: device [N][M]
+ * out; mask: device uint32 [N][ceil(M/32)] out, bit k & 31 of word k >> 5;
+ * u0, bound: device [N][M] (both NULL or both non-NULL).  Buffers are the
+ * caller's; nothing is allocated.  0 <= radius <= 16.
+ * Errors: CT_E_INVALID (null or out-of-range argument), CT_E_DEVICE. */
+int ct_d0_estimate(const ct_plan *p, const float *u_rec, float threshold, int32_t radius,
+                   float kappa, float *chi, float *proj, uint32_t *mask, const float *u0,
+                   float c0, float *bound, ct_stream s);
+
 typedef struct ct_solver ct_solver;
 
 /* Setup (§5.1, §4.3.1): beta (power iteration unless given), data b = u0/beta,

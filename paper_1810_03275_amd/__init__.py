@@ -28,7 +28,7 @@ _L = _lib.load()
 __all__ = [
     "CtpdError", "Plan", "Precond", "Solver", "radon_fwd", "radon_adj", "grad", "div",
     "prox_sino", "tv_project", "power_norm", "reconstruct", "pack_mask", "RadonFn",
-    "RadonAdjFn", "lib",
+    "RadonAdjFn", "estimate_d0", "lib",
 ]
 
 lib = _L
@@ -153,6 +153,31 @@ def radon_fwd(plan: Plan, img: torch.Tensor, out=None) -> torch.Tensor:
 def radon_adj(plan: Plan, sino: torch.Tensor, out=None) -> torch.Tensor:
     """img = R_h^* sino (§3.1)."""
     return plan.radon_adj(sino, out)
+
+
+def estimate_d0(plan: Plan, u_rec: torch.Tensor, threshold: float, radius: int = 5,
+                kappa: float = 1e-3, u0: Optional[torch.Tensor] = None, c0: float = 0.8):
+    """Metal trace from a reconstruction (results chapter, real metal
+    artifacts): pixels of u_rec above threshold, dilated by a disk of the given
+    radius (pixels), projected; D0 = {R_h chi > kappa}.  Returns
+    (chi [n][n], R_h chi [N][M], packed D0 mask [N][ceil(M/32)] int32, bound),
+    bound = c0 u0 on D0 (0 elsewhere) when u0 is given, else None."""
+    n, N, M = plan.n, plan.n_angles, plan.n_bins
+    dev = u_rec.device
+    chi = torch.empty((n, n), device=dev, dtype=torch.float32)
+    proj = torch.empty((N, M), device=dev, dtype=torch.float32)
+    mask = torch.empty((N, (M + 31) // 32), device=dev, dtype=torch.int32)
+    bound = None
+    u0p = None
+    if u0 is not None:
+        u0p = _dev(u0, (N, M), "u0")
+        bound = torch.empty((N, M), device=dev, dtype=torch.float32)
+    _check(_L.ct_d0_estimate(plan.handle, _dev(u_rec, (n, n), "u_rec"), float(threshold),
+                             int(radius), float(kappa), chi.data_ptr(), proj.data_ptr(),
+                             mask.data_ptr(), u0p, float(c0),
+                             bound.data_ptr() if bound is not None else None, _stream()),
+           "ct_d0_estimate")
+    return chi, proj, mask, bound
 
 
 def grad(u: torch.Tensor, h: float = 1.0, out=None) -> torch.Tensor:

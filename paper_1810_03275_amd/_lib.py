@@ -44,6 +44,8 @@ SIGNATURES = {
     "ct_plan_create": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(c_void_p)]),
     "ct_plan_destroy": (c_int32, [c_void_p]),
     "ct_radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ct_d0_estimate": (c_int32, [c_void_p, c_void_p, c_float, c_int32, c_float, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),
     "ct_radon_adj": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_grad": (c_int32, [c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     "ct_div": (c_int32, [c_int32, c_double, c_void_p, c_void_p, c_void_p]),

@@ -313,6 +313,22 @@ int ct_radon_fwd(const ct_plan *p, const float *img, float *sino, ct_stream s) {
   return launch_radon_fwd(p, img, sino, S(s));
 }
 
+int ct_d0_estimate(const ct_plan *p, const float *u_rec, float threshold, int32_t radius,
+                   float kappa, float *chi, float *proj, uint32_t *mask, const float *u0,
+                   float c0, float *bound, ct_stream s) {
+  clear_error();
+  if (!p || !u_rec || !chi || !proj || !mask || ((u0 == nullptr) != (bound == nullptr))) {
+    set_error("ct_d0_estimate: null argument (u0 and bound go together)");
+    return CT_E_INVALID;
+  }
+  if (radius < 0 || radius > kDilMaxRadius || !(kappa >= 0.0f) || !std::isfinite(threshold)) {
+    set_error("ct_d0_estimate: radius must be in [0, 16], kappa >= 0, threshold finite");
+    return CT_E_INVALID;
+  }
+  return launch_d0_estimate(p, u_rec, threshold, radius, kappa, chi, proj, mask, u0, c0, bound,
+                            S(s));
+}
+
 int ct_radon_adj(const ct_plan *p, const float *sino, float *img, ct_stream s) {
   clear_error();
   if (!p || !img || !sino) {

@@ -190,6 +190,13 @@ struct SinoEpi {
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
                      const SinoEpi *epi = nullptr, int nb = 1);
 
+// metal-trace estimate: dilation by a disk of radius <= kDilMaxRadius, R_h,
+// D0 = {R_h chi > kappa}, bound = c0 u0 on D0 (when bound != nullptr)
+constexpr int kDilMaxRadius = 16;
+int launch_d0_estimate(const ct_plan *p, const float *u, float thr, int r, float kappa,
+                       float *chi, float *proj, uint32_t *mask, const float *u0, float c0,
+                       float *bound, hipStream_t s);
+
 int launch_grad(int n, float inv_h, const float *u, float *p, hipStream_t s);
 int launch_div(int n, float inv_h, const float *p, float *d, hipStream_t s);
 int launch_tv_project(int n, const float *q, float radius, float *w, hipStream_t s);
