@@ -20,12 +20,13 @@ Modules (each function cites the thesis passage it follows):
   cp        Algorithm CP (Chambolle-Pock) as an independent solver (§3.4)
   gap       FP64 primal/dual record (a reading; the thesis defines none)
   d0        metal-trace estimate: threshold, dilate, project        (results, real metal)
+  admm      ADMM with inner PCG and isotropic soft thresholding     (§4.6)
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 header of the module that takes them and collected in the repository's design
 notes.  Parity status: every function is pinned by the tests under tests/
 (test_oracle_*.py) except where its docstring says "parity unpinned".
 """
-from . import geometry, radon, tv, precond, prox, power, pdrq, cp, gap, d0  # noqa: F401
+from . import geometry, radon, tv, precond, prox, power, pdrq, cp, gap, d0, admm  # noqa: F401
 
-__all__ = ["geometry", "radon", "tv", "precond", "prox", "power", "pdrq", "cp", "gap", "d0"]
+__all__ = ["geometry", "radon", "tv", "precond", "prox", "power", "pdrq", "cp", "gap", "d0", "admm"]
