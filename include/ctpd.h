@@ -177,12 +177,15 @@ enum {
  *  CP          Algorithm CP (§3.4), sigma = tau = 0.99 / sqrt(1 + 8/h^2) on the
  *              normalized problem (the params' sigma, tau are not used)
  *  PDRQS2      Algorithm PDRQS2 (§4.2, §4.3.1), the unconstrained problem (no D0)
+ *  ADMM        ADMM with an inner PCG u-step (§4.6), the unconstrained problem
+ *              (no D0), one problem per solver; see ct_solver_set_admm
  * ct_gap is defined for PDRQS1 and RICHARDSON; ct_objective serves all. */
 enum {
   CT_METHOD_PDRQS1 = 0,
   CT_METHOD_RICHARDSON = 1,
   CT_METHOD_CP = 2,
-  CT_METHOD_PDRQS2 = 3
+  CT_METHOD_PDRQS2 = 3,
+  CT_METHOD_ADMM = 4
 };
 
 typedef struct ct_params {
@@ -276,6 +279,19 @@ enum {
   CT_FIT_HARD = 4
 };
 int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s);
+
+/* ADMM options (§4.6) of a CT_METHOD_ADMM solver, before its first iteration:
+ * cg_steps in [1, 64] preconditioned conjugate-gradient steps per iteration on
+ * (A^* A - tau^2 Delta_h) u = A^*(z_w - eta_w) - tau^2 div(z_v - eta_v), started
+ * from the current u, preconditioned by rho_eps / (c + tau^2 lambda_Delta
+ * rho_eps) (§4.3.1); the augmented-Lagrangian weight mu > 0 (Lambda = diag(1,
+ * tau) weights the gradient block).  One iteration: the PCG u-step, then
+ * w = (b + mu (A u + eta_w)) / (1 + mu), v = soft(nabla u + eta_v,
+ * lambda~ / (mu tau^2)), eta <- eta - (z - K u).  Defaults: 1 step, mu = 1.
+ * The solver's state export gives (u, eta_w, eta_v).
+ * Errors: CT_E_INVALID, CT_E_UNSUPPORTED (not an ADMM solver), CT_E_STATE
+ * (after the first iteration). */
+int ct_solver_set_admm(ct_solver *sv, int32_t cg_steps, double mu);
 
 /* Run k iterations of PDRQS1 (§4.4) on the solver's state:
  *   u_tmp = -sigma (A^*(vb1 + sigma A u) - tau div(vb2 + sigma tau nabla u))

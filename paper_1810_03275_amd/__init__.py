@@ -299,7 +299,8 @@ class Solver:
                  power_iters: int = 30, validate: bool = False,
                  start_norm: Optional[torch.Tensor] = None,
                  start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0,
-                 nonneg: bool = False, method: str = "pdrqs1"):
+                 nonneg: bool = False, method: str = "pdrqs1", cg_steps: int = 1,
+                 mu: float = 1.0):
         self.plan = plan
         self._keep = (sino, mask_bits, bound, start_norm, start_precond)
         prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
@@ -309,6 +310,9 @@ class Solver:
         _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
                                    ctypes.byref(h)), "ct_solver_create")
         self._h = h
+        if method == "admm":
+            # ADMM (§4.6): PCG steps per iteration and the augmented-Lagrangian weight
+            _check(_L.ct_solver_set_admm(h, int(cg_steps), float(mu)), "ct_solver_set_admm")
 
     def info(self) -> dict:
         o = (ctypes.c_double * 4)()

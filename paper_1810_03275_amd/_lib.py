@@ -16,7 +16,7 @@ ERRORS = {-1: "CT_E_INVALID", -2: "CT_E_UNSUPPORTED", -3: "CT_E_DEVICE",
 CT_FLAG_VALIDATE = 1
 CT_FLAG_NONNEG = 2
 CT_METHOD_SHIFT = 4
-METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3}
+METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3, "admm": 4}
 FITS = {"standard": 0, "weighted": 1, "ignore": 2, "everywhere": 3, "hard": 4}
 
 
@@ -70,6 +70,7 @@ SIGNATURES = {
     "ct_plan_check": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(ctypes.c_int64)]),
     "ct_pd_step": (c_int32, [c_void_p, c_int32, c_void_p]),
     "ct_solver_set_fit": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "ct_solver_set_admm": (c_int32, [c_void_p, c_int32, c_double]),
     "ct_pd_step_timed": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p]),
     "ct_state_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_state_import": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -164,6 +164,12 @@ struct ct_solver {
   double rich_m = 0;          // Richardson: M = rich_m id
   int fit = 0;                // data-term variant (CT_FIT_*)
   float *fit_aux = nullptr;   // its per-bin array (nb sinograms) or NULL
+  // ADMM (§4.6): vb1, vb2 hold eta_w, eta_v; s1, s2 the u-step residual terms
+  // (z_w - eta_w) - A u and (z_v - eta_v) - nabla u; PCG vectors and scalars
+  int admm_cg = 1;
+  double admm_mu = 1.0;
+  float *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Hp = nullptr;
+  double *d_cg = nullptr;     // [0], [1] r.z (alternating), [2] p.Hp, then dot partials
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -183,12 +189,13 @@ static void solver_free(ct_solver *sv) {
   if (!sv) return;
   float *bufs[] = {sv->u, sv->u_next, sv->vb1, sv->s1, sv->vb2, sv->s2, sv->target,
                    sv->rraw, sv->utmp, sv->y1, sv->r, sv->w, sv->bp_part, sv->ubar, sv->ucp,
-                   sv->fit_aux};
+                   sv->fit_aux, sv->cg_r, sv->cg_z, sv->cg_p, sv->cg_Hp};
   for (float *b : bufs) (void)hipFree(b);
   (void)hipFree(sv->mask);
   (void)hipFree(sv->spec);
   (void)hipFree(sv->d_red);
   (void)hipFree(sv->d_out);
+  (void)hipFree(sv->d_cg);
   for (auto &g : sv->gexec)
     if (g) (void)hipGraphExecDestroy(g);
   if (sv->cap_stream) (void)hipStreamDestroy(sv->cap_stream);
@@ -533,9 +540,54 @@ static int cp_iter(ct_solver *sv, hipStream_t st) {
   return CT_OK;
 }
 
+// One ADMM iteration (§4.6) on the normalized unconstrained problem (nb = 1):
+// the PCG u-step on H u = A^*(z_w - eta_w) - tau^2 div(z_v - eta_v),
+// H = A^* A - tau^2 div nabla, from the current u; then the z-step and the
+// multiplier update, fused into the epilogues of R_h u and nabla_h u.
+static int admm_iter(ct_solver *sv, hipStream_t st) {
+  ct_plan *p = sv->plan;
+  const int64_t nn = (int64_t)sv->n * sv->n;
+  const float inv_h = (float)(1.0 / p->g.h);
+  const float t2 = (float)(sv->tau * sv->tau);
+  const float inv_b = (float)(1.0 / sv->beta), inv_b2 = (float)(1.0 / (sv->beta * sv->beta));
+  double *sc = sv->d_cg, *part = sv->d_cg + 4;
+  // r = rhs - H u = A^*((z_w - eta_w) - A u) - tau^2 div((z_v - eta_v) - nabla u)
+  CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, inv_b, -t2, sv->cg_r, st, 1, sv->bp_part,
+                          sv->bp_S));
+  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->cg_r, nullptr, sv->cg_z, st));
+  CT_TRY(launch_dot(sv->cg_r, sv->cg_z, nn, part, sc + 0, st));
+  CT_TRY(launch_cg_dir(nn, nullptr, nullptr, sv->cg_z, sv->cg_p, st));
+  int cur = 0;
+  for (int k = 0; k < sv->admm_cg; ++k) {
+    // Hp = A^*(A p) - tau^2 div(nabla p)
+    CT_TRY(launch_radon_fwd(p, sv->cg_p, sv->r, st));
+    CT_TRY(launch_grad(sv->n, inv_h, sv->cg_p, sv->w, st));
+    CT_TRY(launch_radon_adj(p, sv->r, sv->w, inv_b2, -t2, sv->cg_Hp, st, 1, sv->bp_part,
+                            sv->bp_S));
+    CT_TRY(launch_dot(sv->cg_p, sv->cg_Hp, nn, part, sc + 2, st));
+    CT_TRY(launch_cg_update(nn, sc + cur, sc + 2, sv->cg_p, sv->cg_Hp, sv->u, sv->cg_r, st));
+    if (k + 1 < sv->admm_cg) {  // the direction after the last step is not used
+      CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->cg_r, nullptr, sv->cg_z, st));
+      CT_TRY(launch_dot(sv->cg_r, sv->cg_z, nn, part, sc + (1 - cur), st));
+      CT_TRY(launch_cg_dir(nn, sc + (1 - cur), sc + cur, sv->cg_z, sv->cg_p, st));
+      cur = 1 - cur;
+    }
+  }
+  // z-step and eta update from A u and nabla u (mu travels in the sigma field)
+  const SinoEpi ep{inv_b, (float)sv->admm_mu, sv->target, nullptr, sv->vb1, sv->s1, nullptr,
+                   nullptr, 6};
+  CT_TRY(launch_radon_fwd(p, sv->u, nullptr, st, &ep));
+  CT_TRY(launch_tv_update(sv->n, inv_h, sv->u, 0.f,
+                          (float)(sv->lam_t / (sv->admm_mu * sv->tau * sv->tau)), sv->vb2,
+                          sv->s2, nullptr, 5, st));
+  sv->iters += 1;
+  return CT_OK;
+}
+
 static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev = nullptr,
                        float *q1out = nullptr, float *q2out = nullptr) {
   if (sv->method == CT_METHOD_CP) return cp_iter(sv, st);
+  if (sv->method == CT_METHOD_ADMM) return admm_iter(sv, st);
   ct_plan *p = sv->plan;
   const float sig = (float)sv->sigma, tau = (float)sv->tau;
   const float inv_h = (float)(1.0 / p->g.h);
@@ -632,6 +684,11 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   CT_TRY(solver_alloc(sv));
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
+  if (sv->method == CT_METHOD_ADMM) {
+    for (float **b : {&sv->cg_r, &sv->cg_z, &sv->cg_p, &sv->cg_Hp})
+      CT_TRY_HIP(hipMalloc(b, sizeof(float) * nn));
+    CT_TRY_HIP(hipMalloc(&sv->d_cg, sizeof(double) * (4 + dot_partials_needed())));
+  }
   CT_TRY(solver_set_slices(sv, p->bp_slices));
   for (int b = 0; b < nb; ++b) {
     uint32_t *mb = sv->mask + (size_t)b * N * MW;
@@ -726,8 +783,10 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
                       8.0 * (sv->sigma * sv->tau) * (sv->sigma * sv->tau) / (p->g.h * p->g.h));
   {
     // PDRQS2 (§4.3.1 with Q = A^* A): rho / (sigma c + (sigma tau)^2 lambda_Delta rho)
+    // ADMM (§4.6): rho / (c + tau^2 lambda_Delta rho), i.e. the table at sigma = 1
     const double csig = sv->method == CT_METHOD_PDRQS2 ? sv->c / sv->sigma : sv->c;
-    auto m = multiplier_table(n, sv->sigma, sv->tau, csig, sv->eps, false, sv->ubar != nullptr);
+    const double sig_m = sv->method == CT_METHOD_ADMM ? 1.0 : sv->sigma;
+    auto m = multiplier_table(n, sig_m, sv->tau, csig, sv->eps, false, sv->ubar != nullptr);
     CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, m.data(), sizeof(float) * m.size(),
                               hipMemcpyHostToDevice, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
@@ -843,9 +902,19 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     return CT_E_UNSUPPORTED;
   }
   const int method = (int)((prm->flags >> CT_METHOD_SHIFT) & 15u);
-  if (method > CT_METHOD_PDRQS2) {
+  if (method > CT_METHOD_ADMM) {
     set_error("ct_solver_create: unknown method");
     return CT_E_INVALID;
+  }
+  if (method == CT_METHOD_ADMM) {
+    if (nb != 1) {
+      set_error("ct_solver_create: ADMM runs one problem per solver");
+      return CT_E_UNSUPPORTED;
+    }
+    if (probs[0].mask) {
+      set_error("ct_solver_create: ADMM solves the unconstrained problem (no D0)");
+      return CT_E_UNSUPPORTED;
+    }
   }
   if (method != CT_METHOD_PDRQS1 && method != CT_METHOD_RICHARDSON &&
       (prm->flags & CT_FLAG_NONNEG)) {
@@ -997,6 +1066,25 @@ int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s)
   return CT_OK;
 }
 
+int ct_solver_set_admm(ct_solver *sv, int32_t cg_steps, double mu) {
+  clear_error();
+  if (!sv || cg_steps < 1 || cg_steps > 64 || !(mu > 0) || !std::isfinite(mu)) {
+    set_error("ct_solver_set_admm: need 1 <= cg_steps <= 64 and mu > 0");
+    return CT_E_INVALID;
+  }
+  if (sv->method != CT_METHOD_ADMM) {
+    set_error("ct_solver_set_admm: not an ADMM solver");
+    return CT_E_UNSUPPORTED;
+  }
+  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1]) {
+    set_error("ct_solver_set_admm: set the options before the first iteration");
+    return CT_E_STATE;
+  }
+  sv->admm_cg = cg_steps;
+  sv->admm_mu = mu;
+  return CT_OK;
+}
+
 int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s) {
   clear_error();
   if (!sv || k < 0) {
@@ -1017,6 +1105,10 @@ int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s) {
   if (!sv || k < 1 || !ms_out) {
     set_error("ct_pd_step_timed: invalid argument");
     return CT_E_INVALID;
+  }
+  if (sv->method == CT_METHOD_ADMM) {
+    set_error("ct_pd_step_timed: the phase split is that of the PDRQ iterations");
+    return CT_E_UNSUPPORTED;
   }
   hipStream_t st = S(s);
   hipEvent_t ev[5] = {};
@@ -1097,6 +1189,10 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
     set_error("ct_state_import: null argument");
     return CT_E_INVALID;
   }
+  if (sv->method == CT_METHOD_ADMM) {
+    set_error("ct_state_import: an ADMM state also holds z (not importable)");
+    return CT_E_UNSUPPORTED;
+  }
   const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
   hipStream_t st = S(s);
   CT_TRY_HIP(hipMemcpyAsync(sv->u, u, sizeof(float) * nn, hipMemcpyDeviceToDevice, st));
@@ -1129,7 +1225,8 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
     set_error("ct_gap: no iteration since creation or import");
     return CT_E_STATE;
   }
-  if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2 || sv->fit != CT_FIT_STANDARD) {
+  if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2 ||
+      sv->method == CT_METHOD_ADMM || sv->fit != CT_FIT_STANDARD) {
     set_error("ct_gap: the record is defined for PDRQS1 with the standard data term");
     return CT_E_UNSUPPORTED;
   }

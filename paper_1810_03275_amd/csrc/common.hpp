@@ -181,7 +181,7 @@ struct SinoEpi {
   float *y1;
   float *r;
   int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep,
-                 // 4 Algorithm CP dual step, 5 PDRQS2 residual
+                 // 4 Algorithm CP dual step, 5 PDRQS2 residual, 6 ADMM z-step (mu in sigma)
   float *q1 = nullptr;  // optional: the resolvent input 2 v1 - vb1 (modes 0, 2)
   int fit = 0;          // data term (modes 0, 2): CT_FIT_* of the C ABI
   const float *aux = nullptr;  // weights (weighted fit) or b on every bin (fit everywhere)
@@ -196,6 +196,16 @@ constexpr int kDilMaxRadius = 16;
 int launch_d0_estimate(const ct_plan *p, const float *u, float thr, int r, float kappa,
                        float *chi, float *proj, uint32_t *mask, const float *u0, float c0,
                        float *bound, hipStream_t s);
+
+// ADMM's conjugate gradients: FP64 dot product into out[0]; u += a p,
+// r -= a Hp with a = rz / pHp read on the device; p = z + (rz_new/rz_old) p
+size_t dot_partials_needed();
+int launch_dot(const float *x, const float *y, int64_t count, double *partials, double *out,
+               hipStream_t s);
+int launch_cg_update(int64_t count, const double *rz, const double *pHp, const float *p,
+                     const float *Hp, float *u, float *r, hipStream_t s);
+int launch_cg_dir(int64_t count, const double *rz_new, const double *rz_old, const float *z,
+                  float *p, hipStream_t s);
 
 int launch_grad(int n, float inv_h, const float *u, float *p, hipStream_t s);
 int launch_div(int n, float inv_h, const float *p, float *d, hipStream_t s);

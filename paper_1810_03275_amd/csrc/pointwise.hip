@@ -75,6 +75,20 @@ __global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, flo
   const float g1 = (i < n - 1) ? (u[o + 1] - c) * inv_h : 0.f;
   const float g2 = (j < n - 1) ? (u[o + n] - c) * inv_h : 0.f;
   const float b1 = vb2[o], b2 = vb2[o + nn];
+  if (mode == 5) {
+    // ADMM z-step and multiplier update (§4.6), gradient block: s = nabla u
+    // + eta_v, v = soft(s, radius) (the lemma of §4.6), eta_v <- s - v, and
+    // the next u-step's residual term (v - eta_v) - nabla u = 2 v - s - nabla u
+    const float t1 = g1 + b1, t2 = g2 + b2;
+    const float nq = sqrtf(t1 * t1 + t2 * t2);
+    const float sc = nq > radius ? 1.f - radius / nq : 0.f;
+    const float v1 = sc * t1, v2 = sc * t2;
+    vb2[o] = t1 - v1;
+    vb2[o + nn] = t2 - v2;
+    s2[o] = 2.f * v1 - t1 - g1;
+    s2[o + nn] = 2.f * v2 - t2 - g2;
+    return;
+  }
   if (mode == 1) {
     s2[o] = fmaf(st, g1, b1);
     s2[o + nn] = fmaf(st, g2, b2);

@@ -351,6 +351,16 @@ __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, in
     return;
   }
   const float vb = ep.vb1[o];
+  if (ep.mode == 6) {
+    // ADMM z-step and multiplier update (§4.6), data block, mu in the sigma
+    // field: s = A u + eta_w, w = (b + mu s)/(1 + mu), eta_w <- s - w, and
+    // the next u-step's residual term (w - eta_w) - A u = 2 w - s - A u
+    const float sw = r + vb;
+    const float w = fmaf(ep.sigma, sw, ep.target[o]) / (1.f + ep.sigma);
+    ep.vb1[o] = sw - w;
+    ep.s1[o] = 2.f * w - sw - r;
+    return;
+  }
   if (ep.mode == 4) {
     // Algorithm CP: v <- resolvent of the data term's conjugate, step sigma,
     // at v + sigma A u (here u is the extrapolated iterate)

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import synth
-from oracle import cp, pdrq, pdrq2
+from oracle import admm, cp, pdrq, pdrq2, tv
 
 from oracle_inputs import build, f32
 
@@ -127,8 +127,48 @@ def test_method_errors():
     with pytest.raises(ct.CtpdError):
         ct.Solver(plan, z, 0.01, method="cp", nonneg=True)
     with pytest.raises(ValueError):
-        ct.Solver(plan, z, 0.01, method="admm")
+        ct.Solver(plan, z, 0.01, method="no-such-method")
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, m, method="admm")       # ADMM has no D0
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, method="admm", cg_steps=0)
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, method="admm", mu=-1.0)
+    sa = ct.Solver(plan, z, 0.01, method="admm")
+    sa.step(1)
+    assert ct.lib.ct_solver_set_admm(sa._h, 2, 1.0) != 0  # after the first iteration
+    with pytest.raises(ct.CtpdError):
+        sa.gap()
     sv = ct.Solver(plan, z, 0.01, method="cp")
     sv.step(2)
     with pytest.raises(ct.CtpdError):
         sv.gap()
+
+
+@pytest.mark.parametrize("cg_steps,mu", [(1, 1.0), (2, 1.0), (1, 2.0)])
+def test_admm_matches_oracle(cg_steps, mu):
+    print("admm", cg_steps, mu, flush=True)
+    w, g, u0, mask, bound = _free()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    probe = ct.Solver(plan, gpu(u0), w.alpha)
+    inf = probe.info()
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    st = admm.zero_state(s)
+    done = 0
+    for k, tol in ((1, 1e-5), (2, 1e-5), (3, 1e-5), (40, 1e-4)):
+        sv = ct.Solver(plan, gpu(u0), w.alpha, beta=inf["beta"], c=inf["c"], method="admm",
+                       cg_steps=cg_steps, mu=mu)
+        sv.step(k)
+        while done < k:
+            st = admm.step(s, st, cg_steps, mu)
+            done += 1
+        gu, gew, gev = (host(t) for t in sv.export())
+        assert rel(gu, st.u) <= tol, (k, rel(gu, st.u))
+        # the multipliers are small differences of the projections and
+        # gradients they are formed from (eta_v lies in the ball of radius
+        # lambda~/(mu tau^2)), so their FP32 error is measured on that scale
+        sw = max(np.linalg.norm(s.A(st.u)), np.linalg.norm(st.ew))
+        sv_ = max(np.linalg.norm(tv.grad(st.u, 1.0)), np.linalg.norm(st.ev))
+        assert np.linalg.norm(gew - st.ew) <= 10 * tol * sw
+        assert np.linalg.norm(gev - st.ev) <= 10 * tol * sv_
