@@ -181,7 +181,8 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
     """The preconditioning comparison of the thesis' results (objective value
     relative to the smallest attained, per iteration): PDRQS1 with the
     inverse-norm preconditioner, PDRQS1 with Richardson's M = m id, Algorithm
-    CP and PDRQS2, on an unconstrained random-ellipse phantom (n^2, N = 1.4 n,
+    CP, PDRQS2 and ADMM with 1 and 2 inner PCG steps (mu = 1), on an
+    unconstrained random-ellipse phantom (n^2, N = 1.4 n,
     M = 1.5 n, 1 % noise).  Reports the iterations and seconds each method needs
     to bring (P - P*)/P* below 1, 1e-1 and 1e-2, with P* the smallest
     objective any method reached (the thesis' measure; P* being an attained
@@ -196,11 +197,15 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
     marks = sorted(set([int(round(2 ** (i / 2))) for i in range(0, 60)
                         if 2 ** (i / 2) <= kmax] + [kmax]))
     curves, rates = {}, {}
-    for method in ("pdrqs1", "richardson", "cp", "pdrqs2"):
-        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], method=method)
+    methods = {"pdrqs1": {}, "richardson": {}, "cp": {}, "pdrqs2": {},
+               "admm_cg1": {"method": "admm", "cg_steps": 1},
+               "admm_cg2": {"method": "admm", "cg_steps": 2}}
+    for method, opts in methods.items():
+        kw = opts or {"method": method}
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], **kw)
         done, vals = 0, []
         sv.step(10)   # warm-up (graph capture), then restart from zero
-        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], method=method)
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], **kw)
         torch.cuda.synchronize()
         t_run = 0.0
         for m in marks:
@@ -231,10 +236,11 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
 
 
 def precond_comparisons(ct, torch, kmax: int):
-    """The comparison at the workload's weight and at lambda = 0.3 (the weight
-    of the thesis' comparison figure)."""
+    """The comparison at the workload's weight, at lambda = 0.1 (the weight of
+    the thesis' ADMM figure) and at lambda = 0.3 (that of its preconditioning
+    figure)."""
     return {f"lambda={lam:g}": precond_comparison(ct, torch, lam=lam, kmax=kmax)
-            for lam in (0.005, 0.3)}
+            for lam in (0.005, 0.1, 0.3)}
 
 
 def mar_pipeline(ct, torch, w, plan, u0, true_mask, iters: int, reps: int = 20):
