@@ -81,24 +81,39 @@ class Setup:
 
 def setup(problem: Problem, params: Params, start_norm: np.ndarray | None = None,
           start_precond: np.ndarray | None = None, beta: float | None = None,
-          c: float | None = None, fwd=None, adj=None) -> Setup:
-    """Normalization (§5.1) and preconditioner constant (§4.3.1).
+          c: float | None = None, fwd=None, adj=None, kind: str = "invnorm") -> Setup:
+    """Normalization (§5.1) and preconditioner constant (§4.3.1, §4.3.2).
 
     beta and c are estimated by power iteration from the given start images
     unless passed explicitly.  fwd/adj replace R_h/R_h^* (e.g. by an explicit
     matrix on tiny problems); by default the radon module's pair is used.
+    kind selects the preconditioner of PDRQS1: "invnorm" (§4.3.1: c scales the
+    inverse-norm part) or "impulse" (§4.3.2: c scales M_K, the deconvolution
+    by the impulse response of A^* A plus the periodic Laplacian).
     """
     g = problem.geom
     fwd = fwd or (lambda u: radon.radon_fwd(g, u))
     adj = adj or (lambda v: radon.radon_adj(g, v))
     if beta is None:
         beta = power.radon_norm(fwd, adj, start_norm, params.power_iters)
-    if c is None:
-        lmax = power.precond_constant_eig(lambda u: fwd(u) / beta,
-                                          lambda v: adj(v) / beta,
-                                          start_precond, params.eps, params.power_iters)
-        c = params.c_safety * lmax
-    mult = precond.multiplier(g.n, params.sigma, params.tau, c, params.eps)
+    A = lambda u: fwd(u) / beta
+    At = lambda v: adj(v) / beta
+    if kind == "impulse":
+        sig, tau = params.sigma, params.tau
+        khat = precond.kernel_symbol(precond.impulse_kernel(A, At, g.n))
+        fK = precond.impulse_full_symbol(khat, sig * sig, (sig * tau) ** 2)
+        if not np.all(fK > 0):
+            raise ValueError("impulse-response preconditioner: F(K) is not positive")
+        if c is None:
+            c = params.c_safety * power.impulse_constant_eig(
+                A, At, fK, sig * sig, (sig * tau) ** 2, g.h, start_precond, params.power_iters)
+        mult = precond.impulse_multiplier(fK, c)
+    else:
+        if c is None:
+            lmax = power.precond_constant_eig(A, At, start_precond, params.eps,
+                                              params.power_iters)
+            c = params.c_safety * lmax
+        mult = precond.multiplier(g.n, params.sigma, params.tau, c, params.eps)
     return Setup(problem, params, float(beta), float(c),
                  np.asarray(problem.u0, dtype=np.float64) / beta,
                  np.asarray(problem.bound, dtype=np.float64) / beta,

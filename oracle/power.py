@@ -49,3 +49,18 @@ def precond_constant_eig(fwd_a, adj_a, x0: np.ndarray, eps: float, iters: int = 
         z = adj_a(fwd_a(z))
         return precond.sqrt_inv_norm_precond(z, eps)
     return power_max_eig(op, x0, iters)
+
+
+def impulse_constant_eig(fwd_a, adj_a, fK: np.ndarray, alpha: float, beta: float, h: float,
+                         x0: np.ndarray, iters: int = 30) -> float:
+    """lambda_max(M_K^{-1} T) = lambda_max(M_K^{-1/2} T M_K^{-1/2}) for the
+    impulse-response preconditioner (§4.3.2), T = alpha A^* A - beta div nabla."""
+    from . import tv
+    s = 1.0 / np.sqrt(fK)
+
+    def op(x):
+        y = precond.apply_multiplier(x, s)
+        t = alpha * adj_a(fwd_a(y)) - beta * tv.div(tv.grad(y, h), h)
+        return precond.apply_multiplier(t, s)
+
+    return power_max_eig(op, x0, iters)

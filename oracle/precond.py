@@ -68,3 +68,63 @@ def multiplier_nonneg(n: int, sigma: float, tau: float, c: float, eps: float) ->
     inverse of M = id + c sigma^2 tilde M - (sigma tau)^2 Delta_p."""
     r = rho_eps(n, eps)
     return r / (r + sigma * sigma * c + (sigma * tau) ** 2 * lap_symbol(n) * r)
+
+
+# ---------------------------------------------------------------------------
+# Impulse-response preconditioner (§4.3.2).
+#
+# The response of A^* A to a unit impulse at pixel (n/2, n/2) (n even) is
+# taken as a convolution kernel: k~ = A^* A delta.  Readings:
+#  * the kernel of a periodic deconvolution has its centre at the origin, so
+#    k~ is read centred on the impulse: k(x) = k~(n/2 + x) with x taken
+#    modulo n (the thesis leaves the shift implicit);
+#  * "k = 1/2 (k~ + k~^T) to guarantee a symmetric preconditioner": the
+#    average over the eight symmetries of the square about the origin
+#    (transposition as printed, and the two axis mirrors).  It contains the
+#    printed average, makes k point symmetric (so that deconvolution by it is
+#    a symmetric operator, F(k) real) and even in each axis, as the other
+#    multipliers are;
+#  * with T = alpha A^* A - beta Delta_h (alpha = sigma^2, beta = (sigma tau)^2
+#    for PDRQS1) the full kernel K = alpha k + beta kappa_Delta has the real
+#    symbol F(K) = alpha F(k) + beta lambda_Delta, and the preconditioner is
+#    c M_K with M_K = F^{-1} F(K) F, c = c_safety lambda_max(M_K^{-1} T) (the
+#    constant of "c M - T >= 0" scales the whole M here, as printed).
+#  F(k) itself can dip below zero at the highest frequencies (the
+#  interpolation's response); F(K) must be positive, which the setup checks.
+
+def center_and_symmetrize(kt: np.ndarray) -> np.ndarray:
+    """k(x) = mean over the 8 symmetries g of the square of k~(n/2 + g x),
+    indices modulo n."""
+    n = kt.shape[0]
+    kc = np.roll(kt, (-(n // 2), -(n // 2)), axis=(0, 1))   # k~(n/2 + x) at x
+    out = np.zeros_like(kc, dtype=np.float64)
+    idx = np.arange(n)
+    neg = (-idx) % n
+    for base in (kc, kc.T):
+        for ry in (idx, neg):
+            for rx in (idx, neg):
+                out += base[np.ix_(ry, rx)]
+    return out / 8.0
+
+
+def impulse_kernel(A, At, n: int) -> np.ndarray:
+    """The symmetrized, origin-centred response k of A^* A to delta at (n/2, n/2)."""
+    d = np.zeros((n, n))
+    d[n // 2, n // 2] = 1.0
+    return center_and_symmetrize(At(A(d)))
+
+
+def kernel_symbol(k: np.ndarray) -> np.ndarray:
+    """F(k) for a real kernel that is even in each axis (real-valued)."""
+    f = np.fft.fft2(k)
+    return np.real(f)
+
+
+def impulse_full_symbol(khat: np.ndarray, alpha: float, beta: float) -> np.ndarray:
+    """F(K) = alpha F(k) + beta lambda_Delta."""
+    return alpha * khat + beta * lap_symbol(khat.shape[0])
+
+
+def impulse_multiplier(fK: np.ndarray, c: float) -> np.ndarray:
+    """(c M_K)^{-1} as a Fourier multiplier: 1 / (c F(K))."""
+    return 1.0 / (c * fK)
