@@ -180,6 +180,20 @@ enum {
  *  ADMM        ADMM with an inner PCG u-step (§4.6), the unconstrained problem
  *              (no D0), one problem per solver; see ct_solver_set_admm
  * ct_gap is defined for PDRQS1 and RICHARDSON; ct_objective serves all. */
+/* Preconditioner of PDRQS1 (flags |= kind << CT_PRECOND_SHIFT):
+ *  INVNORM   inverse norm + periodic Laplacian (§4.3.1): rho / (sigma^2 c +
+ *            (sigma tau)^2 lambda_Delta rho), c = c_safety lambda_max(tilde M^{-1} A^* A)
+ *  IMPULSE   impulse response (§4.3.2): k = the response of A^* A to a unit
+ *            impulse at (n/2, n/2), centred at the origin and averaged over the
+ *            symmetries of the square; K = sigma^2 k + (sigma tau)^2 kappa_Delta;
+ *            M = c F^{-1} F(K) F with c = c_safety lambda_max(M_K^{-1} T) (even n;
+ *            CT_E_UNSUPPORTED if F(K) is not positive or for other methods) */
+enum {
+  CT_PRECOND_SHIFT = 8u,
+  CT_PRECOND_INVNORM = 0,
+  CT_PRECOND_IMPULSE = 1
+};
+
 enum {
   CT_METHOD_PDRQS1 = 0,
   CT_METHOD_RICHARDSON = 1,

@@ -259,7 +259,7 @@ def power_norm(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -
 
 
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-            start_norm, start_precond, n, nonneg=False, method="pdrqs1"):
+            start_norm, start_precond, n, nonneg=False, method="pdrqs1", precond="invnorm"):
     p = _lib.CtParams()
     _L.ct_params_default(ctypes.byref(p))
     p.sigma, p.tau, p.eps = sigma, tau, eps
@@ -269,9 +269,12 @@ def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, v
     p.k_max, p.gap_every, p.power_iters = k_max, gap_every, power_iters
     if method not in _lib.METHODS:
         raise ValueError(f"method must be one of {sorted(_lib.METHODS)}")
+    if precond not in _lib.PRECONDS:
+        raise ValueError(f"precond must be one of {sorted(_lib.PRECONDS)}")
     p.flags = ((_lib.CT_FLAG_VALIDATE if validate else 0)
                | (_lib.CT_FLAG_NONNEG if nonneg else 0)
-               | (_lib.METHODS[method] << _lib.CT_METHOD_SHIFT))
+               | (_lib.METHODS[method] << _lib.CT_METHOD_SHIFT)
+               | (_lib.PRECONDS[precond] << _lib.CT_PRECOND_SHIFT))
     p.start_norm = _dev(start_norm, (n, n), "start_norm") if start_norm is not None else None
     p.start_precond = (_dev(start_precond, (n, n), "start_precond")
                        if start_precond is not None else None)
@@ -300,12 +303,12 @@ class Solver:
                  start_norm: Optional[torch.Tensor] = None,
                  start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0,
                  nonneg: bool = False, method: str = "pdrqs1", cg_steps: int = 1,
-                 mu: float = 1.0):
+                 mu: float = 1.0, precond: str = "invnorm"):
         self.plan = plan
         self._keep = (sino, mask_bits, bound, start_norm, start_precond)
         prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n, nonneg, method)
+                      start_norm, start_precond, plan.n, nonneg, method, precond)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
                                    ctypes.byref(h)), "ct_solver_create")

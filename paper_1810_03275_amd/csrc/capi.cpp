@@ -675,6 +675,106 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   return solver_set_slices(sv, bestS);
 }
 
+// Impulse-response preconditioner (§4.3.2) for PDRQS1: k = the response of
+// A^* A to a unit impulse at (n/2, n/2), centred at the origin and averaged
+// over the eight symmetries of the square; F(K) = sigma^2 F(k) + (sigma
+// tau)^2 lambda_Delta; c = c_safety lambda_max(M_K^{-1} T) by power iteration
+// unless given, T = sigma^2 A^* A - (sigma tau)^2 div nabla; multiplier
+// 1 / (c F(K)).  F(k) comes from the FFT pair itself: with the kernel as the
+// multiplier table (unnormalized) and a unit impulse at the origin as input,
+// the pair returns the (even, real) transform of the kernel.
+static int impulse_setup(ct_solver *sv, const ct_params *prm, hipStream_t st) {
+  ct_plan *p = sv->plan;
+  const int n = sv->n, half = n / 2 + 1;
+  const size_t nn = (size_t)n * n;
+  const double sig = sv->sigma, st2 = (sv->sigma * sv->tau) * (sv->sigma * sv->tau);
+  std::vector<float> img(nn, 0.f);
+  img[(size_t)(n / 2) * n + n / 2] = 1.f;
+  CT_TRY_HIP(hipMemcpyAsync(sv->u, img.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+  CT_TRY(launch_radon_fwd(p, sv->u, sv->rraw, st));
+  CT_TRY(launch_radon_adj(p, sv->rraw, nullptr, (float)(1.0 / (sv->beta * sv->beta)), 0.0f,
+                          sv->utmp, st, 1, sv->bp_part, sv->bp_S));
+  std::vector<float> kt(nn);
+  CT_TRY_HIP(hipMemcpyAsync(kt.data(), sv->utmp, sizeof(float) * nn, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  // k(x1, x2) = mean over g of kt(n/2 + g(x)), indices modulo n; as the table
+  // m[x1][x2] for x1 in [0, n/2] (k is even, the other half mirrors it)
+  auto at = [&](int y, int x) {
+    return (double)kt[(size_t)((y + n / 2) % n) * n + (size_t)((x + n / 2) % n)];
+  };
+  std::vector<float> tab((size_t)half * n);
+  for (int x1 = 0; x1 < half; ++x1)
+    for (int x2 = 0; x2 < n; ++x2) {
+      const int a = x1, b = x2, na = (n - a) % n, nb2 = (n - b) % n;
+      const double v = at(b, a) + at(b, na) + at(nb2, a) + at(nb2, na) + at(a, b) + at(a, nb2) +
+                       at(na, b) + at(na, nb2);
+      tab[(size_t)x1 * n + x2] = (float)(v / 8.0);
+    }
+  CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, tab.data(), sizeof(float) * tab.size(),
+                            hipMemcpyHostToDevice, st));
+  std::fill(img.begin(), img.end(), 0.f);
+  img[0] = 1.f;
+  CT_TRY_HIP(hipMemcpyAsync(sv->u, img.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+  CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->u, nullptr, sv->utmp, st));
+  std::vector<float> kh(nn);
+  CT_TRY_HIP(hipMemcpyAsync(kh.data(), sv->utmp, sizeof(float) * nn, hipMemcpyDeviceToHost, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  // F(K) on the multiplier grid: the output image holds F(k) at (x-freq i, y-freq j)
+  std::vector<double> fK((size_t)half * n);
+  for (int k1 = 0; k1 < half; ++k1) {
+    const double s1 = std::sin(M_PI * k1 / n);
+    for (int k2 = 0; k2 < n; ++k2) {
+      const double s2 = std::sin(M_PI * k2 / n);
+      const double v = sig * sig * (double)kh[(size_t)k2 * n + k1] +
+                       st2 * (4.0 * s1 * s1 + 4.0 * s2 * s2);
+      if (!(v > 0.0) || !std::isfinite(v)) {
+        set_error("ct_solver_create: impulse-response kernel symbol F(K) is not positive");
+        return CT_E_UNSUPPORTED;
+      }
+      fK[(size_t)k1 * n + k2] = v;
+    }
+  }
+  const double inv_nn = 1.0 / ((double)n * (double)n);
+  if (prm->c > 0) {
+    sv->c = prm->c;
+  } else {
+    // lambda_max(M_K^{-1/2} T M_K^{-1/2}), T = sigma^2 A^* A - (sigma tau)^2 div nabla
+    for (size_t q = 0; q < tab.size(); ++q) tab[q] = (float)(inv_nn / std::sqrt(fK[q]));
+    CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, tab.data(), sizeof(float) * tab.size(),
+                              hipMemcpyHostToDevice, st));
+    if (prm->start_precond)
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, prm->start_precond, sizeof(float) * nn,
+                                hipMemcpyDeviceToDevice, st));
+    else {
+      auto h0 = default_start(n);
+      CT_TRY_HIP(hipMemcpyAsync(sv->u, h0.data(), sizeof(float) * nn, hipMemcpyHostToDevice, st));
+    }
+    CT_TRY_HIP(hipStreamSynchronize(st));
+    const float inv_h = (float)(1.0 / p->g.h);
+    auto op = [&](float *xin, float *yout) -> int {
+      CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, xin, nullptr, sv->u_next, st));
+      CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st));
+      CT_TRY(launch_grad(n, inv_h, sv->u_next, sv->w, st));
+      CT_TRY(launch_radon_adj(p, sv->rraw, sv->w, (float)(sig * sig / (sv->beta * sv->beta)),
+                              (float)(-st2), sv->u_next, st, 1, sv->bp_part, sv->bp_S));
+      return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->u_next, nullptr, yout, st);
+    };
+    double lam = 0;
+    CT_TRY(power_iterate(n, prm->power_iters, sv->u, sv->utmp, sv->d_red, sv->red_cap,
+                         sv->d_out, op, st, &lam));
+    sv->c = prm->c_safety * lam;
+  }
+  if (!(sv->c > 0) || !std::isfinite(sv->c)) {
+    set_error("ct_solver_create: preconditioner constant is zero or non-finite");
+    return CT_E_INVALID;
+  }
+  for (size_t q = 0; q < tab.size(); ++q) tab[q] = (float)(inv_nn / (sv->c * fK[q]));
+  CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, tab.data(), sizeof(float) * tab.size(),
+                            hipMemcpyHostToDevice, st));
+  CT_TRY_HIP(hipStreamSynchronize(st));
+  return CT_OK;
+}
+
 static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params *prm,
                         hipStream_t st) {
   ct_plan *p = sv->plan;
@@ -744,6 +844,10 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
     set_error("ct_solver_create: operator norm estimate is zero or non-finite");
     return CT_E_INVALID;
   }
+  const int pkind = (int)((prm->flags >> CT_PRECOND_SHIFT) & 15u);
+  if (pkind == CT_PRECOND_IMPULSE) {
+    CT_TRY(impulse_setup(sv, prm, st));
+  } else {
   // c > lambda_max(tilde M^{-1} A^* A) (§4.3.1), by power iteration on
   // tilde M^{-1/2} A^* A tilde M^{-1/2} unless given
   if (prm->c > 0) {
@@ -791,6 +895,8 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
                               hipMemcpyHostToDevice, st));
     CT_TRY_HIP(hipStreamSynchronize(st));
   }
+  }
+  sv->pc.c = sv->c;
   for (int b = 0; b < nb; ++b)
     CT_TRY(launch_build_target(N, M, probs[b].sino, probs[b].bound, probs[b].bound_scalar,
                                sv->mask + (size_t)b * N * MW, (float)(1.0 / sv->beta),
@@ -905,6 +1011,16 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
   if (method > CT_METHOD_ADMM) {
     set_error("ct_solver_create: unknown method");
     return CT_E_INVALID;
+  }
+  const int pkind = (int)((prm->flags >> CT_PRECOND_SHIFT) & 15u);
+  if (pkind > CT_PRECOND_IMPULSE) {
+    set_error("ct_solver_create: unknown preconditioner");
+    return CT_E_INVALID;
+  }
+  if (pkind == CT_PRECOND_IMPULSE &&
+      (method != CT_METHOD_PDRQS1 || (prm->flags & CT_FLAG_NONNEG) || (p->g.n & 1))) {
+    set_error("ct_solver_create: the impulse-response preconditioner is for PDRQS1 (even n)");
+    return CT_E_UNSUPPORTED;
   }
   if (method == CT_METHOD_ADMM) {
     if (nb != 1) {
