@@ -180,7 +180,8 @@ def large_run(ct, torch, iters: int):
 def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 8192):
     """The preconditioning comparison of the thesis' results (objective value
     relative to the smallest attained, per iteration): PDRQS1 with the
-    inverse-norm preconditioner, PDRQS1 with Richardson's M = m id, Algorithm
+    inverse-norm and with the impulse-response preconditioner, PDRQS1 with
+    Richardson's M = m id, Algorithm
     CP, PDRQS2 and ADMM with 1 and 2 inner PCG steps (mu = 1), on an
     unconstrained random-ellipse phantom (n^2, N = 1.4 n,
     M = 1.5 n, 1 % noise).  Reports the iterations and seconds each method needs
@@ -197,15 +198,18 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
     marks = sorted(set([int(round(2 ** (i / 2))) for i in range(0, 60)
                         if 2 ** (i / 2) <= kmax] + [kmax]))
     curves, rates = {}, {}
-    methods = {"pdrqs1": {}, "richardson": {}, "cp": {}, "pdrqs2": {},
+    methods = {"pdrqs1": {}, "pdrqs1_impulse": {"method": "pdrqs1", "precond": "impulse"},
+               "richardson": {}, "cp": {}, "pdrqs2": {},
                "admm_cg1": {"method": "admm", "cg_steps": 1},
                "admm_cg2": {"method": "admm", "cg_steps": 2}}
     for method, opts in methods.items():
         kw = opts or {"method": method}
-        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], **kw)
+        # the impulse-response preconditioner has its own constant c
+        cc = None if kw.get("precond") == "impulse" else inf["c"]
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=cc, **kw)
         done, vals = 0, []
         sv.step(10)   # warm-up (graph capture), then restart from zero
-        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=inf["c"], **kw)
+        sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=cc, **kw)
         torch.cuda.synchronize()
         t_run = 0.0
         for m in marks:
