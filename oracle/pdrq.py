@@ -88,8 +88,10 @@ def setup(problem: Problem, params: Params, start_norm: np.ndarray | None = None
     unless passed explicitly.  fwd/adj replace R_h/R_h^* (e.g. by an explicit
     matrix on tiny problems); by default the radon module's pair is used.
     kind selects the preconditioner of PDRQS1: "invnorm" (§4.3.1: c scales the
-    inverse-norm part) or "impulse" (§4.3.2: c scales M_K, the deconvolution
-    by the impulse response of A^* A plus the periodic Laplacian).
+    inverse-norm part), "impulse" (§4.3.2: c scales M_K, the deconvolution
+    by the impulse response of A^* A plus the periodic Laplacian) or
+    "circulant" (§4.3.3: the same on the vectorized image, with the 1-D DFT;
+    mult then holds the length-n^2 symbol, applied by apply_precond).
     """
     g = problem.geom
     fwd = fwd or (lambda u: radon.radon_fwd(g, u))
@@ -108,6 +110,16 @@ def setup(problem: Problem, params: Params, start_norm: np.ndarray | None = None
             c = params.c_safety * power.impulse_constant_eig(
                 A, At, fK, sig * sig, (sig * tau) ** 2, g.h, start_precond, params.power_iters)
         mult = precond.impulse_multiplier(fK, c)
+    elif kind == "circulant":
+        sig, tau = params.sigma, params.tau
+        fK = precond.circulant_full_symbol(precond.circulant_kernel(A, At, g.n), sig * sig,
+                                           (sig * tau) ** 2)
+        if not np.all(fK > 0):
+            raise ValueError("circulant preconditioner: F_L(K) is not positive")
+        if c is None:
+            c = params.c_safety * power.circulant_constant_eig(
+                A, At, fK, sig * sig, (sig * tau) ** 2, g.h, start_precond, params.power_iters)
+        mult = 1.0 / (c * fK)
     else:
         if c is None:
             lmax = power.precond_constant_eig(A, At, start_precond, params.eps,
@@ -118,6 +130,14 @@ def setup(problem: Problem, params: Params, start_norm: np.ndarray | None = None
                  np.asarray(problem.u0, dtype=np.float64) / beta,
                  np.asarray(problem.bound, dtype=np.float64) / beta,
                  problem.lam / beta ** 2, mult, fwd, adj)
+
+
+def apply_precond(s: Setup, y: np.ndarray) -> np.ndarray:
+    """M^{-1} y: a 2-D Fourier multiplier, or (circulant preconditioner, a
+    length-n^2 symbol) the 1-D one on the vectorized image."""
+    if s.mult.ndim == 1:
+        return precond.apply_circulant(y, s.mult)
+    return precond.apply_multiplier(y, s.mult)
 
 
 def sino_resolvent(s: Setup, q: np.ndarray, step: float) -> np.ndarray:
@@ -174,7 +194,7 @@ def step(s: Setup, st: State, return_dual: bool = False):
     s1 = st.vb1 + sig * st.r
     s2 = st.vb2 + sig * tau * st.g
     u_tmp = -sig * (s.At(s1) - tau * tv.div(s2, h))
-    u_new = st.u + precond.apply_multiplier(u_tmp, s.mult)
+    u_new = st.u + apply_precond(s, u_tmp)
     r_new = s.A(u_new)
     g_new = tv.grad(u_new, h)
     v1 = st.vb1 + sig * r_new

@@ -64,3 +64,17 @@ def impulse_constant_eig(fwd_a, adj_a, fK: np.ndarray, alpha: float, beta: float
         return precond.apply_multiplier(t, s)
 
     return power_max_eig(op, x0, iters)
+
+
+def circulant_constant_eig(fwd_a, adj_a, fK: np.ndarray, alpha: float, beta: float, h: float,
+                           x0: np.ndarray, iters: int = 30) -> float:
+    """lambda_max(M_K^{-1} T) for the circulant preconditioner (§4.3.3)."""
+    from . import tv
+    s = 1.0 / np.sqrt(fK)
+
+    def op(x):
+        y = precond.apply_circulant(x, s)
+        t = alpha * adj_a(fwd_a(y)) - beta * tv.div(tv.grad(y, h), h)
+        return precond.apply_circulant(t, s)
+
+    return power_max_eig(op, x0, iters)

@@ -128,3 +128,61 @@ def impulse_full_symbol(khat: np.ndarray, alpha: float, beta: float) -> np.ndarr
 def impulse_multiplier(fK: np.ndarray, c: float) -> np.ndarray:
     """(c M_K)^{-1} as a Fourier multiplier: 1 / (c F(K))."""
     return 1.0 / (c * fK)
+
+
+# ---------------------------------------------------------------------------
+# Circulant preconditioner (§4.3.3, after Ramani-Fessler).
+#
+# A^* A is approximated by a circulant matrix on the vectorized image: the
+# image is flattened to a length-L vector (L = n^2), the response of A^* A to
+# the impulse at the centre pixel is taken as the circulant's first column,
+# and M^{-1} u = F_L^{-1}(F_L(u) / F_L(K)) with the 1-D DFT F_L.  Readings:
+#  * vectorization: column-major, index m = j + n i for pixel (row j, column i)
+#    (the column-stacking order of the thesis' MATLAB code);
+#  * the impulse at pixel (n/2, n/2), m0 = n/2 + n (n/2); the circulant's
+#    column is the response shifted to index 0, c_m = k~_{(m + m0) mod L},
+#    symmetrized as printed, k_m = (c_m + c_{(L - m) mod L}) / 2;
+#  * the Laplace kernel from -Delta_h applied to the same impulse: 4 at
+#    index 0 and -1 at +-1 (rows) and +-n (columns), symbol
+#    4 - 2 cos(2 pi q / L) - 2 cos(2 pi q / n);
+#  * K = alpha k + beta kappa_Delta (alpha = sigma^2, beta = (sigma tau)^2)
+#    and, as for the impulse-response preconditioner, M = c M_K with
+#    c = c_safety lambda_max(M_K^{-1} T).
+
+def flatten(u: np.ndarray) -> np.ndarray:
+    """Column-major vector of an (n, n) image stored u[j, i]: m = j + n i."""
+    return np.asarray(u, dtype=np.float64).ravel(order="F")
+
+
+def unflatten(x: np.ndarray, n: int) -> np.ndarray:
+    return np.asarray(x).reshape((n, n), order="F")
+
+
+def circulant_kernel(A, At, n: int) -> np.ndarray:
+    """Symmetrized, origin-shifted column of the circulant approximation of A^* A."""
+    L = n * n
+    d = np.zeros((n, n))
+    d[n // 2, n // 2] = 1.0
+    kt = flatten(At(A(d)))
+    m0 = n // 2 + n * (n // 2)
+    c = np.roll(kt, -m0)
+    return 0.5 * (c + c[(L - np.arange(L)) % L])
+
+
+def circulant_lap_symbol(n: int) -> np.ndarray:
+    L = n * n
+    q = np.arange(L)
+    return 4.0 - 2.0 * np.cos(2 * np.pi * q / L) - 2.0 * np.cos(2 * np.pi * q / n)
+
+
+def circulant_full_symbol(k: np.ndarray, alpha: float, beta: float) -> np.ndarray:
+    """F_L(K) = alpha F_L(k) + beta F_L(kappa_Delta) (real: k is symmetric)."""
+    n = int(round(np.sqrt(k.size)))
+    return alpha * np.real(np.fft.fft(k)) + beta * circulant_lap_symbol(n)
+
+
+def apply_circulant(u: np.ndarray, symbol_inv: np.ndarray) -> np.ndarray:
+    """F_L^{-1}(symbol_inv * F_L(u)) on the vectorized image, back as an image."""
+    n = u.shape[0]
+    x = np.fft.ifft(symbol_inv * np.fft.fft(flatten(u)))
+    return unflatten(np.real(x), n)
