@@ -187,11 +187,18 @@ enum {
  *            impulse at (n/2, n/2), centred at the origin and averaged over the
  *            symmetries of the square; K = sigma^2 k + (sigma tau)^2 kappa_Delta;
  *            M = c F^{-1} F(K) F with c = c_safety lambda_max(M_K^{-1} T) (even n;
- *            CT_E_UNSUPPORTED if F(K) is not positive or for other methods) */
+ *            CT_E_UNSUPPORTED if F(K) is not positive or for other methods)
+ *  CIRCULANT circulant approximation (§4.3.3): on the column-major vectorized
+ *            image (index j + n i), the response of A^* A shifted to index 0 and
+ *            symmetrized as the circulant's first column, K = sigma^2 k + (sigma
+ *            tau)^2 kappa_Delta, M = c F_L^{-1} F_L(K) F_L with the length-n^2 DFT
+ *            and c as for IMPULSE (same restrictions)
+ * IMPULSE and CIRCULANT: one problem per solver. */
 enum {
   CT_PRECOND_SHIFT = 8u,
   CT_PRECOND_INVNORM = 0,
-  CT_PRECOND_IMPULSE = 1
+  CT_PRECOND_IMPULSE = 1,
+  CT_PRECOND_CIRCULANT = 2
 };
 
 enum {

@@ -675,15 +675,22 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   return solver_set_slices(sv, bestS);
 }
 
-// Impulse-response preconditioner (§4.3.2) for PDRQS1: k = the response of
-// A^* A to a unit impulse at (n/2, n/2), centred at the origin and averaged
-// over the eight symmetries of the square; F(K) = sigma^2 F(k) + (sigma
-// tau)^2 lambda_Delta; c = c_safety lambda_max(M_K^{-1} T) by power iteration
-// unless given, T = sigma^2 A^* A - (sigma tau)^2 div nabla; multiplier
-// 1 / (c F(K)).  F(k) comes from the FFT pair itself: with the kernel as the
-// multiplier table (unnormalized) and a unit impulse at the origin as input,
-// the pair returns the (even, real) transform of the kernel.
-static int impulse_setup(ct_solver *sv, const ct_params *prm, hipStream_t st) {
+// Kernel preconditioners for PDRQS1, built from the response of A^* A to a
+// unit impulse at pixel (n/2, n/2):
+//  * impulse response (§4.3.2): the response centred at the origin and
+//    averaged over the eight symmetries of the square, a 2-D convolution
+//    kernel k; F(K) = sigma^2 F(k) + (sigma tau)^2 lambda_Delta;
+//  * circulant (§4.3.3): on the column-major vectorized image (index
+//    m = j + n i, length L = n^2), the response shifted to index 0 and
+//    symmetrized, (c_m + c_{L-m}) / 2, the first column of a circulant;
+//    F_L(K) = sigma^2 F_L(k) + (sigma tau)^2 (4 - 2 cos(2 pi q/L) - 2 cos(2 pi q/n)),
+//    applied by the FFT pair with the twiddle between its passes (pc.twist).
+// c = c_safety lambda_max(M_K^{-1} T) by power iteration unless given,
+// T = sigma^2 A^* A - (sigma tau)^2 div nabla; multiplier 1 / (c F(K)).
+// F(k) comes from the FFT pair itself: with the kernel as the multiplier
+// table (unnormalized) and a unit impulse at the origin as input, the pair
+// returns the (even, real) transform of the kernel.
+static int kernel_precond_setup(ct_solver *sv, const ct_params *prm, bool circ, hipStream_t st) {
   ct_plan *p = sv->plan;
   const int n = sv->n, half = n / 2 + 1;
   const size_t nn = (size_t)n * n;
@@ -697,19 +704,36 @@ static int impulse_setup(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   std::vector<float> kt(nn);
   CT_TRY_HIP(hipMemcpyAsync(kt.data(), sv->utmp, sizeof(float) * nn, hipMemcpyDeviceToHost, st));
   CT_TRY_HIP(hipStreamSynchronize(st));
-  // k(x1, x2) = mean over g of kt(n/2 + g(x)), indices modulo n; as the table
-  // m[x1][x2] for x1 in [0, n/2] (k is even, the other half mirrors it)
-  auto at = [&](int y, int x) {
-    return (double)kt[(size_t)((y + n / 2) % n) * n + (size_t)((x + n / 2) % n)];
-  };
   std::vector<float> tab((size_t)half * n);
-  for (int x1 = 0; x1 < half; ++x1)
-    for (int x2 = 0; x2 < n; ++x2) {
-      const int a = x1, b = x2, na = (n - a) % n, nb2 = (n - b) % n;
-      const double v = at(b, a) + at(b, na) + at(nb2, a) + at(nb2, na) + at(a, b) + at(a, nb2) +
-                       at(na, b) + at(na, nb2);
-      tab[(size_t)x1 * n + x2] = (float)(v / 8.0);
-    }
+  if (!circ) {
+    // k(x1, x2) = mean over g of kt(n/2 + g(x)), indices modulo n; as the
+    // table m[x1][x2] for x1 in [0, n/2] (k is even, the other half mirrors it)
+    auto at = [&](int y, int x) {
+      return (double)kt[(size_t)((y + n / 2) % n) * n + (size_t)((x + n / 2) % n)];
+    };
+    for (int x1 = 0; x1 < half; ++x1)
+      for (int x2 = 0; x2 < n; ++x2) {
+        const int a = x1, b = x2, na = (n - a) % n, nb2 = (n - b) % n;
+        const double v = at(b, a) + at(b, na) + at(nb2, a) + at(nb2, na) + at(a, b) +
+                         at(a, nb2) + at(na, b) + at(na, nb2);
+        tab[(size_t)x1 * n + x2] = (float)(v / 8.0);
+      }
+  } else {
+    // k_m = (c_m + c_{L-m}) / 2 with c_m = kt at vector index (m + m0) mod L;
+    // as the table m[k1][k2] = k_{k1 + n k2}, k1 in [0, n/2] (k is symmetric)
+    const int64_t L = (int64_t)n * n, m0 = n / 2 + (int64_t)n * (n / 2);
+    auto cvec = [&](int64_t m) {
+      const int64_t v = ((m + m0) % L + L) % L;
+      const int64_t j = v % n, i = v / n;
+      return (double)kt[(size_t)j * n + (size_t)i];
+    };
+    for (int k1 = 0; k1 < half; ++k1)
+      for (int k2 = 0; k2 < n; ++k2) {
+        const int64_t m = k1 + (int64_t)n * k2;
+        tab[(size_t)k1 * n + k2] = (float)(0.5 * (cvec(m) + cvec((L - m) % L)));
+      }
+  }
+  sv->pc.twist = circ ? 1 : 0;
   CT_TRY_HIP(hipMemcpyAsync(sv->pc.d_mult, tab.data(), sizeof(float) * tab.size(),
                             hipMemcpyHostToDevice, st));
   std::fill(img.begin(), img.end(), 0.f);
@@ -719,16 +743,27 @@ static int impulse_setup(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   std::vector<float> kh(nn);
   CT_TRY_HIP(hipMemcpyAsync(kh.data(), sv->utmp, sizeof(float) * nn, hipMemcpyDeviceToHost, st));
   CT_TRY_HIP(hipStreamSynchronize(st));
-  // F(K) on the multiplier grid: the output image holds F(k) at (x-freq i, y-freq j)
+  // F(K) on the multiplier grid.  Impulse response: the output image holds
+  // F(k) at (x-freq i, y-freq j).  Circulant: it holds F_L(k) at vector index
+  // j + n i, and grid point (k1, k2) is frequency q = k1 + n k2.
   std::vector<double> fK((size_t)half * n);
+  const double L = (double)n * n;
   for (int k1 = 0; k1 < half; ++k1) {
     const double s1 = std::sin(M_PI * k1 / n);
     for (int k2 = 0; k2 < n; ++k2) {
-      const double s2 = std::sin(M_PI * k2 / n);
-      const double v = sig * sig * (double)kh[(size_t)k2 * n + k1] +
-                       st2 * (4.0 * s1 * s1 + 4.0 * s2 * s2);
+      double fk, lap;
+      if (!circ) {
+        const double s2 = std::sin(M_PI * k2 / n);
+        fk = (double)kh[(size_t)k2 * n + k1];
+        lap = 4.0 * s1 * s1 + 4.0 * s2 * s2;
+      } else {
+        const double q = (double)k1 + (double)n * k2;
+        fk = (double)kh[(size_t)k1 * n + k2];
+        lap = 4.0 - 2.0 * std::cos(2.0 * M_PI * q / L) - 2.0 * std::cos(2.0 * M_PI * q / n);
+      }
+      const double v = sig * sig * fk + st2 * lap;
       if (!(v > 0.0) || !std::isfinite(v)) {
-        set_error("ct_solver_create: impulse-response kernel symbol F(K) is not positive");
+        set_error("ct_solver_create: kernel preconditioner symbol F(K) is not positive");
         return CT_E_UNSUPPORTED;
       }
       fK[(size_t)k1 * n + k2] = v;
@@ -845,8 +880,8 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
     return CT_E_INVALID;
   }
   const int pkind = (int)((prm->flags >> CT_PRECOND_SHIFT) & 15u);
-  if (pkind == CT_PRECOND_IMPULSE) {
-    CT_TRY(impulse_setup(sv, prm, st));
+  if (pkind == CT_PRECOND_IMPULSE || pkind == CT_PRECOND_CIRCULANT) {
+    CT_TRY(kernel_precond_setup(sv, prm, pkind == CT_PRECOND_CIRCULANT, st));
   } else {
   // c > lambda_max(tilde M^{-1} A^* A) (§4.3.1), by power iteration on
   // tilde M^{-1/2} A^* A tilde M^{-1/2} unless given
@@ -1013,13 +1048,14 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     return CT_E_INVALID;
   }
   const int pkind = (int)((prm->flags >> CT_PRECOND_SHIFT) & 15u);
-  if (pkind > CT_PRECOND_IMPULSE) {
+  if (pkind > CT_PRECOND_CIRCULANT) {
     set_error("ct_solver_create: unknown preconditioner");
     return CT_E_INVALID;
   }
-  if (pkind == CT_PRECOND_IMPULSE &&
-      (method != CT_METHOD_PDRQS1 || (prm->flags & CT_FLAG_NONNEG) || (p->g.n & 1))) {
-    set_error("ct_solver_create: the impulse-response preconditioner is for PDRQS1 (even n)");
+  if (pkind != CT_PRECOND_INVNORM &&
+      (method != CT_METHOD_PDRQS1 || (prm->flags & CT_FLAG_NONNEG) || (p->g.n & 1) || nb != 1)) {
+    set_error("ct_solver_create: the impulse-response and circulant preconditioners are for "
+              "single-problem PDRQS1 (even n)");
     return CT_E_UNSUPPORTED;
   }
   if (method == CT_METHOD_ADMM) {

@@ -145,6 +145,10 @@ struct ct_precond {
   float2 *d_tw = nullptr;    // twiddles exp(-2 pi i m / n)
   float2 *d_spec = nullptr;  // spectrum workspace [n/2+1][n]
   ctpd::FftPlan fp;
+  // 1: the multiplier acts on the length-n^2 DFT of the column-major
+  // vectorized image (circulant preconditioner), computed as the row pass,
+  // a twiddle exp(-2 pi i j k1 / n^2), the column pass and their inverses
+  int twist = 0;
 };
 
 namespace ctpd {

@@ -206,10 +206,21 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__res
 }
 
 // Column pass: per k1, spec[k1][:] <- IFFT( m[k1][:] * FFT(spec[k1][:]) ).
+// exp(sgn 2 pi i (j k1 mod n^2) / n^2) in FP64, rounded to FP32: the twiddle
+// between the two passes of the length-n^2 DFT of a column-major vector
+// (index j + n i; the row pass has transformed along i into frequency k1)
+__device__ inline float2 flat_twiddle(int j, int k1, int n, float sgn) {
+  const long long L = (long long)n * n;
+  const long long q = ((long long)j * k1) % L;
+  double sn, cs;
+  sincospi(2.0 * (double)q / (double)L, &sn, &cs);
+  return make_float2((float)cs, sgn * (float)sn);
+}
+
 template <bool TWL>
 __global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ spec, int n, int CP,
                                                   FftPlan pl, const float2 *__restrict__ tw,
-                                                  const float *__restrict__ mult) {
+                                                  const float *__restrict__ mult, int twist) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + CP * n;
@@ -219,7 +230,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ s
   const int ncol = min(CP, half - k10);
   spec += (size_t)blockIdx.y * half * n;
   batched(ncol * n, [&](int t) { return spec[(size_t)k10 * n + t]; },
-          [&](int t, float2 v) { a[t] = v; });
+          [&](int t, float2 v) {
+            if (twist) {
+              const int c = t / n;
+              v = cmul(v, flat_twiddle(t - c * n, k10 + c, n, -1.f));
+            }
+            a[t] = v;
+          });
   __syncthreads();
   float2 *z = fft_rows<false>(a, b, ncol, pl, twp);
   float2 *other = (z == a) ? b : a;
@@ -227,7 +244,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ s
           [&](int t, float m) { z[t] = make_float2(m * z[t].x, m * z[t].y); });
   __syncthreads();
   z = fft_rows<true>(z, other, ncol, pl, twp);
-  for (int t = threadIdx.x; t < ncol * n; t += kFftThreads) spec[(size_t)k10 * n + t] = z[t];
+  for (int t = threadIdx.x; t < ncol * n; t += kFftThreads) {
+    float2 v = z[t];
+    if (twist) {
+      const int c = t / n;
+      v = cmul(v, flat_twiddle(t - c * n, k10 + c, n, 1.f));
+    }
+    spec[(size_t)k10 * n + t] = v;
+  }
 }
 
 // Inverse row pass: out[j][i] = (base ? base[j][i] : 0) + x_j[i].
@@ -313,14 +337,14 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
     hipLaunchKernelGGL(k_fft_rows_fwd<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s, y,
                        n, RP, pc->fp, pc->d_tw, spec);
     hipLaunchKernelGGL(k_fft_cols<true>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec, n,
-                       CP, pc->fp, pc->d_tw, mult);
+                       CP, pc->fp, pc->d_tw, mult, pc->twist);
     hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
                        spec, n, RP, pc->fp, pc->d_tw, base, out);
   } else {
     hipLaunchKernelGGL(k_fft_rows_fwd<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
                        y, n, RP, pc->fp, pc->d_tw, spec);
     hipLaunchKernelGGL(k_fft_cols<false>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec,
-                       n, CP, pc->fp, pc->d_tw, mult);
+                       n, CP, pc->fp, pc->d_tw, mult, pc->twist);
     hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
                        spec, n, RP, pc->fp, pc->d_tw, base, out);
   }

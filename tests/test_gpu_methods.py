@@ -174,25 +174,26 @@ def test_admm_matches_oracle(cg_steps, mu):
         assert np.linalg.norm(gev - st.ev) <= 10 * tol * sv_
 
 
-def test_impulse_preconditioner_matches_oracle():
-    print("impulse preconditioner", flush=True)
+@pytest.mark.parametrize("kind", ["impulse", "circulant"])
+def test_kernel_preconditioner_matches_oracle(kind):
+    print("kernel preconditioner", kind, flush=True)
     w, g, u0, mask, bound = _metal()
     plan = ct.Plan(g.n, g.n_angles, g.n_bins)
     mb = ct.pack_mask(mask)
-    sv = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), precond="impulse")
+    sv = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), precond=kind)
     inf = sv.info()
     # c from the oracle's own power iteration (another start vector)
     rng = np.random.default_rng(9)
     s_own = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
                        beta=inf["beta"], start_precond=rng.standard_normal((g.n, g.n)),
-                       kind="impulse")
+                       kind=kind)
     assert inf["c"] == pytest.approx(s_own.c, rel=0.05)
     s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
-                   c=inf["c"], kind="impulse")
+                   c=inf["c"], kind=kind)
     st = pdrq.zero_state(s)
     done = 0
     for k, tol in ((1, 1e-5), (60, 1e-4)):
-        sk = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), precond="impulse",
+        sk = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), precond=kind,
                        beta=inf["beta"], c=inf["c"])
         sk.step(k)
         while done < k:
@@ -201,11 +202,13 @@ def test_impulse_preconditioner_matches_oracle():
         assert rel(host(sk.export()[0]), st.u) <= tol
 
 
-def test_impulse_preconditioner_errors():
+def test_kernel_preconditioner_errors():
     plan = ct.Plan(32, 45, 48)
     z = torch.zeros((45, 48), device=DEV)
     with pytest.raises(ct.CtpdError):
         ct.Solver(plan, z, 0.01, method="cp", precond="impulse")
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(plan, z, 0.01, method="pdrqs2", precond="circulant")
     with pytest.raises(ct.CtpdError):
         ct.Solver(plan, z, 0.01, nonneg=True, precond="impulse")
     with pytest.raises(ValueError):
