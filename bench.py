@@ -180,7 +180,7 @@ def large_run(ct, torch, iters: int):
 def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 8192):
     """The preconditioning comparison of the thesis' results (objective value
     relative to the smallest attained, per iteration): PDRQS1 with the
-    inverse-norm and with the impulse-response preconditioner, PDRQS1 with
+    inverse-norm, the impulse-response and the circulant preconditioner, PDRQS1 with
     Richardson's M = m id, Algorithm
     CP, PDRQS2 and ADMM with 1 and 2 inner PCG steps (mu = 1), on an
     unconstrained random-ellipse phantom (n^2, N = 1.4 n,
@@ -199,13 +199,14 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
                         if 2 ** (i / 2) <= kmax] + [kmax]))
     curves, rates = {}, {}
     methods = {"pdrqs1": {}, "pdrqs1_impulse": {"method": "pdrqs1", "precond": "impulse"},
+               "pdrqs1_circulant": {"method": "pdrqs1", "precond": "circulant"},
                "richardson": {}, "cp": {}, "pdrqs2": {},
                "admm_cg1": {"method": "admm", "cg_steps": 1},
                "admm_cg2": {"method": "admm", "cg_steps": 2}}
     for method, opts in methods.items():
         kw = opts or {"method": method}
-        # the impulse-response preconditioner has its own constant c
-        cc = None if kw.get("precond") == "impulse" else inf["c"]
+        # the kernel preconditioners have their own constant c
+        cc = None if kw.get("precond") in ("impulse", "circulant") else inf["c"]
         sv = ct.Solver(plan, u0, lam, beta=inf["beta"], c=cc, **kw)
         done, vals = 0, []
         sv.step(10)   # warm-up (graph capture), then restart from zero
