@@ -21,12 +21,13 @@ Modules (each function cites the thesis passage it follows):
   gap       FP64 primal/dual record (a reading; the thesis defines none)
   d0        metal-trace estimate: threshold, dilate, project        (results, real metal)
   admm      ADMM with inner PCG and isotropic soft thresholding     (§4.6)
+  pdrq3     the PDRQ3 splitting (fit in the dual's quadratic part)  (§4.4)
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 header of the module that takes them and collected in the repository's design
 notes.  Parity status: every function is pinned by the tests under tests/
 (test_oracle_*.py) except where its docstring says "parity unpinned".
 """
-from . import geometry, radon, tv, precond, prox, power, pdrq, cp, gap, d0, admm  # noqa: F401
+from . import geometry, radon, tv, precond, prox, power, pdrq, cp, gap, d0, admm, pdrq3  # noqa: F401
 
-__all__ = ["geometry", "radon", "tv", "precond", "prox", "power", "pdrq", "cp", "gap", "d0", "admm"]
+__all__ = ["geometry", "radon", "tv", "precond", "prox", "power", "pdrq", "cp", "gap", "d0", "admm", "pdrq3"]
