@@ -180,7 +180,8 @@ def large_run(ct, torch, iters: int):
 def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 8192):
     """The preconditioning comparison of the thesis' results (objective value
     relative to the smallest attained, per iteration): PDRQS1 with the
-    inverse-norm, the impulse-response and the circulant preconditioner, PDRQS1 with
+    inverse-norm, the impulse-response and the circulant preconditioner, its
+    PDRQ3 splitting, PDRQS1 with
     Richardson's M = m id, Algorithm
     CP, PDRQS2 and ADMM with 1 and 2 inner PCG steps (mu = 1), on an
     unconstrained random-ellipse phantom (n^2, N = 1.4 n,
@@ -200,7 +201,7 @@ def precond_comparison(ct, torch, n: int = 256, lam: float = 0.005, kmax: int = 
     curves, rates = {}, {}
     methods = {"pdrqs1": {}, "pdrqs1_impulse": {"method": "pdrqs1", "precond": "impulse"},
                "pdrqs1_circulant": {"method": "pdrqs1", "precond": "circulant"},
-               "richardson": {}, "cp": {}, "pdrqs2": {},
+               "pdrqs3": {}, "richardson": {}, "cp": {}, "pdrqs2": {},
                "admm_cg1": {"method": "admm", "cg_steps": 1},
                "admm_cg2": {"method": "admm", "cg_steps": 2}}
     for method, opts in methods.items():

@@ -179,6 +179,11 @@ enum {
  *  PDRQS2      Algorithm PDRQS2 (§4.2, §4.3.1), the unconstrained problem (no D0)
  *  ADMM        ADMM with an inner PCG u-step (§4.6), the unconstrained problem
  *              (no D0), one problem per solver; see ct_solver_set_admm
+ *  PDRQS3      PDRQS1's iteration with the splitting PDRQ3 of §4.4's table: the
+ *              fit's quadratic part in the dual (S = diag(chi_{D\D0}, 0), g = (b, 0)):
+ *              u_tmp = -sigma (A^* s1 - tau div s2) with s1 = D (vb1 + sigma (A u - g)),
+ *              D = 1/(1 + sigma) off D0; off D0 vb1 <- (vb1 + sigma (A u_new - b)) /
+ *              (1 + sigma), on D0 the constraint's resolvent as in PDRQS1
  * ct_gap is defined for PDRQS1 and RICHARDSON; ct_objective serves all. */
 /* Preconditioner of PDRQS1 (flags |= kind << CT_PRECOND_SHIFT):
  *  INVNORM   inverse norm + periodic Laplacian (§4.3.1): rho / (sigma^2 c +
@@ -206,7 +211,8 @@ enum {
   CT_METHOD_RICHARDSON = 1,
   CT_METHOD_CP = 2,
   CT_METHOD_PDRQS2 = 3,
-  CT_METHOD_ADMM = 4
+  CT_METHOD_ADMM = 4,
+  CT_METHOD_PDRQS3 = 5
 };
 
 typedef struct ct_params {

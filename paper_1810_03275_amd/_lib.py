@@ -16,7 +16,7 @@ ERRORS = {-1: "CT_E_INVALID", -2: "CT_E_UNSUPPORTED", -3: "CT_E_DEVICE",
 CT_FLAG_VALIDATE = 1
 CT_FLAG_NONNEG = 2
 CT_METHOD_SHIFT = 4
-METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3, "admm": 4}
+METHODS = {"pdrqs1": 0, "richardson": 1, "cp": 2, "pdrqs2": 3, "admm": 4, "pdrqs3": 5}
 FITS = {"standard": 0, "weighted": 1, "ignore": 2, "everywhere": 3, "hard": 4}
 PRECONDS = {"invnorm": 0, "impulse": 1, "circulant": 2}
 CT_PRECOND_SHIFT = 8

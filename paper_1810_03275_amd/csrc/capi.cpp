@@ -511,6 +511,12 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   // PDRQS2 caches the residual b - A u, which is b at u = 0
   if (sv->method == CT_METHOD_PDRQS2)
     CT_TRY_HIP(hipMemcpyAsync(sv->s1, sv->target, sizeof(float) * NM, hipMemcpyDeviceToDevice, s));
+  // PDRQS3 caches D (vb1 + sigma (A u - g)), -sigma b / (1 + sigma) off D0 at u = 0
+  if (sv->method == CT_METHOD_PDRQS3) {
+    const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
+                     sv->s1, nullptr, nullptr, 8};
+    CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, s, &ep, sv->nb));
+  }
   sv->iters = 0;
   sv->have_dual = false;
   return CT_OK;
@@ -623,7 +629,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
   // R_h u_new with the sinogram-side update fused into its output stage
   SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
-             sv->y1, sv->r, mode};
+             sv->y1, sv->r, sv->method == CT_METHOD_PDRQS3 ? 7 : mode};
   ep.q1 = q1out;
   ep.fit = sv->fit;
   ep.aux = sv->fit_aux;
@@ -1043,7 +1049,7 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     return CT_E_UNSUPPORTED;
   }
   const int method = (int)((prm->flags >> CT_METHOD_SHIFT) & 15u);
-  if (method > CT_METHOD_ADMM) {
+  if (method > CT_METHOD_PDRQS3) {
     set_error("ct_solver_create: unknown method");
     return CT_E_INVALID;
   }
@@ -1358,7 +1364,8 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
   }
   // caches: s1 = vb1 + sigma A u (PDRQS2: b - A u), s2 = vb2 + sigma tau nabla u
   const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
-                   sv->s1, nullptr, nullptr, sv->method == CT_METHOD_PDRQS2 ? 5 : 1};
+                   sv->s1, nullptr, nullptr,
+                   sv->method == CT_METHOD_PDRQS2 ? 5 : (sv->method == CT_METHOD_PDRQS3 ? 8 : 1)};
   CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep, sv->nb));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
                           (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st,
@@ -1378,7 +1385,8 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
     return CT_E_STATE;
   }
   if (sv->method == CT_METHOD_CP || sv->method == CT_METHOD_PDRQS2 ||
-      sv->method == CT_METHOD_ADMM || sv->fit != CT_FIT_STANDARD) {
+      sv->method == CT_METHOD_ADMM || sv->method == CT_METHOD_PDRQS3 ||
+      sv->fit != CT_FIT_STANDARD) {
     set_error("ct_gap: the record is defined for PDRQS1 with the standard data term");
     return CT_E_UNSUPPORTED;
   }

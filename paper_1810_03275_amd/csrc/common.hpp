@@ -185,7 +185,8 @@ struct SinoEpi {
   float *y1;
   float *r;
   int mode;      // 0 iterate, 1 caches only, 2 iterate and keep y1/r, 3 reverse sweep,
-                 // 4 Algorithm CP dual step, 5 PDRQS2 residual, 6 ADMM z-step (mu in sigma)
+                 // 4 Algorithm CP dual step, 5 PDRQS2 residual, 6 ADMM z-step (mu in sigma),
+                 // 7 PDRQ3 iterate, 8 PDRQ3 cache only
   float *q1 = nullptr;  // optional: the resolvent input 2 v1 - vb1 (modes 0, 2)
   int fit = 0;          // data term (modes 0, 2): CT_FIT_* of the C ABI
   const float *aux = nullptr;  // weights (weighted fit) or b on every bin (fit everywhere)

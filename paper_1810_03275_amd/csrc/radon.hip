@@ -351,6 +351,29 @@ __device__ inline void fp_output(float *__restrict__ sino, const SinoEpi &ep, in
     return;
   }
   const float vb = ep.vb1[o];
+  if (ep.mode == 7 || ep.mode == 8) {
+    // PDRQ3 (§4.4, table of splittings): off D0 the fit's quadratic part is
+    // the dual's, vb1 <- (vb1 + sigma (r - b)) / (1 + sigma); on D0 the
+    // constraint's resolvent as in PDRQS1.  The cache for the next u-step is
+    // s1 = D (vb1 + sigma (r - g)), D = 1/(1 + sigma) and g = b off D0, D = 1
+    // and g = 0 on D0.  Mode 8 writes only that cache.
+    const int MW7 = (M + 31) >> 5;
+    const bool d0 =
+        ep.mask != nullptr && ((ep.mask[(size_t)l * MW7 + (k >> 5)] >> (k & 31)) & 1u);
+    const float sg = ep.sigma, tg = ep.target[o];
+    float nb = vb;
+    if (ep.mode == 7) {
+      if (d0) {
+        const float v1 = fmaf(sg, r, vb);
+        nb = vb + fminf(2.f * v1 - vb - sg * tg, 0.f) - v1;
+      } else {
+        nb = fmaf(sg, r - tg, vb) / (1.f + sg);
+      }
+      ep.vb1[o] = nb;
+    }
+    ep.s1[o] = d0 ? fmaf(sg, r, nb) : fmaf(sg, r - tg, nb) / (1.f + sg);
+    return;
+  }
   if (ep.mode == 6) {
     // ADMM z-step and multiplier update (§4.6), data block, mu in the sigma
     // field: s = A u + eta_w, w = (b + mu s)/(1 + mu), eta_w <- s - w, and

@@ -213,3 +213,41 @@ def test_kernel_preconditioner_errors():
         ct.Solver(plan, z, 0.01, nonneg=True, precond="impulse")
     with pytest.raises(ValueError):
         ct.Solver(plan, z, 0.01, precond="no-such-preconditioner")
+
+
+def test_pdrqs3_matches_oracle():
+    print("pdrqs3", flush=True)
+    from oracle import pdrq3
+    w, g, u0, mask, bound = _metal()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    mb = ct.pack_mask(mask)
+    probe = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound))
+    inf = probe.info()
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    st = pdrq.zero_state(s)
+    done = 0
+    for k, tol in ((1, 1e-5), (60, 1e-4)):
+        sv = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), beta=inf["beta"], c=inf["c"],
+                       method="pdrqs3")
+        sv.step(k)
+        while done < k:
+            st = pdrq3.step3(s, st)
+            done += 1
+        gu, gv1, gv2 = (host(t) for t in sv.export())
+        assert rel(gu, st.u) <= tol
+        assert rel(gv1, st.vb1) <= 10 * tol
+    # one step from an imported random state (the cache rebuilt from it)
+    rng = np.random.default_rng(12)
+    u = f32(rng.uniform(0, 1, (g.n, g.n)))
+    vb1 = f32(0.01 * rng.standard_normal((g.n_angles, g.n_bins)))
+    vb2 = f32(s.lam_t / s.params.tau * rng.standard_normal((2, g.n, g.n)))
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(1)
+    nxt = pdrq3.step3(s, pdrq.state_from(s, u, vb1, vb2))
+    gu, gv1, gv2 = (host(t) for t in sv.export())
+    assert rel(gu, nxt.u) <= 1e-5
+    assert rel(gv1, nxt.vb1) <= 1e-5
+    assert rel(gv2, nxt.vb2) <= 1e-5
+    with pytest.raises(ct.CtpdError):
+        sv.gap()
