@@ -170,6 +170,7 @@ struct ct_solver {
   double admm_mu = 1.0;
   float *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Hp = nullptr;
   double *d_cg = nullptr;     // [0], [1] r.z (alternating), [2] p.Hp, then dot partials
+  bool defer_combine = true;  // form R_h^*'s slice sum in the FFT row pass
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -600,11 +601,13 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   const int nb = sv->nb;
   if (sv->method == CT_METHOD_PDRQS2) {
     // §4.2: u_tmp = sigma A^*(b - A u) + sigma tau div(vb2 + sigma tau nabla u)
+    BpDeferred def{};
     CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(sv->sigma / sv->beta),
                             (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part,
-                            sv->bp_S));
+                            sv->bp_S, nullptr, nullptr, nullptr,
+                            sv->defer_combine ? &def : nullptr));
     CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
-                             sv->spec));
+                             sv->spec, def.S > 1 ? &def : nullptr));
     const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, nullptr, nullptr, sv->s1,
                      nullptr, nullptr, 5};
     CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
@@ -615,17 +618,21 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
     return CT_OK;
   }
   if (ev) CT_TRY_HIP(hipEventRecord(ev[0], st));
-  // u_tmp (u >= 0 variant: plus bar u - u)
+  // u_tmp (u >= 0 variant: plus bar u - u); with angle slices and the FFT
+  // pair next, the slices' sum and epilogue are formed in the FFT's row pass
+  BpDeferred def{};
+  const bool rich = sv->method == CT_METHOD_RICHARDSON;
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
                           (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S,
-                          sv->ubar, sv->ubar ? sv->u : nullptr));
+                          sv->ubar, sv->ubar ? sv->u : nullptr, nullptr,
+                          rich || !sv->defer_combine ? nullptr : &def));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
-  if (sv->method == CT_METHOD_RICHARDSON)
+  if (rich)
     CT_TRY(launch_axpy((int64_t)sv->n * sv->n * nb, sv->u, (float)(1.0 / sv->rich_m), sv->utmp,
                        sv->u_next, st));
   else
     CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
-                             sv->spec));
+                             sv->spec, def.S > 1 ? &def : nullptr));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[2], st));
   // R_h u_new with the sinogram-side update fused into its output stage
   SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
@@ -1100,6 +1107,8 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
   {
     const char *nt = std::getenv("CTPD_NO_TUNE");
     sv->tune = !(nt && nt[0] == '1');
+    const char *nd = std::getenv("CTPD_NO_DEFER");
+    sv->defer_combine = !(nd && nd[0] == '1');
   }
   int rc = solver_setup(sv, probs, prm, S(s));
   if (rc != CT_OK) {

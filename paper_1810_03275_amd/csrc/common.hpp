@@ -160,10 +160,22 @@ namespace ctpd {
 // S: angle slices (0: the plan's choice).
 // base (optional, nb images) is added to the result, base2 (optional)
 // subtracted; out2 (optional, needs base) receives 2 out - base.
+// The angle slices' sum and the epilogue of a sliced backprojection, not yet
+// formed: out = base - base2 + c1 sum_s part[s] + c2 div_h(pfield).  A
+// consumer that reads out once (the preconditioner's row pass) forms it on
+// the fly instead of a separate combine pass.  S = 0: nothing deferred.
+constexpr int kMaxDeferredSlices = 8;  // the plan's largest slice count
+struct BpDeferred {
+  const float *part = nullptr;  // [nb][S][n][n]
+  int S = 0;
+  const float *pfield = nullptr;
+  float c1 = 0.f, c2 = 0.f, inv_h = 0.f;
+  const float *base = nullptr, *base2 = nullptr;
+};
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
                      int S = 0, const float *base = nullptr, const float *base2 = nullptr,
-                     float *out2 = nullptr);
+                     float *out2 = nullptr, BpDeferred *defer = nullptr);
 // out = base + a x over count elements (nb problems contiguous).
 int launch_axpy(int64_t count, const float *base, float a, const float *x, float *out,
                 hipStream_t s);
@@ -245,9 +257,10 @@ int launch_build_target(int N, int M, const float *u0, const float *bound, float
 // FFT-based multiplier application: out = (base ? base : 0) + F^{-1}(mult F(y)).
 // nb problems stored contiguously; spec: nb spectra (NULL: the
 // preconditioner's own buffer, nb = 1 only).
+// y == nullptr with ydef: y is the deferred backprojection ydef (S > 1)
 int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
                       const float *base, float *out, hipStream_t s, int nb = 1,
-                      float2 *spec = nullptr);
+                      float2 *spec = nullptr, const BpDeferred *ydef = nullptr);
 
 // Reductions (FP64, deterministic two-level).
 int launch_norm2(const float *x, int64_t count, double *partials, int cap, double *out,

@@ -11,6 +11,7 @@
 // Twiddles exp(-2 pi i m/n) are precomputed in FP64 and stored as FP32.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -164,26 +165,66 @@ __device__ inline const float2 *stage_twiddles(float2 *lds, const float2 *__rest
   return lds;  // the caller's barrier precedes the first read
 }
 
+// The deferred backprojection at pixel (i, j) from DS = d.S partial images:
+// the slices' sum in slice order and the epilogue, as the combine pass
+// computes them.  DS is a compile-time count so that every load of a pixel
+// is in flight at once.
+template <int DS>
+__device__ inline float deferred_value(const BpDeferred &d, int n, int i, int j) {
+  const size_t nn = (size_t)n * n, o = (size_t)j * n + i;
+  float v[DS];
+#pragma unroll
+  for (int s = 0; s < DS; ++s) v[s] = d.part[s * nn + o];
+  float r = v[0];
+#pragma unroll
+  for (int s = 1; s < DS; ++s) r += v[s];
+  float res = d.c1 * r;
+  if (d.pfield != nullptr) {
+    const float *p1 = d.pfield, *p2 = d.pfield + nn;
+    const float d1 = (i < n - 1 ? p1[o] : 0.f) - (i > 0 ? p1[o - 1] : 0.f);
+    const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
+    res = fmaf(d.c2 * d.inv_h, d1 + d2, res);
+  }
+  if (d.base != nullptr) res += d.base[o];
+  if (d.base2 != nullptr) res -= d.base2[o];
+  return res;
+}
+
 // Row pass: rows [2 rp0, 2 rp0 + 2 RP) of y -> spec[k1][j], k1 in [0, n/2].
-template <bool TWL>
+// With DS > 0, y is the deferred backprojection yd of DS partial images
+// (and epilogue), formed here as the rows are loaded.
+template <bool TWL, int DS>
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__restrict__ y, int n,
                                                       int RP, FftPlan pl,
                                                       const float2 *__restrict__ tw,
-                                                      float2 *__restrict__ spec) {
+                                                      float2 *__restrict__ spec,
+                                                      BpDeferred yd) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + RP * n;
   const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
   const int pair0 = blockIdx.x * RP;
   const int npair = min(RP, n / 2 - pair0);
-  y += (size_t)blockIdx.y * n * n;  // problem blockIdx.y of a batch
+  const size_t nn = (size_t)n * n;
+  if (DS == 0) {
+    y += blockIdx.y * nn;  // problem blockIdx.y of a batch
+  } else {
+    yd.part += blockIdx.y * yd.S * nn;
+    if (yd.pfield != nullptr) yd.pfield += blockIdx.y * 2 * nn;
+    if (yd.base != nullptr) yd.base += blockIdx.y * nn;
+    if (yd.base2 != nullptr) yd.base2 += blockIdx.y * nn;
+  }
   spec += (size_t)blockIdx.y * (n / 2 + 1) * n;
   batched(
       npair * n,
       [&](int t) {
         const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
         const int j = 2 * (pair0 + pr);
-        return make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
+        if constexpr (DS > 0)
+          return make_float2(deferred_value<DS>(yd, n, i, j),
+                             deferred_value<DS>(yd, n, i, j + 1));
+        else
+          return make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
       },
       [&](int t, float2 v) { a[t] = v; });
   __syncthreads();
@@ -317,7 +358,14 @@ static int rows_per_block(int n) {
 }
 
 int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
-                      const float *base, float *out, hipStream_t s, int nb, float2 *spec) {
+                      const float *base, float *out, hipStream_t s, int nb, float2 *spec,
+                      const BpDeferred *ydef) {
+  const BpDeferred yd = ydef ? *ydef : BpDeferred{};
+  const int DS = (ydef != nullptr && yd.part != nullptr) ? yd.S : 0;  // the deferred form wins
+  if ((DS == 0 && y == nullptr) || DS == 1 || DS > kMaxDeferredSlices) {
+    set_error("preconditioner: no input image, or an unsupported slice count");
+    return CT_E_INVALID;
+  }
   const int n = pc->n;
   int RP = rows_per_block(n);
   // a batch fills the chip with its problems: fewer, larger row blocks
@@ -333,16 +381,34 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
   const size_t lds = rows_lds + (twl ? sizeof(float2) * n : 0);
   const dim3 block(kFftThreads);
   const int CP = RP;
+  const dim3 grow((n / 2 + RP - 1) / RP, nb);
+  auto rows_fwd = [&](auto twl_c) {
+    constexpr bool T = decltype(twl_c)::value;
+    switch (DS) {
+#define CT_ROWS_FWD(K)                                                                     \
+  case K:                                                                                  \
+    hipLaunchKernelGGL((k_fft_rows_fwd<T, K>), grow, block, lds, s, y, n, RP, pc->fp,      \
+                       pc->d_tw, spec, yd);                                                \
+    break;
+      CT_ROWS_FWD(0)
+      CT_ROWS_FWD(2)
+      CT_ROWS_FWD(3)
+      CT_ROWS_FWD(4)
+      CT_ROWS_FWD(5)
+      CT_ROWS_FWD(6)
+      CT_ROWS_FWD(7)
+      CT_ROWS_FWD(8)
+#undef CT_ROWS_FWD
+    }
+  };
   if (twl) {
-    hipLaunchKernelGGL(k_fft_rows_fwd<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s, y,
-                       n, RP, pc->fp, pc->d_tw, spec);
+    rows_fwd(std::true_type{});
     hipLaunchKernelGGL(k_fft_cols<true>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec, n,
                        CP, pc->fp, pc->d_tw, mult, pc->twist);
     hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
                        spec, n, RP, pc->fp, pc->d_tw, base, out);
   } else {
-    hipLaunchKernelGGL(k_fft_rows_fwd<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
-                       y, n, RP, pc->fp, pc->d_tw, spec);
+    rows_fwd(std::false_type{});
     hipLaunchKernelGGL(k_fft_cols<false>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec,
                        n, CP, pc->fp, pc->d_tw, mult, pc->twist);
     hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,

@@ -151,7 +151,7 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   {
     const int tiles = ((n + kBpTileI - 1) / kBpTileI) * ((n + kBpTileJ - 1) / kBpTileJ);
     int S = (1024 + tiles - 1) / tiles;
-    S = std::min(S, 8);
+    S = std::min(S, kMaxDeferredSlices);
     S = std::min(S, std::max(1, N / (2 * kBpChunk)));
     p->bp_slices = std::max(S, 1);
   }

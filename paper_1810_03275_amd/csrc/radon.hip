@@ -272,9 +272,10 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb, float *part, int S,
-                     const float *base, const float *base2, float *out2) {
+                     const float *base, const float *base2, float *out2, BpDeferred *defer) {
   const int n = p->g.n;
   if (S <= 0) S = p->bp_slices;
+  if (defer) *defer = BpDeferred{};
   const int slice_len = (p->g.n_angles + S - 1) / S;
   if (nb < 1 || (S > 1 && part == nullptr && (nb > 1 || S > p->bp_slices))) {
     set_error("backprojection: batch needs its own partial-image buffer");
@@ -288,6 +289,11 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
                      p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
                      base, base2, dst, S == 1 ? out2 : nullptr);
   CT_TRY_HIP(hipGetLastError());
+  if (S > 1 && defer != nullptr && out2 == nullptr) {
+    // the consumer forms out from the partial images
+    *defer = BpDeferred{part, S, pfield, c1, c2, (float)(1.0 / p->g.h), base, base2};
+    return CT_OK;
+  }
   if (S > 1) {
     hipLaunchKernelGGL(k_bp_combine, dim3((n + 255) / 256, n, nb), dim3(256), 0, s, part, S, n,
                        pfield, c1, c2, (float)(1.0 / p->g.h), base, base2, out, out2);
