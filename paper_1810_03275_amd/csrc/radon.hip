@@ -533,7 +533,7 @@ __device__ inline void walk_row_ptr(uint32_t &e, const float *&pt, uint32_t A, u
   uint32_t d;
   const bool below = __builtin_sub_overflow(en, A, &d);  // en < A
   e = below ? en : d;
-  pt += below ? stride : stride - 1;
+  pt += (stride - 1) + (int)below;  // one add with the borrow as carry-in
 }
 
 template <bool CHECK_FIRST>
@@ -844,6 +844,18 @@ __device__ inline void acc_row(float x1, float x2, bool in1, bool in2, float ef,
   S += a2;
 }
 
+// The same with the second pixel already zero when it lies outside the strip
+// (read from a zero slot instead of the staged row).
+template <bool CHECK_FIRST>
+__device__ inline void acc_row_z(float x1, float a2, bool in1, float ef, float &P, float &Q,
+                                 float &S) {
+  const float a0 = CHECK_FIRST ? (in1 ? x1 : 0.f) : x1;
+  const float sa = a0 + a2;
+  P += sa;
+  Q = fmaf(ef, sa, Q);
+  S += a2;
+}
+
 template <int SL, bool CHECK_FIRST>
 __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
@@ -854,6 +866,9 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   constexpr int kRows = St::kRows;
   constexpr int kStride = SL * kLdw;  // staged row pitch (floats)
   __shared__ float tile[kFpMultiBufs * kRows * kStride];  // buffers x kRows x SL angles x kLdw
+  // zero slot: a second pixel outside the strip is read from zs + 1 + s kLdw
+  __shared__ float zs[kStride + 1];
+  for (int t = threadIdx.x; t < kStride + 1; t += blockDim.x) zs[t] = 0.f;  // before 1st barrier
   fp_batch_offsets(u, sino, ep, n, N, M);
   const int2 wk = work[blockIdx.x];  // (group, block along the bins)
   const FpGroup grp = groups[wk.x];
@@ -953,12 +968,14 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
       const float *pt = buf + (ps - plo);
       int r0 = 0;
       for (; r0 + RB <= rows; r0 += RB) {
-        const float *pr[RB];
+        const float *pr[RB], *pr2[RB];
         uint32_t ev[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           pr[r] = pt;
           ev[r] = e;
+          // the second pixels of all SL angles come from the row or the zero slot
+          pr2[r] = ev[r] < lim2 ? pt : zs;
           walk_row_ptr(e, pt, A, B, kStride);
         }
         float x1[RB][SL], x2[RB][SL];
@@ -967,17 +984,17 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
 #pragma unroll
           for (int s = 0; s < SL; ++s) {
             x1[r][s] = pr[r][s * kLdw];
-            x2[r][s] = pr[r][s * kLdw + 1];
+            x2[r][s] = pr2[r][s * kLdw + 1];
           }
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           const uint32_t e1 = ev[r];
-          const bool in1 = e1 < one, in2 = e1 < lim2;
+          const bool in1 = e1 < one;
           const float ef = (float)e1;
 #pragma unroll
           for (int s = 0; s < SL; ++s)
-            acc_row<CHECK_FIRST>(x1[r][s], x2[r][s], in1, in2, ef, P[s], Q[s], S[s]);
+            acc_row_z<CHECK_FIRST>(x1[r][s], x2[r][s], in1, ef, P[s], Q[s], S[s]);
         }
       }
       for (int r = r0; r < rows; ++r) {  // ragged last chunk
