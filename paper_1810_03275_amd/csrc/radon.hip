@@ -772,6 +772,17 @@ struct Stage {
     if (!tr) {
       // the wave index in a scalar register, so that the descriptor is one too
       const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+      // byte offset of column p0 = plo + lane; position p0 + 64 mc is 64
+      // columns further along the (possibly mirrored) row; the same offsets
+      // serve every row (each row has its own descriptor)
+      int off[kMultiWidth / 64];
+      {
+        const int p0 = plo + (t & 63);
+        const int o0 = (fi ? n - 1 - p0 : p0) * 4;
+        const int dstep = fi ? -256 : 256;
+#pragma unroll
+        for (int mc = 0; mc < kMultiWidth / 64; ++mc) off[mc] = own_offset(o0 + mc * dstep);
+      }
 #pragma unroll
       for (int mr = 0; mr < kRows / kWaves; ++mr) {
         const int r = wv + kWaves * mr;  // wave-uniform
@@ -779,15 +790,10 @@ struct Stage {
         const float *urow = u + (size_t)(fo ? n - 1 - q : q) * n;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)urow, (short)0, r < rows ? n * 4 : 0, kBufWord3);
-        // byte offset of column p0 = plo + lane; position p0 + 64 mc is
-        // 64 columns further along the (possibly mirrored) row
-        const int p0 = plo + (t & 63);
-        const int o0 = (fi ? n - 1 - p0 : p0) * 4;
-        const int dstep = fi ? -256 : 256;
 #pragma unroll
         for (int mc = 0; mc < kMultiWidth / 64; ++mc)
           v[mr * (kMultiWidth / 64) + mc] =
-              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(o0 + mc * dstep), 0, 0));
+              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off[mc], 0, 0));
       }
     } else {
       const int r = t & (kRows - 1);
@@ -800,9 +806,14 @@ struct Stage {
       const int p0 = plo + t / kRows;
       const int o0 = ((fi ? n - 1 - p0 : p0) * n + qi) * 4;
       const int dstep = (fi ? -4 : 4) * (kThreads / kRows) * n;
+      // a chain of offsets: each load takes its register as it is, one add apart
+      int o = o0;
 #pragma unroll
-      for (int m = 0; m < kPer; ++m)
-        v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(o0 + m * dstep), 0, 0));
+      for (int m = 0; m < kPer; ++m) {
+        o = own_offset(o);
+        v[m] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0));
+        o += dstep;
+      }
     }
   }
 
