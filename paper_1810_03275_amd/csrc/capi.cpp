@@ -655,8 +655,10 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
 static int solver_tune(ct_solver *sv, hipStream_t st) {
   const int N = sv->N;
   int cands[4], nc = 0;
+  // staged chunks of the backprojection's angles (mirror pairs when paired)
+  const int items = sv->plan->n_bpp > 0 ? sv->plan->n_bpp / kBpPairChunk : N / kBpChunk;
   for (int S : {1, 2, 4, 8})
-    if (S == 1 || N / S >= 2 * kBpChunk) cands[nc++] = S;
+    if (S == 1 || items / S >= 2) cands[nc++] = S;
   if (nc == 1) return solver_set_slices(sv, 1);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CT_TRY_HIP(hipEventCreate(&e0));

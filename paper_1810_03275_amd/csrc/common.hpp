@@ -96,6 +96,9 @@ constexpr int kBpPix = 8;
 constexpr int kBpRowStep = 8;
 constexpr int kBpChunk = 16;    // angles staged per chunk
 constexpr int kBpPrefetch = 8;  // staged pairs per thread: kBpChunk * seg <= 2048
+constexpr int kBpPairChunk = kBpChunk / 4;  // mirror pairs per chunk: 2 segments x 2 angles each
+constexpr int kBppPix = 4;                  // pixels per thread of the mirror-pair kernel
+constexpr int kBppTileJ = kBpRowStep * kBppPix;  // its tiles: kBpTileI x kBppTileJ
 
 // FFT plan (mixed radix 2/3/4, Stockham in LDS).
 struct FftPlan {
@@ -113,6 +116,11 @@ struct ct_plan {
   int device;
   // backprojection
   ctpd::BpAngle *d_bp = nullptr;
+  // mirror pairs (theta, pi - theta): entry 2c is angle l's geometry, entry
+  // 2c + 1 its mirror image i -> n - 1 - i (row: the partner m, or -1)
+  ctpd::BpAngle *d_bpp = nullptr;
+  int n_bpp = 0;          // pairs (0: the one-angle backprojector)
+  int seg_pair = 0;       // staged bins per angle per tile of the pair kernel
   int seg = 0;  // staged bins per angle per tile
   int bp_slices = 1;           // angle slices of the backprojection grid
   float *d_bp_part = nullptr;  // [bp_slices][n][n] partial images (bp_slices > 1)

@@ -32,11 +32,12 @@ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > h
 // Everything a plan holds, computed on the host.
 struct HostPlan {
   std::vector<BpAngle> bp;
+  std::vector<BpAngle> bpp;  // mirror pairs, two entries each (empty: unpaired)
   std::vector<FpAngle> dev;
   std::vector<FpGroup> groups;
   std::vector<int2> regions, ranges;
   std::vector<int2> work;  // (group, block) per forward workgroup, in launch order
-  int seg = 0, bp_slices = 1, n_groups = 0, max_blk = 0, n_chunks = 0, wmax = 0;
+  int seg = 0, seg_pair = 0, bp_slices = 1, n_groups = 0, max_blk = 0, n_chunks = 0, wmax = 0;
   bool check_first = false, paired = false;
   int slots = 1, chunk_rows = 16;
 };
@@ -144,15 +145,61 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
     max_extent = std::max(max_extent, (kBpTileI - 1) * std::fabs(bp[l].a) +
                                           (kBpTileJ - 1) * std::fabs(bp[l].b));
   p->seg = (int)std::ceil(max_extent) + 2;
+  {
+    double ext = 0.0;
+    for (int l = 0; l < N; ++l)
+      ext = std::max(ext, (kBpTileI - 1) * std::fabs(bp[l].a) + (kBppTileJ - 1) * std::fabs(bp[l].b));
+    p->seg_pair = (int)std::ceil(ext) + 2;
+  }
   if (kBpChunk * p->seg > 256 * kBpPrefetch) {
     set_error("projector plan: backprojection segment too long (ds/h too small)");
     return CT_E_UNSUPPORTED;
   }
+  // Mirror pairs for the backprojection: angle m with A30_m = -A30_l,
+  // B30_m = B30_l and T30_m = T30_l + (n - 1) A30_l puts pixel (n - 1 - i, j)
+  // exactly where l puts pixel (i, j) (for the default angles, l and N - l).
+  // Angles without a partner are paired with their own mirror image and a
+  // zero sinogram row.  Used when at least half of the angles pair up.
   {
-    const int tiles = ((n + kBpTileI - 1) / kBpTileI) * ((n + kBpTileJ - 1) / kBpTileJ);
+    auto fix = [](double x) { return (int64_t)std::llround(x * kFixOne); };
+    std::map<std::tuple<int64_t, int64_t, int64_t>, int> by_geom;
+    for (int l = 0; l < N; ++l) by_geom.emplace(std::make_tuple(fix(bp[l].a), fix(bp[l].b), fix(bp[l].t0)), l);
+    std::vector<char> used(N, 0);
+    std::vector<BpAngle> pairs;
+    int paired_angles = 0;
+    for (int l = 0; l < N; ++l) {
+      if (used[l]) continue;
+      used[l] = 1;
+      const int64_t A30 = fix(bp[l].a), B30 = fix(bp[l].b), T30 = fix(bp[l].t0);
+      const int64_t Tm = T30 + (int64_t)(n - 1) * A30;
+      int m = -1;
+      const auto it = by_geom.find(std::make_tuple(-A30, B30, Tm));
+      if (it != by_geom.end() && it->second != l && !used[it->second]) {
+        m = it->second;
+        used[m] = 1;
+        paired_angles += 2;
+      }
+      BpAngle mir = bp[l];
+      mir.t0 = (double)Tm / kFixOne;
+      mir.a = (double)(-A30) / kFixOne;
+      mir.a32 = (double)(-A30 * 4);
+      mir.l = m;
+      pairs.push_back(bp[l]);
+      pairs.push_back(mir);
+    }
+    const char *env = std::getenv("CTPD_BP_PAIRS");
+    const bool off = env && env[0] == '0';
+    if (!off && n >= 2 && 2 * paired_angles >= N) p->bpp = pairs;
+  }
+  {
+    // workgroups: tiles (of the left half when paired) x angle slices
+    const int ni = p->bpp.empty() ? n : (n + 1) / 2;
+    const int tj = p->bpp.empty() ? kBpTileJ : kBppTileJ;
+    const int tiles = ((ni + kBpTileI - 1) / kBpTileI) * ((n + tj - 1) / tj);
+    const int items = p->bpp.empty() ? N / kBpChunk : (int)(p->bpp.size() / 2) / kBpPairChunk;
     int S = (1024 + tiles - 1) / tiles;
     S = std::min(S, kMaxDeferredSlices);
-    S = std::min(S, std::max(1, N / (2 * kBpChunk)));
+    S = std::min(S, std::max(1, items / 2));
     p->bp_slices = std::max(S, 1);
   }
   p->check_first = check_first;
@@ -371,6 +418,7 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   CT_TRY(plan_host(g, angles, &hp));
   const int n = g->n, N = g->n_angles;
   p->seg = hp.seg;
+  p->seg_pair = hp.seg_pair;
   p->bp_slices = hp.bp_slices;
   p->check_first = hp.check_first;
   p->paired = hp.paired;
@@ -381,6 +429,12 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   p->n_chunks = hp.n_chunks;
   p->wmax = hp.wmax;
   CT_TRY_HIP(hipMalloc(&p->d_bp, sizeof(BpAngle) * N));
+  p->n_bpp = (int)(hp.bpp.size() / 2);
+  if (p->n_bpp > 0) {
+    CT_TRY_HIP(hipMalloc(&p->d_bpp, sizeof(BpAngle) * hp.bpp.size()));
+    CT_TRY_HIP(hipMemcpy(p->d_bpp, hp.bpp.data(), sizeof(BpAngle) * hp.bpp.size(),
+                         hipMemcpyHostToDevice));
+  }
   if (p->bp_slices > 1)
     CT_TRY_HIP(hipMalloc(&p->d_bp_part, sizeof(float) * (size_t)p->bp_slices * n * n));
   CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * hp.dev.size()));
@@ -504,6 +558,7 @@ int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
 void free_plan(ct_plan *p) {
   if (!p) return;
   (void)hipFree(p->d_bp);
+  (void)hipFree(p->d_bpp);
   (void)hipFree(p->d_bp_part);
   (void)hipFree(p->d_fp);
   (void)hipFree(p->d_groups);

@@ -270,6 +270,227 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
   if (out2 != nullptr) out2[o] = 2.f * res - base[o];
 }
 
+// ---------------------------------------------------------------------------
+// R_h^* over mirror pairs (theta_l, theta_m = pi - theta_l).
+//
+// Angle m puts pixel (n - 1 - i, j) exactly where l puts pixel (i, j), so one
+// bin coordinate serves two (pixel, angle) terms.  A workgroup owns a tile of
+// the left half (i < ceil(n/2)) and its mirror image; a thread evaluates two
+// coordinate chains per pair over its pixels (i, j_p):
+//   chain 0: t(i, j; l)  = t(n-1-i, j; m)  -> v_l to pixel L, v_m to pixel R
+//   chain 1: t(i, j; m)  = t(n-1-i, j; l)  -> v_m to pixel L, v_l to pixel R
+// Each chain has its own staged detector segment, holding for every bin both
+// angles' (v[k], v[k+1] - v[k]), at a constant distance from each other (two
+// single 8-byte LDS reads from one address; paired ds_read2 forms measured
+// slower).  An angle without a partner runs with its mirror image's geometry
+// and a zero sinogram row.  On the centre column of an odd n (i = n - 1 - i)
+// the L terms already hold both angles, and the R terms are dropped.  Tiles
+// are kBpTileI x kBppTileJ (four pixels per thread): more workgroups than the
+// one-angle kernel's tiles, at a register count that keeps them resident.
+
+// Staging of the mirror-pair kernel.  R rounds of 64 bins cover a segment
+// (R = 1: seg <= 64, R = 2: seg <= 128); a chunk holds kBpPrefetch / R pairs,
+// so that every thread stages kBpPrefetch (v[k], v[k+1]) pairs per chunk.
+// LDS float2 entry a kSlot + (2c + g) 64 R + k holds (v[k], v[k+1] - v[k]) of
+// angle slot a (0: l, 1: m) of pair c on chain g's segment: the two angles of
+// a bin are read with one address and a constant offset.
+template <int R>
+struct PairStage {
+  static constexpr int kPairs = kBpPrefetch / R;  // pairs per chunk
+  static constexpr int kStride = 64 * R;          // entries per (pair, chain, slot)
+  // slot 1's offset: neither within a ds_read2_b64's reach nor a multiple of
+  // 64 entries, so the two angles' reads stay single ds_read_b64 instructions
+  static constexpr int kSlot = kPairs * 2 * kStride + 8;
+
+  // Per pair c and chain g: segment start, 2^52 + (t0 - kmin) 2^32 and the
+  // sinogram row of slot g (entry 2c + g of the pair table).
+  __device__ static void meta(const BpAngle *__restrict__ pang, int c0, int nc, int i0, int j0,
+                              int *kmin_s, int *row_s, double *tb_s) {
+    const int t = threadIdx.x;
+    if (t < 2 * nc) {
+      const BpAngle A = pang[2 * c0 + t];
+      const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
+      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBppTileJ - 1);
+      const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
+      const int kmin = (int)floor(tmin);
+      kmin_s[t] = kmin;
+      row_s[t] = A.l;
+      tb_s[t] = fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0);
+    }
+  }
+
+  // Wave w stages chain g = w >> 1 of slot a = w & 1 for every pair of the
+  // chunk, through a descriptor covering the slot's sinogram row (record
+  // count 0 for a missing partner or a pair past the chunk's end).
+  __device__ static void load(float2 (&v)[kBpPrefetch], const float *__restrict__ sino, int M,
+                              int nc, const int *kmin_s, const int *row_s) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = w >> 1, a = w & 1;
+#pragma unroll
+    for (int c = 0; c < kPairs; ++c) {
+      const int cc = min(c, nc - 1);
+      const int row = __builtin_amdgcn_readfirstlane(row_s[2 * cc + a]);
+      const bool ok = c < nc && row >= 0;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(sino + (size_t)(ok ? row : 0) * M), (short)0, ok ? M * 4 : 0, kBufWord3);
+      const int k0 = kmin_s[2 * cc + g] + lane;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int k = k0 + 64 * m;
+        const float v0 =
+            __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(k * 4), 0, 0));
+        const float v1 =
+            __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, own_offset(k * 4 + 4), 0, 0));
+        v[c * R + m] = make_float2(v0, v1);
+      }
+    }
+  }
+
+  __device__ static void store(const float2 (&v)[kBpPrefetch], float2 *vd, int seg, int nc) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = w >> 1, a = w & 1;
+#pragma unroll
+    for (int c = 0; c < kPairs; ++c) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int k = lane + 64 * m;
+        const float2 q = v[c * R + m];
+        if (c < nc && k < seg) vd[a * kSlot + (2 * c + g) * kStride + k] = make_float2(q.x, q.y - q.x);
+      }
+    }
+  }
+};
+
+// gridDim.z = (problems of a batch) x S slices of the pairs: problem b = z / S.
+template <int R>
+__global__ __launch_bounds__(256) void k_radon_adj_pair(
+    const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ pang,
+    int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
+    float inv_h, const float *__restrict__ base, const float *__restrict__ base2,
+    float *__restrict__ out, float *__restrict__ out2, int n_pairs) {
+  using PS = PairStage<R>;
+  constexpr int kPairs = PS::kPairs, kStride = PS::kStride, kSlot = PS::kSlot;
+  __shared__ float2 vq_all[2 * 2 * kSlot];  // 2 buffers x 2 slots x pairs x 2 chains
+  __shared__ int row_s[3][2 * kPairs];
+  __shared__ int kmin_s[3][2 * kPairs];
+  __shared__ double tb_s[3][2 * kPairs];
+  const int tx = threadIdx.x & (kBpTileI - 1);
+  const int ty = threadIdx.x / kBpTileI;  // 0..7
+  const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBppTileJ;
+  const int i = i0 + tx;  // left-half column; its mirror is n - 1 - i
+  const int jb = j0 + ty;
+  double di = (double)i, dj = (double)jb;
+  asm volatile("" : "+v"(di), "+v"(dj));  // converted once, not per pair
+  const int bz = blockIdx.z / S, sl = blockIdx.z - bz * S;
+  const size_t nn = (size_t)n * n;
+  sino += (size_t)bz * N * M;
+  if (pfield != nullptr) pfield += (size_t)bz * 2 * nn;
+  if (base != nullptr) base += (size_t)bz * nn;
+  if (base2 != nullptr) base2 += (size_t)bz * nn;
+  if (out2 != nullptr) out2 += (size_t)bz * nn;
+  out += (size_t)blockIdx.z * nn;  // own image (S == 1) or own partial image
+  const int c_begin = sl * slice_len;
+  const int c_end = min(n_pairs, c_begin + slice_len);
+  const int nchunks =
+      c_end > c_begin ? (c_end - c_begin + kPairs - 1) / kPairs : 0;
+  float lv[kBppPix], ld[kBppPix], rv[kBppPix], rd[kBppPix];
+#pragma unroll
+  for (int p = 0; p < kBppPix; ++p) lv[p] = ld[p] = rv[p] = rd[p] = 0.f;
+
+  float2 pf[kBpPrefetch];
+  if (nchunks > 0) {
+    PS::meta(pang, c_begin, min(kPairs, c_end - c_begin), i0, j0, kmin_s[0], row_s[0],
+             tb_s[0]);
+    __syncthreads();
+    PS::load(pf, sino, M, min(kPairs, c_end - c_begin), kmin_s[0], row_s[0]);
+  }
+  for (int it = 0; it < nchunks; ++it) {
+    const int c0 = c_begin + it * kPairs;
+    const int nc = min(kPairs, c_end - c0);
+    const int slot = it % 3;
+    float2 *vq = vq_all + (it & 1) * (2 * kSlot);
+    PS::store(pf, vq, seg, nc);
+    const int c1n = c0 + kPairs;
+    const int ncn = min(kPairs, c_end - c1n);
+    if (it + 1 < nchunks)
+      PS::meta(pang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3],
+               tb_s[(it + 1) % 3]);
+    __syncthreads();
+    if (it + 1 < nchunks)
+      PS::load(pf, sino, M, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
+    for (int c = 0; c < nc; ++c) {
+      const BpAngle A0 = pang[2 * (c0 + c)];
+      const BpAngle A1 = pang[2 * (c0 + c) + 1];
+      const double x0 = fma(dj, A0.b32, fma(di, A0.a32, tb_s[slot][2 * c]));
+      const double x1 = fma(dj, A1.b32, fma(di, A1.a32, tb_s[slot][2 * c + 1]));
+      const uint64_t step = (uint64_t)A0.b8_fix;  // b is the same for both chains
+      // one chain at a time: v_l and v_m go to (L, R) on chain 0, (R, L) on chain 1
+      auto chain = [&](double x, const float2 *sg, float *va, float *da, float *vb, float *db) {
+        // the high word less the exponent field: the local bin index itself
+        uint64_t f = (uint64_t)__double_as_longlong(x) - ((uint64_t)kMagicHi << 32);
+        uint32_t hh[kBppPix], ll[kBppPix];
+#pragma unroll
+        for (int p = 0; p < kBppPix; ++p) {
+          if (p > 0) {
+            f += step;
+            asm volatile("" : "+v"(f));
+          }
+          hh[p] = (uint32_t)(f >> 32);
+          ll[p] = (uint32_t)f;
+        }
+        float2 qa[kBppPix], qb[kBppPix];
+#pragma unroll
+        for (int p = 0; p < kBppPix; ++p) {
+          qa[p] = sg[hh[p]];          // angle l
+          qb[p] = sg[hh[p] + kSlot];  // angle m
+        }
+#pragma unroll
+        for (int p = 0; p < kBppPix; ++p) {
+          const float al = (float)ll[p];
+          va[p] += qa[p].x;
+          da[p] = fmaf(al, qa[p].y, da[p]);
+          vb[p] += qb[p].x;
+          db[p] = fmaf(al, qb[p].y, db[p]);
+        }
+      };
+      chain(x0, vq + (2 * c) * kStride, lv, ld, rv, rd);
+      chain(x1, vq + (2 * c + 1) * kStride, rv, rd, lv, ld);
+    }
+  }
+  const float inv32 = 2.3283064365386963e-10f;  // 2^-32
+  const bool final_out = (S == 1);
+  const int nh = (n + 1) / 2;
+  if (i >= nh) return;
+  const int ir = n - 1 - i;
+  auto emit = [&](int col, int j, float r) {
+    const size_t o = (size_t)j * n + col;
+    if (!final_out) {
+      out[o] = r;
+      return;
+    }
+    float res = c1 * r;
+    if (pfield != nullptr) {
+      const float *p1 = pfield;
+      const float *p2 = pfield + nn;
+      const float d1 = (col < n - 1 ? p1[o] : 0.f) - (col > 0 ? p1[o - 1] : 0.f);
+      const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
+      res = fmaf(c2 * inv_h, d1 + d2, res);
+    }
+    if (base != nullptr) res += base[o];
+    if (base2 != nullptr) res -= base2[o];
+    out[o] = res;
+    if (out2 != nullptr) out2[o] = 2.f * res - base[o];
+  };
+#pragma unroll
+  for (int p = 0; p < kBppPix; ++p) {
+    const int j = jb + kBpRowStep * p;
+    if (j >= n) continue;
+    emit(i, j, fmaf(ld[p], inv32, lv[p]));
+    if (ir != i) emit(ir, j, fmaf(rd[p], inv32, rv[p]));
+  }
+}
+
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb, float *part, int S,
                      const float *base, const float *base2, float *out2, BpDeferred *defer) {
@@ -282,12 +503,28 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
     return CT_E_INVALID;
   }
   if (part == nullptr) part = p->d_bp_part;
-  dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S * nb);
-  const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;
   float *dst = (S == 1) ? out : part;
-  hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
-                     p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
-                     base, base2, dst, S == 1 ? out2 : nullptr);
+  if (p->n_bpp > 0) {
+    const int nh = (n + 1) / 2;
+    const int pair_len = (p->n_bpp + S - 1) / S;
+    dim3 grid((nh + kBpTileI - 1) / kBpTileI, (n + kBppTileJ - 1) / kBppTileJ, S * nb);
+    if (p->seg_pair <= 64)
+      hipLaunchKernelGGL(k_radon_adj_pair<1>, grid, dim3(256), 0, s, v, n, p->g.n_angles,
+                         p->g.n_bins, p->d_bpp, p->seg_pair, pair_len, S, pfield, c1, c2,
+                         (float)(1.0 / p->g.h), base, base2, dst, S == 1 ? out2 : nullptr,
+                         p->n_bpp);
+    else
+      hipLaunchKernelGGL(k_radon_adj_pair<2>, grid, dim3(256), 0, s, v, n, p->g.n_angles,
+                         p->g.n_bins, p->d_bpp, p->seg_pair, pair_len, S, pfield, c1, c2,
+                         (float)(1.0 / p->g.h), base, base2, dst, S == 1 ? out2 : nullptr,
+                         p->n_bpp);
+  } else {
+    dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S * nb);
+    const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;
+    hipLaunchKernelGGL(k_radon_adj, grid, dim3(256), lds, s, v, n, p->g.n_angles, p->g.n_bins,
+                       p->d_bp, p->seg, slice_len, S, pfield, c1, c2, (float)(1.0 / p->g.h),
+                       base, base2, dst, S == 1 ? out2 : nullptr);
+  }
   CT_TRY_HIP(hipGetLastError());
   if (S > 1 && defer != nullptr && out2 == nullptr) {
     // the consumer forms out from the partial images

@@ -54,6 +54,9 @@ GEOMS = [
     (90, 180, 128, 1.0, 0.8),   # angle pairs, strips that can miss a row
     (90, 180, 128, 1.0, 1.4),   # pairs too wide for the paired kernel
     (66, 4, 100, 1.0, 1.0),     # one pair and two angles alone
+    (63, 90, 96, 1.0, 1.0),     # odd n: the mirror pairs' centre column
+    (65, 36, 100, 1.0, 1.0),    # odd n, a ragged left-half tile
+    (33, 7, 50, 1.0, 1.0),      # odd N
 ]
 
 
@@ -73,6 +76,27 @@ def test_radon_pair_parity(geo):
     # the GPU pair is adjoint to FP32 summation accuracy
     lhs, rhs = np.sum(fx * y), np.sum(x * by)
     assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(fx) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4)],
+                         ids=lambda g: "x".join(map(str, g)))
+def test_backprojection_with_and_without_mirror_pairs(geo, monkeypatch):
+    """The mirror-pair backprojector (theta and pi - theta from one bin
+    coordinate) and the one-angle backprojector agree with the oracle and with
+    each other to FP32 summation accuracy."""
+    n, N, M = geo
+    print("backprojection pairs", geo, flush=True)
+    g = geometry.Geometry(n, N, M)
+    rng = np.random.default_rng(n + N)
+    y = f32(rng.uniform(-1, 1, (N, M)))
+    ref = radon.radon_adj(g, y)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("CTPD_BP_PAIRS", flag)
+        plan = ct.Plan(n, N, M)
+        out.append(host(plan.radon_adj(gpu(y))))
+        assert rel(out[-1], ref) <= 1e-5
+    assert rel(out[0], out[1]) <= 1e-6
 
 
 def test_radon_deterministic_and_arbitrary_angles():
