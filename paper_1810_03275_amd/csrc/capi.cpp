@@ -171,6 +171,7 @@ struct ct_solver {
   float *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Hp = nullptr;
   double *d_cg = nullptr;     // [0], [1] r.z (alternating), [2] p.Hp, then dot partials
   bool defer_combine = true;  // form R_h^*'s slice sum in the FFT row pass
+  bool fuse_tv = true;        // run the gradient-side update in R_h's launch
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   bool tune = true;
@@ -640,10 +641,27 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   ep.q1 = q1out;
   ep.fit = sv->fit;
   ep.aux = sv->fit_aux;
-  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
+  // the gradient-side update reads u_new only: it runs in the same launch
+  // (extra workgroups) unless the phases are being timed one by one
+  TvArgs tv;
+  tv.n = sv->n;
+  tv.inv_h = inv_h;
+  tv.u = sv->u_next;
+  tv.st = sig * tau;
+  tv.radius = (float)(sv->lam_t / sv->tau);
+  tv.vb2 = sv->vb2;
+  tv.s2 = sv->s2;
+  tv.wout = sv->w;
+  tv.mode = mode;
+  tv.q2out = q2out;
+  tv.ubar = sv->ubar;
+  tv.blocks = (ev || !sv->fuse_tv) ? 0 : std::min(sv->n, 256);
+  bool fused = false;
+  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb, &tv, &fused));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
-  CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
-                          sv->vb2, sv->s2, sv->w, mode, st, nb, q2out, sv->ubar));
+  if (!fused)
+    CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
+                            sv->vb2, sv->s2, sv->w, mode, st, nb, q2out, sv->ubar));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[4], st));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
@@ -1111,6 +1129,8 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     sv->tune = !(nt && nt[0] == '1');
     const char *nd = std::getenv("CTPD_NO_DEFER");
     sv->defer_combine = !(nd && nd[0] == '1');
+    const char *nf = std::getenv("CTPD_NO_TV_FUSE");
+    sv->fuse_tv = !(nf && nf[0] == '1');
   }
   int rc = solver_setup(sv, probs, prm, S(s));
   if (rc != CT_OK) {

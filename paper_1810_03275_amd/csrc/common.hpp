@@ -212,8 +212,24 @@ struct SinoEpi {
   const float *aux = nullptr;  // weights (weighted fit) or b on every bin (fit everywhere)
 };
 // out = R(u) (raw), or the epilogue when epi != nullptr
+// Arguments of the gradient-side update (k_tv_update; the device code is in
+// tv_update.hpp).  blocks > 0 in a forward launch: that many extra
+// workgroups per problem run it next to the projection.
+struct TvArgs {
+  int n = 0;
+  float inv_h = 0.f;
+  const float *u = nullptr;
+  float st = 0.f, radius = 0.f;
+  float *vb2 = nullptr, *s2 = nullptr, *wout = nullptr;
+  int mode = 0;
+  float *q2out = nullptr, *ubar = nullptr;
+  int blocks = 0;
+};
+// tv (optional): also run that update in the same launch when the paired
+// kernel projects; *fused tells whether it did (else the caller launches it).
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
-                     const SinoEpi *epi = nullptr, int nb = 1);
+                     const SinoEpi *epi = nullptr, int nb = 1, const TvArgs *tv = nullptr,
+                     bool *fused = nullptr);
 
 // metal-trace estimate: dilation by a disk of radius <= kDilMaxRadius, R_h,
 // D0 = {R_h chi > kappa}, bound = c0 u0 on D0 (when bound != nullptr)

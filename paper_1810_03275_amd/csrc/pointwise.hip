@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "tv_update.hpp"
 
 namespace ctpd {
 
@@ -33,14 +34,6 @@ __global__ void k_div(int n, float inv_h, const float *__restrict__ p, float *__
   d[o] = (d1 + d2) * inv_h;
 }
 
-// Pointwise projection onto the Euclidean ball of the given radius (§3.3).
-__device__ inline void ball_project(float q1, float q2, float radius, float &w1, float &w2) {
-  const float nrm = sqrtf(q1 * q1 + q2 * q2);
-  const float sc = (nrm > radius) ? radius / nrm : 1.f;
-  w1 = q1 * sc;
-  w2 = q2 * sc;
-}
-
 __global__ void k_tv_project(int64_t count, const float *__restrict__ q, float radius,
                              float *__restrict__ w) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,78 +44,11 @@ __global__ void k_tv_project(int64_t count, const float *__restrict__ q, float r
   w[t + count] = w2;
 }
 
-// PDRQS1 gradient-side update (§4.4): v2 = vb2 + sigma tau nabla u,
-// w = proj_{lambda~/tau}(2 v2 - vb2), vb2 <- vb2 + w - v2, and the cache
-// s2 = vb2 + sigma tau nabla u for the next iteration.
-// mode 1: only s2 = vb2 + sigma tau nabla u.  mode 2: also store w.
-__global__ void k_tv_update(int n, float inv_h, const float *__restrict__ u, float st,
-                            float radius, float *__restrict__ vb2, float *__restrict__ s2,
-                            float *__restrict__ wout, int mode, float *__restrict__ q2out,
-                            float *__restrict__ ubar) {
+// PDRQS1 gradient-side update (§4.4), one thread per pixel (tv_update_px).
+__global__ void k_tv_update(TvArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= n) return;
-  const size_t nn = (size_t)n * n;
-  const size_t o = (size_t)j * n + i;
-  // problem blockIdx.z of a batch
-  u += blockIdx.z * nn;
-  vb2 += blockIdx.z * 2 * nn;
-  s2 += blockIdx.z * 2 * nn;
-  if (wout != nullptr) wout += blockIdx.z * 2 * nn;
-  if (q2out != nullptr) q2out += blockIdx.z * 2 * nn;
-  if (ubar != nullptr) ubar += blockIdx.z * nn;
-  const float c = u[o];
-  const float g1 = (i < n - 1) ? (u[o + 1] - c) * inv_h : 0.f;
-  const float g2 = (j < n - 1) ? (u[o + n] - c) * inv_h : 0.f;
-  const float b1 = vb2[o], b2 = vb2[o + nn];
-  if (mode == 5) {
-    // ADMM z-step and multiplier update (§4.6), gradient block: s = nabla u
-    // + eta_v, v = soft(s, radius) (the lemma of §4.6), eta_v <- s - v, and
-    // the next u-step's residual term (v - eta_v) - nabla u = 2 v - s - nabla u
-    const float t1 = g1 + b1, t2 = g2 + b2;
-    const float nq = sqrtf(t1 * t1 + t2 * t2);
-    const float sc = nq > radius ? 1.f - radius / nq : 0.f;
-    const float v1 = sc * t1, v2 = sc * t2;
-    vb2[o] = t1 - v1;
-    vb2[o + nn] = t2 - v2;
-    s2[o] = 2.f * v1 - t1 - g1;
-    s2[o + nn] = 2.f * v2 - t2 - g2;
-    return;
-  }
-  if (mode == 1) {
-    s2[o] = fmaf(st, g1, b1);
-    s2[o + nn] = fmaf(st, g2, b2);
-    return;
-  }
-  if (mode == 4) {
-    // Algorithm CP dual step: w <- projection of w + st nabla u (u extrapolated)
-    float w1, w2;
-    ball_project(fmaf(st, g1, b1), fmaf(st, g2, b2), radius, w1, w2);
-    vb2[o] = w1;
-    vb2[o + nn] = w2;
-    return;
-  }
-  const float v1 = fmaf(st, g1, b1), v2 = fmaf(st, g2, b2);
-  float w1, w2;
-  ball_project(2.f * v1 - b1, 2.f * v2 - b2, radius, w1, w2);
-  if (q2out != nullptr) {
-    q2out[o] = 2.f * v1 - b1;
-    q2out[o + nn] = 2.f * v2 - b2;
-  }
-  if (ubar != nullptr) {
-    // resolvent of the indicator of u >= 0 (§4.5): max(., 0)
-    const float ub = ubar[o];
-    ubar[o] = ub + fmaxf(2.f * c - ub, 0.f) - c;
-  }
-  const float n1 = b1 + w1 - v1, n2 = b2 + w2 - v2;
-  vb2[o] = n1;
-  vb2[o + nn] = n2;
-  s2[o] = fmaf(st, g1, n1);
-  s2[o + nn] = fmaf(st, g2, n2);
-  if (mode == 2) {
-    wout[o] = w1;
-    wout[o + nn] = w2;
-  }
+  if (i >= a.n) return;
+  tv_update_px(a, i, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,8 +269,19 @@ int launch_tv_update(int n, float inv_h, const float *u, float sigtau, float rad
                      float *ubar) {
   dim3 grid = row_grid(n, n);
   grid.z = nb;
-  hipLaunchKernelGGL(k_tv_update, grid, dim3(256), 0, s, n, inv_h, u, sigtau, radius, vb2, s2,
-                     wout, mode, q2out, ubar);
+  TvArgs a;
+  a.n = n;
+  a.inv_h = inv_h;
+  a.u = u;
+  a.st = sigtau;
+  a.radius = radius;
+  a.vb2 = vb2;
+  a.s2 = s2;
+  a.wout = wout;
+  a.mode = mode;
+  a.q2out = q2out;
+  a.ubar = ubar;
+  hipLaunchKernelGGL(k_tv_update, grid, dim3(256), 0, s, a);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

@@ -8,6 +8,7 @@
 // alpha = t - floor(t) is rounded once to FP32 in both, giving bit-identical
 // weights; R_h is the transpose of R_h^* up to FP32 summation order.
 #include "common.hpp"
+#include "tv_update.hpp"
 
 namespace ctpd {
 
@@ -1109,7 +1110,14 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
     const int2 *__restrict__ chunk_range, const int2 *__restrict__ work, int n_chunks,
-    float *__restrict__ sino, SinoEpi ep, int N) {
+    float *__restrict__ sino, SinoEpi ep, int N, int n_work, TvArgs tv) {
+  if ((int)blockIdx.x >= n_work) {
+    // workgroups past the projection's run the gradient-side update (rows
+    // b, b + tv.blocks, ...): memory-bound work next to the ALU-bound walk
+    for (int j = (int)blockIdx.x - n_work; j < tv.n; j += tv.blocks)
+      for (int i = threadIdx.x; i < tv.n; i += blockDim.x) tv_update_px(tv, i, j, blockIdx.z);
+    return;
+  }
   using St = Stage<SL>;
   constexpr int kRows = St::kRows;
   constexpr int kStride = SL * kLdw;  // staged row pitch (floats)
@@ -1277,21 +1285,28 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
 }
 
 int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s,
-                     const SinoEpi *epi, int nb) {
+                     const SinoEpi *epi, int nb, const TvArgs *tv, bool *fused) {
   SinoEpi ep{};
   if (epi) ep = *epi;
   const int N = p->g.n_angles;
   dim3 grid(p->n_work, 1, nb);
+  if (fused) *fused = false;
   if (p->slots == 2) {
     const dim3 block(64 * MultiCfg<2>::kWaves);
+    TvArgs ta{};
+    if (tv != nullptr && tv->blocks > 0) {
+      ta = *tv;
+      grid.x += ta.blocks;
+      if (fused) *fused = true;
+    }
     if (p->check_first)
       hipLaunchKernelGGL((k_radon_fwd_multi<2, true>), grid, block, 0, s, u, p->g.n, p->g.n_bins,
                          p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->d_work,
-                         p->n_chunks, out, ep, N);
+                         p->n_chunks, out, ep, N, p->n_work, ta);
     else
       hipLaunchKernelGGL((k_radon_fwd_multi<2, false>), grid, block, 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->d_work, p->n_chunks, out, ep, N);
+                         p->d_work, p->n_chunks, out, ep, N, p->n_work, ta);
     CT_TRY_HIP(hipGetLastError());
     return CT_OK;
   }
