@@ -136,6 +136,15 @@ __device__ float2 *fft_rows(float2 *a, float2 *b, int nrows, const FftPlan &pl,
   return a;
 }
 
+// Row-pair index of workgroup b of G: workgroups are dealt to the 8 XCDs in
+// turn, so consecutive row pairs -- which share the cache lines of the
+// spectrum's columns -- are given to workgroups on one XCD (one L2).
+__device__ inline int xcd_pair(int b, int G) {
+  const int full = G & ~7;
+  if (b >= full) return b;
+  return (b & 7) * (full >> 3) + (b >> 3);
+}
+
 // A workgroup-strided loop over [0, total) whose loads are issued kIoBatch
 // at a time (all before the first use), so that their latencies overlap.
 constexpr int kIoBatch = 4;
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__res
   float2 *a = sm;
   float2 *b = sm + RP * n;
   const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
-  const int pair0 = blockIdx.x * RP;
+  const int pair0 = xcd_pair(blockIdx.x, gridDim.x) * RP;
   const int npair = min(RP, n / 2 - pair0);
   const size_t nn = (size_t)n * n;
   if (DS == 0) {
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const float2 *__re
   float2 *a = sm;
   float2 *b = sm + RP * n;
   const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
-  const int pair0 = blockIdx.x * RP;
+  const int pair0 = xcd_pair(blockIdx.x, gridDim.x) * RP;
   const int npair = min(RP, n / 2 - pair0);
   const int half = n / 2 + 1;
   spec += (size_t)blockIdx.y * half * n;
