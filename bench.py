@@ -174,6 +174,7 @@ def large_run(ct, torch, iters: int):
             "ms_per_iteration": round(1e3 * dt / iters, 3), "setup_s": round(setup_s, 3),
             "gvox_angles_per_s": round(2 * pairs * iters / dt / 1e9, 1),
             "phase_us": {k: round(v * 1e3, 1) for k, v in ph.items()},
+            "layout": sv.layout(),
             "solve_1000_iterations_s": round(1000 * dt / iters + setup_s, 2)}
 
 
@@ -408,6 +409,7 @@ def main():
         "radon_pairs_unit": "Gvox*angles/s (R+R*)",
         "phase_us": {k: round(v * 1e3, 2) for k, v in ph.items()},
         "setup_ms": round(setup_s * 1e3, 2),
+        "layout": sv.layout(),
         "beta": info["beta"], "c": info["c"],
         "gap_record": [float(x) for x in rec],
         "roofline": {"kernel": ("k_radon_fwd_multi<%d>" % sv.layout()["angles_per_walk"]

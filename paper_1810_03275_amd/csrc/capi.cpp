@@ -668,16 +668,28 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   return CT_OK;
 }
 
-// Choose the number of angle slices of the backprojection for this batch by
-// timing the candidates on the solver's own data (the caches s1, s2).
+// Choose the backprojection kernel (mirror pairs or one angle at a time, when
+// the plan has pairs) and its number of angle slices for this batch by timing
+// the candidates on the solver's own data (the caches s1, s2).
 static int solver_tune(ct_solver *sv, hipStream_t st) {
+  ct_plan *p = sv->plan;
   const int N = sv->N;
-  int cands[4], nc = 0;
-  // staged chunks of the backprojection's angles (mirror pairs when paired)
-  const int items = sv->plan->n_bpp > 0 ? sv->plan->n_bpp / kBpPairChunk : N / kBpChunk;
-  for (int S : {1, 2, 4, 8})
-    if (S == 1 || items / S >= 2) cands[nc++] = S;
-  if (nc == 1) return solver_set_slices(sv, 1);
+  struct Cand {
+    bool pairs;
+    int S;
+  };
+  Cand cands[8];
+  int nc = 0;
+  for (int pr = (p->n_bpp > 0 ? 1 : 0); pr >= 0; --pr) {
+    // staged chunks of the backprojection's angles (mirror pairs when paired)
+    const int items = pr ? p->n_bpp / kBpPairChunk : N / kBpChunk;
+    for (int S : {1, 2, 4, 8})
+      if (S == 1 || items / S >= 2) cands[nc++] = Cand{pr == 1, S};
+  }
+  if (nc == 1) {
+    p->bp_use_pairs = cands[0].pairs;
+    return solver_set_slices(sv, 1);
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CT_TRY_HIP(hipEventCreate(&e0));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g0(
@@ -686,11 +698,12 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(
       e1, hipEventDestroy);
   float best = 0.f;
-  int bestS = cands[0];
+  Cand bestc = cands[0];
   for (int c = 0; c < nc; ++c) {
-    CT_TRY(solver_set_slices(sv, cands[c]));
+    p->bp_use_pairs = cands[c].pairs;
+    CT_TRY(solver_set_slices(sv, cands[c].S));
     auto run = [&]() {
-      return launch_radon_adj(sv->plan, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+      return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
                               sv->bp_part, sv->bp_S);
     };
     CT_TRY(run());  // warm-up
@@ -702,10 +715,11 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
     CT_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
     if (c == 0 || ms < best) {
       best = ms;
-      bestS = cands[c];
+      bestc = cands[c];
     }
   }
-  return solver_set_slices(sv, bestS);
+  p->bp_use_pairs = bestc.pairs;
+  return solver_set_slices(sv, bestc.S);
 }
 
 // Kernel preconditioners for PDRQS1, built from the response of A^* A to a
@@ -1204,7 +1218,7 @@ int ct_solver_info(const ct_solver *sv, double out[4]) {
   return CT_OK;
 }
 
-int ct_solver_layout(const ct_solver *sv, int32_t out[4]) {
+int ct_solver_layout(const ct_solver *sv, int32_t out[5]) {
   clear_error();
   if (!sv || !out) {
     set_error("ct_solver_layout: null argument");
@@ -1214,6 +1228,7 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[4]) {
   out[1] = sv->bp_S;
   out[2] = sv->plan->slots;
   out[3] = sv->plan->n_groups;
+  out[4] = (sv->plan->n_bpp > 0 && sv->plan->bp_use_pairs) ? 2 : 1;
   return CT_OK;
 }
 

@@ -120,6 +120,7 @@ struct ct_plan {
   // 2c + 1 its mirror image i -> n - 1 - i (row: the partner m, or -1)
   ctpd::BpAngle *d_bpp = nullptr;
   int n_bpp = 0;          // pairs (0: the one-angle backprojector)
+  bool bp_use_pairs = true;  // with pairs: use them (a solver's tuning may say no)
   int seg_pair = 0;       // staged bins per angle per tile of the pair kernel
   int seg = 0;  // staged bins per angle per tile
   int bp_slices = 1;           // angle slices of the backprojection grid

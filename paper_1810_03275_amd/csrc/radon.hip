@@ -7,6 +7,8 @@
 // forward projection exactly in integers.  The interpolation weight
 // alpha = t - floor(t) is rounded once to FP32 in both, giving bit-identical
 // weights; R_h is the transpose of R_h^* up to FP32 summation order.
+#include <type_traits>
+
 #include "common.hpp"
 #include "tv_update.hpp"
 
@@ -505,7 +507,7 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   }
   if (part == nullptr) part = p->d_bp_part;
   float *dst = (S == 1) ? out : part;
-  if (p->n_bpp > 0) {
+  if (p->n_bpp > 0 && p->bp_use_pairs) {
     const int nh = (n + 1) / 2;
     const int pair_len = (p->n_bpp + S - 1) / S;
     dim3 grid((nh + kBpTileI - 1) / kBpTileI, (n + kBppTileJ - 1) / kBppTileJ, S * nb);
@@ -1105,13 +1107,15 @@ __device__ inline void acc_row_z(float x1, float a2, bool in1, float ef, float &
   S += a2;
 }
 
-template <int SL, bool CHECK_FIRST>
+// TVF: the launch also holds the gradient-side update's workgroups (a
+// separate instantiation, so that traces tell the two launches apart).
+template <int SL, bool CHECK_FIRST, bool TVF>
 __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     const float *__restrict__ u, int n, int M, const FpAngle *__restrict__ angs,
     const FpGroup *__restrict__ groups, const int2 *__restrict__ regions,
     const int2 *__restrict__ chunk_range, const int2 *__restrict__ work, int n_chunks,
     float *__restrict__ sino, SinoEpi ep, int N, int n_work, TvArgs tv) {
-  if ((int)blockIdx.x >= n_work) {
+  if (TVF && (int)blockIdx.x >= n_work) {
     // workgroups past the projection's run the gradient-side update (rows
     // b, b + tv.blocks, ...): memory-bound work next to the ALU-bound walk
     for (int j = (int)blockIdx.x - n_work; j < tv.n; j += tv.blocks)
@@ -1299,14 +1303,24 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
       grid.x += ta.blocks;
       if (fused) *fused = true;
     }
-    if (p->check_first)
-      hipLaunchKernelGGL((k_radon_fwd_multi<2, true>), grid, block, 0, s, u, p->g.n, p->g.n_bins,
-                         p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range, p->d_work,
-                         p->n_chunks, out, ep, N, p->n_work, ta);
-    else
-      hipLaunchKernelGGL((k_radon_fwd_multi<2, false>), grid, block, 0, s, u, p->g.n,
+    auto go = [&](auto cf, auto tvf) {
+      constexpr bool CF = decltype(cf)::value, TVF = decltype(tvf)::value;
+      hipLaunchKernelGGL((k_radon_fwd_multi<2, CF, TVF>), grid, block, 0, s, u, p->g.n,
                          p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
                          p->d_work, p->n_chunks, out, ep, N, p->n_work, ta);
+    };
+    const bool with_tv = ta.blocks > 0;
+    if (p->check_first) {
+      if (with_tv)
+        go(std::true_type{}, std::true_type{});
+      else
+        go(std::true_type{}, std::false_type{});
+    } else {
+      if (with_tv)
+        go(std::false_type{}, std::true_type{});
+      else
+        go(std::false_type{}, std::false_type{});
+    }
     CT_TRY_HIP(hipGetLastError());
     return CT_OK;
   }

@@ -2,7 +2,7 @@
 
     python -m paper_1810_03275_amd.profiling trace <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1810_03275_amd.profiling traffic <fetch.csv> <write.csv> <kernel> \
-        <copy_bytes> <out.json> "<command>"
+        <copy_bytes> <out.json> "<command>" [median|top]
     python -m paper_1810_03275_amd.profiling counters <counter_collection.csv> <out.md> \
         "<title>" "<command>"
 
@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("radon.hip", "common.hpp", "plan.cpp"):
+    for f in ("radon.hip", "common.hpp", "plan.cpp", "tv_update.hpp"):
         with open(os.path.join(ROOT, "paper_1810_03275_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,7 +66,11 @@ def _per_dispatch(path: str):
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: float, out_json: str,
-            command: str) -> dict:
+            command: str, select: str = "median") -> dict:
+    """select = "median": median over the kernel's dispatches; "top": median
+    over those above 1.5 x the smallest, if any (the in-path launches, which
+    also read and write the sinogram-side update, against the plain
+    projections of the set-up)."""
     out = {}
     for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
         d, names = _per_dispatch(path)
@@ -74,9 +78,13 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: float, out_
         ref = max(copies) * 1024.0
         factor = copy_bytes / ref
         vals = [v * 1024.0 * factor for k, v in d.items() if kernel in names[k]]
+        if select == "top":
+            big = [v for v in vals if v > 1.5 * min(vals)]
+            vals = big or vals
         vals.sort()
         med = vals[len(vals) // 2]
-        out[tag] = {"bytes_per_launch": med, "scale": factor, "dispatches": len(vals)}
+        out[tag] = {"bytes_per_launch": med, "scale": factor, "dispatches": len(vals),
+                    "select": select}
     rec = {"kernel": kernel, "bytes_per_launch": out["fetch"]["bytes_per_launch"]
            + out["write"]["bytes_per_launch"], "fetch": out["fetch"], "write": out["write"],
            "calibration": f"plain device copy of {copy_bytes:.0f} bytes",
@@ -114,6 +122,6 @@ if __name__ == "__main__":
         trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), sys.argv[6],
-                      sys.argv[7]))
+                      sys.argv[7], sys.argv[8] if len(sys.argv) > 8 else "median"))
     elif sys.argv[1] == "counters":
         counters_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
