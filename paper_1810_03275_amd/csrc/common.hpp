@@ -66,7 +66,7 @@ constexpr int kFpThreads = 64 * kFpWaves;
 constexpr int kFpPerThread = 2;
 constexpr int kFpGroup = kFpWaves * kFpPerThread;  // 16 angles
 constexpr int kFpStrips = 64;                       // strips per workgroup (63 outputs)
-constexpr int kFpRows = 16;                         // image rows staged per chunk
+constexpr int kFpRows = 32;                         // image rows staged per chunk
 constexpr int kFpMaxWidth = 192;                    // staged columns per chunk
 constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixels per thread
 
