@@ -670,7 +670,8 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
 
 // Choose the backprojection kernel (mirror pairs or one angle at a time, when
 // the plan has pairs) and its number of angle slices for this batch by timing
-// the candidates on the solver's own data (the caches s1, s2).
+// the candidates on the solver's own data (the caches s1, s2), together with
+// the pass that sums the slices (the FFT pair or the combine).
 static int solver_tune(ct_solver *sv, hipStream_t st) {
   ct_plan *p = sv->plan;
   const int N = sv->N;
@@ -697,14 +698,26 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   CT_TRY_HIP(hipEventCreate(&e1));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(
       e1, hipEventDestroy);
+  const bool with_fft = sv->defer_combine &&
+                        (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_PDRQS2 ||
+                         sv->method == CT_METHOD_PDRQS3);
   float best = 0.f;
   Cand bestc = cands[0];
   for (int c = 0; c < nc; ++c) {
     p->bp_use_pairs = cands[c].pairs;
     CT_TRY(solver_set_slices(sv, cands[c].S));
+    // what the iteration runs: with the FFT pair next, R_h^* with its slice
+    // sum deferred into the row pass and the pair itself; else R_h^* and the
+    // slice combine
     auto run = [&]() {
-      return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
-                              sv->bp_part, sv->bp_S);
+      if (!with_fft)
+        return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+                                sv->bp_part, sv->bp_S);
+      BpDeferred def{};
+      CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb, sv->bp_part,
+                              sv->bp_S, nullptr, nullptr, nullptr, &def));
+      return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, sv->nb,
+                               sv->spec, def.S > 1 ? &def : nullptr);
     };
     CT_TRY(run());  // warm-up
     CT_TRY_HIP(hipEventRecord(e0, st));
