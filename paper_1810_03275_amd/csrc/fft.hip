@@ -174,29 +174,64 @@ __device__ inline const float2 *stage_twiddles(float2 *lds, const float2 *__rest
   return lds;  // the caller's barrier precedes the first read
 }
 
-// The deferred backprojection at pixel (i, j) from DS = d.S partial images:
-// the slices' sum in slice order and the epilogue, as the combine pass
-// computes them.  DS is a compile-time count so that every load of a pixel
-// is in flight at once.
+// Two neighbouring pixels (i0, i0 + 1; i0 even) of rows j and j + 1 of the
+// deferred backprojection from DS = d.S partial images, with 8-byte loads:
+// per pixel the slices' sum in slice order and the epilogue, the same
+// operations in the same order as the stand-alone combine pass.  DS is a
+// compile-time count so that all loads are in flight at once; row j + 1's
+// lower neighbour in the field's second component is row j's own value.
 template <int DS>
-__device__ inline float deferred_value(const BpDeferred &d, int n, int i, int j) {
-  const size_t nn = (size_t)n * n, o = (size_t)j * n + i;
-  float v[DS];
+__device__ inline void deferred_two(const BpDeferred &d, int n, int i0, int j, float2 &r0,
+                                    float2 &r1) {
+  const size_t nn = (size_t)n * n, o0 = (size_t)j * n + i0, o1 = o0 + n;
+  float2 a[DS], b[DS];
 #pragma unroll
-  for (int s = 0; s < DS; ++s) v[s] = d.part[s * nn + o];
-  float r = v[0];
+  for (int s = 0; s < DS; ++s) {
+    a[s] = *reinterpret_cast<const float2 *>(d.part + s * nn + o0);
+    b[s] = *reinterpret_cast<const float2 *>(d.part + s * nn + o1);
+  }
+  float2 u0 = a[0], u1 = b[0];
 #pragma unroll
-  for (int s = 1; s < DS; ++s) r += v[s];
-  float res = d.c1 * r;
+  for (int s = 1; s < DS; ++s) {
+    u0.x += a[s].x;
+    u0.y += a[s].y;
+    u1.x += b[s].x;
+    u1.y += b[s].y;
+  }
+  r0 = make_float2(d.c1 * u0.x, d.c1 * u0.y);
+  r1 = make_float2(d.c1 * u1.x, d.c1 * u1.y);
   if (d.pfield != nullptr) {
     const float *p1 = d.pfield, *p2 = d.pfield + nn;
-    const float d1 = (i < n - 1 ? p1[o] : 0.f) - (i > 0 ? p1[o - 1] : 0.f);
-    const float d2 = (j < n - 1 ? p2[o] : 0.f) - (j > 0 ? p2[o - n] : 0.f);
-    res = fmaf(d.c2 * d.inv_h, d1 + d2, res);
+    const float2 q0 = *reinterpret_cast<const float2 *>(p1 + o0);
+    const float2 q1 = *reinterpret_cast<const float2 *>(p1 + o1);
+    const float l0 = i0 > 0 ? p1[o0 - 1] : 0.f, l1 = i0 > 0 ? p1[o1 - 1] : 0.f;
+    const bool last = i0 + 1 >= n - 1;  // the second pixel is the row's last
+    // d1 = (i < n - 1 ? p1[o] : 0) - (i > 0 ? p1[o - 1] : 0)
+    const float d1a = q0.x - l0, d1b = (last ? 0.f : q0.y) - q0.x;
+    const float e1a = q1.x - l1, e1b = (last ? 0.f : q1.y) - q1.x;
+    // d2 = (j < n - 1 ? p2[o] : 0) - (j > 0 ? p2[o - n] : 0), rows j and j + 1
+    const float2 w0 = *reinterpret_cast<const float2 *>(p2 + o0);
+    const float2 w1 = *reinterpret_cast<const float2 *>(p2 + o1);
+    const float2 wm = j > 0 ? *reinterpret_cast<const float2 *>(p2 + o0 - n) : make_float2(0.f, 0.f);
+    const bool lastrow = j + 1 >= n - 1;
+    const float d2a = w0.x - wm.x, d2b = w0.y - wm.y;
+    const float e2a = (lastrow ? 0.f : w1.x) - w0.x, e2b = (lastrow ? 0.f : w1.y) - w0.y;
+    const float k = d.c2 * d.inv_h;
+    r0 = make_float2(fmaf(k, d1a + d2a, r0.x), fmaf(k, d1b + d2b, r0.y));
+    r1 = make_float2(fmaf(k, e1a + e2a, r1.x), fmaf(k, e1b + e2b, r1.y));
   }
-  if (d.base != nullptr) res += d.base[o];
-  if (d.base2 != nullptr) res -= d.base2[o];
-  return res;
+  if (d.base != nullptr) {
+    const float2 g0 = *reinterpret_cast<const float2 *>(d.base + o0);
+    const float2 g1 = *reinterpret_cast<const float2 *>(d.base + o1);
+    r0 = make_float2(r0.x + g0.x, r0.y + g0.y);
+    r1 = make_float2(r1.x + g1.x, r1.y + g1.y);
+  }
+  if (d.base2 != nullptr) {
+    const float2 g0 = *reinterpret_cast<const float2 *>(d.base2 + o0);
+    const float2 g1 = *reinterpret_cast<const float2 *>(d.base2 + o1);
+    r0 = make_float2(r0.x - g0.x, r0.y - g0.y);
+    r1 = make_float2(r1.x - g1.x, r1.y - g1.y);
+  }
 }
 
 // Row pass: rows [2 rp0, 2 rp0 + 2 RP) of y -> spec[k1][j], k1 in [0, n/2].
@@ -224,18 +259,26 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__res
     if (yd.base2 != nullptr) yd.base2 += blockIdx.y * nn;
   }
   spec += (size_t)blockIdx.y * (n / 2 + 1) * n;
-  batched(
-      npair * n,
-      [&](int t) {
-        const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
-        const int j = 2 * (pair0 + pr);
-        if constexpr (DS > 0)
-          return make_float2(deferred_value<DS>(yd, n, i, j),
-                             deferred_value<DS>(yd, n, i, j + 1));
-        else
+  if constexpr (DS > 0) {
+    // two pixels of both rows per thread and step (n is even)
+    const int hn = n / 2;
+    for (int t2 = threadIdx.x; t2 < npair * hn; t2 += kFftThreads) {
+      const int pr = (int)(((float)t2 + 0.5f) / (float)hn), i0 = 2 * (t2 - pr * hn);
+      float2 r0, r1;
+      deferred_two<DS>(yd, n, i0, 2 * (pair0 + pr), r0, r1);
+      a[pr * n + i0] = make_float2(r0.x, r1.x);
+      a[pr * n + i0 + 1] = make_float2(r0.y, r1.y);
+    }
+  } else {
+    batched(
+        npair * n,
+        [&](int t) {
+          const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
+          const int j = 2 * (pair0 + pr);
           return make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
-      },
-      [&](int t, float2 v) { a[t] = v; });
+        },
+        [&](int t, float2 v) { a[t] = v; });
+  }
   __syncthreads();
   float2 *z = fft_rows<false>(a, b, npair, pl, twp);
   const int half = n / 2 + 1;
