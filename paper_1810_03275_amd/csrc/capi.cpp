@@ -679,12 +679,12 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
     bool pairs;
     int S;
   };
-  Cand cands[8];
+  Cand cands[10];
   int nc = 0;
   for (int pr = (p->n_bpp > 0 ? 1 : 0); pr >= 0; --pr) {
     // staged chunks of the backprojection's angles (mirror pairs when paired)
     const int items = pr ? p->n_bpp / kBpPairChunk : N / kBpChunk;
-    for (int S : {1, 2, 4, 8})
+    for (int S : {1, 2, 4, 8, kMaxSlices})
       if (S == 1 || items / S >= 2) cands[nc++] = Cand{pr == 1, S};
   }
   if (nc == 1) {

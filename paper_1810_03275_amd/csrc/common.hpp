@@ -173,7 +173,10 @@ namespace ctpd {
 // formed: out = base - base2 + c1 sum_s part[s] + c2 div_h(pfield).  A
 // consumer that reads out once (the preconditioner's row pass) forms it on
 // the fly instead of a separate combine pass.  S = 0: nothing deferred.
-constexpr int kMaxDeferredSlices = 8;  // the plan's largest slice count
+constexpr int kMaxDeferredSlices = 8;  // the plan's largest default slice count
+constexpr int kMaxSlices = 16;         // the largest a solver's tuning tries
+// slice counts whose sum the FFT row pass can form (else the combine pass)
+inline bool deferrable_slices(int S) { return (S >= 2 && S <= kMaxDeferredSlices) || S == kMaxSlices; }
 struct BpDeferred {
   const float *part = nullptr;  // [nb][S][n][n]
   int S = 0;

@@ -414,7 +414,7 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
                       const BpDeferred *ydef) {
   const BpDeferred yd = ydef ? *ydef : BpDeferred{};
   const int DS = (ydef != nullptr && yd.part != nullptr) ? yd.S : 0;  // the deferred form wins
-  if ((DS == 0 && y == nullptr) || DS == 1 || DS > kMaxDeferredSlices) {
+  if ((DS == 0 && y == nullptr) || (DS != 0 && !deferrable_slices(DS))) {
     set_error("preconditioner: no input image, or an unsupported slice count");
     return CT_E_INVALID;
   }
@@ -450,6 +450,7 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
       CT_ROWS_FWD(6)
       CT_ROWS_FWD(7)
       CT_ROWS_FWD(8)
+      CT_ROWS_FWD(16)
 #undef CT_ROWS_FWD
     }
   };

@@ -529,7 +529,7 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
                        base, base2, dst, S == 1 ? out2 : nullptr);
   }
   CT_TRY_HIP(hipGetLastError());
-  if (S > 1 && defer != nullptr && out2 == nullptr) {
+  if (defer != nullptr && out2 == nullptr && deferrable_slices(S)) {
     // the consumer forms out from the partial images
     *defer = BpDeferred{part, S, pfield, c1, c2, (float)(1.0 / p->g.h), base, base2};
     return CT_OK;
