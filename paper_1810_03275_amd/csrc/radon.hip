@@ -56,8 +56,16 @@ __device__ inline int own_offset(int off) {
 // exponent field in the high word (kMagicHi, folded into the LDS base).
 constexpr uint32_t kMagicHi = 0x43300000u;  // high word of the double 2^52
 
+// Constants of one coordinate chain in LDS (read by the angle loops with
+// in-order LDS loads rather than scalar loads): 2^52 + (t0 - kmin) 2^32,
+// a 2^32, b 2^32 and the per-pixel step 8 b 2^32.
+struct alignas(16) ChainGeo {
+  double tb, a32, b32;
+  int64_t b8;
+};
+
 __device__ inline void bp_chunk_meta(const BpAngle *__restrict__ ang, int c0, int nc, int i0, int j0,
-                                     int *kmin_s, int *row_s, double *tb_s) {
+                                     int *kmin_s, int *row_s, ChainGeo *geo_s) {
   if ((int)threadIdx.x < nc) {
     const BpAngle A = ang[c0 + threadIdx.x];
     const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
@@ -67,7 +75,8 @@ __device__ inline void bp_chunk_meta(const BpAngle *__restrict__ ang, int c0, in
     kmin_s[threadIdx.x] = kmin;
     row_s[threadIdx.x] = A.l;
     // 2^52 + (t0 - kmin) 2^32: every term and partial sum is an integer below 2^53
-    tb_s[threadIdx.x] = fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0);
+    geo_s[threadIdx.x] = ChainGeo{fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0),
+                                  A.a32, A.b32, A.b8_fix};
   }
 }
 
@@ -136,13 +145,14 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   extern __shared__ float2 vd_all[];  // 2 x kBpChunk * seg
   __shared__ int row_s[3][kBpChunk];
   __shared__ int kmin_s[3][kBpChunk];
-  __shared__ double tb_s[3][kBpChunk];
+  __shared__ ChainGeo geo_s[3][kBpChunk];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
   const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBpTileJ;
   const int i = i0 + tx;
   const int jb = j0 + ty;
-  const double di = (double)i, dj = (double)jb;
+  double di = (double)i, dj = (double)jb;
+  asm volatile("" : "+v"(di), "+v"(dj));  // converted once, not per angle
   const int bz = blockIdx.z / S, sl = blockIdx.z - bz * S;
   const size_t nn = (size_t)n * n;
   sino += (size_t)bz * N * M;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256) void k_radon_adj(
   float2 pf[kBpPrefetch];
   if (nchunks > 0) {
     bp_chunk_meta(ang, a_begin, min(kBpChunk, a_end - a_begin), i0, j0, kmin_s[0], row_s[0],
-                  tb_s[0]);
+                  geo_s[0]);
     __syncthreads();
     bp_stage_load(pf, sino, M, min(kBpChunk, a_end - a_begin), kmin_s[0], row_s[0]);
   }
@@ -181,16 +191,16 @@ __global__ __launch_bounds__(256) void k_radon_adj(
     const int ncn = min(kBpChunk, a_end - c1n);
     if (it + 1 < nchunks)
       bp_chunk_meta(ang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3],
-                    tb_s[(it + 1) % 3]);
+                    geo_s[(it + 1) % 3]);
     __syncthreads();
     if (it + 1 < nchunks)
       bp_stage_load(pf, sino, M, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
     for (int c = 0; c < nc; ++c) {
-      const BpAngle A = ang[c0 + c];
+      const ChainGeo G = geo_s[slot][c];
       // first pixel: 2^52 + t 2^32 with t relative to the staged segment (exact)
-      const double x = fma(dj, A.b32, fma(di, A.a32, tb_s[slot][c]));
+      const double x = fma(dj, G.b32, fma(di, G.a32, G.tb));
       uint64_t tf = (uint64_t)__double_as_longlong(x);
-      const uint64_t step = (uint64_t)A.b8_fix;  // 8 b 2^32, exact
+      const uint64_t step = (uint64_t)G.b8;  // 8 b 2^32, exact
       const float2 *seg_c = vd + c * seg;
       // the high word is kMagicHi + the local bin index, in [0, seg - 2] by construction
       uint32_t hh[kBpPix];
@@ -305,10 +315,12 @@ struct PairStage {
   // 64 entries, so the two angles' reads stay single ds_read_b64 instructions
   static constexpr int kSlot = kPairs * 2 * kStride + 8;
 
-  // Per pair c and chain g: segment start, 2^52 + (t0 - kmin) 2^32 and the
-  // sinogram row of slot g (entry 2c + g of the pair table).
+  // Per pair c and chain g: segment start, the sinogram row of slot g (entry
+  // 2c + g of the pair table) and, for the coordinate chain, 2^52 + (t0 -
+  // kmin) 2^32, a 2^32, b 2^32 and 8 b 2^32 -- in LDS, so that the pair loop
+  // reads them with in-order LDS loads instead of scalar loads.
   __device__ static void meta(const BpAngle *__restrict__ pang, int c0, int nc, int i0, int j0,
-                              int *kmin_s, int *row_s, double *tb_s) {
+                              int *kmin_s, int *row_s, ChainGeo *geo_s) {
     const int t = threadIdx.x;
     if (t < 2 * nc) {
       const BpAngle A = pang[2 * c0 + t];
@@ -318,7 +330,8 @@ struct PairStage {
       const int kmin = (int)floor(tmin);
       kmin_s[t] = kmin;
       row_s[t] = A.l;
-      tb_s[t] = fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0);
+      geo_s[t] = ChainGeo{fma(A.t0 - (double)kmin, 4294967296.0, 4503599627370496.0), A.a32,
+                          A.b32, A.b8_fix};
     }
   }
 
@@ -377,7 +390,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
   __shared__ float2 vq_all[2 * 2 * kSlot];  // 2 buffers x 2 slots x pairs x 2 chains
   __shared__ int row_s[3][2 * kPairs];
   __shared__ int kmin_s[3][2 * kPairs];
-  __shared__ double tb_s[3][2 * kPairs];
+  __shared__ ChainGeo geo_s[3][2 * kPairs];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
   const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBppTileJ;
@@ -404,7 +417,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
   float2 pf[kBpPrefetch];
   if (nchunks > 0) {
     PS::meta(pang, c_begin, min(kPairs, c_end - c_begin), i0, j0, kmin_s[0], row_s[0],
-             tb_s[0]);
+             geo_s[0]);
     __syncthreads();
     PS::load(pf, sino, M, min(kPairs, c_end - c_begin), kmin_s[0], row_s[0]);
   }
@@ -418,16 +431,15 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
     const int ncn = min(kPairs, c_end - c1n);
     if (it + 1 < nchunks)
       PS::meta(pang, c1n, ncn, i0, j0, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3],
-               tb_s[(it + 1) % 3]);
+               geo_s[(it + 1) % 3]);
     __syncthreads();
     if (it + 1 < nchunks)
       PS::load(pf, sino, M, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
     for (int c = 0; c < nc; ++c) {
-      const BpAngle A0 = pang[2 * (c0 + c)];
-      const BpAngle A1 = pang[2 * (c0 + c) + 1];
-      const double x0 = fma(dj, A0.b32, fma(di, A0.a32, tb_s[slot][2 * c]));
-      const double x1 = fma(dj, A1.b32, fma(di, A1.a32, tb_s[slot][2 * c + 1]));
-      const uint64_t step = (uint64_t)A0.b8_fix;  // b is the same for both chains
+      const ChainGeo G0 = geo_s[slot][2 * c], G1 = geo_s[slot][2 * c + 1];
+      const double x0 = fma(dj, G0.b32, fma(di, G0.a32, G0.tb));
+      const double x1 = fma(dj, G1.b32, fma(di, G1.a32, G1.tb));
+      const uint64_t step = (uint64_t)G0.b8;  // b is the same for both chains
       // one chain at a time: v_l and v_m go to (L, R) on chain 0, (R, L) on chain 1
       auto chain = [&](double x, const float2 *sg, float *va, float *da, float *vb, float *db) {
         // the high word less the exponent field: the local bin index itself
