@@ -1207,7 +1207,7 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   for (int s = 0; s < SL; ++s) P[s] = Q[s] = S[s] = 0.f;
 
   const int2 *reg = regions + grp.region + blk * n_chunks;
-  constexpr int RB = 8;  // rows whose LDS reads are issued together
+  constexpr int RB = 16;  // rows whose LDS reads are issued together
   float pf[SL][St::kPer];
   int2 rg_next = make_int2(0, 4);
   if (ch_first <= ch_last) {
