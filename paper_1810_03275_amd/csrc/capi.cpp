@@ -998,7 +998,15 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
                                sv->target + (size_t)b * NM, st));
   sv->lam_t = probs[0].lambda / (sv->beta * sv->beta);
   CT_TRY(solver_zero_state(sv, st));
-  if (sv->tune) CT_TRY(solver_tune(sv, st));
+  {
+    // a fixed slice count instead of the tuning (a test hook: 1 ... kMaxSlices)
+    const char *fs = std::getenv("CTPD_FORCE_SLICES");
+    const int forced = fs ? std::atoi(fs) : 0;
+    if (forced >= 1 && forced <= kMaxSlices)
+      CT_TRY(solver_set_slices(sv, forced));
+    else if (sv->tune)
+      CT_TRY(solver_tune(sv, st));
+  }
   CT_TRY_HIP(hipStreamSynchronize(st));
   return CT_OK;
 }

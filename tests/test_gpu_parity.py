@@ -209,6 +209,36 @@ def test_pd_step_parity(size):
     assert rel(gu2, st2.u) <= 2e-5
 
 
+@pytest.mark.parametrize("slices,pairs", [(1, "1"), (3, "1"), (16, "1"), (16, "0"), (5, "0"), (12, "1")])
+def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
+    """Two PDRQS1 steps with a fixed number of angle slices (their sum and
+    epilogue formed in the FFT row pass, or by the combine pass for a count it
+    does not take) and either backprojector, against the oracle."""
+    n, N, M = 64, 90, 96
+    print("pd step slices", slices, "pairs", pairs, flush=True)
+    monkeypatch.setenv("CTPD_FORCE_SLICES", str(slices))
+    monkeypatch.setenv("CTPD_BP_PAIRS", pairs)
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    lay = sv.layout()
+    assert lay["bp_slices"] == slices
+    assert lay["bp_angles_per_position"] == (2 if pairs == "1" else 1)
+    rng = np.random.default_rng(12)
+    u = f32(rng.uniform(0, 1, (n, n)))
+    vb1 = f32(0.01 * rng.standard_normal((N, M)))
+    vb2 = f32(s.lam_t / s.params.tau * rng.standard_normal((2, n, n)))
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(2)
+    gu, g1, g2 = (host(t) for t in sv.export())
+    st = pdrq.step(s, pdrq.step(s, pdrq.state_from(s, u, vb1, vb2)))
+    assert rel(gu, st.u) <= 2e-5
+    assert rel(g1, st.vb1) <= 2e-5
+    assert rel(g2, st.vb2) <= 2e-5
+
+
 def test_end_to_end_c1():
     """C1 (64^2, 90 x 96, alpha = 0.01, 200 iterations, no metal): the final
     image matches the oracle to 1e-4; the gap records agree."""
