@@ -435,6 +435,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
     __syncthreads();
     if (it + 1 < nchunks)
       PS::load(pf, sino, M, ncn, kmin_s[(it + 1) % 3], row_s[(it + 1) % 3]);
+#pragma unroll 2
     for (int c = 0; c < nc; ++c) {
       const ChainGeo G0 = geo_s[slot][2 * c], G1 = geo_s[slot][2 * c + 1];
       const double x0 = fma(dj, G0.b32, fma(di, G0.a32, G0.tb));
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
         for (int p = 0; p < kBppPix; ++p) {
           if (p > 0) {
             f += step;
-            asm volatile("" : "+v"(f));
+            asm("" : "+v"(f));
           }
           hh[p] = (uint32_t)(f >> 32);
           ll[p] = (uint32_t)f;
