@@ -681,7 +681,9 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   };
   Cand cands[10];
   int nc = 0;
-  for (int pr = (p->n_bpp > 0 ? 1 : 0); pr >= 0; --pr) {
+  // mirror pairs are tried for one problem only: a batch fills the device
+  // with the one-angle kernel's workgroups, where pairs measured slower
+  for (int pr = (p->n_bpp > 0 && sv->nb == 1 ? 1 : 0); pr >= 0; --pr) {
     // staged chunks of the backprojection's angles (mirror pairs when paired)
     const int items = pr ? p->n_bpp / kBpPairChunk : N / kBpChunk;
     for (int S : {1, 2, 4, 8, kMaxSlices})
@@ -877,6 +879,10 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   const size_t nn = (size_t)n * n, NM = (size_t)N * M;
   const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
+  // the set-up's backprojections: mirror pairs for one problem (the grid is
+  // small), one angle at a time for a batch; the tuning below decides for
+  // the iterations
+  p->bp_use_pairs = nb == 1;
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_ADMM) {
