@@ -879,10 +879,11 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   const size_t nn = (size_t)n * n, NM = (size_t)N * M;
   const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
-  // the set-up's backprojections: mirror pairs for one problem (the grid is
-  // small), one angle at a time for a batch; the tuning below decides for
-  // the iterations
-  p->bp_use_pairs = nb == 1;
+  // the set-up's backprojections use the plan's default (mirror pairs when
+  // it has them), whatever an earlier solver's tuning chose, so that a solver
+  // without tuning runs the same kernels for one problem as for a batch; the
+  // tuning below decides for the iterations
+  p->bp_use_pairs = true;
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_ADMM) {
