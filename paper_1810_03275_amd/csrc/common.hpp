@@ -96,7 +96,9 @@ constexpr int kBpPix = 8;
 constexpr int kBpRowStep = 8;
 constexpr int kBpChunk = 16;    // angles staged per chunk
 constexpr int kBpPrefetch = 8;  // staged pairs per thread: kBpChunk * seg <= 2048
-constexpr int kBpPairChunk = kBpChunk / 4;  // mirror pairs per chunk: 2 segments x 2 angles each
+// mirror pairs per staged chunk when a segment needs two rounds of 64 bins
+// (8 when it fits one); the slice heuristics count chunks of this size
+constexpr int kBpPairChunk = kBpChunk / 4;
 constexpr int kBppPix = 4;                  // pixels per thread of the mirror-pair kernel
 constexpr int kBppTileJ = kBpRowStep * kBppPix;  // its tiles: kBpTileI x kBppTileJ
 

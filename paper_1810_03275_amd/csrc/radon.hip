@@ -39,8 +39,9 @@ __device__ inline int own_offset(int off) {
 // R_h^*: pixel-driven gather.
 //
 // One workgroup per kBpTileI x kBpTileJ pixel tile and per angle slice (the
-// angles are split over gridDim.z slices whose partial images are summed by
-// k_bp_combine when there is more than one).  Thread (tx, ty) owns the
+// angles are split over gridDim.z slices whose partial images are summed,
+// with the epilogue, by the preconditioner's FFT row pass or by k_bp_combine
+// when there is more than one).  Thread (tx, ty) owns the
 // kBpPix pixels (i0 + tx, j0 + ty + 8 p).  For every chunk of kBpChunk angles
 // the detector segment the tile projects onto is staged in LDS as pairs
 // (v[k], v[k+1] - v[k]).  Per angle a thread evaluates its first pixel's
