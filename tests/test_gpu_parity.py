@@ -239,6 +239,28 @@ def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
     assert rel(g2, st.vb2) <= 2e-5
 
 
+@pytest.mark.parametrize("hook", ["CTPD_NO_TV_FUSE", "CTPD_NO_DEFER"])
+def test_fusions_are_bitwise_neutral(hook, monkeypatch):
+    """The gradient-side update run inside R_h's launch, and the slice sum
+    formed in the FFT row pass, do the same arithmetic in the same order as
+    the separate kernels: the states after a few iterations are bitwise equal."""
+    n, N, M = 64, 90, 96
+    print("fusion neutral", hook, flush=True)
+    monkeypatch.setenv("CTPD_FORCE_SLICES", "4")
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M)
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv(hook, flag)
+        sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+        sv.step(6)
+        out.append([host(t) for t in sv.export()])
+    for a, b in zip(*out):
+        assert np.all(np.isfinite(a)) and np.array_equal(a, b)
+
+
 def test_end_to_end_c1():
     """C1 (64^2, 90 x 96, alpha = 0.01, 200 iterations, no metal): the final
     image matches the oracle to 1e-4; the gap records agree."""
