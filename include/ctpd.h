@@ -287,8 +287,9 @@ int ct_solver_info(const ct_solver *sv, double out[4]);
  * out[2] = angles that share one walk in R_h (1, 2 or 4),
  * out[3] = forward-projector groups,
  * out[4] = angles that share one bin coordinate in R_h^* (2: mirror pairs
- * theta, pi - theta; 1: one angle at a time; chosen by the solver's tuning). */
-int ct_solver_layout(const ct_solver *sv, int32_t out[5]);
+ * theta, pi - theta; 1: one angle at a time; chosen by the solver's tuning),
+ * out[5] = pixels per thread of the mirror-pair kernel (4 or 8; 0 without). */
+int ct_solver_layout(const ct_solver *sv, int32_t out[6]);
 
 /* Data-term variants of §3.5 for PDRQS1 (and its Richardson form), set before
  * the first iteration:

@@ -349,10 +349,10 @@ class Solver:
         return () if self.nb == 1 else (self.nb,)
 
     def layout(self) -> dict:
-        o = (ctypes.c_int32 * 5)()
+        o = (ctypes.c_int32 * 6)()
         _check(_L.ct_solver_layout(self._h, o), "ct_solver_layout")
         return {"problems": o[0], "bp_slices": o[1], "angles_per_walk": o[2], "fwd_groups": o[3],
-                "bp_angles_per_position": o[4]}
+                "bp_angles_per_position": o[4], "bp_pair_pixels": o[5]}
 
     def export(self):
         n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins

@@ -676,23 +676,37 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   ct_plan *p = sv->plan;
   const int N = sv->N;
   struct Cand {
-    bool pairs;
+    int pix;  // mirror pairs with 4 or 8 pixels per thread; 0: one angle at a time
     int S;
   };
-  Cand cands[10];
+  Cand cands[16];
   int nc = 0;
-  // mirror pairs are tried for one problem only: a batch fills the device
-  // with the one-angle kernel's workgroups, where pairs measured slower
-  for (int pr = (p->n_bpp > 0 && sv->nb == 1 ? 1 : 0); pr >= 0; --pr) {
+  // mirror pairs on small tiles are tried for one problem only (a batch
+  // fills the device with larger tiles' workgroups)
+  for (int pix : {4, 8, 0}) {
+    if (pix != 0 && p->n_bpp == 0) continue;
+    if (pix == 4 && sv->nb != 1) continue;
     // staged chunks of the backprojection's angles (mirror pairs when paired)
-    const int items = pr ? p->n_bpp / kBpPairChunk : N / kBpChunk;
+    const int items = pix ? p->n_bpp / kBpPairChunk : N / kBpChunk;
     for (int S : {1, 2, 4, 8, kMaxSlices})
-      if (S == 1 || items / S >= 2) cands[nc++] = Cand{pr == 1, S};
+      if (S == 1 || items / S >= 2) cands[nc++] = Cand{pix, S};
   }
+  auto choose = [&](const Cand &c) {
+    p->bp_use_pairs = c.pix != 0;
+    if (c.pix != 0) p->bp_pair_pix = c.pix;
+  };
   if (nc == 1) {
-    p->bp_use_pairs = cands[0].pairs;
+    choose(cands[0]);
     return solver_set_slices(sv, 1);
   }
+  const bool with_fft = sv->defer_combine &&
+                        (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_PDRQS2 ||
+                         sv->method == CT_METHOD_PDRQS3);
+  for (const auto &t : p->tune_cache)
+    if (t.nb == sv->nb && t.fft == (int)with_fft) {
+      choose(Cand{t.pix, t.S});
+      return solver_set_slices(sv, t.S);
+    }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CT_TRY_HIP(hipEventCreate(&e0));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g0(
@@ -700,13 +714,10 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   CT_TRY_HIP(hipEventCreate(&e1));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(
       e1, hipEventDestroy);
-  const bool with_fft = sv->defer_combine &&
-                        (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_PDRQS2 ||
-                         sv->method == CT_METHOD_PDRQS3);
   float best = 0.f;
   Cand bestc = cands[0];
   for (int c = 0; c < nc; ++c) {
-    p->bp_use_pairs = cands[c].pairs;
+    choose(cands[c]);
     CT_TRY(solver_set_slices(sv, cands[c].S));
     // what the iteration runs: with the FFT pair next, R_h^* with its slice
     // sum deferred into the row pass and the pair itself; else R_h^* and the
@@ -733,7 +744,8 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
       bestc = cands[c];
     }
   }
-  p->bp_use_pairs = bestc.pairs;
+  choose(bestc);
+  p->tune_cache.push_back(ct_plan::TuneEntry{sv->nb, (int)with_fft, bestc.pix, bestc.S});
   return solver_set_slices(sv, bestc.S);
 }
 
@@ -884,6 +896,7 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   // without tuning runs the same kernels for one problem as for a batch; the
   // tuning below decides for the iterations
   p->bp_use_pairs = true;
+  p->bp_pair_pix = p->bp_pair_pix0;
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_ADMM) {
@@ -1246,7 +1259,7 @@ int ct_solver_info(const ct_solver *sv, double out[4]) {
   return CT_OK;
 }
 
-int ct_solver_layout(const ct_solver *sv, int32_t out[5]) {
+int ct_solver_layout(const ct_solver *sv, int32_t out[6]) {
   clear_error();
   if (!sv || !out) {
     set_error("ct_solver_layout: null argument");
@@ -1256,7 +1269,9 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[5]) {
   out[1] = sv->bp_S;
   out[2] = sv->plan->slots;
   out[3] = sv->plan->n_groups;
-  out[4] = (sv->plan->n_bpp > 0 && sv->plan->bp_use_pairs) ? 2 : 1;
+  const bool pairs = sv->plan->n_bpp > 0 && sv->plan->bp_use_pairs;
+  out[4] = pairs ? 2 : 1;
+  out[5] = pairs ? sv->plan->bp_pair_pix : 0;
   return CT_OK;
 }
 

@@ -123,6 +123,14 @@ struct ct_plan {
   ctpd::BpAngle *d_bpp = nullptr;
   int n_bpp = 0;          // pairs (0: the one-angle backprojector)
   bool bp_use_pairs = true;  // with pairs: use them (a solver's tuning may say no)
+  int bp_pair_pix = 4;       // pixels per thread of the pair kernel (4 or 8; tuned)
+  int bp_pair_pix0 = 4;      // its default, restored at every solver's set-up
+  // set-up tunings done on this plan: (batch size, FFT pair next) -> choice,
+  // so that solvers created again for the same batch size skip the timing
+  struct TuneEntry {
+    int nb, fft, pix, S;
+  };
+  std::vector<TuneEntry> tune_cache;
   int seg_pair = 0;       // staged bins per angle per tile of the pair kernel
   int seg = 0;  // staged bins per angle per tile
   int bp_slices = 1;           // angle slices of the backprojection grid

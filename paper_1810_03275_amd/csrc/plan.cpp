@@ -419,6 +419,10 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
   const int n = g->n, N = g->n_angles;
   p->seg = hp.seg;
   p->seg_pair = hp.seg_pair;
+  {
+    const char *e = std::getenv("CTPD_BP_PIX");  // a test hook: 8 pixels per thread
+    p->bp_pair_pix0 = p->bp_pair_pix = (e && std::atoi(e) == 8) ? 8 : 4;
+  }
   p->bp_slices = hp.bp_slices;
   p->check_first = hp.check_first;
   p->paired = hp.paired;

@@ -299,8 +299,9 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
 // slower).  An angle without a partner runs with its mirror image's geometry
 // and a zero sinogram row.  On the centre column of an odd n (i = n - 1 - i)
 // the L terms already hold both angles, and the R terms are dropped.  Tiles
-// are kBpTileI x kBppTileJ (four pixels per thread): more workgroups than the
-// one-angle kernel's tiles, at a register count that keeps them resident.
+// are kBpTileI x 8 PIX: with PIX = 4, more workgroups than the one-angle
+// kernel's tiles at a register count that keeps them resident; with PIX = 8
+// the one-angle kernel's tiles (less staging per pixel, for large grids).
 
 // Staging of the mirror-pair kernel.  R rounds of 64 bins cover a segment
 // (R = 1: seg <= 64, R = 2: seg <= 128); a chunk holds kBpPrefetch / R pairs,
@@ -308,8 +309,9 @@ __global__ void k_bp_combine(const float *__restrict__ part, int S, int n,
 // LDS float2 entry a kSlot + (2c + g) 64 R + k holds (v[k], v[k+1] - v[k]) of
 // angle slot a (0: l, 1: m) of pair c on chain g's segment: the two angles of
 // a bin are read with one address and a constant offset.
-template <int R>
+template <int R, int PIX>
 struct PairStage {
+  static constexpr int kTileJ = kBpRowStep * PIX;  // tile rows (PIX pixels per thread)
   static constexpr int kPairs = kBpPrefetch / R;  // pairs per chunk
   static constexpr int kStride = 64 * R;          // entries per (pair, chain, slot)
   // slot 1's offset: neither within a ds_read2_b64's reach nor a multiple of
@@ -326,7 +328,7 @@ struct PairStage {
     if (t < 2 * nc) {
       const BpAngle A = pang[2 * c0 + t];
       const double ic = (A.a >= 0.0) ? (double)i0 : (double)(i0 + kBpTileI - 1);
-      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kBppTileJ - 1);
+      const double jc = (A.b >= 0.0) ? (double)j0 : (double)(j0 + kTileJ - 1);
       const double tmin = fma(jc, A.b, fma(ic, A.a, A.t0));
       const int kmin = (int)floor(tmin);
       kmin_s[t] = kmin;
@@ -380,13 +382,14 @@ struct PairStage {
 };
 
 // gridDim.z = (problems of a batch) x S slices of the pairs: problem b = z / S.
-template <int R>
+// PIX pixels per thread: tiles of kBpTileI x 8 PIX.
+template <int R, int PIX>
 __global__ __launch_bounds__(256) void k_radon_adj_pair(
     const float *__restrict__ sino, int n, int N, int M, const BpAngle *__restrict__ pang,
     int seg, int slice_len, int S, const float *__restrict__ pfield, float c1, float c2,
     float inv_h, const float *__restrict__ base, const float *__restrict__ base2,
     float *__restrict__ out, float *__restrict__ out2, int n_pairs) {
-  using PS = PairStage<R>;
+  using PS = PairStage<R, PIX>;
   constexpr int kPairs = PS::kPairs, kStride = PS::kStride, kSlot = PS::kSlot;
   __shared__ float2 vq_all[2 * 2 * kSlot];  // 2 buffers x 2 slots x pairs x 2 chains
   __shared__ int row_s[3][2 * kPairs];
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
   __shared__ ChainGeo geo_s[3][2 * kPairs];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
-  const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * kBppTileJ;
+  const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * PS::kTileJ;
   const int i = i0 + tx;  // left-half column; its mirror is n - 1 - i
   const int jb = j0 + ty;
   double di = (double)i, dj = (double)jb;
@@ -411,9 +414,9 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
   const int c_end = min(n_pairs, c_begin + slice_len);
   const int nchunks =
       c_end > c_begin ? (c_end - c_begin + kPairs - 1) / kPairs : 0;
-  float lv[kBppPix], ld[kBppPix], rv[kBppPix], rd[kBppPix];
+  float lv[PIX], ld[PIX], rv[PIX], rd[PIX];
 #pragma unroll
-  for (int p = 0; p < kBppPix; ++p) lv[p] = ld[p] = rv[p] = rd[p] = 0.f;
+  for (int p = 0; p < PIX; ++p) lv[p] = ld[p] = rv[p] = rd[p] = 0.f;
 
   float2 pf[kBpPrefetch];
   if (nchunks > 0) {
@@ -446,9 +449,9 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
       auto chain = [&](double x, const float2 *sg, float *va, float *da, float *vb, float *db) {
         // the high word less the exponent field: the local bin index itself
         uint64_t f = (uint64_t)__double_as_longlong(x) - ((uint64_t)kMagicHi << 32);
-        uint32_t hh[kBppPix], ll[kBppPix];
+        uint32_t hh[PIX], ll[PIX];
 #pragma unroll
-        for (int p = 0; p < kBppPix; ++p) {
+        for (int p = 0; p < PIX; ++p) {
           if (p > 0) {
             f += step;
             asm("" : "+v"(f));
@@ -456,14 +459,14 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
           hh[p] = (uint32_t)(f >> 32);
           ll[p] = (uint32_t)f;
         }
-        float2 qa[kBppPix], qb[kBppPix];
+        float2 qa[PIX], qb[PIX];
 #pragma unroll
-        for (int p = 0; p < kBppPix; ++p) {
+        for (int p = 0; p < PIX; ++p) {
           qa[p] = sg[hh[p]];          // angle l
           qb[p] = sg[hh[p] + kSlot];  // angle m
         }
 #pragma unroll
-        for (int p = 0; p < kBppPix; ++p) {
+        for (int p = 0; p < PIX; ++p) {
           const float al = (float)ll[p];
           va[p] += qa[p].x;
           da[p] = fmaf(al, qa[p].y, da[p]);
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
     if (out2 != nullptr) out2[o] = 2.f * res - base[o];
   };
 #pragma unroll
-  for (int p = 0; p < kBppPix; ++p) {
+  for (int p = 0; p < PIX; ++p) {
     const int j = jb + kBpRowStep * p;
     if (j >= n) continue;
     emit(i, j, fmaf(ld[p], inv32, lv[p]));
@@ -524,17 +527,30 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   if (p->n_bpp > 0 && p->bp_use_pairs) {
     const int nh = (n + 1) / 2;
     const int pair_len = (p->n_bpp + S - 1) / S;
-    dim3 grid((nh + kBpTileI - 1) / kBpTileI, (n + kBppTileJ - 1) / kBppTileJ, S * nb);
-    if (p->seg_pair <= 64)
-      hipLaunchKernelGGL(k_radon_adj_pair<1>, grid, dim3(256), 0, s, v, n, p->g.n_angles,
-                         p->g.n_bins, p->d_bpp, p->seg_pair, pair_len, S, pfield, c1, c2,
+    // 4 pixels per thread on 32 x 32 tiles, or 8 on 32 x 64 (the one-angle
+    // kernel's tile, whose segment length it shares)
+    const int pix = p->bp_pair_pix == 8 ? 8 : 4;
+    const int seg = pix == 8 ? p->seg : p->seg_pair;
+    dim3 grid((nh + kBpTileI - 1) / kBpTileI, (n + kBpRowStep * pix - 1) / (kBpRowStep * pix),
+              S * nb);
+    auto go = [&](auto r_c, auto pix_c) {
+      constexpr int RR = decltype(r_c)::value, PP = decltype(pix_c)::value;
+      hipLaunchKernelGGL((k_radon_adj_pair<RR, PP>), grid, dim3(256), 0, s, v, n, p->g.n_angles,
+                         p->g.n_bins, p->d_bpp, seg, pair_len, S, pfield, c1, c2,
                          (float)(1.0 / p->g.h), base, base2, dst, S == 1 ? out2 : nullptr,
                          p->n_bpp);
-    else
-      hipLaunchKernelGGL(k_radon_adj_pair<2>, grid, dim3(256), 0, s, v, n, p->g.n_angles,
-                         p->g.n_bins, p->d_bpp, p->seg_pair, pair_len, S, pfield, c1, c2,
-                         (float)(1.0 / p->g.h), base, base2, dst, S == 1 ? out2 : nullptr,
-                         p->n_bpp);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using P4 = std::integral_constant<int, 4>;
+    using P8 = std::integral_constant<int, 8>;
+    if (pix == 4) {
+      if (seg <= 64) go(I1{}, P4{});
+      else go(I2{}, P4{});
+    } else {
+      if (seg <= 64) go(I1{}, P8{});
+      else go(I2{}, P8{});
+    }
   } else {
     dim3 grid((n + kBpTileI - 1) / kBpTileI, (n + kBpTileJ - 1) / kBpTileJ, S * nb);
     const size_t lds = 2 * sizeof(float2) * kBpChunk * p->seg;

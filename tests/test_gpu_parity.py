@@ -78,12 +78,12 @@ def test_radon_pair_parity(geo):
     assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(fx) * np.linalg.norm(y)
 
 
-@pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4)],
+@pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4), (100, 60, 150)],
                          ids=lambda g: "x".join(map(str, g)))
 def test_backprojection_with_and_without_mirror_pairs(geo, monkeypatch):
     """The mirror-pair backprojector (theta and pi - theta from one bin
-    coordinate) and the one-angle backprojector agree with the oracle and with
-    each other to FP32 summation accuracy."""
+    coordinate; 4 or 8 pixels per thread) and the one-angle backprojector
+    agree with the oracle and with each other to FP32 summation accuracy."""
     n, N, M = geo
     print("backprojection pairs", geo, flush=True)
     g = geometry.Geometry(n, N, M)
@@ -91,12 +91,14 @@ def test_backprojection_with_and_without_mirror_pairs(geo, monkeypatch):
     y = f32(rng.uniform(-1, 1, (N, M)))
     ref = radon.radon_adj(g, y)
     out = []
-    for flag in ("1", "0"):
+    for flag, pix in (("1", "4"), ("1", "8"), ("0", "4")):
         monkeypatch.setenv("CTPD_BP_PAIRS", flag)
+        monkeypatch.setenv("CTPD_BP_PIX", pix)
         plan = ct.Plan(n, N, M)
         out.append(host(plan.radon_adj(gpu(y))))
         assert rel(out[-1], ref) <= 1e-5
-    assert rel(out[0], out[1]) <= 1e-6
+    assert rel(out[0], out[2]) <= 1e-6
+    assert rel(out[1], out[2]) <= 1e-6
 
 
 def test_radon_deterministic_and_arbitrary_angles():
@@ -209,7 +211,8 @@ def test_pd_step_parity(size):
     assert rel(gu2, st2.u) <= 2e-5
 
 
-@pytest.mark.parametrize("slices,pairs", [(1, "1"), (3, "1"), (16, "1"), (16, "0"), (5, "0"), (12, "1")])
+@pytest.mark.parametrize("slices,pairs", [(1, "1"), (3, "1"), (16, "1"), (16, "0"), (5, "0"), (12, "1"),
+                                          (4, "8")])
 def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
     """Two PDRQS1 steps with a fixed number of angle slices (their sum and
     epilogue formed in the FFT row pass, or by the combine pass for a count it
@@ -217,7 +220,8 @@ def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
     n, N, M = 64, 90, 96
     print("pd step slices", slices, "pairs", pairs, flush=True)
     monkeypatch.setenv("CTPD_FORCE_SLICES", str(slices))
-    monkeypatch.setenv("CTPD_BP_PAIRS", pairs)
+    monkeypatch.setenv("CTPD_BP_PAIRS", "0" if pairs == "0" else "1")
+    monkeypatch.setenv("CTPD_BP_PIX", "8" if pairs == "8" else "4")
     w, g, u0, mask, bound = _small_metal_problem(n, N, M)
     s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
                    f32(w.start_norm), f32(w.start_precond))
@@ -225,7 +229,8 @@ def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
     sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
     lay = sv.layout()
     assert lay["bp_slices"] == slices
-    assert lay["bp_angles_per_position"] == (2 if pairs == "1" else 1)
+    assert lay["bp_angles_per_position"] == (1 if pairs == "0" else 2)
+    assert lay["bp_pair_pixels"] == {"0": 0, "1": 4, "8": 8}[pairs]
     rng = np.random.default_rng(12)
     u = f32(rng.uniform(0, 1, (n, n)))
     vb1 = f32(0.01 * rng.standard_normal((N, M)))
