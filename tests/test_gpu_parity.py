@@ -244,6 +244,25 @@ def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
     assert rel(g2, st.vb2) <= 2e-5
 
 
+def test_tuning_is_cached_per_plan_and_batch_size():
+    """A second solver of the same batch size on a plan reuses the first one's
+    tuned backprojector and slice count; both match the oracle's step."""
+    n, N, M = 64, 90, 96
+    print("tuning cache", flush=True)
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M)
+    lays = []
+    for _ in range(2):
+        sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+        lays.append(sv.layout())
+        sv.step(1)
+        st = pdrq.step(s, pdrq.zero_state(s))
+        assert rel(host(sv.export()[0]), st.u) <= 1e-5
+    assert lays[0] == lays[1]
+
+
 @pytest.mark.parametrize("hook", ["CTPD_NO_TV_FUSE", "CTPD_NO_DEFER"])
 def test_fusions_are_bitwise_neutral(hook, monkeypatch):
     """The gradient-side update run inside R_h's launch, and the slice sum
