@@ -81,6 +81,23 @@ typedef struct ct_plan ct_plan;
  * Errors: CT_E_INVALID, CT_E_UNSUPPORTED, CT_E_DEVICE. */
 int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
 
+/* Kernel choices fixed at plan creation (ct_plan_create uses all defaults).
+ * bp_kernel: the backprojector of standalone ct_radon_adj calls and of
+ *   solvers whose tuning is off: CT_BP_AUTO (mirror pairs, 4 pixels per
+ *   thread, when at least half of the angles pair as theta, pi - theta, else
+ *   one angle at a time), CT_BP_ONE_ANGLE, CT_BP_PAIRS4 or CT_BP_PAIRS8
+ *   (CT_E_UNSUPPORTED when the angles do not pair).
+ * fwd_angles_per_walk: angles that share one walk of R_h: 0 (2 when at least
+ *   half of the angles pair up, else 1), 1 or 2. */
+enum { CT_BP_AUTO = -1, CT_BP_ONE_ANGLE = 0, CT_BP_PAIRS4 = 4, CT_BP_PAIRS8 = 8 };
+typedef struct ct_plan_opts {
+  int32_t bp_kernel;
+  int32_t fwd_angles_per_walk;
+} ct_plan_opts;
+/* opts NULL: the defaults (CT_BP_AUTO, 0). */
+int ct_plan_create_ex(const ct_geom *g, const double *angles, const ct_plan_opts *opts,
+                      ct_plan **out);
+
 /* Host-only self-check of the plan that ct_plan_create would build (no device
  * call): replays the forward projector's fixed-point walk for every strip and
  * staged row and verifies that each LDS read lies in the staged window and
@@ -88,6 +105,9 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
  * receives the number of (strip, row) steps checked.  CT_E_INVALID with a
  * message naming the strip and row if a check fails. */
 int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps);
+/* The same for the plan that ct_plan_create_ex(g, angles, opts) would build. */
+int ct_plan_check_ex(const ct_geom *g, const double *angles, const ct_plan_opts *opts,
+                     int64_t *steps);
 int ct_plan_destroy(ct_plan *p);
 
 /* sino = R_h img (§3.1: R_h is the transpose of R_h^*; each pixel's value is
@@ -228,9 +248,33 @@ typedef struct ct_params {
   uint32_t flags;        /* CT_FLAG_* */
   const float *start_norm;    /* device [n][n] start of the ||R_h|| iteration or NULL */
   const float *start_precond; /* device [n][n] start of the c iteration or NULL */
+  /* Launch choices of the iteration.  0 in each field: chosen by the
+   * solver's set-up tuning (or the plan's defaults with CT_OPT_NO_TUNE). */
+  int32_t bp_slices;     /* angle slices of R_h^* (1..16), 0: tuned */
+  int32_t bp_kernel;     /* CT_BP_* backprojector of the iteration; CT_BP_AUTO: tuned */
+  int32_t tv_blocks;     /* workgroups of the gradient-side update inside R_h's launch
+                            (1..4096), 0: tuned */
+  uint32_t options;      /* CT_OPT_* */
+  const char *tune_cache; /* path of a JSON file of tuning results, or NULL.  A choice
+                            found there (same GPU, geometry, batch size, method) is
+                            used without timing; a new one is added to the file.
+                            Reusing the file makes the launch choices, and so the
+                            FP32 summation order, the same in every process. */
 } ct_params;
 
-/* Fill *p with the defaults above (k_max = 0, gap_every = 0). */
+/* ct_params.options bits. */
+enum {
+  CT_OPT_NO_TUNE = 1u,     /* no timing at set-up: the plan's backprojector, its default
+                              slice count and 256 gradient-side workgroups (unless fixed) */
+  CT_OPT_NO_DEFER = 2u,    /* sum R_h^*'s angle slices in a pass of its own, not in the
+                              preconditioner's first FFT pass (same arithmetic) */
+  CT_OPT_SEPARATE_TV = 4u, /* run the gradient-side update as its own launch (same
+                              arithmetic) */
+  CT_OPT_NO_GRAPH = 8u     /* launch the iterations one by one, no HIP graph */
+};
+
+/* Fill *p with the defaults above (k_max = 0, gap_every = 0, bp_slices = 0,
+ * bp_kernel = CT_BP_AUTO, tv_blocks = 0, options = 0, tune_cache = NULL). */
 void ct_params_default(ct_params *p);
 
 /* Objective of (C_h) at u [n][n] (device), in the problem's units (§3.2):
@@ -271,9 +315,11 @@ int ct_solver_create(const ct_plan *p, const ct_problem *prob, const ct_params *
 /* A solver for nb >= 1 problems of the plan's geometry (probs[0..nb-1], all
  * with the same lambda), advanced together: every kernel of an iteration
  * covers the nb problems in one launch.  beta and c depend on the geometry
- * only and are estimated once.  The number of angle slices of R_h^* is tuned
- * at setup by timing the candidates on the batch (CTPD_NO_TUNE=1 keeps the
- * plan's choice).  All state arrays of the other calls then hold nb problems
+ * only and are estimated once.  The backprojector, its number of angle
+ * slices and the gradient-side update's workgroups are tuned at set-up by
+ * timing the candidates on the batch, unless fixed by the params (see
+ * ct_params.bp_slices ... options, tune_cache; ct_solver_tuning reports how
+ * the choice was made).  All state arrays of the other calls then hold nb problems
  * one after the other ([nb][n][n], [nb][N][M], [nb][2][n][n]); ct_gap writes
  * 6 doubles per problem.  Errors as ct_solver_create. */
 int ct_solver_create_batch(const ct_plan *p, const ct_problem *probs, int32_t nb,
@@ -282,6 +328,15 @@ int ct_solver_destroy(ct_solver *sv);
 
 /* out[0] = beta, out[1] = c, out[2] = lambda~, out[3] = iterations done. */
 int ct_solver_info(const ct_solver *sv, double out[4]);
+
+/* How the solver's launch choices were made: out[0] = 0 fixed by the
+ * params or CT_OPT_NO_TUNE, 1 timed at set-up, 2 taken from an earlier solver
+ * of the same plan, batch size and method class, 3 read from the tune cache
+ * file; out[1] = candidate launches timed by this solver (0 unless out[0] is
+ * 1); out[2] = workgroups of the gradient-side update inside R_h's launch
+ * (0: a separate launch); out[3] = 1 if the choice was added to the tune
+ * cache file. */
+int ct_solver_tuning(const ct_solver *sv, int32_t out[4]);
 
 /* out[0] = problems in the solver, out[1] = angle slices of R_h^*,
  * out[2] = angles that share one walk in R_h (1, 2 or 4),

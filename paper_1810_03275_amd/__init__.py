@@ -15,6 +15,7 @@ preconditioner (§4.3.1) and the normalization of §5.1.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import math
 from typing import Optional
 
@@ -26,7 +27,7 @@ from . import _lib
 _L = _lib.load()
 
 __all__ = [
-    "CtpdError", "Plan", "Precond", "Solver", "radon_fwd", "radon_adj", "grad", "div",
+    "CtpdError", "Plan", "Precond", "Solver", "Launch", "radon_fwd", "radon_adj", "grad", "div",
     "prox_sino", "tv_project", "power_norm", "reconstruct", "pack_mask", "RadonFn",
     "RadonAdjFn", "estimate_d0", "lib",
 ]
@@ -77,8 +78,15 @@ def pack_mask(mask) -> torch.Tensor:
     return torch.from_numpy(bits.astype(np.int32).copy()).cuda()
 
 
+def _plan_opts(bp_kernel: str, fwd_angles_per_walk: int):
+    if bp_kernel not in _lib.BP_KERNELS:
+        raise ValueError(f"bp_kernel must be one of {sorted(_lib.BP_KERNELS)}")
+    return _lib.CtPlanOpts(_lib.BP_KERNELS[bp_kernel], int(fwd_angles_per_walk))
+
+
 def plan_check(n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1.0,
-               angles: Optional[np.ndarray] = None) -> int:
+               angles: Optional[np.ndarray] = None, bp_kernel: str = "auto",
+               fwd_angles_per_walk: int = 0) -> int:
     """Host-only replay of the forward projector's walk over the plan that
     Plan(...) would build; returns the number of (strip, row) steps checked and
     raises CtpdError if a staged window or a skipped row is wrong."""
@@ -90,27 +98,34 @@ def plan_check(n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1
         if a.shape != (n_angles,):
             raise ValueError("angles must have shape (n_angles,)")
         ptr = a.ctypes.data_as(ctypes.c_void_p)
-    _check(_L.ct_plan_check(ctypes.byref(g), ptr, ctypes.byref(steps)), "ct_plan_check")
+    opts = _plan_opts(bp_kernel, fwd_angles_per_walk)
+    _check(_L.ct_plan_check_ex(ctypes.byref(g), ptr, ctypes.byref(opts), ctypes.byref(steps)),
+           "ct_plan_check")
     return int(steps.value)
 
 
 class Plan:
-    """Projector plan for an n x n image, N angles, M bins (§3.1)."""
+    """Projector plan for an n x n image, N angles, M bins (§3.1).
+
+    bp_kernel: backprojector of standalone calls and untuned solvers ("auto",
+    "one_angle", "pairs4", "pairs8"); fwd_angles_per_walk: angles sharing one
+    walk of R_h (0 automatic, 1 or 2)."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1.0,
-                 angles: Optional[np.ndarray] = None):
+                 angles: Optional[np.ndarray] = None, bp_kernel: str = "auto",
+                 fwd_angles_per_walk: int = 0):
         self.n, self.n_angles, self.n_bins, self.h, self.ds = n, n_angles, n_bins, h, ds
         g = _lib.CtGeom(n, n_angles, n_bins, h, ds)
         handle = ctypes.c_void_p()
+        opts = _plan_opts(bp_kernel, fwd_angles_per_walk)
+        ptr = None
         if angles is not None:
             a = np.ascontiguousarray(angles, dtype=np.float64)
             if a.shape != (n_angles,):
                 raise ValueError("angles must have shape (n_angles,)")
-            _check(_L.ct_plan_create(ctypes.byref(g), a.ctypes.data_as(ctypes.c_void_p),
-                                     ctypes.byref(handle)), "ct_plan_create")
-        else:
-            _check(_L.ct_plan_create(ctypes.byref(g), None, ctypes.byref(handle)),
-                   "ct_plan_create")
+            ptr = a.ctypes.data_as(ctypes.c_void_p)
+        _check(_L.ct_plan_create_ex(ctypes.byref(g), ptr, ctypes.byref(opts),
+                                    ctypes.byref(handle)), "ct_plan_create")
         self._h = handle
 
     @property
@@ -258,10 +273,44 @@ def power_norm(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -
     return out.value
 
 
+@dataclasses.dataclass
+class Launch:
+    """Launch choices of a solver's iteration (ct_params fields).  None: chosen
+    by the set-up tuning.  bp_slices: angle slices of R_h^* (1..16);
+    bp_kernel: "one_angle", "pairs4" or "pairs8"; tv_blocks: workgroups of
+    the gradient-side update inside R_h's launch; tune=False: the plan's
+    defaults instead of timing; defer / fuse_tv / graph=False: the slice sum,
+    the gradient-side update or the iterations as launches of their own
+    (same arithmetic); tune_cache: path of a JSON file of tuning results."""
+    bp_slices: Optional[int] = None
+    bp_kernel: Optional[str] = None
+    tv_blocks: Optional[int] = None
+    tune: bool = True
+    defer: bool = True
+    fuse_tv: bool = True
+    graph: bool = True
+    tune_cache: Optional[str] = None
+
+    def fill(self, p) -> None:
+        p.bp_slices = int(self.bp_slices or 0)
+        if self.bp_kernel is not None and self.bp_kernel not in _lib.BP_KERNELS:
+            raise ValueError(f"bp_kernel must be one of {sorted(_lib.BP_KERNELS)}")
+        p.bp_kernel = _lib.BP_KERNELS[self.bp_kernel or "auto"]
+        p.tv_blocks = int(self.tv_blocks or 0)
+        p.options = ((0 if self.tune else _lib.CT_OPT_NO_TUNE)
+                     | (0 if self.defer else _lib.CT_OPT_NO_DEFER)
+                     | (0 if self.fuse_tv else _lib.CT_OPT_SEPARATE_TV)
+                     | (0 if self.graph else _lib.CT_OPT_NO_GRAPH))
+        p.tune_cache = self.tune_cache.encode() if self.tune_cache else None
+
+
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-            start_norm, start_precond, n, nonneg=False, method="pdrqs1", precond="invnorm"):
+            start_norm, start_precond, n, nonneg=False, method="pdrqs1", precond="invnorm",
+            launch=None):
     p = _lib.CtParams()
     _L.ct_params_default(ctypes.byref(p))
+    if launch is not None:
+        (Launch(**launch) if isinstance(launch, dict) else launch).fill(p)
     p.sigma, p.tau, p.eps = sigma, tau, eps
     p.c = c if c is not None else 0.0
     p.c_safety = c_safety
@@ -303,12 +352,12 @@ class Solver:
                  start_norm: Optional[torch.Tensor] = None,
                  start_precond: Optional[torch.Tensor] = None, bound_scalar: float = 0.0,
                  nonneg: bool = False, method: str = "pdrqs1", cg_steps: int = 1,
-                 mu: float = 1.0, precond: str = "invnorm"):
+                 mu: float = 1.0, precond: str = "invnorm", launch=None):
         self.plan = plan
         self._keep = (sino, mask_bits, bound, start_norm, start_precond)
         prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n, nonneg, method, precond)
+                      start_norm, start_precond, plan.n, nonneg, method, precond, launch)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create(plan.handle, ctypes.byref(prob), ctypes.byref(prm), _stream(),
                                    ctypes.byref(h)), "ct_solver_create")
@@ -353,6 +402,15 @@ class Solver:
         _check(_L.ct_solver_layout(self._h, o), "ct_solver_layout")
         return {"problems": o[0], "bp_slices": o[1], "angles_per_walk": o[2], "fwd_groups": o[3],
                 "bp_angles_per_position": o[4], "bp_pair_pixels": o[5]}
+
+    def tuning(self) -> dict:
+        """How the launch choices were made: source (fixed, timed, plan,
+        file), candidates timed, gradient-side workgroups in R_h's launch (0:
+        own launch), whether the tune cache file was written."""
+        o = (ctypes.c_int32 * 4)()
+        _check(_L.ct_solver_tuning(self._h, o), "ct_solver_tuning")
+        return {"source": ("fixed", "timed", "plan", "file")[o[0]], "timed": o[1],
+                "tv_blocks": o[2], "saved": bool(o[3])}
 
     def export(self):
         n, N, M = self.plan.n, self.plan.n_angles, self.plan.n_bins
@@ -414,7 +472,7 @@ class SolverBatch(Solver):
                  power_iters: int = 30, validate: bool = False,
                  start_norm: Optional[torch.Tensor] = None,
                  start_precond: Optional[torch.Tensor] = None, bound_scalars=None,
-                 nonneg: bool = False):
+                 nonneg: bool = False, launch=None):
         self.plan = plan
         nb = len(sinos)
         masks = masks if masks is not None else [None] * nb
@@ -428,7 +486,7 @@ class SolverBatch(Solver):
         for b in range(nb):
             probs[b] = _problem(plan, sinos[b], masks[b], bounds[b], lam, bsc[b])
         prm = _params(sigma, tau, eps, c, c_safety, beta, 0, 0, power_iters, validate,
-                      start_norm, start_precond, plan.n, nonneg)
+                      start_norm, start_precond, plan.n, nonneg, launch=launch)
         h = ctypes.c_void_p()
         _check(_L.ct_solver_create_batch(plan.handle, probs, nb, ctypes.byref(prm), _stream(),
                                          ctypes.byref(h)), "ct_solver_create_batch")
@@ -465,7 +523,7 @@ def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma
                         tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3,
                         c: Optional[float] = None, c_safety: float = 1.1,
                         beta: Optional[float] = None, power_iters: int = 30,
-                        validate: bool = False, nonneg: bool = False):
+                        validate: bool = False, nonneg: bool = False, launch=None):
     """PDRQS1 solves of many problems, any mix of geometries.  problems: list of
     dicts with keys plan, sino, lam and optionally mask_bits, bound,
     bound_scalar.  Problems sharing a plan and lambda run as one batch; all
@@ -488,7 +546,7 @@ def reconstruct_batched(problems, *, k_max: int = 100, gap_every: int = 0, sigma
         us.append(u)
         outs[i] = u.data_ptr()
     prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-                  None, None, problems[0]["plan"].n, nonneg)
+                  None, None, problems[0]["plan"].n, nonneg, launch=launch)
     nrec = k_max // gap_every if gap_every > 0 else 0
     rep = (ctypes.c_double * max(1, 6 * nrec * count))()
     _check(_L.ct_reconstruct_batched(count, plans, probs, ctypes.byref(prm), outs,
@@ -513,12 +571,13 @@ def reconstruct(plan: Plan, sino: torch.Tensor, lam: float, mask_bits=None, boun
                 tau: float = 1.0 / math.sqrt(8.0), eps: float = 0.3, c: Optional[float] = None,
                 c_safety: float = 1.1, beta: Optional[float] = None, power_iters: int = 30,
                 validate: bool = False, start_norm=None, start_precond=None,
-                bound_scalar: float = 0.0, nonneg: bool = False, method: str = "pdrqs1"):
+                bound_scalar: float = 0.0, nonneg: bool = False, method: str = "pdrqs1",
+                launch=None):
     """One-shot solve (PDRQS1 by default; nonneg: with u >= 0, §4.5); returns
     (u, report (records x 6) or None)."""
     prob = _problem(plan, sino, mask_bits, bound, lam, bound_scalar)
     prm = _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
-                  start_norm, start_precond, plan.n, nonneg, method)
+                  start_norm, start_precond, plan.n, nonneg, method, launch=launch)
     u = torch.empty((plan.n, plan.n), device=sino.device, dtype=torch.float32)
     nrec = k_max // gap_every if gap_every > 0 else 0
     rep = (ctypes.c_double * max(1, 6 * nrec))()

@@ -36,7 +36,22 @@ class CtParams(ctypes.Structure):
     _fields_ = [("sigma", c_double), ("tau", c_double), ("eps", c_double), ("c", c_double),
                 ("c_safety", c_double), ("beta", c_double), ("k_max", c_int32),
                 ("gap_every", c_int32), ("power_iters", c_int32), ("flags", c_uint32),
-                ("start_norm", c_void_p), ("start_precond", c_void_p)]
+                ("start_norm", c_void_p), ("start_precond", c_void_p),
+                ("bp_slices", c_int32), ("bp_kernel", c_int32), ("tv_blocks", c_int32),
+                ("options", c_uint32), ("tune_cache", c_char_p)]
+
+
+class CtPlanOpts(ctypes.Structure):
+    _fields_ = [("bp_kernel", c_int32), ("fwd_angles_per_walk", c_int32)]
+
+
+# backprojector kernels (ct_plan_opts.bp_kernel, ct_params.bp_kernel)
+BP_KERNELS = {"auto": -1, "one_angle": 0, "pairs4": 4, "pairs8": 8}
+# ct_params.options bits
+CT_OPT_NO_TUNE = 1
+CT_OPT_NO_DEFER = 2
+CT_OPT_SEPARATE_TV = 4
+CT_OPT_NO_GRAPH = 8
 
 
 # name -> (restype, argtypes)
@@ -44,6 +59,11 @@ SIGNATURES = {
     "ct_version": (c_int32, []),
     "ct_last_error": (c_char_p, []),
     "ct_plan_create": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(c_void_p)]),
+    "ct_plan_create_ex": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(CtPlanOpts),
+                                    POINTER(c_void_p)]),
+    "ct_plan_check_ex": (c_int32, [POINTER(CtGeom), c_void_p, POINTER(CtPlanOpts),
+                                   POINTER(ctypes.c_int64)]),
+    "ct_solver_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
     "ct_plan_destroy": (c_int32, [c_void_p]),
     "ct_radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_d0_estimate": (c_int32, [c_void_p, c_void_p, c_float, c_int32, c_float, c_void_p,

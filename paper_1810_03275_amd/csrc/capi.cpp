@@ -2,6 +2,7 @@
 // (thesis Algorithm PDRQS1 in §4.4, setup of §5.1 and §4.3.1).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -9,6 +10,8 @@
 #include <type_traits>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "common.hpp"
 
@@ -18,8 +21,8 @@ static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
-int build_plan(const ct_geom *g, const double *angles, ct_plan *p);
-int check_plan(const ct_geom *g, const double *angles, int64_t *steps);
+int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, ct_plan *p);
+int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, int64_t *steps);
 void free_plan(ct_plan *p);
 
 static bool fft_size_ok(int n) {
@@ -174,7 +177,11 @@ struct ct_solver {
   bool fuse_tv = true;        // run the gradient-side update in R_h's launch
   size_t bp_cap = 0;
   int bp_S = 1;               // angle slices of the backprojection (tuned)
-  bool tune = true;
+  int bp_kern = 4;            // backprojector of the iteration (0 one angle, 4 or 8 pairs)
+  int tv_blocks = 256;        // gradient-side workgroups in R_h's launch (0: own launch)
+  uint32_t options = 0;       // CT_OPT_*
+  // how the launch choices were made (ct_solver_tuning)
+  int tune_source = 0, tune_timed = 0, tune_saved = 0;
   double *d_red = nullptr, *d_out = nullptr;
   int red_cap = 0;
   int64_t iters = 0;
@@ -206,7 +213,7 @@ static void solver_free(ct_solver *sv) {
 
 extern "C" {
 
-int ct_version(void) { return 10000; }
+int ct_version(void) { return 10100; }
 
 const char *ct_last_error(void) { return g_err.c_str(); }
 
@@ -223,6 +230,11 @@ void ct_params_default(ct_params *p) {
   p->gap_every = 0;
   p->power_iters = 30;
   p->flags = 0;
+  p->bp_slices = 0;
+  p->bp_kernel = CT_BP_AUTO;
+  p->tv_blocks = 0;
+  p->options = 0;
+  p->tune_cache = nullptr;
 }
 
 static int check_geom(const ct_geom *g, const double *angles) {
@@ -249,7 +261,25 @@ static int check_geom(const ct_geom *g, const double *angles) {
   return CT_OK;
 }
 
+static int check_opts(const ct_plan_opts *o, ct_plan_opts *out) {
+  *out = ct_plan_opts{CT_BP_AUTO, 0};
+  if (!o) return CT_OK;
+  if ((o->bp_kernel != CT_BP_AUTO && o->bp_kernel != CT_BP_ONE_ANGLE &&
+       o->bp_kernel != CT_BP_PAIRS4 && o->bp_kernel != CT_BP_PAIRS8) ||
+      o->fwd_angles_per_walk < 0 || o->fwd_angles_per_walk > 2) {
+    set_error("ct_plan_create: bp_kernel must be a CT_BP_* value, fwd_angles_per_walk 0, 1 or 2");
+    return CT_E_INVALID;
+  }
+  *out = *o;
+  return CT_OK;
+}
+
 int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
+  return ct_plan_create_ex(g, angles, nullptr, out);
+}
+
+int ct_plan_create_ex(const ct_geom *g, const double *angles, const ct_plan_opts *opts,
+                      ct_plan **out) {
   clear_error();
   if (!g || !out) {
     set_error("ct_plan_create: null argument");
@@ -257,11 +287,13 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
   }
   *out = nullptr;
   CT_TRY(check_geom(g, angles));
+  ct_plan_opts opt;
+  CT_TRY(check_opts(opts, &opt));
   ct_plan *p = new (std::nothrow) ct_plan();
   if (!p) return CT_E_DEVICE;
   p->g = *g;
   (void)hipGetDevice(&p->device);
-  int rc = build_plan(g, angles, p);
+  int rc = build_plan(g, angles, opt, p);
   if (rc != CT_OK) {
     free_plan(p);
     delete p;
@@ -272,13 +304,20 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out) {
 }
 
 int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps) {
+  return ct_plan_check_ex(g, angles, nullptr, steps);
+}
+
+int ct_plan_check_ex(const ct_geom *g, const double *angles, const ct_plan_opts *opts,
+                     int64_t *steps) {
   clear_error();
   if (!g) {
     set_error("ct_plan_check: null argument");
     return CT_E_INVALID;
   }
   CT_TRY(check_geom(g, angles));
-  return check_plan(g, angles, steps);
+  ct_plan_opts opt;
+  CT_TRY(check_opts(opts, &opt));
+  return check_plan(g, angles, opt, steps);
 }
 
 int ct_objective(const ct_plan *pc, const ct_problem *prob, const float *u, double out[3],
@@ -542,7 +581,7 @@ static int cp_iter(ct_solver *sv, hipStream_t st) {
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / h), sv->ucp, step, (float)sv->lam_t, sv->vb2,
                           nullptr, nullptr, 4, st, nb));
   CT_TRY(launch_radon_adj(p, sv->vb1, sv->vb2, (float)(-step / sv->beta), step, sv->u_next, st,
-                          nb, sv->bp_part, sv->bp_S, sv->u, nullptr, sv->ucp));
+                          nb, sv->bp_part, sv->bp_S, sv->bp_kern, sv->u, nullptr, sv->ucp));
   std::swap(sv->u, sv->u_next);
   sv->iters += 1;
   return CT_OK;
@@ -561,7 +600,7 @@ static int admm_iter(ct_solver *sv, hipStream_t st) {
   double *sc = sv->d_cg, *part = sv->d_cg + 4;
   // r = rhs - H u = A^*((z_w - eta_w) - A u) - tau^2 div((z_v - eta_v) - nabla u)
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, inv_b, -t2, sv->cg_r, st, 1, sv->bp_part,
-                          sv->bp_S));
+                          sv->bp_S, sv->bp_kern));
   CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->cg_r, nullptr, sv->cg_z, st));
   CT_TRY(launch_dot(sv->cg_r, sv->cg_z, nn, part, sc + 0, st));
   CT_TRY(launch_cg_dir(nn, nullptr, nullptr, sv->cg_z, sv->cg_p, st));
@@ -571,7 +610,7 @@ static int admm_iter(ct_solver *sv, hipStream_t st) {
     CT_TRY(launch_radon_fwd(p, sv->cg_p, sv->r, st));
     CT_TRY(launch_grad(sv->n, inv_h, sv->cg_p, sv->w, st));
     CT_TRY(launch_radon_adj(p, sv->r, sv->w, inv_b2, -t2, sv->cg_Hp, st, 1, sv->bp_part,
-                            sv->bp_S));
+                            sv->bp_S, sv->bp_kern));
     CT_TRY(launch_dot(sv->cg_p, sv->cg_Hp, nn, part, sc + 2, st));
     CT_TRY(launch_cg_update(nn, sc + cur, sc + 2, sv->cg_p, sv->cg_Hp, sv->u, sv->cg_r, st));
     if (k + 1 < sv->admm_cg) {  // the direction after the last step is not used
@@ -605,7 +644,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
     BpDeferred def{};
     CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(sv->sigma / sv->beta),
                             (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part,
-                            sv->bp_S, nullptr, nullptr, nullptr,
+                            sv->bp_S, sv->bp_kern, nullptr, nullptr, nullptr,
                             sv->defer_combine ? &def : nullptr));
     CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, nb,
                              sv->spec, def.S > 1 ? &def : nullptr));
@@ -625,7 +664,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   const bool rich = sv->method == CT_METHOD_RICHARDSON;
   CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, (float)(-sv->sigma / sv->beta),
                           (float)(sv->sigma * sv->tau), sv->utmp, st, nb, sv->bp_part, sv->bp_S,
-                          sv->ubar, sv->ubar ? sv->u : nullptr, nullptr,
+                          sv->bp_kern, sv->ubar, sv->ubar ? sv->u : nullptr, nullptr,
                           rich || !sv->defer_combine ? nullptr : &def));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[1], st));
   if (rich)
@@ -655,7 +694,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   tv.mode = mode;
   tv.q2out = q2out;
   tv.ubar = sv->ubar;
-  tv.blocks = (ev || !sv->fuse_tv) ? 0 : std::min(sv->n, 256);
+  tv.blocks = (ev || !sv->fuse_tv) ? 0 : sv->tv_blocks;
   bool fused = false;
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb, &tv, &fused));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
@@ -668,45 +707,188 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   return CT_OK;
 }
 
-// Choose the backprojection kernel (mirror pairs or one angle at a time, when
-// the plan has pairs) and its number of angle slices for this batch by timing
-// the candidates on the solver's own data (the caches s1, s2), together with
-// the pass that sums the slices (the FFT pair or the combine).
-static int solver_tune(ct_solver *sv, hipStream_t st) {
+// Tuning results kept in a JSON file (ct_params.tune_cache): one entry per
+// line, {"key": "...", "bp_kernel": k, "bp_slices": S, "tv_blocks": b},
+// between a header line and a closing line.  The key names the device (its
+// architecture and compute-unit count), the library version, the geometry,
+// the batch size and the method class.
+struct TuneChoice {
+  int kern = 4, S = 1, tv_blocks = 256;
+};
+
+static std::string tune_key(const ct_solver *sv, bool with_fft, bool tvf) {
+  const ct_plan *p = sv->plan;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char &c : arch)
+    if (c == '"' || c == '\\' || c == '\n') c = '_';
+  char buf[512];
+  std::snprintf(buf, sizeof(buf),
+                "%s/cu%d/v%d/n%d/N%d/M%d/h%.17g/ds%.17g/ang%016llx/walk%d/nb%d/fft%d/tvf%d",
+                arch.c_str(), cus, ct_version(), p->g.n, p->g.n_angles, p->g.n_bins, p->g.h,
+                p->g.ds, (unsigned long long)p->angles_hash, p->slots, sv->nb, with_fft ? 1 : 0,
+                tvf ? 1 : 0);
+  return buf;
+}
+
+static bool tune_line_parse(const std::string &line, std::string *key, TuneChoice *c) {
+  const std::string kk = "{\"key\": \"";
+  if (line.compare(0, kk.size(), kk) != 0) return false;
+  const size_t q = line.find('"', kk.size());
+  if (q == std::string::npos) return false;
+  *key = line.substr(kk.size(), q - kk.size());
+  auto field = [&](const char *name, int *v) {
+    const std::string f = std::string("\"") + name + "\": ";
+    const size_t at = line.find(f, q);
+    if (at == std::string::npos) return false;
+    char *end = nullptr;
+    const long x = std::strtol(line.c_str() + at + f.size(), &end, 10);
+    if (end == line.c_str() + at + f.size()) return false;
+    *v = (int)x;
+    return true;
+  };
+  return field("bp_kernel", &c->kern) && field("bp_slices", &c->S) &&
+         field("tv_blocks", &c->tv_blocks);
+}
+
+static std::vector<std::pair<std::string, TuneChoice>> tune_file_read(const char *path) {
+  std::vector<std::pair<std::string, TuneChoice>> out;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return out;
+  std::string line;
+  int ch;
+  while (true) {
+    line.clear();
+    while ((ch = std::fgetc(f)) != EOF && ch != '\n') line.push_back((char)ch);
+    std::string key;
+    TuneChoice c;
+    if (tune_line_parse(line, &key, &c)) out.emplace_back(key, c);
+    if (ch == EOF) break;
+  }
+  std::fclose(f);
+  return out;
+}
+
+// Adds (or replaces) one entry; the file is rewritten whole through a
+// temporary file and a rename, so that a reader never sees half a file.
+static bool tune_file_store(const char *path, const std::string &key, const TuneChoice &c) {
+  auto all = tune_file_read(path);
+  bool found = false;
+  for (auto &e : all)
+    if (e.first == key) {
+      e.second = c;
+      found = true;
+    }
+  if (!found) all.emplace_back(key, c);
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\"format\": \"ctpd-tune\", \"entries\": [\n");
+  for (size_t q = 0; q < all.size(); ++q)
+    std::fprintf(f, "{\"key\": \"%s\", \"bp_kernel\": %d, \"bp_slices\": %d, \"tv_blocks\": %d}%s\n",
+                 all[q].first.c_str(), all[q].second.kern, all[q].second.S,
+                 all[q].second.tv_blocks, q + 1 < all.size() ? "," : "");
+  std::fprintf(f, "]}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    (void)std::remove(tmp.c_str());
+    return false;
+  }
+  return true;
+}
+
+// A stored choice is used only if it is one this solver could make.
+static bool tune_choice_valid(const ct_solver *sv, const TuneChoice &c) {
+  const bool kern_ok = c.kern == 0 || ((c.kern == 4 || c.kern == 8) && sv->plan->n_bpp > 0);
+  return kern_ok && c.S >= 1 && c.S <= kMaxSlices && c.tv_blocks >= 0 && c.tv_blocks <= 4096;
+}
+
+// The launch choices of the iteration: the backprojector (mirror pairs on
+// 32 x 32 or 32 x 64 tiles, or one angle at a time), its number of angle
+// slices, and the workgroups that run the gradient-side update inside R_h's
+// launch (0: a launch of its own).  What the params fix is kept; with
+// CT_OPT_NO_TUNE the rest are the plan's defaults.  Otherwise, when nothing
+// is fixed, a choice recorded for this plan and batch size (an earlier
+// solver) or in the tune cache file is reused; else the candidates are timed
+// on the solver's own data (the caches s1, s2 of the zero state): the
+// backprojection together with the pass that sums its slices (the FFT pair
+// or the combine), then R_h's launch with each number of extra workgroups.
+static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   ct_plan *p = sv->plan;
   const int N = sv->N;
-  struct Cand {
-    int pix;  // mirror pairs with 4 or 8 pixels per thread; 0: one angle at a time
-    int S;
-  };
-  Cand cands[16];
-  int nc = 0;
-  // mirror pairs on small tiles are tried for one problem only (a batch
-  // fills the device with larger tiles' workgroups)
-  for (int pix : {4, 8, 0}) {
-    if (pix != 0 && p->n_bpp == 0) continue;
-    if (pix == 4 && sv->nb != 1) continue;
-    // staged chunks of the backprojection's angles (mirror pairs when paired)
-    const int items = pix ? p->n_bpp / kBpPairChunk : N / kBpChunk;
-    for (int S : {1, 2, 4, 8, kMaxSlices})
-      if (S == 1 || items / S >= 2) cands[nc++] = Cand{pix, S};
-  }
-  auto choose = [&](const Cand &c) {
-    p->bp_use_pairs = c.pix != 0;
-    if (c.pix != 0) p->bp_pair_pix = c.pix;
-  };
-  if (nc == 1) {
-    choose(cands[0]);
-    return solver_set_slices(sv, 1);
-  }
   const bool with_fft = sv->defer_combine &&
                         (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_PDRQS2 ||
                          sv->method == CT_METHOD_PDRQS3);
-  for (const auto &t : p->tune_cache)
-    if (t.nb == sv->nb && t.fft == (int)with_fft) {
-      choose(Cand{t.pix, t.S});
-      return solver_set_slices(sv, t.S);
+  // the gradient-side update joins R_h's launch in the PDRQS1-type
+  // iterations when R_h walks angle pairs (launch_radon_fwd)
+  const bool tvf = sv->fuse_tv && p->slots == 2 &&
+                   (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_RICHARDSON ||
+                    sv->method == CT_METHOD_PDRQS3);
+  const bool kern_fixed = prm->bp_kernel != CT_BP_AUTO;
+  const bool S_fixed = prm->bp_slices > 0;
+  const bool tv_fixed = prm->tv_blocks > 0 || !tvf;
+  TuneChoice ch;
+  ch.kern = kern_fixed ? (p->n_bpp > 0 ? prm->bp_kernel : 0) : p->bp_kern0;
+  ch.S = S_fixed ? prm->bp_slices : p->bp_slices;
+  ch.tv_blocks = prm->tv_blocks > 0 ? prm->tv_blocks : std::min(sv->n, 256);
+  sv->tune_source = 0;
+  sv->tune_timed = 0;
+  sv->tune_saved = 0;
+  auto apply = [&]() {
+    sv->bp_kern = ch.kern;
+    sv->tv_blocks = ch.tv_blocks;
+    return solver_set_slices(sv, ch.S);
+  };
+  const bool all_free = !kern_fixed && !S_fixed && prm->tv_blocks == 0;
+  if ((prm->options & CT_OPT_NO_TUNE) || (kern_fixed && S_fixed && tv_fixed)) return apply();
+  std::string key;
+  if (all_free) {
+    for (const auto &t : p->tune_cache)
+      if (t.nb == sv->nb && t.fft == (int)with_fft && t.tvf == (int)tvf) {
+        ch = TuneChoice{t.kern, t.S, t.tv_blocks};
+        sv->tune_source = 2;
+        return apply();
+      }
+    if (prm->tune_cache) {
+      key = tune_key(sv, with_fft, tvf);
+      for (const auto &e : tune_file_read(prm->tune_cache))
+        if (e.first == key && tune_choice_valid(sv, e.second)) {
+          ch = e.second;
+          sv->tune_source = 3;
+          p->tune_cache.push_back(
+              ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern, ch.S, ch.tv_blocks});
+          return apply();
+        }
     }
+  }
+  struct Cand {
+    int kern;  // mirror pairs with 4 or 8 pixels per thread; 0: one angle at a time
+    int S;
+  };
+  std::vector<Cand> cands;
+  // mirror pairs on small tiles are tried for one problem only (a batch
+  // fills the device with larger tiles' workgroups)
+  for (int kern : {4, 8, 0}) {
+    if (kern_fixed) {
+      if (kern != ch.kern) continue;
+    } else {
+      if (kern != 0 && p->n_bpp == 0) continue;
+      if (kern == 4 && sv->nb != 1) continue;
+    }
+    if (S_fixed) {
+      cands.push_back(Cand{kern, ch.S});
+      continue;
+    }
+    // staged chunks of the backprojection's angles (mirror pairs when paired)
+    const int items = kern ? p->n_bpp / kBpPairChunk : N / kBpChunk;
+    for (int S : {1, 2, 4, 8, kMaxSlices})
+      if (S == 1 || items / S >= 2) cands.push_back(Cand{kern, S});
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CT_TRY_HIP(hipEventCreate(&e0));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g0(
@@ -714,39 +896,97 @@ static int solver_tune(ct_solver *sv, hipStream_t st) {
   CT_TRY_HIP(hipEventCreate(&e1));
   std::unique_ptr<std::remove_pointer<hipEvent_t>::type, hipError_t (*)(hipEvent_t)> g1(
       e1, hipEventDestroy);
-  float best = 0.f;
-  Cand bestc = cands[0];
-  for (int c = 0; c < nc; ++c) {
-    choose(cands[c]);
-    CT_TRY(solver_set_slices(sv, cands[c].S));
-    // what the iteration runs: with the FFT pair next, R_h^* with its slice
-    // sum deferred into the row pass and the pair itself; else R_h^* and the
-    // slice combine
-    auto run = [&]() {
-      if (!with_fft)
-        return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
-                                sv->bp_part, sv->bp_S);
-      BpDeferred def{};
-      CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb, sv->bp_part,
-                              sv->bp_S, nullptr, nullptr, nullptr, &def));
-      return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, sv->nb,
-                               sv->spec, def.S > 1 ? &def : nullptr);
-    };
+  auto time_it = [&](auto &&run, float *ms) -> int {
     CT_TRY(run());  // warm-up
     CT_TRY_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 3; ++r) CT_TRY(run());
     CT_TRY_HIP(hipEventRecord(e1, st));
     CT_TRY_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    CT_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (c == 0 || ms < best) {
-      best = ms;
-      bestc = cands[c];
+    CT_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+    sv->tune_timed += 1;
+    return CT_OK;
+  };
+  if (cands.size() > 1) {
+    float best = 0.f;
+    Cand bestc = cands[0];
+    for (size_t c = 0; c < cands.size(); ++c) {
+      CT_TRY(solver_set_slices(sv, cands[c].S));
+      const int kern = cands[c].kern;
+      // what the iteration runs: with the FFT pair next, R_h^* with its slice
+      // sum deferred into the row pass and the pair itself; else R_h^* and the
+      // slice combine
+      auto run = [&]() -> int {
+        if (!with_fft)
+          return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+                                  sv->bp_part, sv->bp_S, kern);
+        BpDeferred def{};
+        CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+                                sv->bp_part, sv->bp_S, kern, nullptr, nullptr, nullptr, &def));
+        return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st,
+                                 sv->nb, sv->spec, def.S > 1 ? &def : nullptr);
+      };
+      float ms = 0.f;
+      CT_TRY(time_it(run, &ms));
+      if (c == 0 || ms < best) {
+        best = ms;
+        bestc = cands[c];
+      }
     }
+    ch.kern = bestc.kern;
+    ch.S = bestc.S;
   }
-  choose(bestc);
-  p->tune_cache.push_back(ct_plan::TuneEntry{sv->nb, (int)with_fft, bestc.pix, bestc.S});
-  return solver_set_slices(sv, bestc.S);
+  if (!tv_fixed) {
+    // R_h of the zero image with the gradient-side update of the zero state
+    // (u_new = 0 leaves vb2 = s2 = 0, and bar u = 0): the state is unchanged
+    const size_t nn = (size_t)sv->n * sv->n * sv->nb;
+    CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
+    std::vector<int> blocks;
+    for (int b : {64, 128, 256, 512, 1024})
+      if (b <= sv->n) blocks.push_back(b);
+    if (blocks.empty()) blocks.push_back(sv->n);
+    blocks.push_back(0);  // a launch of its own
+    const float sig = (float)sv->sigma, tau = (float)sv->tau;
+    const float inv_h = (float)(1.0 / p->g.h);
+    float best = 0.f;
+    int bestb = blocks[0];
+    for (size_t c = 0; c < blocks.size(); ++c) {
+      TvArgs tv;
+      tv.n = sv->n;
+      tv.inv_h = inv_h;
+      tv.u = sv->u_next;
+      tv.st = sig * tau;
+      tv.radius = (float)(sv->lam_t / sv->tau);
+      tv.vb2 = sv->vb2;
+      tv.s2 = sv->s2;
+      tv.wout = sv->w;
+      tv.mode = 0;
+      tv.ubar = sv->ubar;
+      tv.blocks = blocks[c];
+      auto run = [&]() -> int {
+        bool fused = false;
+        CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st, nullptr, sv->nb, &tv, &fused));
+        if (!fused)
+          CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2,
+                                  sv->s2, sv->w, 0, st, sv->nb, nullptr, sv->ubar));
+        return CT_OK;
+      };
+      float ms = 0.f;
+      CT_TRY(time_it(run, &ms));
+      if (c == 0 || ms < best) {
+        best = ms;
+        bestb = blocks[c];
+      }
+    }
+    ch.tv_blocks = bestb;
+  }
+  if (!sv->tune_timed) return apply();
+  sv->tune_source = 1;
+  if (all_free) {
+    p->tune_cache.push_back(
+        ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern, ch.S, ch.tv_blocks});
+    if (prm->tune_cache) sv->tune_saved = tune_file_store(prm->tune_cache, key, ch) ? 1 : 0;
+  }
+  return apply();
 }
 
 // Kernel preconditioners for PDRQS1, built from the response of A^* A to a
@@ -891,12 +1131,8 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   const size_t nn = (size_t)n * n, NM = (size_t)N * M;
   const size_t MW = (size_t)(M + 31) / 32;
   CT_TRY(solver_alloc(sv));
-  // the set-up's backprojections use the plan's default (mirror pairs when
-  // it has them), whatever an earlier solver's tuning chose, so that a solver
-  // without tuning runs the same kernels for one problem as for a batch; the
-  // tuning below decides for the iterations
-  p->bp_use_pairs = true;
-  p->bp_pair_pix = p->bp_pair_pix0;
+  // the set-up's backprojections use the plan's default kernel and slice
+  // count; the tuning at the end decides for the iterations
   if (prm->flags & CT_FLAG_NONNEG) CT_TRY_HIP(hipMalloc(&sv->ubar, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_CP) CT_TRY_HIP(hipMalloc(&sv->ucp, sizeof(float) * nn * nb));
   if (sv->method == CT_METHOD_ADMM) {
@@ -1018,15 +1254,7 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
                                sv->target + (size_t)b * NM, st));
   sv->lam_t = probs[0].lambda / (sv->beta * sv->beta);
   CT_TRY(solver_zero_state(sv, st));
-  {
-    // a fixed slice count instead of the tuning (a test hook: 1 ... kMaxSlices)
-    const char *fs = std::getenv("CTPD_FORCE_SLICES");
-    const int forced = fs ? std::atoi(fs) : 0;
-    if (forced >= 1 && forced <= kMaxSlices)
-      CT_TRY(solver_set_slices(sv, forced));
-    else if (sv->tune)
-      CT_TRY(solver_tune(sv, st));
-  }
+  CT_TRY(solver_tune(sv, prm, st));
   CT_TRY_HIP(hipStreamSynchronize(st));
   return CT_OK;
 }
@@ -1057,10 +1285,6 @@ static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap,
   return CT_OK;
 }
 
-static bool use_graphs() {
-  const char *ng = std::getenv("CTPD_NO_GRAPH");
-  return !(ng && ng[0] == '1');
-}
 
 // k iterations of every solver in svs (same iteration count and parity):
 // all but the last in graph-replayed pairs, the last one eager in mode 2 so
@@ -1069,7 +1293,9 @@ static bool use_graphs() {
 static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, hipStream_t *cap,
                       hipGraphExec_t graphs[2], float *graph_u[2]) {
   int left = k;
-  if (use_graphs() && left >= 3) {
+  bool graphs_ok = true;
+  for (int q = 0; q < count; ++q) graphs_ok = graphs_ok && svs[q]->use_graph;
+  if (graphs_ok && left >= 3) {
     const int parity = (svs[0]->u < svs[0]->u_next) ? 0 : 1;
     if (!graphs[parity]) {
       if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
@@ -1130,6 +1356,20 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
     set_error("ct_solver_create: n must be even, 2^a 3^b and <= 4096");
     return CT_E_UNSUPPORTED;
   }
+  if (prm->bp_slices < 0 || prm->bp_slices > kMaxSlices || prm->tv_blocks < 0 ||
+      prm->tv_blocks > 4096 ||
+      (prm->bp_kernel != CT_BP_AUTO && prm->bp_kernel != CT_BP_ONE_ANGLE &&
+       prm->bp_kernel != CT_BP_PAIRS4 && prm->bp_kernel != CT_BP_PAIRS8) ||
+      (prm->options & ~15u) != 0) {
+    set_error("ct_solver_create: need 0 <= bp_slices <= 16, 0 <= tv_blocks <= 4096, a CT_BP_* "
+              "kernel and known CT_OPT_* bits");
+    return CT_E_INVALID;
+  }
+  if ((prm->bp_kernel == CT_BP_PAIRS4 || prm->bp_kernel == CT_BP_PAIRS8) && p->n_bpp == 0) {
+    set_error("ct_solver_create: mirror-pair backprojection needs angles that pair as "
+              "theta, pi - theta");
+    return CT_E_UNSUPPORTED;
+  }
   const int method = (int)((prm->flags >> CT_METHOD_SHIFT) & 15u);
   if (method > CT_METHOD_PDRQS3) {
     set_error("ct_solver_create: unknown method");
@@ -1178,15 +1418,10 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
   sv->sigma = prm->sigma;
   sv->tau = prm->tau;
   sv->eps = prm->eps;
-  sv->use_graph = use_graphs();
-  {
-    const char *nt = std::getenv("CTPD_NO_TUNE");
-    sv->tune = !(nt && nt[0] == '1');
-    const char *nd = std::getenv("CTPD_NO_DEFER");
-    sv->defer_combine = !(nd && nd[0] == '1');
-    const char *nf = std::getenv("CTPD_NO_TV_FUSE");
-    sv->fuse_tv = !(nf && nf[0] == '1');
-  }
+  sv->options = prm->options;
+  sv->use_graph = !(prm->options & CT_OPT_NO_GRAPH);
+  sv->defer_combine = !(prm->options & CT_OPT_NO_DEFER);
+  sv->fuse_tv = !(prm->options & CT_OPT_SEPARATE_TV);
   int rc = solver_setup(sv, probs, prm, S(s));
   if (rc != CT_OK) {
     (void)hipStreamSynchronize(S(s));
@@ -1208,7 +1443,7 @@ static int solver_gap(ct_solver *sv, int b, double out[6], hipStream_t st) {
   // z = A^* y1 - tau div w  (= K^* y), into the first u_tmp image
   CT_TRY(launch_radon_adj(sv->plan, sv->y1 + b * NM, sv->w + b * 2 * nn,
                           (float)(1.0 / sv->beta), (float)(-sv->tau), sv->utmp, st, 1,
-                          sv->bp_part, sv->bp_S));
+                          sv->bp_part, sv->bp_S, sv->bp_kern));
   CT_TRY(launch_img_gap(sv->n, (float)(1.0 / sv->plan->g.h), sv->u + b * nn,
                         sv->u_next + b * nn, sv->utmp, sv->d_red, sv->red_cap, o + 3, st));
   double h[6];
@@ -1269,9 +1504,22 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[6]) {
   out[1] = sv->bp_S;
   out[2] = sv->plan->slots;
   out[3] = sv->plan->n_groups;
-  const bool pairs = sv->plan->n_bpp > 0 && sv->plan->bp_use_pairs;
+  const bool pairs = sv->plan->n_bpp > 0 && sv->bp_kern != 0;
   out[4] = pairs ? 2 : 1;
-  out[5] = pairs ? sv->plan->bp_pair_pix : 0;
+  out[5] = pairs ? sv->bp_kern : 0;
+  return CT_OK;
+}
+
+int ct_solver_tuning(const ct_solver *sv, int32_t out[4]) {
+  clear_error();
+  if (!sv || !out) {
+    set_error("ct_solver_tuning: null argument");
+    return CT_E_INVALID;
+  }
+  out[0] = sv->tune_source;
+  out[1] = sv->tune_timed;
+  out[2] = sv->fuse_tv ? sv->tv_blocks : 0;
+  out[3] = sv->tune_saved;
   return CT_OK;
 }
 
@@ -1791,7 +2039,7 @@ int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *
                                t->partials, t->acc, st));
       // Utot = U + A^* P - div G
       CT_TRY(launch_radon_adj(p, t->P, t->G, (float)(1.0 / sv->beta), -1.0f, t->Utot, st, nb,
-                              sv->bp_part, sv->bp_S, t->U));
+                              sv->bp_part, sv->bp_S, sv->bp_kern, t->U));
       CT_TRY(launch_apply_mult(&sv->pc, sv->pc.d_mult, t->Utot, nullptr, t->X, st, nb,
                                sv->spec));
       SinoEpi ep{(float)(1.0 / sv->beta), sig, nullptr, nullptr, t->Q1, t->V1, t->P, nullptr,

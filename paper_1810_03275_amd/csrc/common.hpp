@@ -122,15 +122,18 @@ struct ct_plan {
   // 2c + 1 its mirror image i -> n - 1 - i (row: the partner m, or -1)
   ctpd::BpAngle *d_bpp = nullptr;
   int n_bpp = 0;          // pairs (0: the one-angle backprojector)
-  bool bp_use_pairs = true;  // with pairs: use them (a solver's tuning may say no)
-  int bp_pair_pix = 4;       // pixels per thread of the pair kernel (4 or 8; tuned)
-  int bp_pair_pix0 = 4;      // its default, restored at every solver's set-up
-  // set-up tunings done on this plan: (batch size, FFT pair next) -> choice,
-  // so that solvers created again for the same batch size skip the timing
+  // backprojector of standalone calls and untuned solvers: 0 one angle at a
+  // time, 4 or 8 mirror pairs with that many pixels per thread (a solver
+  // keeps its own choice; the plan is never changed by a solver)
+  int bp_kern0 = 4;
+  uint64_t angles_hash = 0;  // FNV-1a of explicit angles (0: theta_l = pi l / N)
+  // set-up tunings done on this plan, (batch size, FFT pair next, fused
+  // gradient-side update) -> choice, so that solvers created again for the
+  // same batch size skip the timing (a memo only: each solver copies it)
   struct TuneEntry {
-    int nb, fft, pix, S;
+    int nb, fft, tvf, kern, S, tv_blocks;
   };
-  std::vector<TuneEntry> tune_cache;
+  mutable std::vector<TuneEntry> tune_cache;
   int seg_pair = 0;       // staged bins per angle per tile of the pair kernel
   int seg = 0;  // staged bins per angle per tile
   int bp_slices = 1;           // angle slices of the backprojection grid
@@ -194,10 +197,13 @@ struct BpDeferred {
   float c1 = 0.f, c2 = 0.f, inv_h = 0.f;
   const float *base = nullptr, *base2 = nullptr;
 };
+// kern: the backprojector (0 one angle at a time, 4 or 8 mirror pairs with
+// that many pixels per thread; < 0 the plan's default).
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
                      float c2, float *out, hipStream_t s, int nb = 1, float *part = nullptr,
-                     int S = 0, const float *base = nullptr, const float *base2 = nullptr,
-                     float *out2 = nullptr, BpDeferred *defer = nullptr);
+                     int S = 0, int kern = -1, const float *base = nullptr,
+                     const float *base2 = nullptr, float *out2 = nullptr,
+                     BpDeferred *defer = nullptr);
 // out = base + a x over count elements (nb problems contiguous).
 int launch_axpy(int64_t count, const float *base, float a, const float *x, float *out,
                 hipStream_t s);

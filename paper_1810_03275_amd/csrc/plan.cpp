@@ -70,7 +70,8 @@ static void schedule_work(HostPlan *p) {
   for (const Item &it : items) p->work.push_back(make_int2(it.g, it.b));
 }
 
-static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
+static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
+                     HostPlan *p) {
   const int n = g->n, N = g->n_angles, M = g->n_bins;
   const double h = g->h, ds = g->ds;
   std::vector<BpAngle> &bp = p->bp;
@@ -187,16 +188,22 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
       pairs.push_back(bp[l]);
       pairs.push_back(mir);
     }
-    const char *env = std::getenv("CTPD_BP_PAIRS");
-    const bool off = env && env[0] == '0';
-    if (!off && n >= 2 && 2 * paired_angles >= N) p->bpp = pairs;
+    // the table is kept whenever the angles pair, so that a solver may choose
+    // the pair kernel even when the plan's default is one angle at a time
+    if (n >= 2 && 2 * paired_angles >= N) p->bpp = pairs;
+    if ((opt.bp_kernel == CT_BP_PAIRS4 || opt.bp_kernel == CT_BP_PAIRS8) && p->bpp.empty()) {
+      set_error("ct_plan_create: mirror-pair backprojection needs angles that pair as "
+                "theta, pi - theta");
+      return CT_E_UNSUPPORTED;
+    }
   }
   {
     // workgroups: tiles (of the left half when paired) x angle slices
-    const int ni = p->bpp.empty() ? n : (n + 1) / 2;
-    const int tj = p->bpp.empty() ? kBpTileJ : kBppTileJ;
+    const bool pairs = !p->bpp.empty() && opt.bp_kernel != CT_BP_ONE_ANGLE;
+    const int ni = pairs ? (n + 1) / 2 : n;
+    const int tj = pairs ? (opt.bp_kernel == CT_BP_PAIRS8 ? kBpTileJ : kBppTileJ) : kBpTileJ;
     const int tiles = ((ni + kBpTileI - 1) / kBpTileI) * ((n + tj - 1) / tj);
-    const int items = p->bpp.empty() ? N / kBpChunk : (int)(p->bpp.size() / 2) / kBpPairChunk;
+    const int items = pairs ? (int)(p->bpp.size() / 2) / kBpPairChunk : N / kBpChunk;
     int S = (1024 + tiles - 1) / tiles;
     S = std::min(S, kMaxDeferredSlices);
     S = std::min(S, std::max(1, items / 2));
@@ -225,8 +232,7 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   };
   std::vector<int> modes;
   {
-    const char *env = std::getenv("CTPD_FWD_SLOTS");
-    const int forced = env ? std::atoi(env) : 0;
+    const int forced = opt.fwd_angles_per_walk;
     if (forced == 1 || forced == 2) {
       modes.push_back(forced);
     } else if (N >= 2 && 2 * complete(2) >= N) {
@@ -413,15 +419,26 @@ static int plan_host(const ct_geom *g, const double *angles, HostPlan *p) {
   return CT_OK;
 }
 
-int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
+int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, ct_plan *p) {
   HostPlan hp;
-  CT_TRY(plan_host(g, angles, &hp));
+  CT_TRY(plan_host(g, angles, opt, &hp));
   const int n = g->n, N = g->n_angles;
   p->seg = hp.seg;
   p->seg_pair = hp.seg_pair;
-  {
-    const char *e = std::getenv("CTPD_BP_PIX");  // a test hook: 8 pixels per thread
-    p->bp_pair_pix0 = p->bp_pair_pix = (e && std::atoi(e) == 8) ? 8 : 4;
+  if (hp.bpp.empty() || opt.bp_kernel == CT_BP_ONE_ANGLE)
+    p->bp_kern0 = 0;
+  else
+    p->bp_kern0 = opt.bp_kernel == CT_BP_PAIRS8 ? 8 : 4;
+  p->angles_hash = 0;
+  if (angles) {
+    // FNV-1a over the angles' bytes: part of the tuning cache's key
+    uint64_t hsh = 1469598103934665603ull;
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(angles);
+    for (size_t q = 0; q < sizeof(double) * (size_t)N; ++q) {
+      hsh ^= b[q];
+      hsh *= 1099511628211ull;
+    }
+    p->angles_hash = hsh ? hsh : 1;
   }
   p->bp_slices = hp.bp_slices;
   p->check_first = hp.check_first;
@@ -465,9 +482,10 @@ int build_plan(const ct_geom *g, const double *angles, ct_plan *p) {
 // lane, staged row) of a plan: each LDS read must fall inside the staged
 // window of its chunk, and every row that the kernel skips must hold no pixel
 // of any strip of the block.  Exact integer arithmetic, as on the device.
-int check_plan(const ct_geom *g, const double *angles, int64_t *steps) {
+int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
+               int64_t *steps) {
   HostPlan hp;
-  CT_TRY(plan_host(g, angles, &hp));
+  CT_TRY(plan_host(g, angles, opt, &hp));
   const int n = g->n;
   const int64_t one = (int64_t)1 << kFixBits;
   int64_t count = 0;

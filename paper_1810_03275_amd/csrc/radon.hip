@@ -512,7 +512,7 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
 }
 
 int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, float c1,
-                     float c2, float *out, hipStream_t s, int nb, float *part, int S,
+                     float c2, float *out, hipStream_t s, int nb, float *part, int S, int kern,
                      const float *base, const float *base2, float *out2, BpDeferred *defer) {
   const int n = p->g.n;
   if (S <= 0) S = p->bp_slices;
@@ -524,12 +524,13 @@ int launch_radon_adj(const ct_plan *p, const float *v, const float *pfield, floa
   }
   if (part == nullptr) part = p->d_bp_part;
   float *dst = (S == 1) ? out : part;
-  if (p->n_bpp > 0 && p->bp_use_pairs) {
+  if (kern < 0) kern = p->bp_kern0;
+  if (p->n_bpp > 0 && kern != 0) {
     const int nh = (n + 1) / 2;
     const int pair_len = (p->n_bpp + S - 1) / S;
     // 4 pixels per thread on 32 x 32 tiles, or 8 on 32 x 64 (the one-angle
     // kernel's tile, whose segment length it shares)
-    const int pix = p->bp_pair_pix == 8 ? 8 : 4;
+    const int pix = kern == 8 ? 8 : 4;
     const int seg = pix == 8 ? p->seg : p->seg_pair;
     dim3 grid((nh + kBpTileI - 1) / kBpTileI, (n + kBpRowStep * pix - 1) / (kBpRowStep * pix),
               S * nb);

@@ -31,3 +31,14 @@ def build(w: synth.Workload):
 
 def oracle_problem(g, u0, mask, bound, lam):
     return pdrq.Problem(g, u0, mask, bound, lam)
+
+
+def random_state(n: int, N: int, M: int, seed: int, vb2_scale: float):
+    """A seeded iterate (u, vb1, vb2) for one-step parity checks, float64
+    holding float32-representable values: u ~ U[0, 1), vb1 ~ 0.01 N(0, 1),
+    vb2 ~ vb2_scale N(0, 1) (callers pass lambda~/tau, the dual ball's radius)."""
+    rng = np.random.default_rng(seed)
+    u = f32(rng.uniform(0.0, 1.0, (n, n)))
+    vb1 = f32(0.01 * rng.standard_normal((N, M)))
+    vb2 = f32(vb2_scale * rng.standard_normal((2, n, n)))
+    return u, vb1, vb2

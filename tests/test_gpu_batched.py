@@ -5,8 +5,6 @@ all batches of a solve replay as one HIP graph.  Each slice's result must be
 the single-slice result (bitwise when both use the same backprojection
 slicing) and match the FP64 oracle run with the same beta and c.
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -48,21 +46,16 @@ def small_batch(count, seed, sizes=(32, 48, 64)):
     return out
 
 
-@pytest.fixture
-def no_tune():
-    old = os.environ.get("CTPD_NO_TUNE")
-    os.environ["CTPD_NO_TUNE"] = "1"
-    yield
-    if old is None:
-        del os.environ["CTPD_NO_TUNE"]
-    else:
-        os.environ["CTPD_NO_TUNE"] = old
+NO_TUNE = ct.Launch(tune=False)
 
 
-def test_batch_equals_single_slices(no_tune):
-    """Three slices of one geometry in a batch solver vs three single solvers:
-    bitwise equal state after 25 iterations (same kernels, same order)."""
-    print("batch vs single", flush=True)
+@pytest.mark.parametrize("kern", ["auto", "pairs8", "one_angle"])
+def test_batch_equals_single_slices(kern):
+    """Three slices of one geometry in a batch solver vs three single solvers
+    with the same launch choices: bitwise equal state after 25 iterations
+    (same kernels, same order)."""
+    print("batch vs single", kern, flush=True)
+    launch = NO_TUNE if kern == "auto" else ct.Launch(tune=False, bp_kernel=kern)
     n, N, M = 64, 90, 96
     ws = [synth.batched_workload(i, (n, N, M, i % 3), iters=25) for i in range(3)]
     data = [build(w) for w in ws]
@@ -70,7 +63,7 @@ def test_batch_equals_single_slices(no_tune):
     sinos = [gpu(d[1]) for d in data]
     masks = [ct.pack_mask(d[2]) for d in data]
     bounds = [gpu(d[3]) for d in data]
-    sb = ct.SolverBatch(plan, sinos, 0.005, masks, bounds)
+    sb = ct.SolverBatch(plan, sinos, 0.005, masks, bounds, launch=launch)
     info = sb.info()
     assert sb.layout()["problems"] == 3
     sb.step(25)
@@ -78,7 +71,7 @@ def test_batch_equals_single_slices(no_tune):
     gb = sb.gap()
     for b in range(3):
         sv = ct.Solver(plan, sinos[b], 0.005, masks[b], bounds[b], beta=info["beta"],
-                       c=info["c"])
+                       c=info["c"], launch=launch)
         sv.step(25)
         u, vb1, vb2 = (host(t) for t in sv.export())
         assert np.array_equal(u, ub[b])
@@ -154,7 +147,7 @@ def test_batched_groups_and_errors():
         ct.SolverBatch(plan, [], 0.01)
 
 
-def test_group_step_equals_separate_steps(no_tune):
+def test_group_step_equals_separate_steps():
     """Two batches of different geometries stepped as one group (one graph)
     give bitwise the same state as stepping each batch on its own."""
     print("group step", flush=True)
@@ -167,8 +160,8 @@ def test_group_step_equals_separate_steps(no_tune):
         args = ([gpu(d[1]) for d in data], 0.005, [ct.pack_mask(d[2]) for d in data],
                 [gpu(d[3]) for d in data])
         made.append((plan, args))
-    grouped = [ct.SolverBatch(p, *a) for p, a in made]
-    alone = [ct.SolverBatch(p, *a) for p, a in made]
+    grouped = [ct.SolverBatch(p, *a, launch=NO_TUNE) for p, a in made]
+    alone = [ct.SolverBatch(p, *a, launch=NO_TUNE) for p, a in made]
     grp = ct.SolverGroup(grouped)
     grp.step(9)
     for sv in alone:

@@ -60,15 +60,31 @@ GEOMS = [
 ]
 
 
+def _plan_or_skip(n, N, M, h=1.0, ds=1.0, bp_kernel="auto"):
+    """A plan with the given backprojector; the pair kernels need angles that
+    pair as theta, pi - theta (CT_E_UNSUPPORTED otherwise: skipped)."""
+    try:
+        return ct.Plan(n, N, M, h, ds, bp_kernel=bp_kernel)
+    except ct.CtpdError as e:
+        if bp_kernel != "auto" and e.code == -2:
+            pytest.skip("angles do not pair")
+        raise
+
+
+@pytest.mark.parametrize("kern", ["auto", "pairs8"])
 @pytest.mark.parametrize("geo", GEOMS, ids=lambda g: "x".join(map(str, g)))
-def test_radon_pair_parity(geo):
+def test_radon_pair_parity(geo, kern):
+    """R_h and R_h^* against the oracle on each geometry, with the plan's
+    default backprojector and with the mirror pairs on 32 x 64 tiles (8
+    pixels per thread; one 64-bin staging round per segment where ds/h is
+    large enough)."""
     n, N, M, h, ds = geo
-    print("radon parity", geo, flush=True)
+    print("radon parity", geo, kern, flush=True)
     g = geometry.Geometry(n, N, M, h, ds)
     rng = np.random.default_rng(n * 1000 + N)
     x = f32(rng.uniform(-1, 1, (n, n)))
     y = f32(rng.uniform(-1, 1, (N, M)))
-    plan = ct.Plan(n, N, M, h, ds)
+    plan = _plan_or_skip(n, N, M, h, ds, kern)
     fx = host(plan.radon_fwd(gpu(x)))
     by = host(plan.radon_adj(gpu(y)))
     assert rel(fx, radon.radon_fwd(g, x)) <= 1e-5
@@ -80,7 +96,7 @@ def test_radon_pair_parity(geo):
 
 @pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4), (100, 60, 150)],
                          ids=lambda g: "x".join(map(str, g)))
-def test_backprojection_with_and_without_mirror_pairs(geo, monkeypatch):
+def test_backprojection_with_and_without_mirror_pairs(geo):
     """The mirror-pair backprojector (theta and pi - theta from one bin
     coordinate; 4 or 8 pixels per thread) and the one-angle backprojector
     agree with the oracle and with each other to FP32 summation accuracy."""
@@ -90,15 +106,13 @@ def test_backprojection_with_and_without_mirror_pairs(geo, monkeypatch):
     rng = np.random.default_rng(n + N)
     y = f32(rng.uniform(-1, 1, (N, M)))
     ref = radon.radon_adj(g, y)
-    out = []
-    for flag, pix in (("1", "4"), ("1", "8"), ("0", "4")):
-        monkeypatch.setenv("CTPD_BP_PAIRS", flag)
-        monkeypatch.setenv("CTPD_BP_PIX", pix)
-        plan = ct.Plan(n, N, M)
-        out.append(host(plan.radon_adj(gpu(y))))
-        assert rel(out[-1], ref) <= 1e-5
-    assert rel(out[0], out[2]) <= 1e-6
-    assert rel(out[1], out[2]) <= 1e-6
+    out = {}
+    for kern in ("one_angle", "pairs4", "pairs8"):
+        plan = ct.Plan(n, N, M, bp_kernel=kern)
+        out[kern] = host(plan.radon_adj(gpu(y)))
+        assert rel(out[kern], ref) <= 1e-5
+    assert rel(out["pairs4"], out["one_angle"]) <= 1e-6
+    assert rel(out["pairs8"], out["one_angle"]) <= 1e-6
 
 
 def test_radon_deterministic_and_arbitrary_angles():
@@ -211,26 +225,25 @@ def test_pd_step_parity(size):
     assert rel(gu2, st2.u) <= 2e-5
 
 
-@pytest.mark.parametrize("slices,pairs", [(1, "1"), (3, "1"), (16, "1"), (16, "0"), (5, "0"), (12, "1"),
-                                          (4, "8")])
-def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
+@pytest.mark.parametrize("slices,kern", [(1, "pairs4"), (3, "pairs4"), (16, "pairs4"),
+                                         (16, "one_angle"), (5, "one_angle"), (12, "pairs4"),
+                                         (4, "pairs8"), (16, "pairs8"), (12, "pairs8")])
+def test_pd_step_parity_slices_and_backprojectors(slices, kern):
     """Two PDRQS1 steps with a fixed number of angle slices (their sum and
     epilogue formed in the FFT row pass, or by the combine pass for a count it
-    does not take) and either backprojector, against the oracle."""
+    does not take) and each backprojector, against the oracle."""
     n, N, M = 64, 90, 96
-    print("pd step slices", slices, "pairs", pairs, flush=True)
-    monkeypatch.setenv("CTPD_FORCE_SLICES", str(slices))
-    monkeypatch.setenv("CTPD_BP_PAIRS", "0" if pairs == "0" else "1")
-    monkeypatch.setenv("CTPD_BP_PIX", "8" if pairs == "8" else "4")
+    print("pd step slices", slices, kern, flush=True)
     w, g, u0, mask, bound = _small_metal_problem(n, N, M)
     s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
                    f32(w.start_norm), f32(w.start_precond))
     plan = ct.Plan(n, N, M)
-    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c,
+                   launch=ct.Launch(bp_slices=slices, bp_kernel=kern))
     lay = sv.layout()
     assert lay["bp_slices"] == slices
-    assert lay["bp_angles_per_position"] == (1 if pairs == "0" else 2)
-    assert lay["bp_pair_pixels"] == {"0": 0, "1": 4, "8": 8}[pairs]
+    assert lay["bp_angles_per_position"] == (1 if kern == "one_angle" else 2)
+    assert lay["bp_pair_pixels"] == {"one_angle": 0, "pairs4": 4, "pairs8": 8}[kern]
     rng = np.random.default_rng(12)
     u = f32(rng.uniform(0, 1, (n, n)))
     vb1 = f32(0.01 * rng.standard_normal((N, M)))
@@ -245,40 +258,94 @@ def test_pd_step_parity_slices_and_backprojectors(slices, pairs, monkeypatch):
 
 
 def test_tuning_is_cached_per_plan_and_batch_size():
-    """A second solver of the same batch size on a plan reuses the first one's
-    tuned backprojector and slice count; both match the oracle's step."""
+    """A second solver of the same batch size on a plan reuses the first
+    one's tuned choice without timing; a batch of another size is timed on
+    its own; each solver keeps its own choice (solvers created later change
+    neither its layout nor its results); all match the oracle's step."""
     n, N, M = 64, 90, 96
     print("tuning cache", flush=True)
     w, g, u0, mask, bound = _small_metal_problem(n, N, M)
     s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
                    f32(w.start_norm), f32(w.start_precond))
     plan = ct.Plan(n, N, M)
-    lays = []
-    for _ in range(2):
-        sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
-        lays.append(sv.layout())
+    args = (gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound))
+    first = ct.Solver(plan, *args, beta=s.beta, c=s.c)
+    t0 = first.tuning()
+    assert t0["source"] == "timed" and t0["timed"] > 1
+    lay0 = first.layout()
+    first.step(1)
+    ref1 = host(first.export()[0])
+    second = ct.Solver(plan, *args, beta=s.beta, c=s.c)
+    assert second.tuning()["source"] == "plan" and second.tuning()["timed"] == 0
+    assert second.layout() == lay0
+    batch = ct.SolverBatch(plan, [args[0], args[0]], w.alpha, [args[2], args[2]],
+                           [args[3], args[3]], beta=s.beta, c=s.c)
+    assert batch.tuning()["source"] == "timed"
+    # a solver whose choice is fixed otherwise, created after the first one
+    other = "one_angle" if lay0["bp_pair_pixels"] else "pairs4"
+    fixed = ct.Solver(plan, *args, beta=s.beta, c=s.c,
+                      launch=ct.Launch(bp_kernel=other, bp_slices=3))
+    assert fixed.tuning()["source"] == "fixed"
+    assert first.layout() == lay0
+    st = pdrq.step(s, pdrq.zero_state(s))
+    assert rel(ref1, st.u) <= 1e-5
+    # the first solver's kernels are unchanged: from the zero state again,
+    # its first iterate is bitwise the same
+    first.import_state(*(gpu(a) for a in (np.zeros((n, n)), np.zeros((N, M)),
+                                          np.zeros((2, n, n)))))
+    first.step(1)
+    assert np.array_equal(host(first.export()[0]), ref1)
+    for sv in (second, fixed):
         sv.step(1)
-        st = pdrq.step(s, pdrq.zero_state(s))
         assert rel(host(sv.export()[0]), st.u) <= 1e-5
-    assert lays[0] == lays[1]
 
 
-@pytest.mark.parametrize("hook", ["CTPD_NO_TV_FUSE", "CTPD_NO_DEFER"])
-def test_fusions_are_bitwise_neutral(hook, monkeypatch):
-    """The gradient-side update run inside R_h's launch, and the slice sum
-    formed in the FFT row pass, do the same arithmetic in the same order as
-    the separate kernels: the states after a few iterations are bitwise equal."""
+def test_tune_cache_file(tmp_path):
+    """The tuning result goes to the JSON file named by the params; a solver
+    on a new plan of the same geometry reads it instead of timing, and its
+    iterates are bitwise those of the first solver (same kernels, same slice
+    count, so the same FP32 summation order)."""
+    import json
+    n, N, M = 64, 90, 96
+    path = str(tmp_path / "tune.json")
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    args = (gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound))
+    a = ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0,
+                  launch=ct.Launch(tune_cache=path))
+    assert a.tuning()["source"] == "timed" and a.tuning()["saved"]
+    doc = json.load(open(path))
+    assert len(doc["entries"]) == 1
+    b = ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0,
+                  launch=ct.Launch(tune_cache=path))
+    assert b.tuning()["source"] == "file" and b.tuning()["timed"] == 0
+    assert b.layout() == a.layout()
+    assert b.tuning()["tv_blocks"] == a.tuning()["tv_blocks"]
+    a.step(7)
+    b.step(7)
+    for x, y in zip(a.export(), b.export()):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("hook", ["fuse_tv", "defer", "tv_blocks"])
+def test_fusions_are_bitwise_neutral(hook):
+    """The gradient-side update run inside R_h's launch (with any number of
+    extra workgroups), and the slice sum formed in the FFT row pass, do the
+    same arithmetic in the same order as the separate kernels: the states
+    after a few iterations are bitwise equal."""
     n, N, M = 64, 90, 96
     print("fusion neutral", hook, flush=True)
-    monkeypatch.setenv("CTPD_FORCE_SLICES", "4")
     w, g, u0, mask, bound = _small_metal_problem(n, N, M)
     s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
                    f32(w.start_norm), f32(w.start_precond))
     plan = ct.Plan(n, N, M)
     out = []
-    for flag in ("0", "1"):
-        monkeypatch.setenv(hook, flag)
-        sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    variants = ({"tv_blocks": 7}, {"tv_blocks": 64}) if hook == "tv_blocks" else \
+        ({hook: False}, {hook: True})
+    for var in variants:
+        la = ct.Launch(bp_slices=4, bp_kernel="pairs4", tv_blocks=var.get("tv_blocks", 64),
+                       **{k: v for k, v in var.items() if k != "tv_blocks"})
+        sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c,
+                       launch=la)
         sv.step(6)
         out.append([host(t) for t in sv.export()])
     for a, b in zip(*out):

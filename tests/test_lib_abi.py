@@ -86,15 +86,67 @@ def test_params_default(lib):
     lib.ct_params_default(ctypes.byref(p))
     assert p.sigma == 1.0 and abs(p.tau - 8 ** -0.5) < 1e-15 and p.eps == 0.3
     assert p.c_safety == pytest.approx(1.1) and p.power_iters == 30 and p.c == 0.0
+    # launch choices: all left to the tuning, no cache file
+    assert p.bp_slices == 0 and p.bp_kernel == -1 and p.tv_blocks == 0 and p.options == 0
+    assert p.tune_cache is None
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the ABI structs have the C layout (x86-64 SysV)."""
+def test_plan_options_validation(lib):
+    """Plan options are checked on the host: unknown values are invalid, and
+    the mirror-pair backprojector needs angles that pair as theta, pi - theta
+    (one angle has no partner)."""
     from paper_1810_03275_amd import _lib
-    assert ctypes.sizeof(_lib.CtGeom) == 32
-    assert _lib.CtGeom.h.offset == 16 and _lib.CtGeom.ds.offset == 24
-    assert ctypes.sizeof(_lib.CtProblem) == 40 and _lib.CtProblem.lambda_.offset == 32
-    assert ctypes.sizeof(_lib.CtParams) == 80 and _lib.CtParams.start_norm.offset == 64
+    g = _lib.CtGeom(64, 90, 96, 1.0, 1.0)
+    steps = ctypes.c_int64()
+    for bad in (_lib.CtPlanOpts(5, 0), _lib.CtPlanOpts(-1, 3)):
+        assert lib.ct_plan_check_ex(ctypes.byref(g), None, ctypes.byref(bad),
+                                    ctypes.byref(steps)) == -1
+    ok = _lib.CtPlanOpts(8, 2)
+    assert lib.ct_plan_check_ex(ctypes.byref(g), None, ctypes.byref(ok), ctypes.byref(steps)) == 0
+    one = _lib.CtGeom(64, 1, 96, 1.0, 1.0)
+    pairs = _lib.CtPlanOpts(4, 0)
+    assert lib.ct_plan_check_ex(ctypes.byref(one), None, ctypes.byref(pairs),
+                                ctypes.byref(steps)) == -2
+    assert b"pair" in lib.ct_last_error()
+    walk1 = _lib.CtPlanOpts(-1, 1)
+    assert lib.ct_plan_check_ex(ctypes.byref(g), None, ctypes.byref(walk1),
+                                ctypes.byref(steps)) == 0
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the C layout: a probe built
+    from the header by the host C compiler prints every size and offset."""
+    import shutil
+    import subprocess
+    from paper_1810_03275_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"ct_geom": _lib.CtGeom, "ct_problem": _lib.CtProblem,
+               "ct_params": _lib.CtParams, "ct_plan_opts": _lib.CtPlanOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ctpd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname   # a Python keyword
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, what, val = line.split()
+        py = structs[cname]
+        got = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), (cname, what, got, val)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())
 
 
 def test_package_import_requires_library(monkeypatch, tmp_path):

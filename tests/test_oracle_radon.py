@@ -200,3 +200,100 @@ def test_reversed_weights_fail_ellipse_pin(monkeypatch):
     monkeypatch.setattr(radon, "_floor_and_weight", reversed_weights)
     bad = np.linalg.norm(radon.radon_fwd(g, img) - ref) / np.linalg.norm(ref)
     assert bad > 5 * good
+
+
+# ---------------------------------------------------------------------------
+# The one-by-one evaluators behind the full-size GPU spot checks.  They are
+# pinned here against the whole-array projector pair, which the brute-force
+# matrix and the adjoint identity pin above (§3.1: R_h is the transpose of
+# R_h^*), at every pixel and bin of small geometries, explicit angles
+# included.
+
+SAMPLED_GEOMS = [
+    geometry.Geometry(10, 8, 16),
+    geometry.Geometry(9, 7, 13, h=1.0, ds=1.3),                         # odd n and M, ds != h
+    geometry.Geometry(12, 5, 20, thetas=(0.3, 2.9, -1.1, 4.0, 1.5707963267948966)),
+]
+
+
+def _all_pixels(g):
+    return [(j, i) for j in range(g.n) for i in range(g.n)]
+
+
+def _all_bins(g):
+    return [(l, k) for l in range(g.n_angles) for k in range(g.n_bins)]
+
+
+def _adj_at_pin(g, adj_at, seed=31):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((g.n_angles, g.n_bins))
+    ref = radon.radon_adj(g, v).ravel()
+    got = adj_at(g, v, _all_pixels(g))
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def _fwd_at_pin(g, fwd_at, seed=32):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((g.n, g.n))
+    ref = radon.radon_fwd(g, u).ravel()
+    got = fwd_at(g, u, _all_bins(g))
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("g", SAMPLED_GEOMS)
+def test_sampled_evaluators_match_whole_arrays(g):
+    """radon_adj_at / radon_fwd_at equal the whole-array R_h^* / R_h at every
+    pixel and every bin (bins are visited angle by angle, then in a shuffled
+    order so that the per-angle cache is refilled)."""
+    assert _adj_at_pin(g, radon.radon_adj_at) <= 1e-13
+    assert _fwd_at_pin(g, radon.radon_fwd_at) <= 1e-13
+    rng = np.random.default_rng(33)
+    u = rng.standard_normal((g.n, g.n))
+    bins = _all_bins(g)
+    order = rng.permutation(len(bins))
+    got = radon.radon_fwd_at(g, u, [bins[q] for q in order])
+    assert np.max(np.abs(got - radon.radon_fwd(g, u).ravel()[order])) <= 1e-12
+
+
+def _fwd_at_offbyone(g, u, bins):
+    # planted mistake: the alpha term taken from the strip of bin k itself
+    out = np.zeros(len(bins))
+    for q, (l, k) in enumerate(bins):
+        t = g.bin_coordinate(l)
+        kk = np.floor(t)
+        a = t - kk
+        out[q] = np.sum(((1.0 - a) * u)[kk == k]) + np.sum((a * u)[kk == k])
+    return out
+
+
+def _adj_at_swapped(g, v, pixels):
+    # planted mistake: the weights of the two bins exchanged
+    out = np.zeros(len(pixels))
+    for q, (j, i) in enumerate(pixels):
+        for l in range(g.n_angles):
+            t = g.bin_coordinate_scalar(i, j, l)
+            k = math.floor(t)
+            a = t - k
+            if 0 <= k < g.n_bins:
+                out[q] += a * v[l, k]
+            if 0 <= k + 1 < g.n_bins:
+                out[q] += (1.0 - a) * v[l, k + 1]
+    return out
+
+
+def _default_angles(fn):
+    # planted mistake: the explicit angles ignored (theta_l = pi l / N used)
+    import dataclasses
+    return lambda g, x, idx: fn(dataclasses.replace(g, thetas=None), x, idx)
+
+
+@pytest.mark.parametrize("mutant,kind", [
+    (_fwd_at_offbyone, "fwd"), (_adj_at_swapped, "adj"),
+    (_default_angles(radon.radon_fwd_at), "fwd"), (_default_angles(radon.radon_adj_at), "adj"),
+])
+def test_sampled_evaluator_pin_catches_planted_mistakes(mutant, kind):
+    """Each planted mistake in a sampled evaluator fails the pin above on the
+    geometry with explicit angles."""
+    g = SAMPLED_GEOMS[2]
+    err = _fwd_at_pin(g, mutant) if kind == "fwd" else _adj_at_pin(g, mutant)
+    assert err > 1e-2
