@@ -170,6 +170,23 @@ int ct_tv_project(int32_t n, const float *q, double radius, float *w, ct_stream 
 int ct_power_norm(const ct_plan *p, int32_t iters, const float *x0, double *out,
                   ct_stream s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * power iteration as ct_power_norm, with its work image, sinogram and FP64
+ * reduction partials in a 64 MiB array that the library holds on each device
+ * it runs on (for the life of the process) instead of the plan's scratch.  It
+ * calls no allocating routine.  Its backprojections run with one angle
+ * slice, so the estimate agrees with ct_power_norm's to FP32 rounding.
+ * Limit: 4 (n^2 + N M) bytes plus 12 KiB of partials must fit the array
+ * (n^2 + N M up to about 16.7 million; CT_E_INVALID beyond).  x0 (device
+ * [n][n], not modified) or NULL for ct_power_norm's default start.  Calls
+ * on one device share the array: calls that overlap in time on one device
+ * (other host threads, other streams) race and must be serialized by the
+ * caller.  Synchronizes s.  Errors: CT_E_INVALID, CT_E_UNSUPPORTED,
+ * CT_E_DEVICE. */
+int ct_power_norm_noalloc(const ct_plan *p, int32_t iters, const float *x0, double *out,
+                          ct_stream s);
+
 /* ------------------------------------------------------------------------ */
 /* Solver: problem setup and Algorithm PDRQS1                               */
 
@@ -388,13 +405,15 @@ int ct_solver_set_admm(ct_solver *sv, int32_t cg_steps, double mu);
  * iteration).  Asynchronous; k >= 0. */
 int ct_pd_step(ct_solver *sv, int32_t k, ct_stream s);
 
-/* Same iterations as ct_pd_step (k >= 1), launched one by one with HIP events
- * on s around each phase; ms_out receives the average duration per iteration
- * in milliseconds of [0] R_h^* with the u_tmp epilogue, [1] the preconditioner
- * update u + M^{-1} u_tmp (§4.3.1), [2] R_h with the sinogram-side update,
- * [3] the gradient-side update, [4] their sum.  Synchronizes s after every
- * iteration, so it measures kernels, not throughput.  The state advances as
- * with ct_pd_step. */
+/* Same iterations as ct_pd_step (k >= 1), with the same launches, launched
+ * one by one with HIP events on s around each phase; ms_out receives the
+ * average duration per iteration in milliseconds of [0] R_h^* with the u_tmp
+ * epilogue, [1] the preconditioner update u + M^{-1} u_tmp (§4.3.1), [2] R_h
+ * with the sinogram-side update (and the gradient-side update when that runs
+ * in R_h's launch), [3] the gradient-side update when it is a launch of its
+ * own (else about 0), [4] their sum.  Synchronizes s after every iteration,
+ * so it measures kernels, not throughput.  The state advances as with
+ * ct_pd_step. */
 int ct_pd_step_timed(ct_solver *sv, int32_t k, double ms_out[5], ct_stream s);
 
 /* Copy the state out: u [n][n], vb1 [N][M], vb2 [2][n][n] (any may be NULL). */

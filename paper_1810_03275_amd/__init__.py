@@ -304,6 +304,16 @@ class Launch:
         p.tune_cache = self.tune_cache.encode() if self.tune_cache else None
 
 
+def power_norm_noalloc(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -> float:
+    """power_norm without any device allocation (scratch in the library's
+    static device array; see ct_power_norm_noalloc); synchronizes."""
+    out = ctypes.c_double()
+    xp = _dev(x0, (plan.n, plan.n), "x0") if x0 is not None else None
+    _check(_L.ct_power_norm_noalloc(plan.handle, iters, xp, ctypes.byref(out), _stream()),
+           "ct_power_norm_noalloc")
+    return out.value
+
+
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
             start_norm, start_precond, n, nonneg=False, method="pdrqs1", precond="invnorm",
             launch=None):

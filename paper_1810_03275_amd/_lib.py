@@ -79,6 +79,8 @@ SIGNATURES = {
                                c_void_p, c_void_p, c_void_p]),
     "ct_tv_project": (c_int32, [c_int32, c_void_p, c_double, c_void_p, c_void_p]),
     "ct_power_norm": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_double), c_void_p]),
+    "ct_power_norm_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_double),
+                                        c_void_p]),
     "ct_params_default": (None, [POINTER(CtParams)]),
     "ct_solver_create": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                    POINTER(c_void_p)]),

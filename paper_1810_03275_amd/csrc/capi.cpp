@@ -189,8 +189,9 @@ struct ct_solver {
   // Two PDRQS1 iterations captured as a HIP graph, one per ping-pong parity of
   // (u, u_next); captured on a private stream, replayed on the caller's stream.
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  float *gexec_u[2] = {nullptr, nullptr};
+  // index parity + 2 * (the second iteration keeps y1, w and A u for a record)
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  float *gexec_u[4] = {nullptr, nullptr, nullptr, nullptr};
   bool use_graph = true;
 };
 
@@ -513,6 +514,7 @@ static int solver_alloc(ct_solver *sv) {
   CT_TRY_HIP(hipMalloc(&sv->vb1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->s1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->target, sizeof(float) * NM));
+  // one sinogram: the set-up's projections of a single image
   CT_TRY_HIP(hipMalloc(&sv->rraw, sizeof(float) * (size_t)sv->N * sv->M));
   CT_TRY_HIP(hipMalloc(&sv->y1, sizeof(float) * NM));
   CT_TRY_HIP(hipMalloc(&sv->r, sizeof(float) * NM));
@@ -681,7 +683,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   ep.fit = sv->fit;
   ep.aux = sv->fit_aux;
   // the gradient-side update reads u_new only: it runs in the same launch
-  // (extra workgroups) unless the phases are being timed one by one
+  // (extra workgroups), also when the phases are timed one by one
   TvArgs tv;
   tv.n = sv->n;
   tv.inv_h = inv_h;
@@ -694,7 +696,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   tv.mode = mode;
   tv.q2out = q2out;
   tv.ubar = sv->ubar;
-  tv.blocks = (ev || !sv->fuse_tv) ? 0 : sv->tv_blocks;
+  tv.blocks = sv->fuse_tv ? sv->tv_blocks : 0;
   bool fused = false;
   CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb, &tv, &fused));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
@@ -937,7 +939,9 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   }
   if (!tv_fixed) {
     // R_h of the zero image with the gradient-side update of the zero state
-    // (u_new = 0 leaves vb2 = s2 = 0, and bar u = 0): the state is unchanged
+    // (u_new = 0 leaves vb2 = s2 = 0, and bar u = 0): the state is unchanged.
+    // The raw projections of the nb problems go to y1 ([nb][N][M]; it holds
+    // nothing before the first iteration)
     const size_t nn = (size_t)sv->n * sv->n * sv->nb;
     CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
     std::vector<int> blocks;
@@ -964,7 +968,7 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
       tv.blocks = blocks[c];
       auto run = [&]() -> int {
         bool fused = false;
-        CT_TRY(launch_radon_fwd(p, sv->u_next, sv->rraw, st, nullptr, sv->nb, &tv, &fused));
+        CT_TRY(launch_radon_fwd(p, sv->u_next, sv->y1, st, nullptr, sv->nb, &tv, &fused));
         if (!fused)
           CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2,
                                   sv->s2, sv->w, 0, st, sv->nb, nullptr, sv->ubar));
@@ -1259,10 +1263,11 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   return CT_OK;
 }
 
-// Capture two mode-0 iterations of every solver in svs (all at the same
-// ping-pong parity) as one HIP graph on a private stream; the pointers are
-// back in place after them.
-static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap,
+// Capture two iterations of every solver in svs (all at the same ping-pong
+// parity) as one HIP graph on a private stream, the second in mode last_mode
+// (0, or 2 to keep y1, w and A u for a record); the pointers are back in
+// place after them.
+static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap, int last_mode,
                         hipGraphExec_t *out) {
   hipGraph_t graph = nullptr;
   CT_TRY_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -1270,7 +1275,7 @@ static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap,
   for (int it = 0; it < 2 && rc == CT_OK; ++it)
     for (int q = 0; q < count && rc == CT_OK; ++q) {
       const int64_t it0 = svs[q]->iters;
-      rc = solver_iter(svs[q], 0, cap);
+      rc = solver_iter(svs[q], it == 1 ? last_mode : 0, cap);
       svs[q]->iters = it0;  // nothing ran
     }
   hipError_t e = hipStreamEndCapture(cap, &graph);
@@ -1286,30 +1291,45 @@ static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap,
 }
 
 
-// k iterations of every solver in svs (same iteration count and parity):
-// all but the last in graph-replayed pairs, the last one eager in mode 2 so
-// that y1, w and A u are there for a record.  graphs[2] and cap are the
-// caller's cache (captured on first use per parity).
+// k iterations of every solver in svs (same iteration count and parity).
+// With k >= 3 they replay from HIP graphs of two iterations each: an odd k
+// first runs one iteration eagerly, the last pair is the graph whose second
+// iteration keeps y1, w and A u for a record, the others the plain one.
+// Smaller k run eagerly, the last in mode 2.  graphs[4] and cap are the
+// caller's cache (captured on first use per parity and kind).
 static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, hipStream_t *cap,
-                      hipGraphExec_t graphs[2], float *graph_u[2]) {
+                      hipGraphExec_t graphs[4], float *graph_u[4]) {
   int left = k;
   bool graphs_ok = true;
   for (int q = 0; q < count; ++q) graphs_ok = graphs_ok && svs[q]->use_graph;
   if (graphs_ok && left >= 3) {
+    if (left & 1) {
+      for (int q = 0; q < count; ++q) CT_TRY(solver_iter(svs[q], 0, st));
+      left -= 1;
+    }
     const int parity = (svs[0]->u < svs[0]->u_next) ? 0 : 1;
-    if (!graphs[parity]) {
-      if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
-      CT_TRY(capture_pair(svs, count, *cap, &graphs[parity]));
-      graph_u[parity] = svs[0]->u;
-    }
-    if (graph_u[parity] != svs[0]->u) {
-      set_error("ct_pd_step: graph parity mismatch");
-      return CT_E_STATE;
-    }
-    const int pairs = (left - 1) / 2;
-    for (int q = 0; q < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(graphs[parity], st));
-    for (int q = 0; q < count; ++q) svs[q]->iters += 2 * pairs;
-    left -= 2 * pairs;
+    auto graph = [&](int last_mode, hipGraphExec_t *g) -> int {
+      const int idx = parity + (last_mode == 2 ? 2 : 0);
+      if (!graphs[idx]) {
+        if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+        CT_TRY(capture_pair(svs, count, *cap, last_mode, &graphs[idx]));
+        graph_u[idx] = svs[0]->u;
+      }
+      if (graph_u[idx] != svs[0]->u) {
+        set_error("ct_pd_step: graph parity mismatch");
+        return CT_E_STATE;
+      }
+      *g = graphs[idx];
+      return CT_OK;
+    };
+    const int pairs = left / 2;
+    hipGraphExec_t g0 = nullptr, g2 = nullptr;
+    if (pairs > 1) CT_TRY(graph(0, &g0));
+    CT_TRY(graph(2, &g2));
+    for (int q = 0; q + 1 < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(g0, st));
+    CT_TRY_HIP(hipGraphLaunch(g2, st));
+    for (int q = 0; q < count; ++q) svs[q]->iters += left;
+    left = 0;
   }
   for (int it = 0; it < left; ++it)
     for (int q = 0; q < count; ++q) CT_TRY(solver_iter(svs[q], it == left - 1 ? 2 : 0, st));
@@ -1533,7 +1553,7 @@ int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s)
     set_error("ct_solver_set_fit: the data-term variants are for PDRQS1");
     return CT_E_UNSUPPORTED;
   }
-  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1]) {
+  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1] || sv->gexec[2] || sv->gexec[3]) {
     set_error("ct_solver_set_fit: set the data term before the first iteration");
     return CT_E_STATE;
   }
@@ -1571,7 +1591,7 @@ int ct_solver_set_admm(ct_solver *sv, int32_t cg_steps, double mu) {
     set_error("ct_solver_set_admm: not an ADMM solver");
     return CT_E_UNSUPPORTED;
   }
-  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1]) {
+  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1] || sv->gexec[2] || sv->gexec[3]) {
     set_error("ct_solver_set_admm: set the options before the first iteration");
     return CT_E_STATE;
   }
@@ -1736,8 +1756,8 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
 struct ct_group {
   std::vector<ct_solver *> svs;
   hipStream_t cap = nullptr;
-  hipGraphExec_t graphs[2] = {nullptr, nullptr};
-  float *graph_u[2] = {nullptr, nullptr};
+  hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
+  float *graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
   ~ct_group() {
     for (auto g : graphs)
       if (g) (void)hipGraphExecDestroy(g);

@@ -33,12 +33,27 @@ def oracle_problem(g, u0, mask, bound, lam):
     return pdrq.Problem(g, u0, mask, bound, lam)
 
 
-def random_state(n: int, N: int, M: int, seed: int, vb2_scale: float):
+def random_state(n: int, N: int, M: int, seed: int, vb2_scale: float, u_scale: float = 1.0):
     """A seeded iterate (u, vb1, vb2) for one-step parity checks, float64
-    holding float32-representable values: u ~ U[0, 1), vb1 ~ 0.01 N(0, 1),
-    vb2 ~ vb2_scale N(0, 1) (callers pass lambda~/tau, the dual ball's radius)."""
+    holding float32-representable values: u ~ u_scale U[0, 1), vb1 ~ 0.01 N(0, 1),
+    vb2 ~ vb2_scale N(0, 1) (callers pass lambda~/tau, the dual ball's radius).
+    A small u_scale keeps the projection of u below the bounds on the metal
+    trace, so that its constraints are active."""
     rng = np.random.default_rng(seed)
-    u = f32(rng.uniform(0.0, 1.0, (n, n)))
+    u = f32(u_scale * rng.uniform(0.0, 1.0, (n, n)))
     vb1 = f32(0.01 * rng.standard_normal((N, M)))
     vb2 = f32(vb2_scale * rng.standard_normal((2, n, n)))
     return u, vb1, vb2
+
+
+def random_problem(N: int, M: int, seed: int, trace_fraction: float = 0.03):
+    """Seeded problem data for one-step checks at sizes where projecting a
+    phantom on the host would take too long: u0 = 50 |z| (the scale of a
+    projection of unit densities over tens of pixels), a metal-trace mask of
+    about trace_fraction of the bins, and bounds C = 0.9 u0 on it.  Returns
+    (u0, mask, bound) in float64 holding float32-representable values."""
+    rng = np.random.default_rng(seed)
+    u0 = f32(50.0 * np.abs(rng.standard_normal((N, M))))
+    mask = rng.uniform(0.0, 1.0, (N, M)) < trace_fraction
+    bound = f32(np.where(mask, 0.9 * u0, 0.0))
+    return u0, mask, bound

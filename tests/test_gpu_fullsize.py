@@ -1,0 +1,255 @@
+"""Full-size parity of Algorithm PDRQS1 (§4.4) through the C ABI.
+
+* 512^2 x 720 x 768 with 2 metal discs (the benchmark workload): one step
+  from a seeded iterate against the oracle's step, element by element, and
+  the FP64 record of that state (its metal-trace terms included); 500
+  iterations from the zero state against the oracle's stored run
+  (tests/golden/c2_pdrqs1_500.npz).
+* 64^2 with metal: the record of one step from a shared state, every entry.
+* 2048^2 x 2880 x 3072: one step from a seeded iterate on seeded problem data
+  against the oracle's stored sampled entries (tests/golden/c5_step_sampled.npz).
+* The five image sizes of the uneven batch (256 ... 1024, N = 1.4 n,
+  M = 1.5 n): one batched step per size against the oracle's stored sampled
+  entries (tests/golden/c3_step_sampled.npz), and the batch bitwise equal to
+  single solvers with the same launch choices.
+
+Stored values are written by tests/golden/make_golden.py, which calls only
+the oracle.  Tolerances (relative L2): 1e-5 per step and for the record of a
+shared state, 1e-4 for the image after 500 iterations.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gap as ogap
+from oracle import pdrq
+
+from oracle_inputs import build, f32, random_problem, random_state
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_golden as mg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ct = pytest.importorskip("paper_1810_03275_amd")
+
+DEV = torch.device("cuda")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def golden(name):
+    path = os.path.join(HERE, "golden", name)
+    assert os.path.exists(path), f"missing stored oracle values {path}"
+    return np.load(path)
+
+
+def dual_scale(lam, beta):
+    """lambda~/tau as the oracle's set-up forms it (the seeded vb2's scale)."""
+    return (lam / beta ** 2) / pdrq.Params().tau
+
+
+def check_record(got, ref, tol):
+    """The six record entries (P, G*, gap, rho_D, V, du) of a shared state.
+    gap = P + G* is compared on the scale of |P| + |G*| (the two may nearly
+    cancel); V is compared absolutely when the reference is zero."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    for q in (0, 1, 3, 5):
+        assert abs(got[q] - ref[q]) <= tol * abs(ref[q]), (q, got[q], ref[q])
+    assert abs(got[2] - ref[2]) <= tol * (abs(ref[0]) + abs(ref[1]))
+    assert abs(got[4] - ref[4]) <= tol * max(abs(ref[4]), 1e-6 * abs(ref[0]) ** 0.5)
+
+
+def one_step_vs_oracle(g, u0, mask, bound, lam, beta, c, seed, u_scale, launch=None):
+    """GPU and oracle advance the same seeded iterate by one PDRQS1 step;
+    returns (gpu state, oracle state, gpu record, oracle record, oracle setup,
+    oracle y1)."""
+    n, N, M = g.n, g.n_angles, g.n_bins
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, lam), pdrq.Params(), beta=beta, c=c)
+    u, vb1, vb2 = random_state(n, N, M, seed, s.lam_t / s.params.tau, u_scale)
+    plan = ct.Plan(n, N, M)
+    sv = ct.Solver(plan, gpu(u0), lam, ct.pack_mask(mask) if mask.any() else None,
+                   gpu(bound) if mask.any() else None, beta=beta, c=c, launch=launch)
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(1)
+    got = [host(t) for t in sv.export()]
+    rec_gpu = sv.gap()
+    st = pdrq.state_from(s, u, vb1, vb2)
+    new, y1, w = pdrq.step(s, st, return_dual=True)
+    rec_ref = ogap.record(s, new.u, y1, w, u)
+    return got, new, rec_gpu, rec_ref, s, y1
+
+
+def test_gap_record_metal_small():
+    """64^2 with two metal discs: from a shared seeded iterate, one step and
+    the FP64 record on both sides; every entry agrees to 1e-5, and the
+    record's metal-trace term (the sum over D0 of y1 C~ in G*) is a sizeable
+    part of G* (so that the D0 branch of the record is exercised)."""
+    w = synth.workload("C2", n=64, n_angles=90, n_bins=96)
+    g, u0, mask, bound = build(w)
+    assert mask.any()
+    s0 = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                    f32(w.start_norm), f32(w.start_precond))
+    got, new, rec_gpu, rec_ref, s, y1 = one_step_vs_oracle(g, u0, mask, bound, w.alpha,
+                                                           s0.beta, s0.c, 6401, mg.STEP_U_SCALE)
+    print("metal small: rel u %.2e vb1 %.2e vb2 %.2e" % tuple(
+        rel(a, b) for a, b in zip(got, (new.u, new.vb1, new.vb2))), flush=True)
+    print("records", rec_gpu, rec_ref, flush=True)
+    for a, b in zip(got, (new.u, new.vb1, new.vb2)):
+        assert rel(a, b) <= 1e-5
+    d0_term = float(np.sum((y1 * s.cb)[mask]))
+    assert abs(d0_term) > 1e-3 * abs(rec_ref[1])
+    check_record(rec_gpu, rec_ref, 1e-5)
+
+
+def test_c2_one_step_and_record():
+    """512^2 x 720 x 768 with 2 metal discs, the benchmark's launch
+    configuration (tuned): one step from a seeded iterate matches the
+    oracle's step in u, vb1 and vb2 (1e-5), and the FP64 records agree (1e-5)."""
+    print("c2 one step", flush=True)
+    w = synth.workload("C2")
+    g, u0, mask, bound = build(w)
+    got, new, rec_gpu, rec_ref, s, y1 = one_step_vs_oracle(g, u0, mask, bound, w.alpha,
+                                                           600.0, 1.25, 5121, mg.STEP_U_SCALE)
+    print("c2 one step: rel u %.2e vb1 %.2e vb2 %.2e" % tuple(
+        rel(a, b) for a, b in zip(got, (new.u, new.vb1, new.vb2))), flush=True)
+    print("records", rec_gpu, rec_ref, flush=True)
+    d0_term = float(np.sum((y1 * s.cb)[mask]))
+    assert abs(d0_term) > 1e-3 * abs(rec_ref[1])
+    for a, b in zip(got, (new.u, new.vb1, new.vb2)):
+        assert rel(a, b) <= 1e-5
+    check_record(rec_gpu, rec_ref, 1e-5)
+
+
+def test_c2_500_iterations():
+    """The benchmark workload solved as the benchmark solves it (set-up by
+    power iterations from the workload's start images, tuned launch, graph
+    replay): beta and c match the oracle's (1e-5); after 500 iterations the
+    image matches the oracle's stored run (1e-4), and the records after every
+    100th iteration agree in P, G* and the gap (1e-4; rho_D, V and du are
+    residuals of the iterate itself, so a 1e-5 difference of iterates makes
+    them differ by more: 5e-2)."""
+    print("c2 500 iterations", flush=True)
+    z = golden("c2_pdrqs1_500.npz")
+    w = synth.workload("C2")
+    g, u0, mask, bound = build(w)
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound),
+                   start_norm=gpu(f32(w.start_norm)), start_precond=gpu(f32(w.start_precond)))
+    info = sv.info()
+    assert abs(info["beta"] - float(z["beta"])) <= 1e-5 * float(z["beta"])
+    assert abs(info["c"] - float(z["c"])) <= 1e-5 * float(z["c"])
+    recs = []
+    for _ in range(5):
+        sv.step(100)
+        recs.append(sv.gap())
+    assert rel(host(sv.export()[0]), z["u"]) <= 1e-4
+    ref = z["records"]
+    for r, q in zip(recs, ref):
+        assert abs(r[0] - q[0]) <= 1e-4 * abs(q[0])
+        assert abs(r[1] - q[1]) <= 1e-4 * abs(q[1])
+        assert abs(r[2] - q[2]) <= 1e-4 * (abs(q[0]) + abs(q[1]))
+        assert r[3] == pytest.approx(q[3], rel=5e-2)
+        assert r[4] == pytest.approx(q[4], rel=5e-2, abs=1e-6 * abs(q[0]) ** 0.5)
+        assert r[5] == pytest.approx(q[5], rel=5e-2)
+
+
+def test_c5_one_step_sampled():
+    """2048^2 x 2880 x 3072: one step from a seeded iterate on seeded problem
+    data (the inputs the stored oracle step used), in the launch
+    configuration the benchmark's largest workload uses; the new u, vb1 and
+    vb2 at the stored sampled pixels and bins match (1e-5), and so do the
+    three arrays' norms."""
+    print("c5 one step", flush=True)
+    z = golden("c5_step_sampled.npz")
+    n, N, M = 2048, 2880, 3072
+    u0, mask, bound = random_problem(N, M, mg.C5_PROBLEM_SEED)
+    beta, c, lam = float(z["beta"]), float(z["c"]), float(z["lam"])
+    u, vb1, vb2 = random_state(n, N, M, mg.C5_STATE_SEED, dual_scale(lam, beta),
+                               mg.STEP_U_SCALE)
+    plan = ct.Plan(n, N, M)
+    sv = ct.Solver(plan, gpu(u0), lam, ct.pack_mask(mask), gpu(bound), beta=beta, c=c)
+    del u0, bound
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    del u, vb1, vb2
+    sv.step(1)
+    gu, g1, g2 = sv.export()
+    pix, bins = z["pix"], z["bins"]
+    pj, pi = torch.as_tensor(pix[:, 0], device=DEV), torch.as_tensor(pix[:, 1], device=DEV)
+    bl, bk = torch.as_tensor(bins[:, 0], device=DEV), torch.as_tensor(bins[:, 1], device=DEV)
+    assert rel(host(gu[pj, pi]), z["u"]) <= 1e-5
+    assert rel(host(g1[bl, bk]), z["vb1"]) <= 1e-5
+    assert rel(host(g2[0][pj, pi]), z["vb2_0"]) <= 1e-5
+    assert rel(host(g2[1][pj, pi]), z["vb2_1"]) <= 1e-5
+    norms = [float(torch.linalg.vector_norm(t.double())) for t in (gu, g1, g2)]
+    assert rel(norms, z["norms"]) <= 1e-5
+
+
+def _launch_of(sv):
+    """The launch choices a solver ended up with, as fixed params."""
+    lay, tun = sv.layout(), sv.tuning()
+    kern = {0: "one_angle", 4: "pairs4", 8: "pairs8"}[lay["bp_pair_pixels"]]
+    tvb = tun["tv_blocks"]
+    return ct.Launch(bp_slices=lay["bp_slices"], bp_kernel=kern, tv_blocks=tvb or None,
+                     fuse_tv=tvb > 0)
+
+
+@pytest.mark.parametrize("n", mg.C3_SIZES)
+def test_c3_shape_batched_step(n):
+    """Each image size of the uneven batch: two problems (seeded data and
+    iterates) advanced as one batch solver with tuned launch choices, one
+    step; each problem's new state at the stored sampled pixels and bins
+    matches the oracle (1e-5), and single solvers with the batch's launch
+    choices give bitwise the batch's state."""
+    print("c3 shape", n, flush=True)
+    z = golden("c3_step_sampled.npz")
+    n, N, M = mg.c3_geometry(n)
+    beta, c, lam = mg.c3_beta(n), mg.C3_C, mg.C3_LAMBDA
+    probs, states = [], []
+    for b in range(2):
+        ps, ss, _ = mg.c3_seeds(n, b)
+        probs.append(random_problem(N, M, ps))
+        states.append(random_state(n, N, M, ss, dual_scale(lam, beta), mg.STEP_U_SCALE))
+    plan = ct.Plan(n, N, M)
+    sinos = [gpu(p[0]) for p in probs]
+    masks = [ct.pack_mask(p[1]) for p in probs]
+    bounds = [gpu(p[2]) for p in probs]
+    sb = ct.SolverBatch(plan, sinos, lam, masks, bounds, beta=beta, c=c)
+    stack = [torch.stack([gpu(states[b][q]) for b in range(2)]) for q in range(3)]
+    sb.import_state(*stack)
+    sb.step(1)
+    bu, b1, b2 = sb.export()
+    launch = _launch_of(sb)
+    for b in range(2):
+        pre = f"n{n}_b{b}_"
+        pix, bins = z[pre + "pix"], z[pre + "bins"]
+        pj, pi = torch.as_tensor(pix[:, 0], device=DEV), torch.as_tensor(pix[:, 1], device=DEV)
+        bl, bk = torch.as_tensor(bins[:, 0], device=DEV), torch.as_tensor(bins[:, 1], device=DEV)
+        assert rel(host(bu[b][pj, pi]), z[pre + "u"]) <= 1e-5
+        assert rel(host(b1[b][bl, bk]), z[pre + "vb1"]) <= 1e-5
+        assert rel(host(b2[b][0][pj, pi]), z[pre + "vb2_0"]) <= 1e-5
+        assert rel(host(b2[b][1][pj, pi]), z[pre + "vb2_1"]) <= 1e-5
+        sv = ct.Solver(plan, sinos[b], lam, masks[b], bounds[b], beta=beta, c=c, launch=launch)
+        sv.import_state(*(gpu(a) for a in states[b]))
+        sv.step(1)
+        for x, y in zip(sv.export(), (bu[b], b1[b], b2[b])):
+            assert torch.equal(x, y)

@@ -284,7 +284,7 @@ def test_tuning_is_cached_per_plan_and_batch_size():
     # a solver whose choice is fixed otherwise, created after the first one
     other = "one_angle" if lay0["bp_pair_pixels"] else "pairs4"
     fixed = ct.Solver(plan, *args, beta=s.beta, c=s.c,
-                      launch=ct.Launch(bp_kernel=other, bp_slices=3))
+                      launch=ct.Launch(bp_kernel=other, bp_slices=3, tv_blocks=64))
     assert fixed.tuning()["source"] == "fixed"
     assert first.layout() == lay0
     st = pdrq.step(s, pdrq.zero_state(s))

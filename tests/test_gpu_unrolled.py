@@ -148,3 +148,85 @@ def test_unrolled_lambda_fd_on_gpu():
     d = 5e-2 * lam
     fd = (loss(lam + d) - loss(lam - d)) / (2 * d)
     assert an == pytest.approx(fd, rel=5e-2)
+
+
+@pytest.fixture(scope="module")
+def oracle_128():
+    """A 128^2 x 179 x 192 problem with metal (the uneven batch's shape rule
+    N = 1.4 n, M = 1.5 n), the GPU's beta and c, and the oracle's reverse
+    mode of 6 unrolled iterations (MSE loss against the phantom)."""
+    w, g, u0, mask, bound, truth = _problem(11, n=128, N=179, M=192, metal=2)
+    assert mask.any()
+    plan = ct.Plan(g.n, g.n_angles, g.n_bins)
+    lam = 0.02
+    probe = ct.Solver(plan, gpu(u0), lam, ct.pack_mask(mask), gpu(bound))
+    inf = probe.info()
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, lam), pdrq.Params(), beta=inf["beta"],
+                   c=inf["c"])
+    K = 6
+    states = unrolled.forward(s, K)
+    _, gbar = unrolled.mse_loss(states[-1].u, truth)
+    du0, dlam = unrolled.backward(s, states, gbar)
+    return dict(plan=plan, u0=u0, mask=mask, bound=bound, truth=truth, lam=lam, K=K,
+                beta=inf["beta"], c=inf["c"], uK=states[-1].u, du0=du0, dlam=dlam)
+
+
+@pytest.mark.parametrize("slices,kern", [(4, "pairs8"), (16, "pairs4"), (3, "one_angle")])
+def test_unrolled_gradients_launch_paths(oracle_128, slices, kern):
+    """The reverse sweep on the launch paths of the large differentiation
+    workload: R_h^* split into angle slices (the sweep's backprojection with
+    its base image summed by the combine pass), the mirror pairs on 32 x 64
+    tiles and the one-angle kernel.  u_K, dL/du0 and dL/dlambda against the
+    oracle's reverse mode (1e-5, 1e-4, 1e-4)."""
+    o = oracle_128
+    print("unrolled launch path", slices, kern, flush=True)
+    sino = gpu(o["u0"])[None].requires_grad_(True)
+    lt = torch.tensor(o["lam"], device=DEV, requires_grad=True)
+    launch = ct.Launch(bp_slices=slices, bp_kernel=kern)
+    u = ct.unrolled_pd(o["plan"], sino, lt, [ct.pack_mask(o["mask"])], [gpu(o["bound"])],
+                       K=o["K"], every=4, beta=o["beta"], c=o["c"], launch=launch)
+    ((u[0] - gpu(o["truth"])) ** 2).mean().backward()
+    assert rel(host(u[0]), o["uK"]) <= 1e-5
+    assert rel(host(sino.grad[0]), o["du0"]) <= 1e-4
+    assert float(lt.grad) == pytest.approx(o["dlam"], rel=1e-4)
+
+
+def test_unrolled_lambda_fd_large_slice():
+    """A 1024^2 x 1440 x 1536 slice (the differentiation workload's size; 6
+    unrolled iterations, checkpoints every 3, 4 angle slices on 32 x 64 pair
+    tiles): the reverse sweep's dL/dlambda agrees with a central difference
+    of the GPU map in lambda to 5 %.  The data are the GPU projection of the
+    workload's phantom plus 1 % noise (a GPU-to-GPU check; no oracle).
+    lambda = 2000 (lambda~ = lambda / beta^2 ~ 1.4e-3 at this size): large
+    enough that the TV term moves the iterates and the loss by far more than
+    FP32 rounding within 6 iterations (at the workload's 0.01 the change of
+    the loss over the difference step is below its rounding)."""
+    print("unrolled fd 1024", flush=True)
+    w = synth.workload("C4")
+    n, N, M = w.n, w.n_angles, w.n_bins
+    plan = ct.Plan(n, N, M)
+    clean = plan.radon_fwd(gpu(w.phantom))
+    tissue_max = float(plan.radon_fwd(gpu(w.tissue)).max())
+    sino = (clean + w.noise_level * tissue_max * gpu(w.noise))[None].contiguous()
+    tr = gpu(w.phantom)
+    lam, K = 2000.0, 6
+    launch = ct.Launch(bp_slices=4, bp_kernel="pairs8")
+    probe = ct.Solver(plan, sino[0], lam, launch=launch)
+    opts = dict(beta=probe.info()["beta"], c=probe.info()["c"], launch=launch)
+    del probe
+
+    def loss(lv, grad=False):
+        lt = torch.tensor(lv, device=DEV, requires_grad=grad)
+        u = ct.unrolled_pd(plan, sino, lt, K=K, every=3, **opts)
+        L = ((u[0] - tr) ** 2).double().mean()
+        if grad:
+            L.backward()
+            return float(L.detach()), float(lt.grad)
+        return float(L)
+
+    _, an = loss(lam, True)
+    d = 5e-2 * lam
+    fd = (loss(lam + d) - loss(lam - d)) / (2 * d)
+    print("dL/dlambda reverse %.6e, central difference %.6e" % (an, fd), flush=True)
+    assert np.isfinite(an) and an != 0.0
+    assert an == pytest.approx(fd, rel=5e-2)

@@ -1,0 +1,60 @@
+"""ct_power_norm_noalloc through the C ABI: the same estimate as
+ct_power_norm (its scratch comes from the library's static device array
+instead of the plan's), on two calls in a row with the second on a smaller
+geometry, without changing the device's free memory; sizes beyond the
+array are rejected."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+ct = pytest.importorskip("paper_1810_03275_amd")
+from paper_1810_03275_amd import _lib  # noqa: E402
+
+DEV = torch.device("cuda")
+L = ct.lib
+
+
+def _norms(plan, x0):
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ptr = x0.data_ptr() if x0 is not None else None
+    ref, got = ctypes.c_double(), ctypes.c_double()
+    assert L.ct_power_norm(plan.handle, 30, ptr, ctypes.byref(ref), s) == 0
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    assert L.ct_power_norm_noalloc(plan.handle, 30, ptr, ctypes.byref(got), s) == 0, \
+        L.ct_last_error()
+    free1 = torch.cuda.mem_get_info()[0]
+    return ref.value, got.value, free0, free1
+
+
+@pytest.mark.parametrize("with_start", [True, False])
+def test_noalloc_power_norm_matches(with_start):
+    print("noalloc power norm", with_start, flush=True)
+    rng = np.random.default_rng(77)
+    for n, N, M in ((96, 135, 144), (48, 67, 72)):   # the second call is smaller
+        plan = ct.Plan(n, N, M)
+        x0 = None
+        if with_start:
+            x0 = torch.from_numpy(rng.standard_normal((n, n)).astype(np.float32)).to(DEV)
+            keep = x0.clone()
+        ref, got, free0, free1 = _norms(plan, x0)
+        assert np.isfinite(got) and got > 0
+        assert abs(got - ref) <= 1e-5 * ref
+        assert free1 == free0
+        if with_start:
+            assert torch.equal(x0, keep)            # the start image is not modified
+
+
+def test_noalloc_rejects_sizes_beyond_the_array():
+    print("noalloc size limit", flush=True)
+    plan = ct.Plan(2048, 6000, 3072)               # n^2 + N M = 22.6 million
+    out = ctypes.c_double()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.ct_power_norm_noalloc(plan.handle, 30, None, ctypes.byref(out), s) == -1
+    assert b"scratch" in L.ct_last_error()
+    assert L.ct_power_norm_noalloc(None, 30, None, ctypes.byref(out), s) == -1
+    assert L.ct_power_norm_noalloc(plan.handle, 0, None, ctypes.byref(out), s) == -1
