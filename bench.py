@@ -28,10 +28,13 @@ N_IMG, N_ANG, N_BIN = 512, 720, 768
 # Published MI355X peaks used for the roofline fields.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP32 work of one pixel-angle pair in R_h or R_h^*: the weight
-# application (1 - alpha) v_k + alpha v_{k+1} as v_k + alpha (v_{k+1} - v_k)
-# (subtract, multiply-add) and the accumulation (add): 4 flops.
-FLOPS_PER_PAIR = 4.0
+# Plain VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s.
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
+# Algorithmic FP32 work of one pixel-angle pair in R_h or R_h^*: the step of
+# the bin coordinate (1 add), the weight application (1 - alpha) v_k +
+# alpha v_{k+1} as v_k + alpha (v_{k+1} - v_k) (subtract, multiply-add: 3)
+# and the accumulation (1 add): 5 flops.
+FLOPS_PER_PAIR = 5.0
 # Algorithmic HBM bytes of one R_h launch inside the iteration: read the image
 # once; read the target and vb1 and write vb1 and s1 once per bin (the fused
 # sinogram-side update), plus the packed trace mask.
@@ -39,19 +42,83 @@ def radon_fwd_bytes(n, N, M):
     return 4.0 * (n * n + 4 * N * M) + N * ((M + 31) // 32) * 4.0
 
 
-def measured_traffic():
-    """HBM traffic per R_h launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "radon_fwd_512x720x768_traffic.json")
+# ... of one R_h^* launch inside the iteration: read s1 once, write the
+# image (its angle slices' partial images are written and read once more by
+# the preconditioner's row pass; counted there).
+def radon_adj_bytes(n, N, M):
+    return 4.0 * (N * M + n * n)
+
+
+# ... of the preconditioner pair: u_tmp (formed from the slices as it is read)
+# and the field s2 for its divergence, u, u_new, and the complex half
+# spectrum written and read once by the column pass and once more by the
+# inverse rows: 4 (n^2 (1 + 2 + 1 + 1) + 4 n (n/2 + 1)) bytes.
+def fft_pair_bytes(n):
+    return 4.0 * (5 * n * n + 4 * n * (n // 2 + 1))
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def profile_records():
+    """The committed counter records of the benchmark workload (each None
+    when missing or taken on other kernel sources)."""
+    from paper_1810_03275_amd.profiling import load_record
+    stem = os.path.join(PROFILES, "pdrqs1_512x720x768_")
+    return {"sq": load_record(stem + "sq_counters.json"),
+            "tcc": load_record(stem + "tcc_counters.json"),
+            "traffic": load_record(stem + "traffic.json")}
+
+
+def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, peak, unit):
+    """The roofline object of one kernel: achieved = algorithmic work per
+    launch / its average duration (HIP events), against the published peak;
+    with the committed counters: the HBM bytes per launch, the VALU issue
+    fraction (SQ_INSTS_VALU wave-instructions x 64 lanes against the plain
+    issue rate over the same duration) and the L2 hit rate (TCC hits over
+    hits + misses)."""
+    from paper_1810_03275_amd.profiling import find_kernel
+    if bound == "hbm":
+        achieved = alg_bytes / duration_s / 1e9
+    else:
+        achieved = flops / duration_s / 1e12
+    out = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+           "frac": round(achieved / peak, 4), "duration_us": round(duration_s * 1e6, 2),
+           "algorithmic_bytes": alg_bytes,
+           "hbm_gbs_algorithmic": round(alg_bytes / duration_s / 1e9, 1)}
+    tr = find_kernel(recs["traffic"], prefix, suffix)
+    out["traffic"] = (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None
+    out["kernel"] = tr["name"] if tr else prefix + "..." + suffix
+    if tr:
+        out["hbm_gbs_counters"] = round(out["traffic"] / duration_s / 1e9, 1)
+        out["hbm_frac_counters"] = round(out["traffic"] / duration_s / 1e9 / PEAK_HBM_GBS, 4)
+    sq = find_kernel(recs["sq"], prefix, suffix)
+    out["valu_issue_frac"] = (round(sq["SQ_INSTS_VALU"] * 64 / duration_s / VALU_LANE_INSTR_PER_S,
+                                    4) if sq else None)
+    tc = find_kernel(recs["tcc"], prefix, suffix)
+    if tc and (tc.get("TCC_HIT_sum", 0) + tc.get("TCC_MISS_sum", 0)) > 0:
+        out["l2_hit_rate"] = round(tc["TCC_HIT_sum"] / (tc["TCC_HIT_sum"] + tc["TCC_MISS_sum"]), 4)
+    else:
+        out["l2_hit_rate"] = None
+    return out
+
+
+def system_info(torch):
+    """GPU SKU, ROCm/HIP version and the clocks rocm-smi reports."""
+    import subprocess
+    p = torch.cuda.get_device_properties(0)
+    info = {"gpu": p.name, "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count,
+            "memory_gib": round(p.total_memory / 2 ** 30, 1), "hip": torch.version.hip,
+            "torch": torch.__version__}
     try:
-        with open(path) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    from paper_1810_03275_amd.profiling import kernel_source_hash
-    if rec.get("source_hash") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=20)
+        card = next(iter(json.loads(r.stdout).values()))
+        info["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception as e:   # noqa: BLE001 (the clocks are informational)
+        info["clocks"] = f"unavailable ({type(e).__name__})"
+    return info
 
 
 def build_inputs(ct, torch, w, plan=None):
@@ -304,30 +371,46 @@ def mar_pipeline(ct, torch, w, plan, u0, true_mask, iters: int, reps: int = 20):
 
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle timed on this host on a bounded sample of the same
-    workload: setup with beta and c given, then PDRQS1 iterations until about
-    budget_s seconds have passed (at least one)."""
+    workload (setup with beta and c given, not timed): PDRQS1 iterations for
+    about budget_s / 2 seconds on one core, then for as long with its
+    projector pair split over angle blocks on all the host's cores (at most
+    16, a GPU's share of the host) and numpy.fft on one thread."""
     import numpy as np
     from oracle import geometry, pdrq, radon
+    from oracle.parallel import AngleBlocks
     g = geometry.Geometry(w.n, w.n_angles, w.n_bins)
     tissue = radon.radon_fwd(g, w.tissue)
     u0 = radon.radon_fwd(g, w.phantom) + w.noise_level * tissue.max() * w.noise
     mask = radon.radon_fwd(g, w.metal.astype(float)) > 0
     bound = np.where(mask, 0.95 * tissue, 0.0)
     prob = pdrq.Problem(g, u0, mask, bound, w.alpha)
-    s = pdrq.setup(prob, pdrq.Params(), beta=1.0e3, c=1.0)
-    st = pdrq.zero_state(s)
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        st = pdrq.step(s, st)
-        k += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "it/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} PDRQS1 iteration(s) of the 512^2 x 720 x 768 workload in FP64 "
-                      f"NumPy ({dt:.1f} s, single-threaded NumPy/pocketfft; setup with "
-                      f"beta and c given, not timed)"}
+
+    def rate(s, budget):
+        st = pdrq.zero_state(s)
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            st = pdrq.step(s, st)
+            k += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return k, time.perf_counter() - t0
+
+    k1, dt1 = rate(pdrq.setup(prob, pdrq.Params(), beta=1.0e3, c=1.0), budget_s / 2)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ab = AngleBlocks(g, workers)
+    try:
+        ab.fwd(np.zeros((g.n, g.n)))   # start the worker processes
+        kn, dtn = rate(pdrq.setup(prob, pdrq.Params(), beta=1.0e3, c=1.0, fwd=ab.fwd,
+                                  adj=ab.adj), budget_s / 2)
+    finally:
+        ab.close()
+    return {"value": kn / dtn, "unit": "it/s", "cores": workers, "kind": "oracle",
+            "single_core_value": k1 / dt1, "host_cpus": os.cpu_count(),
+            "sample": f"PDRQS1 iterations of the 512^2 x 720 x 768 workload in FP64 NumPy: "
+                      f"{kn} in {dtn:.1f} s with the projector pair on {workers} worker "
+                      f"processes, {k1} in {dt1:.1f} s on one core (setup with beta and c "
+                      f"given, not timed)"}
 
 
 def main():
@@ -350,10 +433,12 @@ def main():
                     help="iterations per solve of the metal-artifact workflow (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (for counter scaling)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of launch-choice tuning results to reuse (and extend)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding of the path is described in DESIGN.md, not run.",
+              "how the path would shard over GPUs is described in the design notes, not run.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -365,7 +450,9 @@ def main():
     plan, u0, mask, bound, x0, x1 = build_inputs(ct, torch, w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1)
+    launch = ct.Launch(tune_cache=args.tune_cache) if args.tune_cache else None
+    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1,
+                   launch=launch)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = sv.info()
@@ -379,15 +466,55 @@ def main():
     it_s = args.steps / dt
     rec = sv.gap()
 
-    # per-phase kernel durations of the same iterations, HIP events on the
-    # solver's stream (the current stream)
+    # the same iterations timed with HIP events on the solver's stream (the
+    # current stream): median over repeats of blocks of iterations
+    reps, block = 25, 20
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for r in range(reps):
+        sv.step(block)
+        ev[r + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(ev[r].elapsed_time(ev[r + 1]) / block for r in range(reps))
+    event_ms = per[reps // 2]
+
+    # the FP64 record inside the loop: a record every 10 iterations
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sv.step(10)
+        sv.gap()
+    torch.cuda.synchronize()
+    with_gap = 100 / (time.perf_counter() - t0)
+
+    # per-phase kernel durations of the same iterations with the same
+    # launches, HIP events on the solver's stream (the current stream)
     ph = sv.step_timed(args.kernel_reps)
     t_fwd = ph["radon_fwd"] * 1e-3
     t_adj = ph["radon_adj"] * 1e-3
+    t_fft = ph["precond"] * 1e-3
     pairs = float(N_IMG * N_IMG * N_ANG)
-    achieved = FLOPS_PER_PAIR * pairs / t_fwd / 1e12
-    traffic = measured_traffic()
-
+    lay, tun = sv.layout(), sv.tuning()
+    recs = profile_records()
+    fwd_suffix = "true>" if tun["tv_blocks"] > 0 else "false>"
+    roof = kernel_roofline(recs, "ctpd::k_radon_fwd_multi<2", fwd_suffix, t_fwd,
+                           FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN), "alu",
+                           PEAK_FP32_TFLOPS, "TFLOP/s")
+    adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
+                  else "ctpd::k_radon_adj")
+    adj_suffix = f", {lay['bp_pair_pixels']}>" if lay["bp_angles_per_position"] == 2 else ""
+    roof_adj = kernel_roofline(recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
+                               radon_adj_bytes(N_IMG, N_ANG, N_BIN), "alu", PEAK_FP32_TFLOPS,
+                               "TFLOP/s")
+    fft = {"duration_us": round(t_fft * 1e6, 2), "bound": "hbm", "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "algorithmic_bytes": fft_pair_bytes(N_IMG),
+           "achieved": round(fft_pair_bytes(N_IMG) / t_fft / 1e9, 1)}
+    fft["frac"] = round(fft["achieved"] / PEAK_HBM_GBS, 4)
+    if recs["traffic"]:
+        tb = [e["fetch_bytes"] + e["write_bytes"] for nm, e in recs["traffic"]["kernels"].items()
+              if nm.startswith("ctpd::k_fft_") and e["fetch_bytes"] and e["write_bytes"]
+              and "<true" in nm]
+        fft["traffic_note"] = "sum of the median bytes of the in-path FFT kernels"
+        fft["traffic"] = sum(tb) if tb else None
     out = {
         "metric": METRIC,
         "value": round(it_s, 2),
@@ -405,22 +532,21 @@ def main():
                                "768 bins, alpha=0.005, inequality constraints on the metal trace",
                    "image": N_IMG, "angles": N_ANG, "bins": N_BIN, "alpha": w.alpha,
                    "iterations_per_solve": w.iters},
+        "event_timing": {"repeats": reps, "iterations_per_repeat": block,
+                         "median_ms_per_iteration": round(event_ms, 5),
+                         "it_per_s": round(1e3 / event_ms, 1)},
+        "it_per_s_with_record_every_10": round(with_gap, 1),
         "radon_pairs_per_s": round(2 * pairs / (t_fwd + t_adj) / 1e9, 2),
         "radon_pairs_unit": "Gvox*angles/s (R+R*)",
         "phase_us": {k: round(v * 1e3, 2) for k, v in ph.items()},
         "setup_ms": round(setup_s * 1e3, 2),
-        "layout": sv.layout(),
+        "layout": lay, "tuning": tun,
         "beta": info["beta"], "c": info["c"],
         "gap_record": [float(x) for x in rec],
-        "roofline": {"kernel": ("k_radon_fwd_multi<%d>" % sv.layout()["angles_per_walk"]
-                                if sv.layout()["angles_per_walk"] > 1 else "k_radon_fwd"),
-                     "bound": "alu", "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic,
-                     "hbm_gbs_algorithmic": round(radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
-                                                  / t_fwd / 1e9, 1),
-                     "duration_us": round(t_fwd * 1e6, 2)},
+        "roofline": roof,
+        "roofline_radon_adj": roof_adj,
+        "roofline_fft_pair": fft,
+        "system": system_info(torch),
     }
     if args.batched_iters > 0:
         del sv

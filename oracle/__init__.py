@@ -22,6 +22,7 @@ Modules (each function cites the thesis passage it follows):
   d0        metal-trace estimate: threshold, dilate, project        (results, real metal)
   admm      ADMM with inner PCG and isotropic soft thresholding     (§4.6)
   pdrq3     the PDRQ3 splitting (fit in the dual's quadratic part)  (§4.4)
+  parallel  R_h / R_h^* split over angle blocks in worker processes (§3.1)
 
 Readings of passages that are silent, ambiguous or garbled are listed in the
 header of the module that takes them and collected in the repository's design

@@ -45,7 +45,8 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 import synth  # noqa: E402
 from oracle import pdrq  # noqa: E402
-from oracle import geometry, radon  # noqa: E402
+from oracle import geometry  # noqa: E402
+from oracle.parallel import AngleBlocks  # noqa: E402
 from oracle_inputs import build, f32, random_problem, random_state  # noqa: E402
 
 C5_BETA = 2430.0
@@ -62,32 +63,6 @@ STEP_U_SCALE = 0.02
 C3_SIZES = (256, 384, 512, 768, 1024)
 C3_C = 1.25
 C3_LAMBDA = 0.005
-
-
-class AngleBlocks:
-    """The oracle's R_h and R_h^* with the angles split into blocks that
-    worker processes project (sub-geometries with the same angle values).
-    Each bin is the oracle's own sum; R_h^* adds the blocks' partial images
-    in block order."""
-
-    def __init__(self, g, workers: int):
-        from concurrent.futures import ProcessPoolExecutor
-        self.pool = ProcessPoolExecutor(workers)
-        th = g.angles()
-        self.blocks = np.array_split(np.arange(g.n_angles), 4 * workers)
-        self.subs = [geometry.Geometry(g.n, len(b), g.n_bins, g.h, g.ds,
-                                       thetas=tuple(float(t) for t in th[b]))
-                     for b in self.blocks]
-
-    def fwd(self, u):
-        return np.concatenate(list(self.pool.map(radon.radon_fwd, self.subs,
-                                                 [u] * len(self.subs))), axis=0)
-
-    def adj(self, v):
-        out = None
-        for part in self.pool.map(radon.radon_adj, self.subs, [v[b] for b in self.blocks]):
-            out = part if out is None else out + part
-        return out
 
 
 def workers() -> int:

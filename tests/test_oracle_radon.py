@@ -297,3 +297,21 @@ def test_sampled_evaluator_pin_catches_planted_mistakes(mutant, kind):
     g = SAMPLED_GEOMS[2]
     err = _fwd_at_pin(g, mutant) if kind == "fwd" else _adj_at_pin(g, mutant)
     assert err > 1e-2
+
+
+def test_angle_blocks_equal_serial_pair():
+    """The angle-block split of the pair (worker processes) gives the serial
+    oracle's R_h exactly and its R_h^* to FP64 rounding, explicit angles
+    included."""
+    from oracle.parallel import AngleBlocks
+    for g in (geometry.Geometry(20, 17, 30), SAMPLED_GEOMS[2]):
+        ab = AngleBlocks(g, 2)
+        try:
+            rng = np.random.default_rng(41)
+            u = rng.standard_normal((g.n, g.n))
+            v = rng.standard_normal((g.n_angles, g.n_bins))
+            assert np.array_equal(ab.fwd(u), radon.radon_fwd(g, u))
+            ref = radon.radon_adj(g, v)
+            assert np.max(np.abs(ab.adj(v) - ref)) <= 1e-13 * np.max(np.abs(ref))
+        finally:
+            ab.close()

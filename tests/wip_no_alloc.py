@@ -1,8 +1,8 @@
 """ct_power_norm_noalloc through the C ABI: the same estimate as
 ct_power_norm (its scratch comes from the library's static device array
 instead of the plan's), on two calls in a row with the second on a smaller
-geometry, without changing the device's free memory; sizes beyond the
-array are rejected."""
+geometry, without lowering the device's free memory (the runtime may raise
+it, releasing memory of its own); sizes beyond the array are rejected."""
 import ctypes
 
 import numpy as np
@@ -44,7 +44,7 @@ def test_noalloc_power_norm_matches(with_start):
         ref, got, free0, free1 = _norms(plan, x0)
         assert np.isfinite(got) and got > 0
         assert abs(got - ref) <= 1e-5 * ref
-        assert free1 == free0
+        assert free1 >= free0   # an allocation could only lower the free memory
         if with_start:
             assert torch.equal(x0, keep)            # the start image is not modified
 
