@@ -103,21 +103,40 @@ def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, p
     return out
 
 
+def _dpm_levels(path):
+    """The levels of an amdgpu pp_dpm_* file, in MHz, and the current one."""
+    levels, cur = [], None
+    for line in open(path).read().splitlines():
+        parts = line.split()
+        if len(parts) >= 2 and parts[1].lower().endswith("mhz"):
+            mhz = int(parts[1][:-3])
+            levels.append(mhz)
+            if "*" in parts[2:]:
+                cur = mhz
+    return levels, cur
+
+
 def system_info(torch):
-    """GPU SKU, ROCm/HIP version and the clocks rocm-smi reports."""
-    import subprocess
+    """GPU SKU, ROCm/HIP version and the clock levels the amdgpu driver lists
+    in sysfs (read as files: no tool process is started, so that the benchmark
+    also runs unchanged under a profiler)."""
+    import glob
     p = torch.cuda.get_device_properties(0)
     info = {"gpu": p.name, "arch": getattr(p, "gcnArchName", None),
             "compute_units": p.multi_processor_count,
             "memory_gib": round(p.total_memory / 2 ** 30, 1), "hip": torch.version.hip,
             "torch": torch.__version__}
+    clocks = {}
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
-                           text=True, timeout=20)
-        card = next(iter(json.loads(r.stdout).values()))
-        info["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
-    except Exception as e:   # noqa: BLE001 (the clocks are informational)
-        info["clocks"] = f"unavailable ({type(e).__name__})"
+        for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+            for dom in ("sclk", "mclk"):
+                f = os.path.join(dev, f"pp_dpm_{dom}")
+                if os.path.exists(f) and dom not in clocks:
+                    levels, cur = _dpm_levels(f)
+                    clocks[dom] = {"levels_mhz": levels, "current_mhz": cur}
+    except (OSError, ValueError) as e:   # the clocks are informational
+        clocks["error"] = type(e).__name__
+    info["clocks"] = clocks or "unavailable (no pp_dpm files)"
     return info
 
 

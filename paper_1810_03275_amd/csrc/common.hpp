@@ -57,7 +57,27 @@ struct FpAngle {
   uint32_t B;
   int32_t l;   // sinogram row
   int32_t pad;
+  // the paired forward projector's position walk: pixels per bin 2^62 / A
+  // and pixels moved per row B 2^32 / A, both in units of 2^-32, rounded
+  uint64_t dfix;
+  uint64_t dlt;
 };
+
+// Position walk of the paired forward projector.  For strip k (bin k) in
+// walk row q, s = (k 2^30 - T - q B) / A is where the strip starts along the
+// row: its pixels are floor(s + 1) ... (the boundary pixel of an integer s
+// goes to the strip before, whose last pixel it is with weight 1 on bin k: the
+// same contribution).  The walk keeps y = 2^32 (s + 1) as a 64-bit fixed-point
+// number whose high word is the pixel index and low word the fraction g; the
+// first pixel's interpolation weight is alpha = (1 - g) A 2^-30, and strip
+// k + 1 starts where y + dfix floors.  y of one strip and row, rounded to
+// 2^-32 in the same way on host and device (a correctly rounded division).
+__host__ __device__ inline uint64_t walk_y0(int64_t k, int64_t q, int64_t T, uint32_t A,
+                                            uint32_t B) {
+  const int64_t num = k * ((int64_t)1 << kFixBits) - T - q * (int64_t)B;
+  const double s = (double)num / (double)A + 1.0;
+  return (uint64_t)(int64_t)rint(s * 4294967296.0);
+}
 
 // A group of up to kFpGroup angles of the same walk class, processed by one
 // workgroup (one wave per kFpPerThread angles, 64 bins per workgroup).

@@ -139,6 +139,12 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
     fp[l].B = (uint32_t)Bo;
     fp[l].l = l;
     fp[l].pad = 0;
+    {
+      using u128 = unsigned __int128;
+      const u128 a = (u128)(uint64_t)Ai;
+      fp[l].dfix = (uint64_t)((((u128)1 << 62) + a / 2) / a);
+      fp[l].dlt = (uint64_t)((((u128)(uint64_t)Bo << 32) + a / 2) / a);
+    }
     cls[l] = (tr ? 1 : 0) | (fi ? 2 : 0) | (fo ? 4 : 0);
   }
   double max_extent = 0.0;  // largest detector span of a tile, in bins
@@ -481,7 +487,9 @@ int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, 
 // Host replay of the forward projector's walk over every (group, block, wave,
 // lane, staged row) of a plan: each LDS read must fall inside the staged
 // window of its chunk, and every row that the kernel skips must hold no pixel
-// of any strip of the block.  Exact integer arithmetic, as on the device.
+// of any strip of the block.  The same integer arithmetic as on the device:
+// the exact walk of the one-angle kernel, the fixed-point walk of the paired
+// one.
 int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
                int64_t *steps) {
   HostPlan hp;
@@ -529,6 +537,43 @@ int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
           }
           if (cr.x > cr.y) continue;
           const int64_t q_first = (int64_t)cr.x * hp.chunk_rows;
+          if (hp.paired) {
+            // the paired kernel's fixed-point walk (walk_y0 + lane dfix, then
+            // dlt per row): the first pixel is read when it lies in the
+            // strip, the second one when the strip holds two pixels
+            uint64_t y = walk_y0(k - lane, q_first, fa.T, fa.A, fa.B) + (uint64_t)lane * fa.dfix;
+            const bool two = (fa.dfix >> 32) != 0;
+            const uint32_t dlo = (uint32_t)fa.dfix;
+            if (!two && !hp.check_first) {
+              set_error("plan check: a strip narrower than a pixel in a kernel that reads "
+                        "every first pixel");
+              return CT_E_INVALID;
+            }
+            for (int ch = cr.x; ch <= cr.y; ++ch) {
+              const int rows = std::min(hp.chunk_rows, n - ch * hp.chunk_rows);
+              const int2 rg = reg[ch];
+              if (rg.y > hp.wmax) {
+                set_error("plan check: window wider than the plan's width");
+                return CT_E_INVALID;
+              }
+              for (int r = 0; r < rows; ++r) {
+                const int64_t X = (int64_t)(int32_t)(uint32_t)(y >> 32);
+                const uint32_t lo = (uint32_t)y;
+                const bool in1 = two || lo >= 0u - dlo;
+                const bool in2 = two && lo > ~dlo;
+                const int64_t c = X - rg.x;
+                const int64_t last = c + (in2 ? 1 : 0);
+                if ((in1 || in2) && (c < 0 || last > rg.y - 1)) {
+                  set_error("plan check: staged window misses strip " + std::to_string(k) +
+                            " at row " + std::to_string(ch * hp.chunk_rows + r));
+                  return CT_E_INVALID;
+                }
+                ++count;
+                y -= fa.dlt;
+              }
+            }
+            continue;
+          }
           const int64_t num = k * one - fa.T - q_first * (int64_t)fa.B;
           int64_t pp = (int64_t)std::ceil((double)num / (double)fa.A);
           int64_t ee = pp * (int64_t)fa.A - num;
@@ -544,7 +589,7 @@ int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
             set_error("plan check: initial walk state is not exact");
             return CT_E_INVALID;
           }
-          if (!hp.paired) pp = clamp64(pp, -(1 << 29), 1 << 29);
+          pp = clamp64(pp, -(1 << 29), 1 << 29);
           int64_t ps = pp;
           uint32_t e = (uint32_t)ee;
           for (int ch = cr.x; ch <= cr.y; ++ch) {
@@ -555,7 +600,7 @@ int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
               return CT_E_INVALID;
             }
             for (int r = 0; r < rows; ++r) {
-              const int64_t pos = hp.paired ? ps : clamp64(ps, -2, n);
+              const int64_t pos = clamp64(ps, -2, n);
               const int64_t c = pos - rg.x;
               if (c < 0 || c + 1 > rg.y - 1) {
                 set_error("plan check: staged window misses strip " + std::to_string(k) +

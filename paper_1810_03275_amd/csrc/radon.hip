@@ -999,9 +999,11 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
 // angles theta, pi/2 - theta, pi - theta and pi/2 + theta have identical walk
 // constants (T, A, B) and differ only in how (p, q) maps to image pixels.
 // (Four angles per walk were measured slower on gfx950: half as many waves
-// to hide LDS latency, and twice the staging per wave.)  The strips, the walk and the output are those of
-// k_radon_fwd; a wave owns SL angles (all walk the same (e, ps) sequence), a
-// workgroup MultiCfg<SL>::kWaves such sets.  Each chunk stages the same
+// to hide LDS latency, and twice the staging per wave.)  The strips and the
+// output are those of k_radon_fwd, the walk a 64-bit fixed-point one
+// (walk_y0): its high word addresses the staged pixel, its low word is the
+// interpolation fraction, and a row costs one add.  A wave owns SL angles
+// (all walk the same positions), a workgroup MultiCfg<SL>::kWaves such sets.  Each chunk stages the same
 // (row, column) window SL times -- once per angle, through that angle's
 // transpose/mirror mapping -- as rows of pitch kLdw, the SL copies of a row
 // adjacent, so that the reads of all SL angles at (row, ps) share addresses.
@@ -1163,7 +1165,8 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   fp_batch_offsets(u, sino, ep, n, N, M);
   const int2 wk = work[blockIdx.x];  // (group, block along the bins)
   const FpGroup grp = groups[wk.x];
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform in a scalar register, so that the per-wave walk constants are too
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int blk = wk.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
@@ -1199,31 +1202,31 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   const int q_first = ch_first * kRows;
   const bool active = wave < grp.count;  // wave-uniform
 
-  uint32_t e = 0u, A = one, B = 0u;
-  int ps = 0;
+  // Lane state: the 64-bit fixed-point position y of the strip's first
+  // pixel (walk_y0), its high word relative to the staged window while a
+  // chunk is processed.  Neighbouring lanes differ by exactly dfix, so a
+  // strip's last pixel is always the pixel before the next strip's first
+  // one.  A strip holds one or two pixels when dfix >= 2^32 (the second one
+  // iff the fraction lies above ~lo(dfix)), else none or one (the first one
+  // iff the fraction is at least 2^32 - dfix).
+  uint64_t y = 0, E = 0;
+  uint32_t L1 = 0u, L2 = 0xffffffffu;
+  float a30 = 0.f;
   if (active) {
     const FpAngle fa = pa[SL * wave];
-    A = fa.A;
-    B = fa.B;
-    const int64_t num = (int64_t)k * ((int64_t)1 << kFixBits) - fa.T -
-                        (int64_t)q_first * (int64_t)fa.B;
-    int64_t pp = (int64_t)ceil((double)num / (double)fa.A);
-    int64_t ee = pp * (int64_t)fa.A - num;
-    if (ee < 0) {
-      pp += 1;
-      ee += fa.A;
-    } else if (ee >= (int64_t)fa.A) {
-      pp -= 1;
-      ee -= fa.A;
+    a30 = (float)fa.A * (1.0f / (float)one);
+    E = ((uint64_t)kStride << 32) - fa.dlt;
+    y = walk_y0(kb - 1, q_first, fa.T, fa.A, fa.B) + (uint64_t)lane * fa.dfix;
+    const uint32_t dlo = (uint32_t)fa.dfix;
+    if ((fa.dfix >> 32) != 0) {
+      L2 = ~dlo;
+    } else {
+      L1 = 0u - dlo;
     }
-    ps = (int)pp;
-    e = (uint32_t)ee;
   }
-  // the second pixel (fraction e + A) is in the strip iff e < 2^30 - A
-  const uint32_t lim2 = A < one ? one - A : 0u;
-  float P[SL], Q[SL], S[SL];
+  float P[SL], G[SL], S[SL];
 #pragma unroll
-  for (int s = 0; s < SL; ++s) P[s] = Q[s] = S[s] = 0.f;
+  for (int s = 0; s < SL; ++s) P[s] = G[s] = S[s] = 0.f;
 
   const int2 *reg = regions + grp.region + blk * n_chunks;
   constexpr int RB = 16;  // rows whose LDS reads are issued together
@@ -1253,21 +1256,23 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
       for (int s = 0; s < SL; ++s) St::load(pf[s], u, n, cls[s], q1, rows1, rg_next.x);
     }
     if (active) {
-      // pt walks the strip start through the staged rows: row r of the
-      // window starts at buf + r kStride, and the strip start moves one
-      // position left per row unless the fraction did not wrap.
-      const float *pt = buf + (ps - plo);
+      // high word: index into the staged rows (row r of the window starts at
+      // buf + r kStride, and E moves one row down and B / A pixels left)
+      uint64_t yc = y - ((uint64_t)(int64_t)plo << 32);
       int r0 = 0;
       for (; r0 + RB <= rows; r0 += RB) {
         const float *pr[RB], *pr2[RB];
-        uint32_t ev[RB];
+        uint32_t lo[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          pr[r] = pt;
-          ev[r] = e;
+          const float *pt = buf + (int32_t)(yc >> 32);
+          lo[r] = (uint32_t)yc;
+          pr[r] = (!CHECK_FIRST || lo[r] >= L1) ? pt : zs;
           // the second pixels of all SL angles come from the row or the zero slot
-          pr2[r] = ev[r] < lim2 ? pt : zs;
-          walk_row_ptr(e, pt, A, B, kStride);
+          pr2[r] = lo[r] > L2 ? pt : zs;
+          yc += E;
+          // keep the walk one 64-bit add per row (not 16 running offsets)
+          asm("" : "+v"(yc));
         }
         float x1[RB][SL], x2[RB][SL];
 #pragma unroll
@@ -1280,40 +1285,51 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const uint32_t e1 = ev[r];
-          const bool in1 = e1 < one;
-          const float ef = (float)e1;
+          const float gf = (float)lo[r];
 #pragma unroll
-          for (int s = 0; s < SL; ++s)
-            acc_row_z<CHECK_FIRST>(x1[r][s], x2[r][s], in1, ef, P[s], Q[s], S[s]);
+          for (int s = 0; s < SL; ++s) {
+            const float sa = x1[r][s] + x2[r][s];
+            P[s] += sa;
+            G[s] = fmaf(gf, sa, G[s]);
+            S[s] += x2[r][s];
+          }
         }
       }
       for (int r = r0; r < rows; ++r) {  // ragged last chunk
-        const uint32_t e1 = e;
-        const bool in1 = e1 < one, in2 = e1 < lim2;
-        const float ef = (float)e1;
+        const float *pt = buf + (int32_t)(yc >> 32);
+        const uint32_t l0 = (uint32_t)yc;
+        const float *p1 = (!CHECK_FIRST || l0 >= L1) ? pt : zs;
+        const float *p2 = l0 > L2 ? pt : zs;
+        const float gf = (float)l0;
 #pragma unroll
-        for (int s = 0; s < SL; ++s)
-          acc_row<CHECK_FIRST>(pt[s * kLdw], pt[s * kLdw + 1], in1, in2, ef, P[s], Q[s], S[s]);
-        walk_row_ptr(e, pt, A, B, kStride);
+        for (int s = 0; s < SL; ++s) {
+          const float x1 = p1[s * kLdw], x2 = p2[s * kLdw + 1];
+          const float sa = x1 + x2;
+          P[s] += sa;
+          G[s] = fmaf(gf, sa, G[s]);
+          S[s] += x2;
+        }
+        yc += E;
       }
-      ps = plo + (int)(pt - buf) - rows * kStride;
+      y = yc + ((uint64_t)(int64_t)(plo - rows * kStride) << 32);
     }
   }
 
   if (active) {
-    const float inv = 1.0f / (float)one;
+    // the strip's fraction-weighted sum: its pixels lie 1 - g and 2 - g
+    // pixel widths past the strip's start, i.e. A (1 - g) and A (2 - g) bin
+    // widths in 2^-30 units, with g = lo 2^-32
     float qt[SL], qp[SL];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      qt[s] = fmaf((float)A, S[s], Q[s]);  // sum of fraction * u, in 2^-30 units
+      qt[s] = a30 * fmaf(G[s], -2.3283064365386963e-10f, P[s] + S[s]);
       qp[s] = __shfl_up(qt[s], 1, 64);
     }
     if (lane >= 1 && k <= grp.kmax && k < M) {
 #pragma unroll
       for (int s = 0; s < SL; ++s) {
         const int l = pa[SL * wave + s].l;
-        if (l >= 0) fp_output(sino, ep, M, l, k, fmaf(qp[s] - qt[s], inv, P[s]));
+        if (l >= 0) fp_output(sino, ep, M, l, k, P[s] + (qp[s] - qt[s]));
       }
     }
   }
