@@ -175,7 +175,8 @@ int ct_power_norm(const ct_plan *p, int32_t iters, const float *x0, double *out,
  * power iteration as ct_power_norm, with its work image, sinogram and FP64
  * reduction partials in a 64 MiB array that the library holds on each device
  * it runs on (for the life of the process) instead of the plan's scratch.  It
- * calls no allocating routine.  Its backprojections run with one angle
+ * calls no allocating routine: the array is looked up (and so loaded by the
+ * runtime) on a device when the first plan is created there.  Its backprojections run with one angle
  * slice, so the estimate agrees with ct_power_norm's to FP32 rounding.
  * Limit: 4 (n^2 + N M) bytes plus 12 KiB of partials must fit the array
  * (n^2 + N M up to about 16.7 million; CT_E_INVALID beyond).  x0 (device

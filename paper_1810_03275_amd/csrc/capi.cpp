@@ -24,6 +24,7 @@ void clear_error() { g_err.clear(); }
 int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, ct_plan *p);
 int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, int64_t *steps);
 void free_plan(ct_plan *p);
+int noalloc_prepare_device();
 
 static bool fft_size_ok(int n) {
   if (n < 2 || n > 4096 || (n & 1)) return false;
@@ -295,6 +296,7 @@ int ct_plan_create_ex(const ct_geom *g, const double *angles, const ct_plan_opts
   p->g = *g;
   (void)hipGetDevice(&p->device);
   int rc = build_plan(g, angles, opt, p);
+  if (rc == CT_OK) rc = noalloc_prepare_device();
   if (rc != CT_OK) {
     free_plan(p);
     delete p;

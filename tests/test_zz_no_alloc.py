@@ -1,8 +1,9 @@
 """ct_power_norm_noalloc through the C ABI: the same estimate as
 ct_power_norm (its scratch comes from the library's static device array
 instead of the plan's), on two calls in a row with the second on a smaller
-geometry, without lowering the device's free memory (the runtime may raise
-it, releasing memory of its own); sizes beyond the array are rejected."""
+geometry, without lowering the device's free memory (the array is loaded when
+the plan is created; the runtime may raise the free memory, releasing memory
+of its own); sizes beyond the array are rejected."""
 import ctypes
 
 import numpy as np
