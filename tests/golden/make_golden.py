@@ -14,8 +14,10 @@ many worker processes.
 c2: the 512^2 x 720 x 768 workload with 2 metal discs (alpha = 0.005), set up
     by the oracle's power iterations from the workload's start images (§5.1,
     §4.3.1), then 500 PDRQS1 iterations (§4.4) from the zero state.  Stored:
-    beta, c, lambda~, the image after 500 iterations (float32) and the gap
-    records after every 100th iteration.
+    beta, c, lambda~, the image after 500 iterations (float32), the gap
+    records after every 100th iteration and, with each record, ||y1||, ||wg||
+    (wg = y1 + b off the metal trace, C~ on it: G*'s first-order change is
+    <dy1, wg>) and ||u||.
 c5: the 2048^2 x 2880 x 3072 geometry; one PDRQS1 step from a seeded
     random iterate (image scale STEP_U_SCALE), on seeded problem data (tests/oracle_inputs.py
     random_problem: projecting a phantom on the host would take three more
@@ -108,19 +110,25 @@ def make_c2(path: str) -> None:
                    f32(w.start_norm), f32(w.start_precond), **kw)
     print(f"c2 setup: beta {s.beta:.9g} c {s.c:.9g} ({time.time() - t0:.0f} s)", flush=True)
     st = pdrq.zero_state(s)
-    records = []
+    records, scales = [], []
     for k in range(w.iters):
         if (k + 1) % 100 == 0:
             from oracle import gap
             prev = st.u
             st, y1, wd = pdrq.step(s, st, return_dual=True)
             records.append(gap.record(s, st.u, y1, wd, prev))
-            print(f"c2 iteration {k + 1} ({time.time() - t0:.0f} s) record {records[-1]}",
-                  flush=True)
+            # sizes that bound how much G* moves with the dual iterate: its
+            # first-order change is <dy1, wg>, wg = y1 + b off the trace and C~ on it
+            mask = s.problem.mask
+            wg = np.where(mask, s.cb, y1 + s.b)
+            scales.append([np.linalg.norm(y1), np.linalg.norm(wg), np.linalg.norm(st.u)])
+            print(f"c2 iteration {k + 1} ({time.time() - t0:.0f} s) record {records[-1]} "
+                  f"scales {scales[-1]}", flush=True)
         else:
             st = pdrq.step(s, st)
     np.savez_compressed(path, u=st.u.astype(np.float32), beta=s.beta, c=s.c, lam_t=s.lam_t,
                         iters=w.iters, records=np.array(records),
+                        record_scales=np.array(scales),
                         record_iters=np.arange(100, w.iters + 1, 100))
     print("wrote", path, flush=True)
 

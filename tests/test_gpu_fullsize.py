@@ -14,8 +14,9 @@
   single solvers with the same launch choices.
 
 Stored values are written by tests/golden/make_golden.py, which calls only
-the oracle.  Tolerances (relative L2): 1e-5 per step and for the record of a
-shared state, 1e-4 for the image after 500 iterations.
+the oracle.  Tolerances (relative L2): 1e-5 per step (vb2: plus the error of
+u_new carried through the gradient, vb2_tol) and for the record of a shared
+state, 1e-4 for the image after 500 iterations.
 """
 import os
 import sys
@@ -67,6 +68,23 @@ def dual_scale(lam, beta):
     return (lam / beta ** 2) / pdrq.Params().tau
 
 
+def vb2_tol(rel_u, norm_u, norm_vb2, h=1.0):
+    """Tolerance (relative L2) of vb2 after one step.  vb2_new = vb2 + w - v2
+    with v2 = vb2 + sigma tau grad u_new and w the projection of 2 v2 - vb2
+    (§4.4): an error e of u_new reaches vb2 through sigma tau grad, whose norm
+    is at most sigma tau sqrt(8) / h = 1 / h (sigma tau = 1 / sqrt 8), once in
+    v2 and, through the nonexpansive projection, twice in w; so
+    ||d vb2|| <= 3 ||e|| / h beyond vb2's own FP32 rounding (1e-5)."""
+    return 1e-5 + 3.0 * rel_u * norm_u / (h * norm_vb2)
+
+
+def check_step(got, new, h=1.0):
+    """u and vb1 of a step to 1e-5, vb2 to vb2_tol."""
+    ru, r1, r2 = (rel(a, b) for a, b in zip(got, (new.u, new.vb1, new.vb2)))
+    assert ru <= 1e-5 and r1 <= 1e-5
+    assert r2 <= vb2_tol(ru, np.linalg.norm(new.u), np.linalg.norm(new.vb2), h), (r2, ru)
+
+
 def check_record(got, ref, tol):
     """The six record entries (P, G*, gap, rho_D, V, du) of a shared state.
     gap = P + G* is compared on the scale of |P| + |G*| (the two may nearly
@@ -114,8 +132,7 @@ def test_gap_record_metal_small():
     print("metal small: rel u %.2e vb1 %.2e vb2 %.2e" % tuple(
         rel(a, b) for a, b in zip(got, (new.u, new.vb1, new.vb2))), flush=True)
     print("records", rec_gpu, rec_ref, flush=True)
-    for a, b in zip(got, (new.u, new.vb1, new.vb2)):
-        assert rel(a, b) <= 1e-5
+    check_step(got, new, g.h)
     d0_term = float(np.sum((y1 * s.cb)[mask]))
     assert abs(d0_term) > 1e-3 * abs(rec_ref[1])
     check_record(rec_gpu, rec_ref, 1e-5)
@@ -124,7 +141,8 @@ def test_gap_record_metal_small():
 def test_c2_one_step_and_record():
     """512^2 x 720 x 768 with 2 metal discs, the benchmark's launch
     configuration (tuned): one step from a seeded iterate matches the
-    oracle's step in u, vb1 and vb2 (1e-5), and the FP64 records agree (1e-5)."""
+    oracle's step in u and vb1 (1e-5) and vb2 (vb2_tol), and the FP64 records
+    agree (1e-5)."""
     print("c2 one step", flush=True)
     w = synth.workload("C2")
     g, u0, mask, bound = build(w)
@@ -135,8 +153,7 @@ def test_c2_one_step_and_record():
     print("records", rec_gpu, rec_ref, flush=True)
     d0_term = float(np.sum((y1 * s.cb)[mask]))
     assert abs(d0_term) > 1e-3 * abs(rec_ref[1])
-    for a, b in zip(got, (new.u, new.vb1, new.vb2)):
-        assert rel(a, b) <= 1e-5
+    check_step(got, new, g.h)
     check_record(rec_gpu, rec_ref, 1e-5)
 
 
@@ -145,9 +162,10 @@ def test_c2_500_iterations():
     power iterations from the workload's start images, tuned launch, graph
     replay): beta and c match the oracle's (1e-5); after 500 iterations the
     image matches the oracle's stored run (1e-4), and the records after every
-    100th iteration agree in P, G* and the gap (1e-4; rho_D, V and du are
-    residuals of the iterate itself, so a 1e-5 difference of iterates makes
-    them differ by more: 5e-2)."""
+    100th iteration agree in P (1e-4), G* and the gap (to the first-order
+    bound below: G* sums terms of both signs); rho_D, V and du are residuals
+    of the iterate itself, so a 1e-5 difference of iterates makes them differ
+    by more: 5e-2."""
     print("c2 500 iterations", flush=True)
     z = golden("c2_pdrqs1_500.npz")
     w = synth.workload("C2")
@@ -164,10 +182,15 @@ def test_c2_500_iterations():
         recs.append(sv.gap())
     assert rel(host(sv.export()[0]), z["u"]) <= 1e-4
     ref = z["records"]
-    for r, q in zip(recs, ref):
+    for r, q, (ny1, nwg, nu) in zip(recs, ref, z["record_scales"]):
         assert abs(r[0] - q[0]) <= 1e-4 * abs(q[0])
-        assert abs(r[1] - q[1]) <= 1e-4 * abs(q[1])
-        assert abs(r[2] - q[2]) <= 1e-4 * (abs(q[0]) + abs(q[1]))
+        # G* = sum y1 (y1/2 + b) + sum_D0 y1 C~ moves to first order by
+        # <dy1, wg> <= ||dy1|| ||wg||: with the dual iterate held to the
+        # image's 1e-4, ||dy1|| <= 1e-4 ||y1||
+        tol_g = 1e-4 * ny1 * nwg
+        print("record: dG* %.3e (bound %.3e)" % (abs(r[1] - q[1]), tol_g), flush=True)
+        assert abs(r[1] - q[1]) <= tol_g
+        assert abs(r[2] - q[2]) <= 1e-4 * abs(q[0]) + tol_g
         assert r[3] == pytest.approx(q[3], rel=5e-2)
         assert r[4] == pytest.approx(q[4], rel=5e-2, abs=1e-6 * abs(q[0]) ** 0.5)
         assert r[5] == pytest.approx(q[5], rel=5e-2)
@@ -177,8 +200,8 @@ def test_c5_one_step_sampled():
     """2048^2 x 2880 x 3072: one step from a seeded iterate on seeded problem
     data (the inputs the stored oracle step used), in the launch
     configuration the benchmark's largest workload uses; the new u, vb1 and
-    vb2 at the stored sampled pixels and bins match (1e-5), and so do the
-    three arrays' norms."""
+    vb2 at the stored sampled pixels and bins match (1e-5; vb2: vb2_tol), and
+    so do the three arrays' norms."""
     print("c5 one step", flush=True)
     z = golden("c5_step_sampled.npz")
     n, N, M = 2048, 2880, 3072
@@ -196,12 +219,16 @@ def test_c5_one_step_sampled():
     pix, bins = z["pix"], z["bins"]
     pj, pi = torch.as_tensor(pix[:, 0], device=DEV), torch.as_tensor(pix[:, 1], device=DEV)
     bl, bk = torch.as_tensor(bins[:, 0], device=DEV), torch.as_tensor(bins[:, 1], device=DEV)
-    assert rel(host(gu[pj, pi]), z["u"]) <= 1e-5
+    ru = rel(host(gu[pj, pi]), z["u"])
+    assert ru <= 1e-5
     assert rel(host(g1[bl, bk]), z["vb1"]) <= 1e-5
-    assert rel(host(g2[0][pj, pi]), z["vb2_0"]) <= 1e-5
-    assert rel(host(g2[1][pj, pi]), z["vb2_1"]) <= 1e-5
+    tol2 = vb2_tol(ru, z["norms"][0], z["norms"][2])
+    print("c5: rel u %.2e, vb2 tolerance %.2e" % (ru, tol2), flush=True)
+    assert rel(host(g2[0][pj, pi]), z["vb2_0"]) <= tol2
+    assert rel(host(g2[1][pj, pi]), z["vb2_1"]) <= tol2
     norms = [float(torch.linalg.vector_norm(t.double())) for t in (gu, g1, g2)]
-    assert rel(norms, z["norms"]) <= 1e-5
+    assert rel(norms[:2], z["norms"][:2]) <= 1e-5
+    assert abs(norms[2] - z["norms"][2]) <= tol2 * z["norms"][2]
 
 
 def _launch_of(sv):
@@ -218,7 +245,7 @@ def test_c3_shape_batched_step(n):
     """Each image size of the uneven batch: two problems (seeded data and
     iterates) advanced as one batch solver with tuned launch choices, one
     step; each problem's new state at the stored sampled pixels and bins
-    matches the oracle (1e-5), and single solvers with the batch's launch
+    matches the oracle (1e-5; vb2: vb2_tol), and single solvers with the batch's launch
     choices give bitwise the batch's state."""
     print("c3 shape", n, flush=True)
     z = golden("c3_step_sampled.npz")
@@ -244,10 +271,12 @@ def test_c3_shape_batched_step(n):
         pix, bins = z[pre + "pix"], z[pre + "bins"]
         pj, pi = torch.as_tensor(pix[:, 0], device=DEV), torch.as_tensor(pix[:, 1], device=DEV)
         bl, bk = torch.as_tensor(bins[:, 0], device=DEV), torch.as_tensor(bins[:, 1], device=DEV)
-        assert rel(host(bu[b][pj, pi]), z[pre + "u"]) <= 1e-5
+        ru = rel(host(bu[b][pj, pi]), z[pre + "u"])
+        assert ru <= 1e-5
         assert rel(host(b1[b][bl, bk]), z[pre + "vb1"]) <= 1e-5
-        assert rel(host(b2[b][0][pj, pi]), z[pre + "vb2_0"]) <= 1e-5
-        assert rel(host(b2[b][1][pj, pi]), z[pre + "vb2_1"]) <= 1e-5
+        tol2 = vb2_tol(ru, z[pre + "norms"][0], z[pre + "norms"][2])
+        assert rel(host(b2[b][0][pj, pi]), z[pre + "vb2_0"]) <= tol2
+        assert rel(host(b2[b][1][pj, pi]), z[pre + "vb2_1"]) <= tol2
         sv = ct.Solver(plan, sinos[b], lam, masks[b], bounds[b], beta=beta, c=c, launch=launch)
         sv.import_state(*(gpu(a) for a in states[b]))
         sv.step(1)
