@@ -60,11 +60,11 @@ def fft_pair_bytes(n):
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def profile_records():
-    """The committed counter records of the benchmark workload (each None
+def profile_records(workload: str = "512x720x768"):
+    """The committed counter records of a workload (n x N x M; each None
     when missing or taken on other kernel sources)."""
     from paper_1810_03275_amd.profiling import load_record
-    stem = os.path.join(PROFILES, "pdrqs1_512x720x768_")
+    stem = os.path.join(PROFILES, f"pdrqs1_{workload}_")
     return {"sq": load_record(stem + "sq_counters.json"),
             "tcc": load_record(stem + "tcc_counters.json"),
             "traffic": load_record(stem + "traffic.json")}
@@ -236,15 +236,19 @@ def unrolled_run(ct, torch, K: int = 50, every: int = 10, count: int = 8):
             "dL_dlambda": float(lam.grad), "loss": float(loss.detach())}
 
 
-def large_run(ct, torch, iters: int):
+def large_run(ct, torch, iters: int, tune_cache=None):
     """The largest single slice: 2048^2, 2880 angles x 3072 bins, 4 metal discs,
-    alpha = 0.005; PDRQS1 iterations/s after setup and 10 warm-up iterations."""
+    alpha = 0.005; PDRQS1 iterations/s after setup and 10 warm-up iterations,
+    per-phase kernel durations (HIP events) and the rooflines of R_h, R_h^*
+    and the FFT pair (with the counters of this workload's profile records)."""
     import synth
     w = synth.workload("C5")
     plan, u0, mask, bound, x0, x1 = build_inputs(ct, torch, w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1)
+    launch = ct.Launch(tune_cache=tune_cache) if tune_cache else None
+    sv = ct.Solver(plan, u0, w.alpha, mask, bound, start_norm=x0, start_precond=x1,
+                   launch=launch)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sv.step(10)
@@ -254,13 +258,38 @@ def large_run(ct, torch, iters: int):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ph = sv.step_timed(5)
-    pairs = w.n * w.n * w.n_angles
+    pairs = float(w.n * w.n * w.n_angles)
+    lay, tun = sv.layout(), sv.tuning()
+    recs = profile_records(f"{w.n}x{w.n_angles}x{w.n_bins}")
+    fwd_suffix = "true>" if tun["tv_blocks"] > 0 else "false>"
+    t_fwd, t_adj, t_fft = (ph[k] * 1e-3 for k in ("radon_fwd", "radon_adj", "precond"))
+    adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
+                  else "ctpd::k_radon_adj")
+    adj_suffix = f", {lay['bp_pair_pixels']}>" if lay["bp_angles_per_position"] == 2 else ""
+    fft = {"duration_us": round(t_fft * 1e6, 2), "bound": "hbm", "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "algorithmic_bytes": fft_pair_bytes(w.n),
+           "achieved": round(fft_pair_bytes(w.n) / t_fft / 1e9, 1)}
+    fft["frac"] = round(fft["achieved"] / PEAK_HBM_GBS, 4)
+    if recs["traffic"]:
+        tb = [e["fetch_bytes"] + e["write_bytes"] for nm, e in recs["traffic"]["kernels"].items()
+              if nm.startswith("ctpd::k_fft_") and e["fetch_bytes"] and e["write_bytes"]
+              and "<true" in nm]
+        fft["traffic"] = sum(tb) if tb else None
+        if tb:
+            fft["hbm_frac_counters"] = round(sum(tb) / t_fft / 1e9 / PEAK_HBM_GBS, 4)
     return {"workload": "2048x2048, 2880 angles, 3072 bins, 4 metal discs, alpha=0.005",
             "iterations": iters, "it_per_s": round(iters / dt, 2),
             "ms_per_iteration": round(1e3 * dt / iters, 3), "setup_s": round(setup_s, 3),
             "gvox_angles_per_s": round(2 * pairs * iters / dt / 1e9, 1),
             "phase_us": {k: round(v * 1e3, 1) for k, v in ph.items()},
-            "layout": sv.layout(),
+            "layout": lay, "tuning": tun,
+            "roofline_radon_fwd": kernel_roofline(
+                recs, "ctpd::k_radon_fwd_multi<2", fwd_suffix, t_fwd, FLOPS_PER_PAIR * pairs,
+                radon_fwd_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
+            "roofline_radon_adj": kernel_roofline(
+                recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
+                radon_adj_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
+            "roofline_fft_pair": fft,
             "solve_1000_iterations_s": round(1000 * dt / iters + setup_s, 2)}
 
 
@@ -432,6 +461,16 @@ def cpu_baseline(w, budget_s: float):
                       f"given, not timed)"}
 
 
+def copy_calibration(torch):
+    """A plain 64 MiB device copy, three times: the reference dispatch of
+    known size that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    x = torch.ones(16 * 1024 * 1024, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +493,9 @@ def main():
                     help="also run a plain 64 MiB device copy (for counter scaling)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of launch-choice tuning results to reuse (and extend)")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 2048^2 workload (--large-iters iterations) and print "
+                         "its results (for profiling its kernels apart from the others)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -464,6 +506,14 @@ def main():
     import torch
     import paper_1810_03275_amd as ct
     import synth
+
+    if args.large_only:
+        out = {"large": large_run(ct, torch, max(args.large_iters, 1), args.tune_cache),
+               "system": system_info(torch)}
+        if args.copy_calibration:
+            copy_calibration(torch)
+        print(json.dumps(out), flush=True)
+        return
 
     w = synth.workload("C2")
     plan, u0, mask, bound, x0, x1 = build_inputs(ct, torch, w)
@@ -578,16 +628,12 @@ def main():
         out["preconditioning"] = precond_comparisons(ct, torch, args.comparison_iters)
     if args.large_iters > 0:
         torch.cuda.empty_cache()
-        out["large"] = large_run(ct, torch, args.large_iters)
+        out["large"] = large_run(ct, torch, args.large_iters, args.tune_cache)
     if args.unrolled_iters > 0:
         torch.cuda.empty_cache()
         out["unrolled"] = unrolled_run(ct, torch, args.unrolled_iters)
     if args.copy_calibration:
-        x = torch.ones(16 * 1024 * 1024, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
+        copy_calibration(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
