@@ -91,9 +91,21 @@ constexpr int kFpMaxWidth = 192;                    // staged columns per chunk
 constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixels per thread
 
 // Paired variant: 2 angles whose walk constants (T, A, B) are identical
-// share one walk; a wave owns one pair, a workgroup kPrWaves pairs.
+// share one walk.  A workgroup of kPrWaves waves owns kPrPairs pairs and a
+// block of kPrStrips strips (kPrStrips - 1 output bins); a wave owns two
+// pairs, its lanes in groups of 16 strips: lanes 0-15 pair A strips 0-15,
+// 16-31 pair B strips 0-15, 32-47 pair A strips 16-31, 48-63 pair B strips
+// 16-31.  So each half-wave reads 16 strips of two neighbouring angles at
+// nearly the same staged positions: at most ~25 distinct columns, within the
+// 32 LDS banks.
 constexpr int kPrWaves = 4;
+constexpr int kPrPairs = 2 * kPrWaves;
+constexpr int kPrStrips = 32;
 constexpr int kMultiMaxWidth = 128;  // staged columns per chunk
+
+// Strip offset and pair (0 = A, 1 = B) of lane `lane` of a paired wave.
+__host__ __device__ inline int pr_strip(int lane) { return ((lane >> 5) << 4) | (lane & 15); }
+__host__ __device__ inline int pr_pair(int lane) { return (lane >> 4) & 1; }
 
 struct FpGroup {
   int32_t first;  // index into the FpAngle array (pairs: pair index, 2 entries each)

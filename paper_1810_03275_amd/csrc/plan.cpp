@@ -252,7 +252,8 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
     const int rows_c = kFpRows;
     const int n_chunks = (n + rows_c - 1) / rows_c;
     const int max_width = multi ? kMultiMaxWidth : kFpMaxWidth;
-    const int per_group = (SL == 2) ? kPrWaves : kFpGroup;
+    const int per_group = (SL == 2) ? kPrPairs : kFpGroup;
+    const int strips = multi ? kPrStrips : kFpStrips;  // strips per block (one halo strip)
 
     // Work items (angles, or sets of SL angles) in class order; rep[i] holds
     // the walk constants of item i, icls[i] its classes (one per slot).
@@ -330,12 +331,12 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
       } else {
         G.kmin = (int)kmin;
         G.kmax = (int)kmax;
-        G.nblk = (int)((kmax - kmin + 1 + (kFpStrips - 2)) / (kFpStrips - 1));
+        G.nblk = (int)((kmax - kmin + 1 + (strips - 2)) / (strips - 1));
       }
       int wmax_g = 0;
       for (int b = 0; b < G.nblk; ++b) {
-        const int64_t kb = G.kmin + (int64_t)b * (kFpStrips - 1);
-        const int64_t klo = kb - 1, khi = kb + kFpStrips - 2;
+        const int64_t kb = G.kmin + (int64_t)b * (strips - 1);
+        const int64_t klo = kb - 1, khi = kb + strips - 2;
         // Chunks where some strip of the block meets the image: strip k meets
         // row q iff ps(k+1, q) > 0 and ps(k, q) < n, and ps decreases along q,
         // so a chunk [q0, q1] can be skipped when ps(khi+1, q0) <= 0 or
@@ -522,8 +523,9 @@ int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt,
       const int2 *reg = hp.regions.data() + G.region + (size_t)b * hp.n_chunks;
       for (int w = 0; w < slots; ++w) {
         const FpAngle fa = hp.dev[(size_t)hp.slots * (G.first + w)];
-        for (int lane = 0; lane < kFpStrips; ++lane) {
-          const int64_t k = G.kmin + (int64_t)b * (kFpStrips - 1) - 1 + lane;
+        const int strips = hp.paired ? kPrStrips : kFpStrips;
+        for (int lane = 0; lane < strips; ++lane) {
+          const int64_t k = G.kmin + (int64_t)b * (strips - 1) - 1 + lane;
           // rows of skipped chunks: no pixel of the strip inside the image
           for (int64_t q = 0; q < n; ++q) {
             const int64_t ch = q / hp.chunk_rows;

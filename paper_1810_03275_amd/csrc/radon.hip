@@ -1002,8 +1002,10 @@ __global__ __launch_bounds__(kFpThreads) void k_radon_fwd(
 // to hide LDS latency, and twice the staging per wave.)  The strips and the
 // output are those of k_radon_fwd, the walk a 64-bit fixed-point one
 // (walk_y0): its high word addresses the staged pixel, its low word is the
-// interpolation fraction, and a row costs one add.  A wave owns SL angles
-// (all walk the same positions), a workgroup MultiCfg<SL>::kWaves such sets.  Each chunk stages the same
+// interpolation fraction, and a row costs one add.  The SL angles of a set
+// walk the same positions; a wave owns two sets (pairs A and B) of 32
+// strips, interleaved in groups of 16 lanes (pr_strip, pr_pair), and a
+// workgroup MultiCfg<SL>::kWaves waves over one block of kPrStrips strips.  Each chunk stages the same
 // (row, column) window SL times -- once per angle, through that angle's
 // transpose/mirror mapping -- as rows of pitch kLdw, the SL copies of a row
 // adjacent, so that the reads of all SL angles at (row, ps) share addresses.
@@ -1165,9 +1167,10 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   fp_batch_offsets(u, sino, ep, n, N, M);
   const int2 wk = work[blockIdx.x];  // (group, block along the bins)
   const FpGroup grp = groups[wk.x];
-  // wave-uniform in a scalar register, so that the per-wave walk constants are too
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
+  const int so = pr_strip(lane);              // strip offset in the block
+  const int item = 2 * wave + pr_pair(lane);  // this lane's pair in the group
   const int blk = wk.y;
   const int nblk_eff = grp.nblk > 0 ? grp.nblk : 1;
   const FpAngle *pa = angs + SL * grp.first;
@@ -1194,17 +1197,17 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   }
   if (blk >= grp.nblk) return;
 
-  const int kb = grp.kmin + blk * (kFpStrips - 1);  // first output bin
-  const int k = kb - 1 + lane;                      // this lane's strip
+  const int kb = grp.kmin + blk * (kPrStrips - 1);  // first output bin
+  const int k = kb - 1 + so;                        // this lane's strip
   const uint32_t one = 1u << kFixBits;
   const int2 crange = chunk_range[grp.range + blk];
   const int ch_first = crange.x, ch_last = crange.y;
   const int q_first = ch_first * kRows;
-  const bool active = wave < grp.count;  // wave-uniform
+  const bool active = item < grp.count;
 
   // Lane state: the 64-bit fixed-point position y of the strip's first
   // pixel (walk_y0), its high word relative to the staged window while a
-  // chunk is processed.  Neighbouring lanes differ by exactly dfix, so a
+  // chunk is processed.  Neighbouring strips differ by exactly dfix, so a
   // strip's last pixel is always the pixel before the next strip's first
   // one.  A strip holds one or two pixels when dfix >= 2^32 (the second one
   // iff the fraction lies above ~lo(dfix)), else none or one (the first one
@@ -1213,10 +1216,10 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
   uint32_t L1 = 0u, L2 = 0xffffffffu;
   float a30 = 0.f;
   if (active) {
-    const FpAngle fa = pa[SL * wave];
+    const FpAngle fa = pa[SL * item];
     a30 = (float)fa.A * (1.0f / (float)one);
     E = ((uint64_t)kStride << 32) - fa.dlt;
-    y = walk_y0(kb - 1, q_first, fa.T, fa.A, fa.B) + (uint64_t)lane * fa.dfix;
+    y = walk_y0(kb - 1, q_first, fa.T, fa.A, fa.B) + (uint64_t)so * fa.dfix;
     const uint32_t dlo = (uint32_t)fa.dfix;
     if ((fa.dfix >> 32) != 0) {
       L2 = ~dlo;
@@ -1315,22 +1318,22 @@ __global__ __launch_bounds__(64 * MultiCfg<SL>::kWaves) void k_radon_fwd_multi(
     }
   }
 
-  if (active) {
-    // the strip's fraction-weighted sum: its pixels lie 1 - g and 2 - g
-    // pixel widths past the strip's start, i.e. A (1 - g) and A (2 - g) bin
-    // widths in 2^-30 units, with g = lo 2^-32
-    float qt[SL], qp[SL];
+  // the strip's fraction-weighted sum: its pixels lie 1 - g and 2 - g pixel
+  // widths past the strip's start, i.e. A (1 - g) and A (2 - g) bin widths
+  // in 2^-30 units, with g = lo 2^-32; the previous strip of the same pair
+  // is one lane down, or 17 for strip 16
+  float qt[SL], qp[SL];
+  const int src = lane - (so == 16 ? 17 : 1);
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    qt[s] = a30 * fmaf(G[s], -2.3283064365386963e-10f, P[s] + S[s]);
+    qp[s] = __shfl(qt[s], src < 0 ? 0 : src, 64);
+  }
+  if (active && so >= 1 && k <= grp.kmax && k < M) {
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      qt[s] = a30 * fmaf(G[s], -2.3283064365386963e-10f, P[s] + S[s]);
-      qp[s] = __shfl_up(qt[s], 1, 64);
-    }
-    if (lane >= 1 && k <= grp.kmax && k < M) {
-#pragma unroll
-      for (int s = 0; s < SL; ++s) {
-        const int l = pa[SL * wave + s].l;
-        if (l >= 0) fp_output(sino, ep, M, l, k, P[s] + (qp[s] - qt[s]));
-      }
+      const int l = pa[SL * item + s].l;
+      if (l >= 0) fp_output(sino, ep, M, l, k, P[s] + (qp[s] - qt[s]));
     }
   }
 }

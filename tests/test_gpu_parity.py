@@ -7,6 +7,7 @@ bound), 1e-6 for the pointwise kernels (a few FP32 roundings per element),
 1e-4 for the image after a fixed number of iterations.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -324,6 +325,48 @@ def test_tune_cache_file(tmp_path):
     b.step(7)
     for x, y in zip(a.export(), b.export()):
         assert torch.equal(x, y)
+
+
+_CHILD = r"""
+import sys
+import numpy as np
+import torch
+import paper_1810_03275_amd as ct
+z = np.load(sys.argv[1])
+dev = torch.device("cuda")
+t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+n, N, M = (int(v) for v in z["shape"])
+sv = ct.Solver(ct.Plan(n, N, M), t(z["u0"]), float(z["alpha"]), ct.pack_mask(z["mask"]), t(z["bound"]),
+               beta=500.0, c=2.0, launch=ct.Launch(tune_cache=sys.argv[2]))
+assert sv.tuning()["source"] == "file", sv.tuning()
+sv.step(7)
+np.savez(sys.argv[3], *[x.cpu().numpy() for x in sv.export()])
+"""
+
+
+def test_tune_cache_second_process(tmp_path):
+    """A second process that reads the tuning file makes the same launch
+    choices without timing and gives bitwise the same iterates as the
+    process that wrote it."""
+    import subprocess
+    import sys
+    n, N, M = 64, 90, 96
+    path = str(tmp_path / "tune.json")
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    a = ct.Solver(ct.Plan(n, N, M), gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=500.0,
+                  c=2.0, launch=ct.Launch(tune_cache=path))
+    assert a.tuning()["source"] == "timed" and a.tuning()["saved"]
+    a.step(7)
+    mine = [x.cpu().numpy() for x in a.export()]
+    inp, out = str(tmp_path / "in.npz"), str(tmp_path / "out.npz")
+    np.savez(inp, shape=np.array([n, N, M]), u0=u0, alpha=w.alpha, mask=mask, bound=bound)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _CHILD, inp, path, out], cwd=root,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    z = np.load(out)
+    for k, x in enumerate(mine):
+        assert np.array_equal(z[f"arr_{k}"], x)
 
 
 @pytest.mark.parametrize("hook", ["fuse_tv", "defer", "tv_blocks"])
