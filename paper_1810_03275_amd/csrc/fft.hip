@@ -165,15 +165,6 @@ __device__ inline void batched(int total, Load load, Use use) {
   }
 }
 
-// Twiddle table of a workgroup: copied into LDS behind the two row buffers
-// when it fits (TWL), else read from global memory.
-template <bool TWL>
-__device__ inline const float2 *stage_twiddles(float2 *lds, const float2 *__restrict__ tw, int L) {
-  if (!TWL) return tw;
-  batched(L, [&](int t) { return tw[t]; }, [&](int t, float2 v) { lds[t] = v; });
-  return lds;  // the caller's barrier precedes the first read
-}
-
 // Two neighbouring pixels (i0, i0 + 1; i0 even) of rows j and j + 1 of the
 // deferred backprojection from DS = d.S partial images, with 8-byte loads:
 // per pixel the slices' sum in slice order and the epilogue, the same
@@ -246,7 +237,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__res
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + RP * n;
-  const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
+  // the twiddle table is copied into LDS by the same loops that load the
+  // rows (its loads in flight with theirs: one memory round trip)
+  float2 *twl = sm + 2 * RP * n;
+  const float2 *twp = TWL ? twl : tw;
   const int pair0 = xcd_pair(blockIdx.x, gridDim.x) * RP;
   const int npair = min(RP, n / 2 - pair0);
   const size_t nn = (size_t)n * n;
@@ -262,22 +256,37 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_fwd(const float *__res
   if constexpr (DS > 0) {
     // two pixels of both rows per thread and step (n is even)
     const int hn = n / 2;
-    for (int t2 = threadIdx.x; t2 < npair * hn; t2 += kFftThreads) {
+    const int tot = npair * hn;  // >= n / 2: twiddles t2 and t2 + tot cover [0, n)
+    for (int t2 = threadIdx.x; t2 < tot; t2 += kFftThreads) {
       const int pr = (int)(((float)t2 + 0.5f) / (float)hn), i0 = 2 * (t2 - pr * hn);
+      float2 w0 = make_float2(0.f, 0.f), w1 = w0;
+      if (TWL && t2 < n) w0 = tw[t2];
+      if (TWL && t2 + tot < n) w1 = tw[t2 + tot];
       float2 r0, r1;
       deferred_two<DS>(yd, n, i0, 2 * (pair0 + pr), r0, r1);
       a[pr * n + i0] = make_float2(r0.x, r1.x);
       a[pr * n + i0 + 1] = make_float2(r0.y, r1.y);
+      if (TWL && t2 < n) twl[t2] = w0;
+      if (TWL && t2 + tot < n) twl[t2 + tot] = w1;
     }
   } else {
+    struct Ld {
+      float2 v, w;
+    };
     batched(
         npair * n,
         [&](int t) {
           const int pr = (int)(((float)t + 0.5f) / (float)n), i = t - pr * n;
           const int j = 2 * (pair0 + pr);
-          return make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]);
+          Ld r{make_float2(y[(size_t)j * n + i], y[(size_t)(j + 1) * n + i]),
+               make_float2(0.f, 0.f)};
+          if (TWL && t < n) r.w = tw[t];
+          return r;
         },
-        [&](int t, float2 v) { a[t] = v; });
+        [&](int t, Ld r) {
+          a[t] = r.v;
+          if (TWL && t < n) twl[t] = r.w;
+        });
   }
   __syncthreads();
   float2 *z = fft_rows<false>(a, b, npair, pl, twp);
@@ -313,28 +322,54 @@ __device__ inline float2 flat_twiddle(int j, int k1, int n, float sgn) {
 template <bool TWL>
 __global__ __launch_bounds__(kFftThreads) void k_fft_cols(float2 *__restrict__ spec, int n, int CP,
                                                   FftPlan pl, const float2 *__restrict__ tw,
-                                                  const float *__restrict__ mult, int twist) {
+                                                  const float *__restrict__ mult, int twist,
+                                                  int mpre) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + CP * n;
-  const float2 *twp = stage_twiddles<TWL>(sm + 2 * CP * n, tw, n);
+  // twiddles (TWL) and, with mpre, the multipliers are copied into LDS by
+  // the loop that loads the columns: one memory round trip for all three
+  float2 *twl = sm + 2 * CP * n;
+  float *mb = reinterpret_cast<float *>(twl + (TWL ? n : 0));
+  const float2 *twp = TWL ? twl : tw;
   const int half = n / 2 + 1;
   const int k10 = blockIdx.x * CP;
   const int ncol = min(CP, half - k10);
   spec += (size_t)blockIdx.y * half * n;
-  batched(ncol * n, [&](int t) { return spec[(size_t)k10 * n + t]; },
-          [&](int t, float2 v) {
-            if (twist) {
-              const int c = t / n;
-              v = cmul(v, flat_twiddle(t - c * n, k10 + c, n, -1.f));
-            }
-            a[t] = v;
-          });
+  struct Ld {
+    float2 v, w;
+    float m;
+  };
+  batched(
+      ncol * n,
+      [&](int t) {
+        Ld r{spec[(size_t)k10 * n + t], make_float2(0.f, 0.f), 0.f};
+        if (TWL && t < n) r.w = tw[t];
+        if (mpre) r.m = mult[(size_t)k10 * n + t];
+        return r;
+      },
+      [&](int t, Ld r) {
+        float2 v = r.v;
+        if (twist) {
+          const int c = t / n;
+          v = cmul(v, flat_twiddle(t - c * n, k10 + c, n, -1.f));
+        }
+        a[t] = v;
+        if (TWL && t < n) twl[t] = r.w;
+        if (mpre) mb[t] = r.m;
+      });
   __syncthreads();
   float2 *z = fft_rows<false>(a, b, ncol, pl, twp);
   float2 *other = (z == a) ? b : a;
-  batched(ncol * n, [&](int t) { return mult[(size_t)k10 * n + t]; },
-          [&](int t, float m) { z[t] = make_float2(m * z[t].x, m * z[t].y); });
+  if (mpre) {
+    for (int t = threadIdx.x; t < ncol * n; t += kFftThreads) {
+      const float m = mb[t];
+      z[t] = make_float2(m * z[t].x, m * z[t].y);
+    }
+  } else {
+    batched(ncol * n, [&](int t) { return mult[(size_t)k10 * n + t]; },
+            [&](int t, float m) { z[t] = make_float2(m * z[t].x, m * z[t].y); });
+  }
   __syncthreads();
   z = fft_rows<true>(z, other, ncol, pl, twp);
   for (int t = threadIdx.x; t < ncol * n; t += kFftThreads) {
@@ -353,17 +388,26 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const float2 *__re
                                                       int RP, FftPlan pl,
                                                       const float2 *__restrict__ tw,
                                                       const float *__restrict__ base,
-                                                      float *__restrict__ out) {
+                                                      float *__restrict__ out, int bpre) {
   extern __shared__ float2 sm[];
   float2 *a = sm;
   float2 *b = sm + RP * n;
-  const float2 *twp = stage_twiddles<TWL>(sm + 2 * RP * n, tw, n);
+  // twiddles (TWL) and, with bpre, the base rows are copied into LDS by the
+  // loop that loads the spectrum: one memory round trip for all three
+  float2 *twl = sm + 2 * RP * n;
+  float2 *gb = twl + (TWL ? n : 0);
+  const float2 *twp = TWL ? twl : tw;
   const int pair0 = xcd_pair(blockIdx.x, gridDim.x) * RP;
   const int npair = min(RP, n / 2 - pair0);
   const int half = n / 2 + 1;
   spec += (size_t)blockIdx.y * half * n;
   if (base != nullptr) base += (size_t)blockIdx.y * n * n;
   out += (size_t)blockIdx.y * n * n;
+  const bool pre = bpre && base != nullptr;
+  struct Ld {
+    float4 xy;
+    float2 w, g;
+  };
   batched(
       npair * n,
       [&](int t) {
@@ -371,19 +415,38 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows_inv(const float2 *__re
         const int j = 2 * (pair0 + pr);
         const int kk = k < half ? k : n - k;
         // X and Y of row pair j at frequency kk (contiguous in spec)
-        return *reinterpret_cast<const float4 *>(spec + (size_t)kk * n + j);
+        Ld r{*reinterpret_cast<const float4 *>(spec + (size_t)kk * n + j), make_float2(0.f, 0.f),
+             make_float2(0.f, 0.f)};
+        if (TWL && t < n) r.w = tw[t];
+        if (pre) {
+          const size_t o0 = (size_t)j * n + k;  // pixel k of rows j, j + 1
+          r.g = make_float2(base[o0], base[o0 + n]);
+        }
+        return r;
       },
-      [&](int t, float4 xy) {
+      [&](int t, Ld r) {
         const int k = t - (t / n) * n;
-        float2 X = make_float2(xy.x, xy.y), Y = make_float2(xy.z, xy.w);
+        float2 X = make_float2(r.xy.x, r.xy.y), Y = make_float2(r.xy.z, r.xy.w);
         if (k >= half) {  // Hermitian symmetry: conjugates of frequency n - k
           X.y = -X.y;
           Y.y = -Y.y;
         }
         a[t] = make_float2(X.x - Y.y, X.y + Y.x);  // X + i Y
+        if (TWL && t < n) twl[t] = r.w;
+        if (pre) gb[t] = r.g;
       });
   __syncthreads();
   float2 *z = fft_rows<true>(a, b, npair, pl, twp);
+  if (pre) {
+    for (int t = threadIdx.x; t < npair * n; t += kFftThreads) {
+      const int pr = t / n, i = t - pr * n;
+      const size_t o0 = (size_t)(2 * (pair0 + pr)) * n + i;
+      const float2 v = z[t], g = gb[t];
+      out[o0] = g.x + v.x;
+      out[o0 + n] = g.y + v.y;
+    }
+    return;
+  }
   batched(
       npair * n,
       [&](int t) {
@@ -431,6 +494,11 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
   const size_t rows_lds = 2 * sizeof(float2) * (size_t)RP * n;
   const bool twl = rows_lds + sizeof(float2) * n <= 65536;
   const size_t lds = rows_lds + (twl ? sizeof(float2) * n : 0);
+  // the column pass's multipliers and the inverse pass's base rows go to LDS
+  // with the loads they share a round trip with, where they fit
+  const size_t lds_cols = lds + sizeof(float) * (size_t)RP * n;
+  const size_t lds_inv = lds + sizeof(float2) * (size_t)RP * n;
+  const int mpre = lds_cols <= 65536, bpre = lds_inv <= 65536;
   const dim3 block(kFftThreads);
   const int CP = RP;
   const dim3 grow((n / 2 + RP - 1) / RP, nb);
@@ -456,16 +524,18 @@ int launch_apply_mult(const ct_precond *pc, const float *mult, const float *y,
   };
   if (twl) {
     rows_fwd(std::true_type{});
-    hipLaunchKernelGGL(k_fft_cols<true>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec, n,
-                       CP, pc->fp, pc->d_tw, mult, pc->twist);
-    hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
-                       spec, n, RP, pc->fp, pc->d_tw, base, out);
+    hipLaunchKernelGGL(k_fft_cols<true>, dim3((half + CP - 1) / CP, nb), block,
+                       mpre ? lds_cols : lds, s, spec, n, CP, pc->fp, pc->d_tw, mult, pc->twist,
+                       mpre);
+    hipLaunchKernelGGL(k_fft_rows_inv<true>, dim3((n / 2 + RP - 1) / RP, nb), block,
+                       bpre ? lds_inv : lds, s, spec, n, RP, pc->fp, pc->d_tw, base, out, bpre);
   } else {
     rows_fwd(std::false_type{});
-    hipLaunchKernelGGL(k_fft_cols<false>, dim3((half + CP - 1) / CP, nb), block, lds, s, spec,
-                       n, CP, pc->fp, pc->d_tw, mult, pc->twist);
-    hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3((n / 2 + RP - 1) / RP, nb), block, lds, s,
-                       spec, n, RP, pc->fp, pc->d_tw, base, out);
+    hipLaunchKernelGGL(k_fft_cols<false>, dim3((half + CP - 1) / CP, nb), block,
+                       mpre ? lds_cols : lds, s, spec, n, CP, pc->fp, pc->d_tw, mult, pc->twist,
+                       mpre);
+    hipLaunchKernelGGL(k_fft_rows_inv<false>, dim3((n / 2 + RP - 1) / RP, nb), block,
+                       bpre ? lds_inv : lds, s, spec, n, RP, pc->fp, pc->d_tw, base, out, bpre);
   }
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
