@@ -7,6 +7,7 @@ read from the GPU path.  Run from the repository root:
   GOLDEN_WORKERS=4 python tests/golden/make_golden.py c2   # ~100 core-minutes
   GOLDEN_WORKERS=2 python tests/golden/make_golden.py c5   # ~40 core-minutes
   python tests/golden/make_golden.py c3                    # ~15 min, one core
+  GOLDEN_WORKERS=7 python tests/golden/make_golden.py c5run  # ~2 hours
 
 GOLDEN_WORKERS > 1 splits the oracle's projector over angle blocks in that
 many worker processes.
@@ -27,6 +28,9 @@ c5: the 2048^2 x 2880 x 3072 geometry; one PDRQS1 step from a seeded
     size takes three projector passes of ~11 min each, so only sampled
     entries are stored: u_new at sampled pixels, vb1 at sampled bins, vb2 at
     sampled pixels of both planes, and the L2 norms of the three arrays.
+c5run: the 2048^2 geometry on the same kind of seeded problem data, beta and c
+    fixed as for c5, 20 PDRQS1 iterations from the zero state; the image at
+    sampled pixels, vb1 at sampled bins and the three arrays' norms.
 c3: the five image sizes of the uneven batch (n in {256, 384, 512, 768,
     1024}, N = round(1.4 n), M = 1.5 n); per size, two problems on seeded
     problem data and seeded iterates, one PDRQS1 step each with beta =
@@ -163,6 +167,38 @@ def make_c5(path: str) -> None:
     print("wrote", path, flush=True)
 
 
+C5_RUN_ITERS = 20
+C5_RUN_SEED = 5008
+
+
+def make_c5_run(path: str) -> None:
+    """20 PDRQS1 iterations from the zero state on the 2048^2 x 2880 x 3072
+    geometry, seeded problem data (the one-step check's kind), beta and c
+    fixed as there; the image at sampled pixels and its norm, and the norms of
+    vb1 and vb2, after the last iteration."""
+    n, N, M = 2048, 2880, 3072
+    g = geometry.Geometry(n, N, M)
+    u0, mask, bound = random_problem(N, M, C5_PROBLEM_SEED)
+    kw = {}
+    if workers() > 1:
+        ab = AngleBlocks(g, workers())
+        kw = dict(fwd=ab.fwd, adj=ab.adj)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, C5_LAMBDA), pdrq.Params(), beta=C5_BETA,
+                   c=C5_C, **kw)
+    st = pdrq.zero_state(s)
+    t0 = time.time()
+    for k in range(C5_RUN_ITERS):
+        st = pdrq.step(s, st)
+        print(f"  iteration {k + 1} ({time.time() - t0:.0f} s)", flush=True)
+    pix, bins = c5_samples(n, N, M, C5_RUN_SEED, 2000)
+    np.savez_compressed(path, beta=C5_BETA, c=C5_C, lam=C5_LAMBDA, iters=C5_RUN_ITERS, pix=pix,
+                        bins=bins, u=st.u[pix[:, 0], pix[:, 1]],
+                        vb1=st.vb1[bins[:, 0], bins[:, 1]],
+                        norms=np.array([np.linalg.norm(st.u), np.linalg.norm(st.vb1),
+                                        np.linalg.norm(st.vb2)]))
+    print("wrote", path, flush=True)
+
+
 def make_c3(path: str) -> None:
     arrays = {}
     for n in C3_SIZES:
@@ -184,5 +220,7 @@ if __name__ == "__main__":
         make_c5(os.path.join(HERE, "c5_step_sampled.npz"))
     elif which == "c3":
         make_c3(os.path.join(HERE, "c3_step_sampled.npz"))
+    elif which == "c5run":
+        make_c5_run(os.path.join(HERE, "c5_pdrqs1_20_sampled.npz"))
     else:
-        raise SystemExit("usage: make_golden.py c2|c5|c3")
+        raise SystemExit("usage: make_golden.py c2|c5|c3|c5run")
