@@ -87,8 +87,11 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
  *   thread, when at least half of the angles pair as theta, pi - theta, else
  *   one angle at a time), CT_BP_ONE_ANGLE, CT_BP_PAIRS4 or CT_BP_PAIRS8
  *   (CT_E_UNSUPPORTED when the angles do not pair).
- * fwd_angles_per_walk: angles that share one walk of R_h: 0 (2 when at least
- *   half of the angles pair up, else 1), 1 or 2. */
+ * fwd_angles_per_walk: angles that share one walk of R_h: 0 (4 for n >= 1024
+ *   when at least half of the angles form quadruples theta, pi/2 - theta,
+ *   pi - theta, pi/2 + theta; else 2 when at least half of them pair up; else
+ *   1), 1, 2 or 4 (a mode whose staged windows do not fit falls back to the
+ *   next one). */
 enum { CT_BP_AUTO = -1, CT_BP_ONE_ANGLE = 0, CT_BP_PAIRS4 = 4, CT_BP_PAIRS8 = 8 };
 typedef struct ct_plan_opts {
   int32_t bp_kernel;
@@ -108,6 +111,11 @@ int ct_plan_check(const ct_geom *g, const double *angles, int64_t *steps);
 /* The same for the plan that ct_plan_create_ex(g, angles, opts) would build. */
 int ct_plan_check_ex(const ct_geom *g, const double *angles, const ct_plan_opts *opts,
                      int64_t *steps);
+/* out[0] = angles that share one walk of R_h (1, 2 or 4), out[1] = forward-
+ * projector groups, out[2] = forward-projector workgroups per problem,
+ * out[3] = pixels per thread of the plan's default mirror-pair backprojector
+ * (4 or 8; 0: one angle at a time).  Errors: CT_E_INVALID. */
+int ct_plan_layout(const ct_plan *p, int32_t out[4]);
 int ct_plan_destroy(ct_plan *p);
 
 /* sino = R_h img (§3.1: R_h is the transpose of R_h^*; each pixel's value is

@@ -109,7 +109,8 @@ class Plan:
 
     bp_kernel: backprojector of standalone calls and untuned solvers ("auto",
     "one_angle", "pairs4", "pairs8"); fwd_angles_per_walk: angles sharing one
-    walk of R_h (0 automatic, 1 or 2)."""
+    walk of R_h (0 automatic, 1, 2 or 4; a mode whose windows do not fit falls
+    back to the next)."""
 
     def __init__(self, n: int, n_angles: int, n_bins: int, h: float = 1.0, ds: float = 1.0,
                  angles: Optional[np.ndarray] = None, bp_kernel: str = "auto",
@@ -131,6 +132,15 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def layout(self) -> dict:
+        """The plan's forward-projector layout (angles per walk, groups,
+        workgroups per problem) and default backprojector (mirror-pair
+        pixels per thread, 0: one angle at a time)."""
+        o = (ctypes.c_int32 * 4)()
+        _check(_L.ct_plan_layout(self.handle, o), "ct_plan_layout")
+        return {"angles_per_walk": o[0], "fwd_groups": o[1], "fwd_workgroups": o[2],
+                "bp_pair_pixels": o[3]}
 
     def close(self):
         if self._h:

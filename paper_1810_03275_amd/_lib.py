@@ -65,6 +65,7 @@ SIGNATURES = {
                                    POINTER(ctypes.c_int64)]),
     "ct_solver_tuning": (c_int32, [c_void_p, POINTER(c_int32)]),
     "ct_plan_destroy": (c_int32, [c_void_p]),
+    "ct_plan_layout": (c_int32, [c_void_p, POINTER(c_int32)]),
     "ct_radon_fwd": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ct_d0_estimate": (c_int32, [c_void_p, c_void_p, c_float, c_int32, c_float, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),

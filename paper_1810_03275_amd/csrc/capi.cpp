@@ -268,8 +268,9 @@ static int check_opts(const ct_plan_opts *o, ct_plan_opts *out) {
   if (!o) return CT_OK;
   if ((o->bp_kernel != CT_BP_AUTO && o->bp_kernel != CT_BP_ONE_ANGLE &&
        o->bp_kernel != CT_BP_PAIRS4 && o->bp_kernel != CT_BP_PAIRS8) ||
-      o->fwd_angles_per_walk < 0 || o->fwd_angles_per_walk > 2) {
-    set_error("ct_plan_create: bp_kernel must be a CT_BP_* value, fwd_angles_per_walk 0, 1 or 2");
+      o->fwd_angles_per_walk < 0 || o->fwd_angles_per_walk > 4 || o->fwd_angles_per_walk == 3) {
+    set_error("ct_plan_create: bp_kernel must be a CT_BP_* value, fwd_angles_per_walk 0, 1, 2 "
+              "or 4");
     return CT_E_INVALID;
   }
   *out = *o;
@@ -303,6 +304,19 @@ int ct_plan_create_ex(const ct_geom *g, const double *angles, const ct_plan_opts
     return rc;
   }
   *out = p;
+  return CT_OK;
+}
+
+int ct_plan_layout(const ct_plan *p, int32_t out[4]) {
+  clear_error();
+  if (!p || !out) {
+    set_error("ct_plan_layout: null argument");
+    return CT_E_INVALID;
+  }
+  out[0] = p->slots;
+  out[1] = p->n_groups;
+  out[2] = p->n_work;
+  out[3] = p->bp_kern0;
   return CT_OK;
 }
 
@@ -829,8 +843,8 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
                         (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_PDRQS2 ||
                          sv->method == CT_METHOD_PDRQS3);
   // the gradient-side update joins R_h's launch in the PDRQS1-type
-  // iterations when R_h walks angle pairs (launch_radon_fwd)
-  const bool tvf = sv->fuse_tv && p->slots == 2 &&
+  // iterations when R_h walks several angles at a time (launch_radon_fwd)
+  const bool tvf = sv->fuse_tv && p->slots >= 2 &&
                    (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_RICHARDSON ||
                     sv->method == CT_METHOD_PDRQS3);
   const bool kern_fixed = prm->bp_kernel != CT_BP_AUTO;

@@ -101,6 +101,13 @@ constexpr int kFpPrefetch = kFpRows * kFpMaxWidth / kFpThreads;  // staged pixel
 constexpr int kPrWaves = 4;
 constexpr int kPrPairs = 2 * kPrWaves;
 constexpr int kPrStrips = 32;
+// Four angles per walk (theta, pi/2 - theta, pi - theta, pi/2 + theta): the
+// same lane layout with quadruples in place of pairs, eight waves per
+// workgroup sharing the four staged copies; used for images of at least
+// kQuadMinN pixels a side.
+constexpr int kQuadWaves = 8;
+constexpr int kQuadItems = 2 * kQuadWaves;
+constexpr int kQuadMinN = 1024;
 constexpr int kMultiMaxWidth = 128;  // staged columns per chunk
 
 // Strip offset and pair (0 = A, 1 = B) of lane `lane` of a paired wave.

@@ -238,13 +238,16 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
   };
   std::vector<int> modes;
   {
+    // automatic: four angles per walk for large images whose angles form
+    // quadruples (there the projector is bound by VALU issue and the grid is
+    // large enough for workgroups of 16 quadruples), else pairs, else one
+    // (a forced mode whose windows come out too wide falls back to the next)
     const int forced = opt.fwd_angles_per_walk;
-    if (forced == 1 || forced == 2) {
-      modes.push_back(forced);
-    } else if (N >= 2 && 2 * complete(2) >= N) {
-      modes.push_back(2);
-    }
-    if (modes.empty() || modes.back() != 1) modes.push_back(1);
+    const bool quads = N >= 4 && 2 * complete(4) >= N;
+    const bool pairs = N >= 2 && 2 * complete(2) >= N;
+    if (forced == 4 || (forced == 0 && n >= kQuadMinN && quads)) modes.push_back(4);
+    if (forced == 2 || ((forced == 0 || forced == 4) && pairs)) modes.push_back(2);
+    modes.push_back(1);
   }
   for (size_t attempt = 0; attempt < modes.size(); ++attempt) {
     const int SL = modes[attempt];
@@ -252,7 +255,7 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
     const int rows_c = kFpRows;
     const int n_chunks = (n + rows_c - 1) / rows_c;
     const int max_width = multi ? kMultiMaxWidth : kFpMaxWidth;
-    const int per_group = (SL == 2) ? kPrPairs : kFpGroup;
+    const int per_group = (SL == 4) ? kQuadItems : (SL == 2) ? kPrPairs : kFpGroup;
     const int strips = multi ? kPrStrips : kFpStrips;  // strips per block (one halo strip)
 
     // Work items (angles, or sets of SL angles) in class order; rep[i] holds

@@ -1017,6 +1017,10 @@ template <>
 struct MultiCfg<2> {
   static constexpr int kWaves = kPrWaves, kRows = kFpRows;
 };
+template <>
+struct MultiCfg<4> {
+  static constexpr int kWaves = kQuadWaves, kRows = kFpRows;
+};
 
 constexpr int kMultiWidth = 128;              // staged columns per chunk
 // LDS buffers of staged rows: with 2, chunk c + 1 is stored while chunk c is
@@ -1345,8 +1349,8 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
   const int N = p->g.n_angles;
   dim3 grid(p->n_work, 1, nb);
   if (fused) *fused = false;
-  if (p->slots == 2) {
-    const dim3 block(64 * MultiCfg<2>::kWaves);
+  if (p->slots == 2 || p->slots == 4) {
+    const dim3 block(64 * (p->slots == 4 ? MultiCfg<4>::kWaves : MultiCfg<2>::kWaves));
     TvArgs ta{};
     if (tv != nullptr && tv->blocks > 0) {
       ta = *tv;
@@ -1355,9 +1359,14 @@ int launch_radon_fwd(const ct_plan *p, const float *u, float *out, hipStream_t s
     }
     auto go = [&](auto cf, auto tvf) {
       constexpr bool CF = decltype(cf)::value, TVF = decltype(tvf)::value;
-      hipLaunchKernelGGL((k_radon_fwd_multi<2, CF, TVF>), grid, block, 0, s, u, p->g.n,
-                         p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
-                         p->d_work, p->n_chunks, out, ep, N, p->n_work, ta);
+      if (p->slots == 4)
+        hipLaunchKernelGGL((k_radon_fwd_multi<4, CF, TVF>), grid, block, 0, s, u, p->g.n,
+                           p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
+                           p->d_work, p->n_chunks, out, ep, N, p->n_work, ta);
+      else
+        hipLaunchKernelGGL((k_radon_fwd_multi<2, CF, TVF>), grid, block, 0, s, u, p->g.n,
+                           p->g.n_bins, p->d_fp, p->d_groups, p->d_regions, p->d_chunk_range,
+                           p->d_work, p->n_chunks, out, ep, N, p->n_work, ta);
     };
     const bool with_tv = ta.blocks > 0;
     if (p->check_first) {

@@ -95,6 +95,53 @@ def test_radon_pair_parity(geo, kern):
     assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(fx) * np.linalg.norm(y)
 
 
+WALK_GEOMS = [(64, 90, 96, 1.0, 1.0), (63, 92, 96, 1.0, 1.0), (128, 180, 192, 0.7, 0.7),
+              (96, 1, 140, 1.0, 1.0), (66, 6, 100, 1.0, 1.0), (90, 180, 128, 1.0, 1.4),
+              (90, 180, 128, 1.0, 0.8)]
+
+
+@pytest.mark.parametrize("walk", [1, 2, 4])
+@pytest.mark.parametrize("geo", WALK_GEOMS, ids=lambda g: "x".join(map(str, g)))
+def test_forward_projector_walk_modes(geo, walk):
+    """R_h with one, two or four angles per walk (theta, pi/2 - theta,
+    pi - theta, pi/2 + theta; a mode whose windows do not fit, or whose angles
+    do not group, falls back to the next) against the oracle, on geometries
+    with incomplete quadruples (N = 92, 6, 1), ds != h and odd n; the mode the
+    plan took is at most the one asked for."""
+    n, N, M, h, ds = geo
+    print("walk modes", geo, walk, flush=True)
+    g = geometry.Geometry(n, N, M, h, ds)
+    rng = np.random.default_rng(n * 7 + N)
+    x = f32(rng.uniform(-1, 1, (n, n)))
+    plan = ct.Plan(n, N, M, h, ds, fwd_angles_per_walk=walk)
+    fx = host(plan.radon_fwd(gpu(x)))
+    assert rel(fx, radon.radon_fwd(g, x)) <= 1e-5
+    assert plan.layout()["angles_per_walk"] <= walk
+
+
+def test_pd_step_parity_four_angles_per_walk():
+    """Two PDRQS1 steps with R_h walking four angles at a time (metal trace,
+    tuned launch) against the oracle."""
+    n, N, M = 128, 180, 192
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M, fwd_angles_per_walk=4)
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c)
+    assert sv.layout()["angles_per_walk"] == 4
+    rng = np.random.default_rng(12)
+    u = f32(0.02 * rng.uniform(0, 1, (n, n)))
+    vb1 = f32(0.01 * rng.standard_normal((N, M)))
+    vb2 = f32(s.lam_t / s.params.tau * rng.standard_normal((2, n, n)))
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(2)
+    gu, g1, g2 = (host(t) for t in sv.export())
+    st = pdrq.step(s, pdrq.step(s, pdrq.state_from(s, u, vb1, vb2)))
+    assert rel(gu, st.u) <= 2e-5
+    assert rel(g1, st.vb1) <= 2e-5
+    assert rel(g2, st.vb2) <= 1e-4
+
+
 @pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4), (100, 60, 150)],
                          ids=lambda g: "x".join(map(str, g)))
 def test_backprojection_with_and_without_mirror_pairs(geo):
