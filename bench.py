@@ -103,6 +103,16 @@ def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, p
     return out
 
 
+def fwd_kernel(lay, tun):
+    """Name prefix and suffix of the R_h kernel a solver's iteration runs:
+    the multi-angle walk with its angles per walk and the fused
+    gradient-side update (or not), else the one-angle walk."""
+    w = lay["angles_per_walk"]
+    if w == 1:
+        return "ctpd::k_radon_fwd<", ">"
+    return f"ctpd::k_radon_fwd_multi<{w}", "true>" if tun["tv_blocks"] > 0 else "false>"
+
+
 def fft_pair_traffic(recs, lay):
     """Counter HBM bytes of the preconditioner's three kernels as the
     iteration runs them (the row pass that sums lay's slice count), or None."""
@@ -274,7 +284,7 @@ def large_run(ct, torch, iters: int, tune_cache=None):
     pairs = float(w.n * w.n * w.n_angles)
     lay, tun = sv.layout(), sv.tuning()
     recs = profile_records(f"{w.n}x{w.n_angles}x{w.n_bins}")
-    fwd_suffix = "true>" if tun["tv_blocks"] > 0 else "false>"
+    fwd_prefix, fwd_suffix = fwd_kernel(lay, tun)
     t_fwd, t_adj, t_fft = (ph[k] * 1e-3 for k in ("radon_fwd", "radon_adj", "precond"))
     adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
                   else "ctpd::k_radon_adj")
@@ -294,7 +304,7 @@ def large_run(ct, torch, iters: int, tune_cache=None):
             "phase_us": {k: round(v * 1e3, 1) for k, v in ph.items()},
             "layout": lay, "tuning": tun,
             "roofline_radon_fwd": kernel_roofline(
-                recs, "ctpd::k_radon_fwd_multi<2", fwd_suffix, t_fwd, FLOPS_PER_PAIR * pairs,
+                recs, fwd_prefix, fwd_suffix, t_fwd, FLOPS_PER_PAIR * pairs,
                 radon_fwd_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
             "roofline_radon_adj": kernel_roofline(
                 recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
@@ -574,8 +584,8 @@ def main():
     pairs = float(N_IMG * N_IMG * N_ANG)
     lay, tun = sv.layout(), sv.tuning()
     recs = profile_records()
-    fwd_suffix = "true>" if tun["tv_blocks"] > 0 else "false>"
-    roof = kernel_roofline(recs, "ctpd::k_radon_fwd_multi<2", fwd_suffix, t_fwd,
+    fwd_prefix, fwd_suffix = fwd_kernel(lay, tun)
+    roof = kernel_roofline(recs, fwd_prefix, fwd_suffix, t_fwd,
                            FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN), "alu",
                            PEAK_FP32_TFLOPS, "TFLOP/s")
     adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2

@@ -91,7 +91,9 @@ int ct_plan_create(const ct_geom *g, const double *angles, ct_plan **out);
  *   when at least half of the angles form quadruples theta, pi/2 - theta,
  *   pi - theta, pi/2 + theta; else 2 when at least half of them pair up; else
  *   1), 1, 2 or 4 (a mode whose staged windows do not fit falls back to the
- *   next one). */
+ *   next one).  Standalone calls and the solvers' set-up use this walk; a
+ *   solver's iteration uses it when it is fixed here, else the one its tuning
+ *   chooses (ct_params.fwd_walk). */
 enum { CT_BP_AUTO = -1, CT_BP_ONE_ANGLE = 0, CT_BP_PAIRS4 = 4, CT_BP_PAIRS8 = 8 };
 typedef struct ct_plan_opts {
   int32_t bp_kernel;
@@ -286,12 +288,18 @@ typedef struct ct_params {
                             used without timing; a new one is added to the file.
                             Reusing the file makes the launch choices, and so the
                             FP32 summation order, the same in every process. */
+  int32_t fwd_walk;      /* angles per walk of R_h in the iteration: 1, 2 or 4 (a mode
+                            whose staged windows do not fit falls back as in
+                            ct_plan_opts), 0: the plan's walk when its
+                            fwd_angles_per_walk was fixed, else tuned.  A walk other
+                            than the plan's gets forward tables of the solver's own. */
 } ct_params;
 
 /* ct_params.options bits. */
 enum {
-  CT_OPT_NO_TUNE = 1u,     /* no timing at set-up: the plan's backprojector, its default
-                              slice count and 256 gradient-side workgroups (unless fixed) */
+  CT_OPT_NO_TUNE = 1u,     /* no timing at set-up: the plan's walk and backprojector, its
+                              default slice count and 256 gradient-side workgroups (unless
+                              fixed) */
   CT_OPT_NO_DEFER = 2u,    /* sum R_h^*'s angle slices in a pass of its own, not in the
                               preconditioner's first FFT pass (same arithmetic) */
   CT_OPT_SEPARATE_TV = 4u, /* run the gradient-side update as its own launch (same
@@ -300,7 +308,8 @@ enum {
 };
 
 /* Fill *p with the defaults above (k_max = 0, gap_every = 0, bp_slices = 0,
- * bp_kernel = CT_BP_AUTO, tv_blocks = 0, options = 0, tune_cache = NULL). */
+ * bp_kernel = CT_BP_AUTO, tv_blocks = 0, options = 0, tune_cache = NULL,
+ * fwd_walk = 0). */
 void ct_params_default(ct_params *p);
 
 /* Objective of (C_h) at u [n][n] (device), in the problem's units (§3.2):
@@ -365,8 +374,9 @@ int ct_solver_info(const ct_solver *sv, double out[4]);
 int ct_solver_tuning(const ct_solver *sv, int32_t out[4]);
 
 /* out[0] = problems in the solver, out[1] = angle slices of R_h^*,
- * out[2] = angles that share one walk in R_h (1, 2 or 4),
- * out[3] = forward-projector groups,
+ * out[2] = angles that share one walk in R_h's iteration launches (1, 2 or
+ * 4; chosen by the solver's tuning unless fixed),
+ * out[3] = forward-projector groups of that walk,
  * out[4] = angles that share one bin coordinate in R_h^* (2: mirror pairs
  * theta, pi - theta; 1: one angle at a time; chosen by the solver's tuning),
  * out[5] = pixels per thread of the mirror-pair kernel (4 or 8; 0 without). */

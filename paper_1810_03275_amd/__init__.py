@@ -291,10 +291,13 @@ class Launch:
     the gradient-side update inside R_h's launch; tune=False: the plan's
     defaults instead of timing; defer / fuse_tv / graph=False: the slice sum,
     the gradient-side update or the iterations as launches of their own
-    (same arithmetic); tune_cache: path of a JSON file of tuning results."""
+    (same arithmetic); tune_cache: path of a JSON file of tuning results;
+    fwd_walk: angles per walk of R_h in the iteration (1, 2 or 4; None: the
+    plan's when its walk was fixed, else tuned)."""
     bp_slices: Optional[int] = None
     bp_kernel: Optional[str] = None
     tv_blocks: Optional[int] = None
+    fwd_walk: Optional[int] = None
     tune: bool = True
     defer: bool = True
     fuse_tv: bool = True
@@ -312,6 +315,7 @@ class Launch:
                      | (0 if self.fuse_tv else _lib.CT_OPT_SEPARATE_TV)
                      | (0 if self.graph else _lib.CT_OPT_NO_GRAPH))
         p.tune_cache = self.tune_cache.encode() if self.tune_cache else None
+        p.fwd_walk = int(self.fwd_walk or 0)
 
 
 def power_norm_noalloc(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] = None) -> float:

@@ -38,7 +38,7 @@ class CtParams(ctypes.Structure):
                 ("gap_every", c_int32), ("power_iters", c_int32), ("flags", c_uint32),
                 ("start_norm", c_void_p), ("start_precond", c_void_p),
                 ("bp_slices", c_int32), ("bp_kernel", c_int32), ("tv_blocks", c_int32),
-                ("options", c_uint32), ("tune_cache", c_char_p)]
+                ("options", c_uint32), ("tune_cache", c_char_p), ("fwd_walk", c_int32)]
 
 
 class CtPlanOpts(ctypes.Structure):

@@ -22,6 +22,7 @@ void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
 int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, ct_plan *p);
+int build_fwd_plan(const ct_plan *base, int walk, ct_plan *p);
 int check_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, int64_t *steps);
 void free_plan(ct_plan *p);
 int noalloc_prepare_device();
@@ -180,6 +181,11 @@ struct ct_solver {
   int bp_S = 1;               // angle slices of the backprojection (tuned)
   int bp_kern = 4;            // backprojector of the iteration (0 one angle, 4 or 8 pairs)
   int tv_blocks = 256;        // gradient-side workgroups in R_h's launch (0: own launch)
+  // R_h of the iteration: the plan itself, or forward tables of the solver's
+  // own for another number of angles per walk (fwd_alt, built for fwd_alt_walk)
+  const ct_plan *fwd = nullptr;
+  ct_plan *fwd_alt = nullptr;
+  int fwd_alt_walk = 0;
   uint32_t options = 0;       // CT_OPT_*
   // how the launch choices were made (ct_solver_tuning)
   int tune_source = 0, tune_timed = 0, tune_saved = 0;
@@ -211,6 +217,11 @@ static void solver_free(ct_solver *sv) {
     if (g) (void)hipGraphExecDestroy(g);
   if (sv->cap_stream) (void)hipStreamDestroy(sv->cap_stream);
   precond_free(&sv->pc);
+  if (sv->fwd_alt) {
+    free_plan(sv->fwd_alt);
+    delete sv->fwd_alt;
+    sv->fwd_alt = nullptr;
+  }
 }
 
 extern "C" {
@@ -237,6 +248,7 @@ void ct_params_default(ct_params *p) {
   p->tv_blocks = 0;
   p->options = 0;
   p->tune_cache = nullptr;
+  p->fwd_walk = 0;
 }
 
 static int check_geom(const ct_geom *g, const double *angles) {
@@ -557,6 +569,37 @@ static int solver_set_slices(ct_solver *sv, int S) {
   return CT_OK;
 }
 
+// R_h of the iteration with `walk` angles per walk: the plan's own tables
+// when they have that walk, else forward tables of the solver's own (a mode
+// that falls back to the plan's walk uses the plan's tables).
+static int solver_set_walk(ct_solver *sv, int walk) {
+  ct_plan *p = sv->plan;
+  if (walk != p->slots && sv->fwd_alt && sv->fwd_alt_walk == walk) {
+    sv->fwd = sv->fwd_alt;
+    return CT_OK;
+  }
+  if (sv->fwd_alt) {
+    free_plan(sv->fwd_alt);
+    delete sv->fwd_alt;
+    sv->fwd_alt = nullptr;
+    sv->fwd_alt_walk = 0;
+  }
+  sv->fwd = p;
+  if (walk == p->slots) return CT_OK;
+  ct_plan *a = new (std::nothrow) ct_plan();
+  if (!a) return CT_E_DEVICE;
+  const int rc = build_fwd_plan(p, walk, a);
+  if (rc != CT_OK || a->slots == p->slots) {
+    free_plan(a);
+    delete a;
+    return rc;
+  }
+  sv->fwd_alt = a;
+  sv->fwd_alt_walk = walk;
+  sv->fwd = a;
+  return CT_OK;
+}
+
 static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   const size_t nn = (size_t)sv->n * sv->n * sv->nb, NM = (size_t)sv->N * sv->M * sv->nb;
   CT_TRY_HIP(hipMemsetAsync(sv->u, 0, sizeof(float) * nn, s));
@@ -574,7 +617,7 @@ static int solver_zero_state(ct_solver *sv, hipStream_t s) {
   if (sv->method == CT_METHOD_PDRQS3) {
     const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
                      sv->s1, nullptr, nullptr, 8};
-    CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, s, &ep, sv->nb));
+    CT_TRY(launch_radon_fwd(sv->fwd, sv->u, nullptr, s, &ep, sv->nb));
   }
   sv->iters = 0;
   sv->have_dual = false;
@@ -595,7 +638,7 @@ static int cp_iter(ct_solver *sv, hipStream_t st) {
   const int nb = sv->nb;
   const SinoEpi ep{(float)(1.0 / sv->beta), step, sv->target, sv->mask, sv->vb1, nullptr,
                    nullptr, nullptr, 4};
-  CT_TRY(launch_radon_fwd(p, sv->ucp, nullptr, st, &ep, nb));
+  CT_TRY(launch_radon_fwd(sv->fwd, sv->ucp, nullptr, st, &ep, nb));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / h), sv->ucp, step, (float)sv->lam_t, sv->vb2,
                           nullptr, nullptr, 4, st, nb));
   CT_TRY(launch_radon_adj(p, sv->vb1, sv->vb2, (float)(-step / sv->beta), step, sv->u_next, st,
@@ -625,7 +668,7 @@ static int admm_iter(ct_solver *sv, hipStream_t st) {
   int cur = 0;
   for (int k = 0; k < sv->admm_cg; ++k) {
     // Hp = A^*(A p) - tau^2 div(nabla p)
-    CT_TRY(launch_radon_fwd(p, sv->cg_p, sv->r, st));
+    CT_TRY(launch_radon_fwd(sv->fwd, sv->cg_p, sv->r, st));
     CT_TRY(launch_grad(sv->n, inv_h, sv->cg_p, sv->w, st));
     CT_TRY(launch_radon_adj(p, sv->r, sv->w, inv_b2, -t2, sv->cg_Hp, st, 1, sv->bp_part,
                             sv->bp_S, sv->bp_kern));
@@ -641,7 +684,7 @@ static int admm_iter(ct_solver *sv, hipStream_t st) {
   // z-step and eta update from A u and nabla u (mu travels in the sigma field)
   const SinoEpi ep{inv_b, (float)sv->admm_mu, sv->target, nullptr, sv->vb1, sv->s1, nullptr,
                    nullptr, 6};
-  CT_TRY(launch_radon_fwd(p, sv->u, nullptr, st, &ep));
+  CT_TRY(launch_radon_fwd(sv->fwd, sv->u, nullptr, st, &ep));
   CT_TRY(launch_tv_update(sv->n, inv_h, sv->u, 0.f,
                           (float)(sv->lam_t / (sv->admm_mu * sv->tau * sv->tau)), sv->vb2,
                           sv->s2, nullptr, 5, st));
@@ -668,7 +711,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
                              sv->spec, def.S > 1 ? &def : nullptr));
     const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, nullptr, nullptr, sv->s1,
                      nullptr, nullptr, 5};
-    CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb));
+    CT_TRY(launch_radon_fwd(sv->fwd, sv->u_next, nullptr, st, &ep, nb));
     CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
                             sv->vb2, sv->s2, sv->w, mode == 2 ? 2 : 0, st, nb));
     std::swap(sv->u, sv->u_next);
@@ -714,7 +757,7 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
   tv.ubar = sv->ubar;
   tv.blocks = sv->fuse_tv ? sv->tv_blocks : 0;
   bool fused = false;
-  CT_TRY(launch_radon_fwd(p, sv->u_next, nullptr, st, &ep, nb, &tv, &fused));
+  CT_TRY(launch_radon_fwd(sv->fwd, sv->u_next, nullptr, st, &ep, nb, &tv, &fused));
   if (ev) CT_TRY_HIP(hipEventRecord(ev[3], st));
   if (!fused)
     CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, (float)(sv->lam_t / sv->tau),
@@ -726,12 +769,12 @@ static int solver_iter(ct_solver *sv, int mode, hipStream_t st, hipEvent_t *ev =
 }
 
 // Tuning results kept in a JSON file (ct_params.tune_cache): one entry per
-// line, {"key": "...", "bp_kernel": k, "bp_slices": S, "tv_blocks": b},
-// between a header line and a closing line.  The key names the device (its
-// architecture and compute-unit count), the library version, the geometry,
-// the batch size and the method class.
+// line, {"key": "...", "bp_kernel": k, "bp_slices": S, "tv_blocks": b,
+// "fwd_walk": w}, between a header line and a closing line.  The key names
+// the device (its architecture and compute-unit count), the library version,
+// the geometry, the plan's own walk, the batch size and the method class.
 struct TuneChoice {
-  int kern = 4, S = 1, tv_blocks = 256;
+  int kern = 4, S = 1, tv_blocks = 256, walk = 2;
 };
 
 static std::string tune_key(const ct_solver *sv, bool with_fft, bool tvf) {
@@ -771,7 +814,7 @@ static bool tune_line_parse(const std::string &line, std::string *key, TuneChoic
     return true;
   };
   return field("bp_kernel", &c->kern) && field("bp_slices", &c->S) &&
-         field("tv_blocks", &c->tv_blocks);
+         field("tv_blocks", &c->tv_blocks) && field("fwd_walk", &c->walk);
 }
 
 static std::vector<std::pair<std::string, TuneChoice>> tune_file_read(const char *path) {
@@ -808,9 +851,11 @@ static bool tune_file_store(const char *path, const std::string &key, const Tune
   if (!f) return false;
   std::fprintf(f, "{\"format\": \"ctpd-tune\", \"entries\": [\n");
   for (size_t q = 0; q < all.size(); ++q)
-    std::fprintf(f, "{\"key\": \"%s\", \"bp_kernel\": %d, \"bp_slices\": %d, \"tv_blocks\": %d}%s\n",
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"bp_kernel\": %d, \"bp_slices\": %d, \"tv_blocks\": %d, "
+                 "\"fwd_walk\": %d}%s\n",
                  all[q].first.c_str(), all[q].second.kern, all[q].second.S,
-                 all[q].second.tv_blocks, q + 1 < all.size() ? "," : "");
+                 all[q].second.tv_blocks, all[q].second.walk, q + 1 < all.size() ? "," : "");
   std::fprintf(f, "]}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), path) != 0) {
@@ -823,19 +868,23 @@ static bool tune_file_store(const char *path, const std::string &key, const Tune
 // A stored choice is used only if it is one this solver could make.
 static bool tune_choice_valid(const ct_solver *sv, const TuneChoice &c) {
   const bool kern_ok = c.kern == 0 || ((c.kern == 4 || c.kern == 8) && sv->plan->n_bpp > 0);
-  return kern_ok && c.S >= 1 && c.S <= kMaxSlices && c.tv_blocks >= 0 && c.tv_blocks <= 4096;
+  return kern_ok && c.S >= 1 && c.S <= kMaxSlices && c.tv_blocks >= 0 && c.tv_blocks <= 4096 &&
+         (c.walk == 1 || c.walk == 2 || c.walk == 4);
 }
 
-// The launch choices of the iteration: the backprojector (mirror pairs on
-// 32 x 32 or 32 x 64 tiles, or one angle at a time), its number of angle
-// slices, and the workgroups that run the gradient-side update inside R_h's
-// launch (0: a launch of its own).  What the params fix is kept; with
+// The launch choices of the iteration: the angles per walk of R_h, the
+// backprojector (mirror pairs on 32 x 32 or 32 x 64 tiles, or one angle at a
+// time), its number of angle slices, and the workgroups that run the
+// gradient-side update inside R_h's launch (0: a launch of its own).  What
+// the params (or a plan created with a fixed walk) fix is kept; with
 // CT_OPT_NO_TUNE the rest are the plan's defaults.  Otherwise, when nothing
 // is fixed, a choice recorded for this plan and batch size (an earlier
 // solver) or in the tune cache file is reused; else the candidates are timed
-// on the solver's own data (the caches s1, s2 of the zero state): the
-// backprojection together with the pass that sums its slices (the FFT pair
-// or the combine), then R_h's launch with each number of extra workgroups.
+// on the solver's own data (the caches s1, s2 of the zero state): R_h of the
+// zero image with each walk, together with the gradient-side update as the
+// iteration runs it; the backprojection together with the pass that sums its
+// slices (the FFT pair or the combine); then R_h's launch with each number of
+// extra workgroups.
 static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   ct_plan *p = sv->plan;
   const int N = sv->N;
@@ -844,31 +893,35 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
                          sv->method == CT_METHOD_PDRQS3);
   // the gradient-side update joins R_h's launch in the PDRQS1-type
   // iterations when R_h walks several angles at a time (launch_radon_fwd)
-  const bool tvf = sv->fuse_tv && p->slots >= 2 &&
+  const bool tvf = sv->fuse_tv &&
                    (sv->method == CT_METHOD_PDRQS1 || sv->method == CT_METHOD_RICHARDSON ||
                     sv->method == CT_METHOD_PDRQS3);
   const bool kern_fixed = prm->bp_kernel != CT_BP_AUTO;
   const bool S_fixed = prm->bp_slices > 0;
-  const bool tv_fixed = prm->tv_blocks > 0 || !tvf;
+  const bool walk_fixed = prm->fwd_walk != 0 || p->walk_opt != 0;
   TuneChoice ch;
   ch.kern = kern_fixed ? (p->n_bpp > 0 ? prm->bp_kernel : 0) : p->bp_kern0;
   ch.S = S_fixed ? prm->bp_slices : p->bp_slices;
   ch.tv_blocks = prm->tv_blocks > 0 ? prm->tv_blocks : std::min(sv->n, 256);
+  ch.walk = prm->fwd_walk != 0 ? prm->fwd_walk : p->slots;
+  const bool tv_fixed = prm->tv_blocks > 0 || !tvf || (walk_fixed && ch.walk == 1);
   sv->tune_source = 0;
   sv->tune_timed = 0;
   sv->tune_saved = 0;
-  auto apply = [&]() {
+  auto apply = [&]() -> int {
     sv->bp_kern = ch.kern;
     sv->tv_blocks = ch.tv_blocks;
+    CT_TRY(solver_set_walk(sv, ch.walk));
     return solver_set_slices(sv, ch.S);
   };
-  const bool all_free = !kern_fixed && !S_fixed && prm->tv_blocks == 0;
-  if ((prm->options & CT_OPT_NO_TUNE) || (kern_fixed && S_fixed && tv_fixed)) return apply();
+  const bool all_free = !kern_fixed && !S_fixed && prm->tv_blocks == 0 && !walk_fixed;
+  if ((prm->options & CT_OPT_NO_TUNE) || (kern_fixed && S_fixed && tv_fixed && walk_fixed))
+    return apply();
   std::string key;
   if (all_free) {
     for (const auto &t : p->tune_cache)
       if (t.nb == sv->nb && t.fft == (int)with_fft && t.tvf == (int)tvf) {
-        ch = TuneChoice{t.kern, t.S, t.tv_blocks};
+        ch = TuneChoice{t.kern, t.S, t.tv_blocks, t.walk};
         sv->tune_source = 2;
         return apply();
       }
@@ -878,8 +931,8 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
         if (e.first == key && tune_choice_valid(sv, e.second)) {
           ch = e.second;
           sv->tune_source = 3;
-          p->tune_cache.push_back(
-              ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern, ch.S, ch.tv_blocks});
+          p->tune_cache.push_back(ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern,
+                                                     ch.S, ch.tv_blocks, ch.walk});
           return apply();
         }
     }
@@ -924,6 +977,83 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
     sv->tune_timed += 1;
     return CT_OK;
   };
+  // R_h of the zero image with the gradient-side update of the zero state
+  // (u_new = 0 leaves vb2 = s2 = 0, and bar u = 0): the state is unchanged.
+  // The raw projections of the nb problems go to y1 ([nb][N][M]; it holds
+  // nothing before the first iteration).  blocks: the update's workgroups in
+  // R_h's launch (0: a launch of its own); R_h alone where the method does
+  // not run the update next to it.
+  const size_t nn = (size_t)sv->n * sv->n * sv->nb;
+  CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
+  const float sig = (float)sv->sigma, tau = (float)sv->tau;
+  const float inv_h = (float)(1.0 / p->g.h);
+  auto time_fwd = [&](const ct_plan *fp, int blocks, float *ms) -> int {
+    TvArgs tv;
+    tv.n = sv->n;
+    tv.inv_h = inv_h;
+    tv.u = sv->u_next;
+    tv.st = sig * tau;
+    tv.radius = (float)(sv->lam_t / sv->tau);
+    tv.vb2 = sv->vb2;
+    tv.s2 = sv->s2;
+    tv.wout = sv->w;
+    tv.mode = 0;
+    tv.ubar = sv->ubar;
+    tv.blocks = blocks;
+    auto run = [&]() -> int {
+      bool fused = false;
+      CT_TRY(launch_radon_fwd(fp, sv->u_next, sv->y1, st, nullptr, sv->nb, tvf ? &tv : nullptr,
+                              &fused));
+      if (tvf && !fused)
+        CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2,
+                                sv->s2, sv->w, 0, st, sv->nb, nullptr, sv->ubar));
+      return CT_OK;
+    };
+    return time_it(run, ms);
+  };
+  if (!walk_fixed) {
+    // 4, 2 and 1 angles per walk, each with its forward tables as built (a
+    // mode that falls back to another is timed as that other one)
+    struct PlanFree {
+      void operator()(ct_plan *a) const {
+        free_plan(a);
+        delete a;
+      }
+    };
+    std::unique_ptr<ct_plan, PlanFree> keep;  // the best walk's own tables
+    float best = 0.f;
+    int bestw = 0;
+    for (int w : {4, 2, 1}) {
+      std::unique_ptr<ct_plan, PlanFree> own;
+      const ct_plan *fp = p;
+      if (w != p->slots) {
+        own.reset(new (std::nothrow) ct_plan());
+        if (!own) return CT_E_DEVICE;
+        if (build_fwd_plan(p, w, own.get()) != CT_OK || own->slots != w) {
+          clear_error();
+          continue;
+        }
+        fp = own.get();
+      }
+      float ms = 0.f;
+      CT_TRY(time_fwd(fp, w >= 2 ? ch.tv_blocks : 0, &ms));
+      if (bestw == 0 || ms < best) {
+        best = ms;
+        bestw = w;
+        keep = std::move(own);
+      }
+    }
+    ch.walk = bestw;
+    if (keep) {
+      if (sv->fwd_alt) {
+        free_plan(sv->fwd_alt);
+        delete sv->fwd_alt;
+      }
+      sv->fwd_alt = keep.release();
+      sv->fwd_alt_walk = bestw;
+    }
+  }
+  CT_TRY(solver_set_walk(sv, ch.walk));
   if (cands.size() > 1) {
     float best = 0.f;
     Cand bestc = cands[0];
@@ -953,45 +1083,17 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
     ch.kern = bestc.kern;
     ch.S = bestc.S;
   }
-  if (!tv_fixed) {
-    // R_h of the zero image with the gradient-side update of the zero state
-    // (u_new = 0 leaves vb2 = s2 = 0, and bar u = 0): the state is unchanged.
-    // The raw projections of the nb problems go to y1 ([nb][N][M]; it holds
-    // nothing before the first iteration)
-    const size_t nn = (size_t)sv->n * sv->n * sv->nb;
-    CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
+  if (!tv_fixed && sv->fwd->slots >= 2) {
     std::vector<int> blocks;
     for (int b : {64, 128, 256, 512, 1024})
       if (b <= sv->n) blocks.push_back(b);
     if (blocks.empty()) blocks.push_back(sv->n);
     blocks.push_back(0);  // a launch of its own
-    const float sig = (float)sv->sigma, tau = (float)sv->tau;
-    const float inv_h = (float)(1.0 / p->g.h);
     float best = 0.f;
     int bestb = blocks[0];
     for (size_t c = 0; c < blocks.size(); ++c) {
-      TvArgs tv;
-      tv.n = sv->n;
-      tv.inv_h = inv_h;
-      tv.u = sv->u_next;
-      tv.st = sig * tau;
-      tv.radius = (float)(sv->lam_t / sv->tau);
-      tv.vb2 = sv->vb2;
-      tv.s2 = sv->s2;
-      tv.wout = sv->w;
-      tv.mode = 0;
-      tv.ubar = sv->ubar;
-      tv.blocks = blocks[c];
-      auto run = [&]() -> int {
-        bool fused = false;
-        CT_TRY(launch_radon_fwd(p, sv->u_next, sv->y1, st, nullptr, sv->nb, &tv, &fused));
-        if (!fused)
-          CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2,
-                                  sv->s2, sv->w, 0, st, sv->nb, nullptr, sv->ubar));
-        return CT_OK;
-      };
       float ms = 0.f;
-      CT_TRY(time_it(run, &ms));
+      CT_TRY(time_fwd(sv->fwd, blocks[c], &ms));
       if (c == 0 || ms < best) {
         best = ms;
         bestb = blocks[c];
@@ -1002,8 +1104,8 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   if (!sv->tune_timed) return apply();
   sv->tune_source = 1;
   if (all_free) {
-    p->tune_cache.push_back(
-        ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern, ch.S, ch.tv_blocks});
+    p->tune_cache.push_back(ct_plan::TuneEntry{sv->nb, (int)with_fft, (int)tvf, ch.kern, ch.S,
+                                               ch.tv_blocks, ch.walk});
     if (prm->tune_cache) sv->tune_saved = tune_file_store(prm->tune_cache, key, ch) ? 1 : 0;
   }
   return apply();
@@ -1396,9 +1498,10 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
       prm->tv_blocks > 4096 ||
       (prm->bp_kernel != CT_BP_AUTO && prm->bp_kernel != CT_BP_ONE_ANGLE &&
        prm->bp_kernel != CT_BP_PAIRS4 && prm->bp_kernel != CT_BP_PAIRS8) ||
-      (prm->options & ~15u) != 0) {
+      (prm->options & ~15u) != 0 || prm->fwd_walk < 0 || prm->fwd_walk > 4 ||
+      prm->fwd_walk == 3) {
     set_error("ct_solver_create: need 0 <= bp_slices <= 16, 0 <= tv_blocks <= 4096, a CT_BP_* "
-              "kernel and known CT_OPT_* bits");
+              "kernel, known CT_OPT_* bits and fwd_walk 0, 1, 2 or 4");
     return CT_E_INVALID;
   }
   if ((prm->bp_kernel == CT_BP_PAIRS4 || prm->bp_kernel == CT_BP_PAIRS8) && p->n_bpp == 0) {
@@ -1446,6 +1549,7 @@ static int solver_create(const ct_plan *p, const ct_problem *probs, int nb, cons
   ct_solver *sv = new (std::nothrow) ct_solver();
   if (!sv) return CT_E_DEVICE;
   sv->plan = const_cast<ct_plan *>(p);
+  sv->fwd = p;
   sv->nb = nb;
   sv->method = method;
   sv->n = p->g.n;
@@ -1538,8 +1642,8 @@ int ct_solver_layout(const ct_solver *sv, int32_t out[6]) {
   }
   out[0] = sv->nb;
   out[1] = sv->bp_S;
-  out[2] = sv->plan->slots;
-  out[3] = sv->plan->n_groups;
+  out[2] = sv->fwd->slots;
+  out[3] = sv->fwd->n_groups;
   const bool pairs = sv->plan->n_bpp > 0 && sv->bp_kern != 0;
   out[4] = pairs ? 2 : 1;
   out[5] = pairs ? sv->bp_kern : 0;
@@ -1739,7 +1843,7 @@ int ct_state_import(ct_solver *sv, const float *u, const float *vb1, const float
   const SinoEpi ep{(float)(1.0 / sv->beta), (float)sv->sigma, sv->target, sv->mask, sv->vb1,
                    sv->s1, nullptr, nullptr,
                    sv->method == CT_METHOD_PDRQS2 ? 5 : (sv->method == CT_METHOD_PDRQS3 ? 8 : 1)};
-  CT_TRY(launch_radon_fwd(sv->plan, sv->u, nullptr, st, &ep, sv->nb));
+  CT_TRY(launch_radon_fwd(sv->fwd, sv->u, nullptr, st, &ep, sv->nb));
   CT_TRY(launch_tv_update(sv->n, (float)(1.0 / sv->plan->g.h), sv->u,
                           (float)(sv->sigma * sv->tau), 0.0f, sv->vb2, sv->s2, nullptr, 1, st,
                           sv->nb));
@@ -2063,7 +2167,7 @@ int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *
     {
       const SinoEpi ep{(float)(1.0 / sv->beta), sig, sv->target, sv->mask, sv->vb1, sv->s1,
                        nullptr, nullptr, 1};
-      CT_TRY(launch_radon_fwd(p, sv->u, nullptr, st, &ep, nb));
+      CT_TRY(launch_radon_fwd(sv->fwd, sv->u, nullptr, st, &ep, nb));
       CT_TRY(launch_tv_update(n, inv_h, sv->u, st_, 0.0f, sv->vb2, sv->s2, nullptr, 1, st, nb));
     }
     for (int i = 0; i < cnt; ++i)
@@ -2080,7 +2184,7 @@ int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *
                                sv->spec));
       SinoEpi ep{(float)(1.0 / sv->beta), sig, nullptr, nullptr, t->Q1, t->V1, t->P, nullptr,
                  3};
-      CT_TRY(launch_radon_fwd(p, t->X, nullptr, st, &ep, nb));
+      CT_TRY(launch_radon_fwd(sv->fwd, t->X, nullptr, st, &ep, nb));
       CT_TRY(launch_img_tail(n, nb, st_, inv_h, t->X, t->Q2, t->Utot, t->U, t->V2, st));
     }
   }

@@ -166,11 +166,13 @@ struct ct_plan {
   // keeps its own choice; the plan is never changed by a solver)
   int bp_kern0 = 4;
   uint64_t angles_hash = 0;  // FNV-1a of explicit angles (0: theta_l = pi l / N)
+  std::vector<double> angles;  // the explicit angles (empty: theta_l = pi l / N)
+  int walk_opt = 0;            // angles per walk the plan was created with (0: automatic)
   // set-up tunings done on this plan, (batch size, FFT pair next, fused
   // gradient-side update) -> choice, so that solvers created again for the
   // same batch size skip the timing (a memo only: each solver copies it)
   struct TuneEntry {
-    int nb, fft, tvf, kern, S, tv_blocks;
+    int nb, fft, tvf, kern, S, tv_blocks, walk;
   };
   mutable std::vector<TuneEntry> tune_cache;
   int seg_pair = 0;       // staged bins per angle per tile of the pair kernel

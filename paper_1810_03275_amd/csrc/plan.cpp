@@ -429,6 +429,35 @@ static int plan_host(const ct_geom *g, const double *angles, const ct_plan_opts 
   return CT_OK;
 }
 
+// The forward projector's tables of a host plan, to the device.
+static int upload_fwd(const HostPlan &hp, ct_plan *p) {
+  p->check_first = hp.check_first;
+  p->paired = hp.paired;
+  p->slots = hp.slots;
+  p->chunk_rows = hp.chunk_rows;
+  p->n_groups = hp.n_groups;
+  p->max_blk = hp.max_blk;
+  p->n_chunks = hp.n_chunks;
+  p->wmax = hp.wmax;
+  p->n_work = (int)hp.work.size();
+  CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * hp.dev.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * hp.groups.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * hp.regions.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * hp.ranges.size()));
+  CT_TRY_HIP(hipMalloc(&p->d_work, sizeof(int2) * hp.work.size()));
+  CT_TRY_HIP(hipMemcpy(p->d_work, hp.work.data(), sizeof(int2) * hp.work.size(),
+                       hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_chunk_range, hp.ranges.data(), sizeof(int2) * hp.ranges.size(),
+                       hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_fp, hp.dev.data(), sizeof(FpAngle) * hp.dev.size(),
+                       hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_groups, hp.groups.data(), sizeof(FpGroup) * hp.groups.size(),
+                       hipMemcpyHostToDevice));
+  CT_TRY_HIP(hipMemcpy(p->d_regions, hp.regions.data(), sizeof(int2) * hp.regions.size(),
+                       hipMemcpyHostToDevice));
+  return CT_OK;
+}
+
 int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, ct_plan *p) {
   HostPlan hp;
   CT_TRY(plan_host(g, angles, opt, &hp));
@@ -440,7 +469,9 @@ int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, 
   else
     p->bp_kern0 = opt.bp_kernel == CT_BP_PAIRS8 ? 8 : 4;
   p->angles_hash = 0;
+  p->angles.clear();
   if (angles) {
+    p->angles.assign(angles, angles + N);
     // FNV-1a over the angles' bytes: part of the tuning cache's key
     uint64_t hsh = 1469598103934665603ull;
     const unsigned char *b = reinterpret_cast<const unsigned char *>(angles);
@@ -450,15 +481,8 @@ int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, 
     }
     p->angles_hash = hsh ? hsh : 1;
   }
+  p->walk_opt = opt.fwd_angles_per_walk;
   p->bp_slices = hp.bp_slices;
-  p->check_first = hp.check_first;
-  p->paired = hp.paired;
-  p->slots = hp.slots;
-  p->chunk_rows = hp.chunk_rows;
-  p->n_groups = hp.n_groups;
-  p->max_blk = hp.max_blk;
-  p->n_chunks = hp.n_chunks;
-  p->wmax = hp.wmax;
   CT_TRY_HIP(hipMalloc(&p->d_bp, sizeof(BpAngle) * N));
   p->n_bpp = (int)(hp.bpp.size() / 2);
   if (p->n_bpp > 0) {
@@ -468,24 +492,25 @@ int build_plan(const ct_geom *g, const double *angles, const ct_plan_opts &opt, 
   }
   if (p->bp_slices > 1)
     CT_TRY_HIP(hipMalloc(&p->d_bp_part, sizeof(float) * (size_t)p->bp_slices * n * n));
-  CT_TRY_HIP(hipMalloc(&p->d_fp, sizeof(FpAngle) * hp.dev.size()));
-  CT_TRY_HIP(hipMalloc(&p->d_groups, sizeof(FpGroup) * hp.groups.size()));
-  CT_TRY_HIP(hipMalloc(&p->d_regions, sizeof(int2) * hp.regions.size()));
-  CT_TRY_HIP(hipMalloc(&p->d_chunk_range, sizeof(int2) * hp.ranges.size()));
-  p->n_work = (int)hp.work.size();
-  CT_TRY_HIP(hipMalloc(&p->d_work, sizeof(int2) * hp.work.size()));
-  CT_TRY_HIP(hipMemcpy(p->d_work, hp.work.data(), sizeof(int2) * hp.work.size(),
-                       hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_chunk_range, hp.ranges.data(), sizeof(int2) * hp.ranges.size(),
-                       hipMemcpyHostToDevice));
   CT_TRY_HIP(hipMemcpy(p->d_bp, hp.bp.data(), sizeof(BpAngle) * N, hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_fp, hp.dev.data(), sizeof(FpAngle) * hp.dev.size(),
-                       hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_groups, hp.groups.data(), sizeof(FpGroup) * hp.groups.size(),
-                       hipMemcpyHostToDevice));
-  CT_TRY_HIP(hipMemcpy(p->d_regions, hp.regions.data(), sizeof(int2) * hp.regions.size(),
-                       hipMemcpyHostToDevice));
-  return CT_OK;
+  return upload_fwd(hp, p);
+}
+
+// A plan holding only the geometry and the forward projector's tables for
+// `walk` angles per walk (1, 2 or 4, falling back as plan creation does when
+// the staged windows come out too wide), built from the angles of `base`.
+// Only launch_radon_fwd may be given it.
+int build_fwd_plan(const ct_plan *base, int walk, ct_plan *p) {
+  ct_plan_opts opt{CT_BP_AUTO, walk};
+  HostPlan hp;
+  CT_TRY(plan_host(&base->g, base->angles.empty() ? nullptr : base->angles.data(), opt, &hp));
+  p->g = base->g;
+  p->device = base->device;
+  p->angles_hash = base->angles_hash;
+  p->walk_opt = walk;
+  p->n_bpp = 0;
+  p->bp_slices = 1;
+  return upload_fwd(hp, p);
 }
 
 // Host replay of the forward projector's walk over every (group, block, wave,

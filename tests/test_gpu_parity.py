@@ -142,6 +142,54 @@ def test_pd_step_parity_four_angles_per_walk():
     assert rel(g2, st.vb2) <= 1e-4
 
 
+@pytest.mark.parametrize("walk", [1, 2, 4])
+def test_pd_step_parity_solver_walk(walk):
+    """A solver whose iteration walks 1, 2 or 4 angles at a time on a plan
+    whose own walk is 2 (its standalone calls keep it): two PDRQS1 steps
+    against the oracle."""
+    n, N, M = 128, 180, 192
+    print("solver walk", walk, flush=True)
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    s = pdrq.setup(pdrq.Problem(g, u0, mask, bound, w.alpha), pdrq.Params(),
+                   f32(w.start_norm), f32(w.start_precond))
+    plan = ct.Plan(n, N, M)
+    assert plan.layout()["angles_per_walk"] == 2
+    sv = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), beta=s.beta, c=s.c,
+                   launch=ct.Launch(fwd_walk=walk))
+    assert sv.layout()["angles_per_walk"] == walk
+    assert plan.layout()["angles_per_walk"] == 2
+    rng = np.random.default_rng(12)
+    u = f32(0.02 * rng.uniform(0, 1, (n, n)))
+    vb1 = f32(0.01 * rng.standard_normal((N, M)))
+    vb2 = f32(s.lam_t / s.params.tau * rng.standard_normal((2, n, n)))
+    sv.import_state(gpu(u), gpu(vb1), gpu(vb2))
+    sv.step(2)
+    gu, g1, g2 = (host(t) for t in sv.export())
+    st = pdrq.step(s, pdrq.step(s, pdrq.state_from(s, u, vb1, vb2)))
+    assert rel(gu, st.u) <= 2e-5
+    assert rel(g1, st.vb1) <= 2e-5
+    assert rel(g2, st.vb2) <= 1e-4
+
+
+def test_tuning_times_the_walks():
+    """The set-up tuning times R_h with each number of angles per walk the
+    angles allow (4, 2 and 1 here), keeps a walk fixed by the plan, and
+    rejects an unknown walk."""
+    n, N, M = 128, 180, 192
+    w, g, u0, mask, bound = _small_metal_problem(n, N, M)
+    args = (gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound))
+    tuned = ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0)
+    t = tuned.tuning()
+    assert t["source"] == "timed"
+    # 3 walks, at least 2 backprojector choices and 2 update placements
+    assert t["timed"] >= 3 + 2 + 2
+    assert tuned.layout()["angles_per_walk"] in (1, 2, 4)
+    one = ct.Solver(ct.Plan(n, N, M, fwd_angles_per_walk=1), *args, beta=500.0, c=2.0)
+    assert one.layout()["angles_per_walk"] == 1
+    with pytest.raises(ct.CtpdError):
+        ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0, launch=ct.Launch(fwd_walk=3))
+
+
 @pytest.mark.parametrize("geo", [(64, 90, 96), (63, 90, 96), (2, 3, 4), (100, 60, 150)],
                          ids=lambda g: "x".join(map(str, g)))
 def test_backprojection_with_and_without_mirror_pairs(geo):
@@ -331,9 +379,12 @@ def test_tuning_is_cached_per_plan_and_batch_size():
     assert batch.tuning()["source"] == "timed"
     # a solver whose choice is fixed otherwise, created after the first one
     other = "one_angle" if lay0["bp_pair_pixels"] else "pairs4"
+    other_walk = 1 if lay0["angles_per_walk"] != 1 else 2
     fixed = ct.Solver(plan, *args, beta=s.beta, c=s.c,
-                      launch=ct.Launch(bp_kernel=other, bp_slices=3, tv_blocks=64))
+                      launch=ct.Launch(bp_kernel=other, bp_slices=3, tv_blocks=64,
+                                       fwd_walk=other_walk))
     assert fixed.tuning()["source"] == "fixed"
+    assert fixed.layout()["angles_per_walk"] == other_walk
     assert first.layout() == lay0
     st = pdrq.step(s, pdrq.zero_state(s))
     assert rel(ref1, st.u) <= 1e-5
@@ -363,6 +414,7 @@ def test_tune_cache_file(tmp_path):
     assert a.tuning()["source"] == "timed" and a.tuning()["saved"]
     doc = json.load(open(path))
     assert len(doc["entries"]) == 1
+    assert doc["entries"][0]["fwd_walk"] == a.layout()["angles_per_walk"]
     b = ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0,
                   launch=ct.Launch(tune_cache=path))
     assert b.tuning()["source"] == "file" and b.tuning()["timed"] == 0

@@ -83,12 +83,13 @@ def test_validation_errors_without_device(lib):
 def test_params_default(lib):
     from paper_1810_03275_amd import _lib
     p = _lib.CtParams()
+    p.fwd_walk = 7
     lib.ct_params_default(ctypes.byref(p))
     assert p.sigma == 1.0 and abs(p.tau - 8 ** -0.5) < 1e-15 and p.eps == 0.3
     assert p.c_safety == pytest.approx(1.1) and p.power_iters == 30 and p.c == 0.0
     # launch choices: all left to the tuning, no cache file
     assert p.bp_slices == 0 and p.bp_kernel == -1 and p.tv_blocks == 0 and p.options == 0
-    assert p.tune_cache is None
+    assert p.tune_cache is None and p.fwd_walk == 0
 
 
 def test_plan_options_validation(lib):
