@@ -7,7 +7,9 @@
   (tests/golden/c2_pdrqs1_500.npz).
 * 64^2 with metal: the record of one step from a shared state, every entry.
 * 2048^2 x 2880 x 3072: one step from a seeded iterate on seeded problem data
-  against the oracle's stored sampled entries (tests/golden/c5_step_sampled.npz).
+  against the oracle's stored sampled entries (tests/golden/c5_step_sampled.npz),
+  and 20 iterations from the zero state on the same kind of data
+  (tests/golden/c5_pdrqs1_20_sampled.npz).
 * The five image sizes of the uneven batch (256 ... 1024, N = 1.4 n,
   M = 1.5 n): one batched step per size against the oracle's stored sampled
   entries (tests/golden/c3_step_sampled.npz), and the batch bitwise equal to
@@ -231,13 +233,43 @@ def test_c5_one_step_sampled():
     assert abs(norms[2] - z["norms"][2]) <= tol2 * z["norms"][2]
 
 
+def test_c5_20_iterations_sampled():
+    """2048^2 x 2880 x 3072 on seeded problem data (the one-step check's kind),
+    beta and c fixed: 20 PDRQS1 iterations from the zero state as the solver
+    runs them (tuned launch, graph replay); the image at the stored sampled
+    pixels and its norm match the oracle's run (1e-4, the bound for the image
+    after a fixed iteration count), and so do vb1 at the sampled bins and the
+    norm of vb1; vb2's norm within 1e-3 (it carries the image's error through
+    the gradient, see vb2_tol)."""
+    print("c5 20 iterations", flush=True)
+    z = golden("c5_pdrqs1_20_sampled.npz")
+    n, N, M = 2048, 2880, 3072
+    u0, mask, bound = random_problem(N, M, mg.C5_PROBLEM_SEED)
+    plan = ct.Plan(n, N, M)
+    sv = ct.Solver(plan, gpu(u0), float(z["lam"]), ct.pack_mask(mask), gpu(bound),
+                   beta=float(z["beta"]), c=float(z["c"]))
+    del u0, bound
+    sv.step(int(z["iters"]))
+    gu, g1, g2 = sv.export()
+    pix, bins = z["pix"], z["bins"]
+    pj, pi = torch.as_tensor(pix[:, 0], device=DEV), torch.as_tensor(pix[:, 1], device=DEV)
+    bl, bk = torch.as_tensor(bins[:, 0], device=DEV), torch.as_tensor(bins[:, 1], device=DEV)
+    ru, r1 = rel(host(gu[pj, pi]), z["u"]), rel(host(g1[bl, bk]), z["vb1"])
+    norms = [float(torch.linalg.vector_norm(t.double())) for t in (gu, g1, g2)]
+    print("c5 20 iterations: rel u %.2e vb1 %.2e norms %s vs %s" % (ru, r1, norms, z["norms"]),
+          flush=True)
+    assert ru <= 1e-4 and r1 <= 1e-4
+    assert rel(norms[:2], z["norms"][:2]) <= 1e-4
+    assert abs(norms[2] - z["norms"][2]) <= 1e-3 * z["norms"][2]
+
+
 def _launch_of(sv):
     """The launch choices a solver ended up with, as fixed params."""
     lay, tun = sv.layout(), sv.tuning()
     kern = {0: "one_angle", 4: "pairs4", 8: "pairs8"}[lay["bp_pair_pixels"]]
     tvb = tun["tv_blocks"]
     return ct.Launch(bp_slices=lay["bp_slices"], bp_kernel=kern, tv_blocks=tvb or None,
-                     fuse_tv=tvb > 0)
+                     fuse_tv=tvb > 0, fwd_walk=lay["angles_per_walk"])
 
 
 @pytest.mark.parametrize("n", mg.C3_SIZES)
