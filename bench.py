@@ -42,6 +42,12 @@ def radon_fwd_bytes(n, N, M):
     return 4.0 * (n * n + 4 * N * M) + N * ((M + 31) // 32) * 4.0
 
 
+# ... of the gradient-side update when it runs inside R_h's launch: read vb2,
+# write vb2 and s2 (two components each); the image is R_h's read.
+def tv_fused_bytes(n):
+    return 4.0 * 6 * n * n
+
+
 # ... of one R_h^* launch inside the iteration: read s1 once, write the
 # image (its angle slices' partial images are written and read once more by
 # the preconditioner's row pass; counted there).
@@ -305,7 +311,9 @@ def large_run(ct, torch, iters: int, tune_cache=None):
             "layout": lay, "tuning": tun,
             "roofline_radon_fwd": kernel_roofline(
                 recs, fwd_prefix, fwd_suffix, t_fwd, FLOPS_PER_PAIR * pairs,
-                radon_fwd_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
+                radon_fwd_bytes(w.n, w.n_angles, w.n_bins)
+                + (tv_fused_bytes(w.n) if tun["tv_blocks"] > 0 else 0.0), "alu", PEAK_FP32_TFLOPS,
+                "TFLOP/s"),
             "roofline_radon_adj": kernel_roofline(
                 recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
                 radon_adj_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
@@ -586,7 +594,8 @@ def main():
     recs = profile_records()
     fwd_prefix, fwd_suffix = fwd_kernel(lay, tun)
     roof = kernel_roofline(recs, fwd_prefix, fwd_suffix, t_fwd,
-                           FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN), "alu",
+                           FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
+                           + (tv_fused_bytes(N_IMG) if tun["tv_blocks"] > 0 else 0.0), "alu",
                            PEAK_FP32_TFLOPS, "TFLOP/s")
     adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
                   else "ctpd::k_radon_adj")
