@@ -119,6 +119,15 @@ def fwd_kernel(lay, tun):
     return f"ctpd::k_radon_fwd_multi<{w}", "true>" if tun["tv_blocks"] > 0 else "false>"
 
 
+def adj_kernel(lay):
+    """Name prefix and suffix of the R_h^* kernel a solver's iteration runs:
+    mirror pairs (with their pixels per thread) or one angle at a time."""
+    per = lay["bp_angles_per_position"]
+    if per == 2:
+        return "ctpd::k_radon_adj_pair<", f", {lay['bp_pair_pixels']}>"
+    return "ctpd::k_radon_adj", "_adj"
+
+
 def fft_pair_traffic(recs, lay):
     """Counter HBM bytes of the preconditioner's three kernels as the
     iteration runs them (the row pass that sums lay's slice count), or None."""
@@ -292,9 +301,7 @@ def large_run(ct, torch, iters: int, tune_cache=None):
     recs = profile_records(f"{w.n}x{w.n_angles}x{w.n_bins}")
     fwd_prefix, fwd_suffix = fwd_kernel(lay, tun)
     t_fwd, t_adj, t_fft = (ph[k] * 1e-3 for k in ("radon_fwd", "radon_adj", "precond"))
-    adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
-                  else "ctpd::k_radon_adj")
-    adj_suffix = f", {lay['bp_pair_pixels']}>" if lay["bp_angles_per_position"] == 2 else ""
+    adj_prefix, adj_suffix = adj_kernel(lay)
     fft = {"duration_us": round(t_fft * 1e6, 2), "bound": "hbm", "peak": PEAK_HBM_GBS,
            "unit": "GB/s", "algorithmic_bytes": fft_pair_bytes(w.n),
            "achieved": round(fft_pair_bytes(w.n) / t_fft / 1e9, 1)}
@@ -597,9 +604,7 @@ def main():
                            FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
                            + (tv_fused_bytes(N_IMG) if tun["tv_blocks"] > 0 else 0.0), "alu",
                            PEAK_FP32_TFLOPS, "TFLOP/s")
-    adj_prefix = ("ctpd::k_radon_adj_pair<" if lay["bp_angles_per_position"] == 2
-                  else "ctpd::k_radon_adj")
-    adj_suffix = f", {lay['bp_pair_pixels']}>" if lay["bp_angles_per_position"] == 2 else ""
+    adj_prefix, adj_suffix = adj_kernel(lay)
     roof_adj = kernel_roofline(recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
                                radon_adj_bytes(N_IMG, N_ANG, N_BIN), "alu", PEAK_FP32_TFLOPS,
                                "TFLOP/s")

@@ -25,6 +25,9 @@ import torch
 from . import _lib
 
 _L = _lib.load()
+# backprojector codes (CT_BP_*) to names, and the names' pixels per thread
+_BP_NAMES = {v: k for k, v in _lib.BP_KERNELS.items() if v >= 0}
+_BP_PIXELS = {"one_angle": 0, "pairs4": 4, "pairs8": 8}
 
 __all__ = [
     "CtpdError", "Plan", "Precond", "Solver", "Launch", "radon_fwd", "radon_adj", "grad", "div",
@@ -135,12 +138,13 @@ class Plan:
 
     def layout(self) -> dict:
         """The plan's forward-projector layout (angles per walk, groups,
-        workgroups per problem) and default backprojector (mirror-pair
-        pixels per thread, 0: one angle at a time)."""
+        workgroups per problem) and default backprojector (its name, and
+        mirror-pair pixels per thread, 0: one angle at a time)."""
         o = (ctypes.c_int32 * 4)()
         _check(_L.ct_plan_layout(self.handle, o), "ct_plan_layout")
+        name = _BP_NAMES[o[3]]
         return {"angles_per_walk": o[0], "fwd_groups": o[1], "fwd_workgroups": o[2],
-                "bp_pair_pixels": o[3]}
+                "bp_kernel": name, "bp_pair_pixels": _BP_PIXELS[name]}
 
     def close(self):
         if self._h:
@@ -424,8 +428,9 @@ class Solver:
     def layout(self) -> dict:
         o = (ctypes.c_int32 * 6)()
         _check(_L.ct_solver_layout(self._h, o), "ct_solver_layout")
+        name = "one_angle" if o[4] == 1 else f"pairs{o[5]}"
         return {"problems": o[0], "bp_slices": o[1], "angles_per_walk": o[2], "fwd_groups": o[3],
-                "bp_angles_per_position": o[4], "bp_pair_pixels": o[5]}
+                "bp_angles_per_position": o[4], "bp_pair_pixels": o[5], "bp_kernel": name}
 
     def tuning(self) -> dict:
         """How the launch choices were made: source (fixed, timed, plan,

@@ -266,7 +266,7 @@ def test_c5_20_iterations_sampled():
 def _launch_of(sv):
     """The launch choices a solver ended up with, as fixed params."""
     lay, tun = sv.layout(), sv.tuning()
-    kern = {0: "one_angle", 4: "pairs4", 8: "pairs8"}[lay["bp_pair_pixels"]]
+    kern = lay["bp_kernel"]
     tvb = tun["tv_blocks"]
     return ct.Launch(bp_slices=lay["bp_slices"], bp_kernel=kern, tv_blocks=tvb or None,
                      fuse_tv=tvb > 0, fwd_walk=lay["angles_per_walk"])
