@@ -49,13 +49,17 @@ def small_batch(count, seed, sizes=(32, 48, 64)):
 NO_TUNE = ct.Launch(tune=False)
 
 
-@pytest.mark.parametrize("kern", ["auto", "pairs8", "one_angle"])
+@pytest.mark.parametrize("kern", ["auto", "pairs8", "one_angle", "walk4"])
 def test_batch_equals_single_slices(kern):
     """Three slices of one geometry in a batch solver vs three single solvers
     with the same launch choices: bitwise equal state after 25 iterations
-    (same kernels, same order)."""
+    (same kernels, same order); also with R_h walking four angles at a time
+    on a plan that walks two (forward tables of each solver's own)."""
     print("batch vs single", kern, flush=True)
-    launch = NO_TUNE if kern == "auto" else ct.Launch(tune=False, bp_kernel=kern)
+    if kern == "walk4":
+        launch = ct.Launch(tune=False, fwd_walk=4)
+    else:
+        launch = NO_TUNE if kern == "auto" else ct.Launch(tune=False, bp_kernel=kern)
     n, N, M = 64, 90, 96
     ws = [synth.batched_workload(i, (n, N, M, i % 3), iters=25) for i in range(3)]
     data = [build(w) for w in ws]
@@ -66,6 +70,8 @@ def test_batch_equals_single_slices(kern):
     sb = ct.SolverBatch(plan, sinos, 0.005, masks, bounds, launch=launch)
     info = sb.info()
     assert sb.layout()["problems"] == 3
+    if kern == "walk4":
+        assert sb.layout()["angles_per_walk"] == 4 and plan.layout()["angles_per_walk"] == 2
     sb.step(25)
     ub, vb1b, vb2b = (host(t) for t in sb.export())
     gb = sb.gap()

@@ -577,12 +577,16 @@ def test_errors_from_gpu_side():
     assert e.value.code == -4
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("walk", [None, 4, 1])
+def test_graph_replay_matches_eager(walk):
     """k iterations replayed from the captured HIP graph give bitwise the same
-    state as k single eager steps (same kernels, same order, no atomics)."""
+    state as k single eager steps (same kernels, same order, no atomics), also
+    when the solver's R_h walks another number of angles than the plan (its
+    own forward tables, captured into the graph)."""
+    print("graph replay, walk", walk, flush=True)
     w, g, u0, mask, bound = _small_metal_problem()
     plan = ct.Plan(g.n, g.n_angles, g.n_bins)
-    kw = dict(beta=500.0, c=2.0)
+    kw = dict(beta=500.0, c=2.0, launch=ct.Launch(fwd_walk=walk))
     a = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), **kw)
     b = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), **kw)
     a.step(11)           # 5 graph replays of 2 iterations + 1 eager
@@ -593,3 +597,5 @@ def test_graph_replay_matches_eager():
         assert torch.equal(x, y)
     assert a.info()["iters"] == b.info()["iters"] == 18
     assert np.array_equal(a.gap(), b.gap())
+    if walk is not None:
+        assert a.layout()["angles_per_walk"] == walk
