@@ -151,6 +151,12 @@ static int power_iterate(int n, int iters, float *x, float *y, double *d_red, in
 
 using namespace ctpd;
 
+// Cached iteration graphs per ping-pong parity: [parity] two iterations,
+// [2 + parity] two iterations whose last keeps y1, w and A u for a record,
+// [4 + parity] 2 kLongPairs iterations (the bulk of a long run in one launch).
+constexpr int kGraphSlots = 6;
+constexpr int kLongPairs = 8;
+
 struct ct_solver {
   ct_plan *plan = nullptr;
   ct_precond pc{};
@@ -197,10 +203,16 @@ struct ct_solver {
   // (u, u_next); captured on a private stream, replayed on the caller's stream.
   hipStream_t cap_stream = nullptr;
   // index parity + 2 * (the second iteration keeps y1, w and A u for a record)
-  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-  float *gexec_u[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[kGraphSlots] = {};
+  float *gexec_u[kGraphSlots] = {};
   bool use_graph = true;
 };
+
+static bool has_graphs(const ct_solver *sv) {
+  for (auto g : sv->gexec)
+    if (g) return true;
+  return false;
+}
 
 static void solver_free(ct_solver *sv) {
   if (!sv) return;
@@ -1381,19 +1393,20 @@ static int solver_setup(ct_solver *sv, const ct_problem *probs, const ct_params 
   return CT_OK;
 }
 
-// Capture two iterations of every solver in svs (all at the same ping-pong
-// parity) as one HIP graph on a private stream, the second in mode last_mode
-// (0, or 2 to keep y1, w and A u for a record); the pointers are back in
-// place after them.
-static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap, int last_mode,
-                        hipGraphExec_t *out) {
+// Capture 2 npairs iterations of every solver in svs (all at the same
+// ping-pong parity) as one HIP graph on a private stream, the last in mode
+// last_mode (0, or 2 to keep y1, w and A u for a record); the pointers are
+// back in place after them.
+static int capture_pairs(ct_solver *const *svs, int count, hipStream_t cap, int npairs,
+                         int last_mode, hipGraphExec_t *out) {
   hipGraph_t graph = nullptr;
   CT_TRY_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   int rc = CT_OK;
-  for (int it = 0; it < 2 && rc == CT_OK; ++it)
+  const int n_it = 2 * npairs;
+  for (int it = 0; it < n_it && rc == CT_OK; ++it)
     for (int q = 0; q < count && rc == CT_OK; ++q) {
       const int64_t it0 = svs[q]->iters;
-      rc = solver_iter(svs[q], it == 1 ? last_mode : 0, cap);
+      rc = solver_iter(svs[q], it == n_it - 1 ? last_mode : 0, cap);
       svs[q]->iters = it0;  // nothing ran
     }
   hipError_t e = hipStreamEndCapture(cap, &graph);
@@ -1410,13 +1423,15 @@ static int capture_pair(ct_solver *const *svs, int count, hipStream_t cap, int l
 
 
 // k iterations of every solver in svs (same iteration count and parity).
-// With k >= 3 they replay from HIP graphs of two iterations each: an odd k
-// first runs one iteration eagerly, the last pair is the graph whose second
-// iteration keeps y1, w and A u for a record, the others the plain one.
-// Smaller k run eagerly, the last in mode 2.  graphs[4] and cap are the
-// caller's cache (captured on first use per parity and kind).
+// With k >= 3 they replay from HIP graphs: an odd k first runs one iteration
+// eagerly; the last pair is the graph whose second iteration keeps y1, w and
+// A u for a record; the pairs before it run kLongPairs at a time from the
+// long graph, the rest from the plain two-iteration graph (the same
+// launches in the same order as eager steps).  Smaller k run eagerly, the
+// last in mode 2.  graphs[kGraphSlots] and cap are the caller's cache
+// (captured on first use per parity and kind).
 static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, hipStream_t *cap,
-                      hipGraphExec_t graphs[4], float *graph_u[4]) {
+                      hipGraphExec_t graphs[kGraphSlots], float *graph_u[kGraphSlots]) {
   int left = k;
   bool graphs_ok = true;
   for (int q = 0; q < count; ++q) graphs_ok = graphs_ok && svs[q]->use_graph;
@@ -1426,11 +1441,13 @@ static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, h
       left -= 1;
     }
     const int parity = (svs[0]->u < svs[0]->u_next) ? 0 : 1;
-    auto graph = [&](int last_mode, hipGraphExec_t *g) -> int {
-      const int idx = parity + (last_mode == 2 ? 2 : 0);
+    // kind 0: a plain pair, 1: the record pair, 2: kLongPairs plain pairs
+    auto graph = [&](int kind, hipGraphExec_t *g) -> int {
+      const int idx = parity + 2 * kind;
       if (!graphs[idx]) {
         if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
-        CT_TRY(capture_pair(svs, count, *cap, last_mode, &graphs[idx]));
+        CT_TRY(capture_pairs(svs, count, *cap, kind == 2 ? kLongPairs : 1, kind == 1 ? 2 : 0,
+                             &graphs[idx]));
         graph_u[idx] = svs[0]->u;
       }
       if (graph_u[idx] != svs[0]->u) {
@@ -1441,10 +1458,14 @@ static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, h
       return CT_OK;
     };
     const int pairs = left / 2;
-    hipGraphExec_t g0 = nullptr, g2 = nullptr;
-    if (pairs > 1) CT_TRY(graph(0, &g0));
-    CT_TRY(graph(2, &g2));
-    for (int q = 0; q + 1 < pairs; ++q) CT_TRY_HIP(hipGraphLaunch(g0, st));
+    const int longs = (pairs - 1) / kLongPairs;
+    const int singles = pairs - 1 - longs * kLongPairs;
+    hipGraphExec_t g0 = nullptr, g2 = nullptr, gl = nullptr;
+    if (longs > 0) CT_TRY(graph(2, &gl));
+    if (singles > 0) CT_TRY(graph(0, &g0));
+    CT_TRY(graph(1, &g2));
+    for (int q = 0; q < longs; ++q) CT_TRY_HIP(hipGraphLaunch(gl, st));
+    for (int q = 0; q < singles; ++q) CT_TRY_HIP(hipGraphLaunch(g0, st));
     CT_TRY_HIP(hipGraphLaunch(g2, st));
     for (int q = 0; q < count; ++q) svs[q]->iters += left;
     left = 0;
@@ -1673,7 +1694,7 @@ int ct_solver_set_fit(ct_solver *sv, int32_t fit, const float *aux, ct_stream s)
     set_error("ct_solver_set_fit: the data-term variants are for PDRQS1");
     return CT_E_UNSUPPORTED;
   }
-  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1] || sv->gexec[2] || sv->gexec[3]) {
+  if (sv->iters != 0 || has_graphs(sv)) {
     set_error("ct_solver_set_fit: set the data term before the first iteration");
     return CT_E_STATE;
   }
@@ -1711,7 +1732,7 @@ int ct_solver_set_admm(ct_solver *sv, int32_t cg_steps, double mu) {
     set_error("ct_solver_set_admm: not an ADMM solver");
     return CT_E_UNSUPPORTED;
   }
-  if (sv->iters != 0 || sv->gexec[0] || sv->gexec[1] || sv->gexec[2] || sv->gexec[3]) {
+  if (sv->iters != 0 || has_graphs(sv)) {
     set_error("ct_solver_set_admm: set the options before the first iteration");
     return CT_E_STATE;
   }
@@ -1876,8 +1897,8 @@ int ct_gap(ct_solver *sv, double *out, ct_stream s) {
 struct ct_group {
   std::vector<ct_solver *> svs;
   hipStream_t cap = nullptr;
-  hipGraphExec_t graphs[4] = {nullptr, nullptr, nullptr, nullptr};
-  float *graph_u[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t graphs[kGraphSlots] = {};
+  float *graph_u[kGraphSlots] = {};
   ~ct_group() {
     for (auto g : graphs)
       if (g) (void)hipGraphExecDestroy(g);

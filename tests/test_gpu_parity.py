@@ -591,11 +591,13 @@ def test_graph_replay_matches_eager(walk):
     b = ct.Solver(plan, gpu(u0), w.alpha, ct.pack_mask(mask), gpu(bound), **kw)
     a.step(11)           # 5 graph replays of 2 iterations + 1 eager
     a.step(7)            # other parity: second graph
-    for _ in range(18):
+    a.step(37)           # 1 eager, 2 replays of 16 iterations, 2 of 2
+    a.step(40)           # the other parity's long graph
+    for _ in range(95):
         b.step(1)
     for x, y in zip(a.export(), b.export()):
         assert torch.equal(x, y)
-    assert a.info()["iters"] == b.info()["iters"] == 18
+    assert a.info()["iters"] == b.info()["iters"] == 95
     assert np.array_equal(a.gap(), b.gap())
     if walk is not None:
         assert a.layout()["angles_per_walk"] == walk
