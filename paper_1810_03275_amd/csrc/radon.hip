@@ -381,6 +381,22 @@ struct PairStage {
   }
 };
 
+// Tile of workgroup (bx, by) of the gx x gy tiles of a z-slice.  Workgroups
+// are dealt to the 8 XCDs in turn by linear index; where gy is a multiple of
+// 8, the workgroups that land on XCD x take the tile rows of the x-th eighth
+// of the image, which are the rows the preconditioner's row pass reads on
+// XCD x, so that it finds the partial images in the L2 that wrote them (a
+// bijection of the grid onto itself).
+__device__ inline void xcd_row_tile(int &bx, int &by) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  if ((gy & 7) != 0) return;
+  const int L = bx + gx * by;
+  const int x = L & 7, k = L >> 3;
+  const int q = k / gx;
+  by = x * (gy >> 3) + q;
+  bx = k - q * gx;
+}
+
 // gridDim.z = (problems of a batch) x S slices of the pairs: problem b = z / S.
 // PIX pixels per thread: tiles of kBpTileI x 8 PIX.
 template <int R, int PIX>
@@ -397,7 +413,9 @@ __global__ __launch_bounds__(256) void k_radon_adj_pair(
   __shared__ ChainGeo geo_s[3][2 * kPairs];
   const int tx = threadIdx.x & (kBpTileI - 1);
   const int ty = threadIdx.x / kBpTileI;  // 0..7
-  const int i0 = blockIdx.x * kBpTileI, j0 = blockIdx.y * PS::kTileJ;
+  int bx = blockIdx.x, by = blockIdx.y;
+  xcd_row_tile(bx, by);
+  const int i0 = bx * kBpTileI, j0 = by * PS::kTileJ;
   const int i = i0 + tx;  // left-half column; its mirror is n - 1 - i
   const int jb = j0 + ty;
   double di = (double)i, dj = (double)jb;
