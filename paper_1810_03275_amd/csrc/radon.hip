@@ -384,9 +384,9 @@ struct PairStage {
 // Tile of workgroup (bx, by) of the gx x gy tiles of a z-slice.  Workgroups
 // are dealt to the 8 XCDs in turn by linear index; where gy is a multiple of
 // 8, the workgroups that land on XCD x take the tile rows of the x-th eighth
-// of the image, which are the rows the preconditioner's row pass reads on
-// XCD x, so that it finds the partial images in the L2 that wrote them (a
-// bijection of the grid onto itself).
+// of the image (a bijection of the grid onto itself): the tiles of one band
+// read overlapping detector segments of every angle and so share their XCD's
+// L2.
 __device__ inline void xcd_row_tile(int &bx, int &by) {
   const int gx = gridDim.x, gy = gridDim.y;
   if ((gy & 7) != 0) return;
