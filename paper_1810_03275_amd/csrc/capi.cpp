@@ -982,11 +982,30 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   auto time_it = [&](auto &&run, float *ms) -> int {
     CT_TRY(run());  // warm-up
     CT_TRY_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; ++r) CT_TRY(run());
+    for (int r = 0; r < 4; ++r) CT_TRY(run());
     CT_TRY_HIP(hipEventRecord(e1, st));
     CT_TRY_HIP(hipEventSynchronize(e1));
     CT_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
     sv->tune_timed += 1;
+    return CT_OK;
+  };
+  // The index of the fastest of count candidates: each is timed once per
+  // round (prepare(c), then run(c) through time_it), rounds interleaved so
+  // that clock and thermal drift reach every candidate alike, and its best
+  // round kept; ties go to the earlier candidate.
+  constexpr int kTuneRounds = 3;
+  auto pick = [&](int count, auto &&prepare, auto &&run, int *best) -> int {
+    std::vector<float> t(count, 0.f);
+    for (int r = 0; r < kTuneRounds; ++r)
+      for (int c = 0; c < count; ++c) {
+        CT_TRY(prepare(c));
+        float ms = 0.f;
+        CT_TRY(time_it([&]() { return run(c); }, &ms));
+        if (r == 0 || ms < t[c]) t[c] = ms;
+      }
+    *best = 0;
+    for (int c = 1; c < count; ++c)
+      if (t[c] < t[*best]) *best = c;
     return CT_OK;
   };
   // R_h of the zero image with the gradient-side update of the zero state
@@ -999,7 +1018,7 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
   const float sig = (float)sv->sigma, tau = (float)sv->tau;
   const float inv_h = (float)(1.0 / p->g.h);
-  auto time_fwd = [&](const ct_plan *fp, int blocks, float *ms) -> int {
+  auto time_fwd_run = [&](const ct_plan *fp, int blocks) -> int {
     TvArgs tv;
     tv.n = sv->n;
     tv.inv_h = inv_h;
@@ -1012,16 +1031,13 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
     tv.mode = 0;
     tv.ubar = sv->ubar;
     tv.blocks = blocks;
-    auto run = [&]() -> int {
-      bool fused = false;
-      CT_TRY(launch_radon_fwd(fp, sv->u_next, sv->y1, st, nullptr, sv->nb, tvf ? &tv : nullptr,
-                              &fused));
-      if (tvf && !fused)
-        CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2,
-                                sv->s2, sv->w, 0, st, sv->nb, nullptr, sv->ubar));
-      return CT_OK;
-    };
-    return time_it(run, ms);
+    bool fused = false;
+    CT_TRY(launch_radon_fwd(fp, sv->u_next, sv->y1, st, nullptr, sv->nb, tvf ? &tv : nullptr,
+                            &fused));
+    if (tvf && !fused)
+      CT_TRY(launch_tv_update(sv->n, inv_h, sv->u_next, sig * tau, tv.radius, sv->vb2, sv->s2,
+                              sv->w, 0, st, sv->nb, nullptr, sv->ubar));
+    return CT_OK;
   };
   if (!walk_fixed) {
     // 4, 2 and 1 angles per walk, each with its forward tables as built (a
@@ -1032,12 +1048,10 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
         delete a;
       }
     };
-    std::unique_ptr<ct_plan, PlanFree> keep;  // the best walk's own tables
-    float best = 0.f;
-    int bestw = 0;
+    std::vector<int> walks;
+    std::vector<std::unique_ptr<ct_plan, PlanFree>> tabs;  // null: the plan's own
     for (int w : {4, 2, 1}) {
       std::unique_ptr<ct_plan, PlanFree> own;
-      const ct_plan *fp = p;
       if (w != p->slots) {
         own.reset(new (std::nothrow) ct_plan());
         if (!own) return CT_E_DEVICE;
@@ -1045,73 +1059,64 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
           clear_error();
           continue;
         }
-        fp = own.get();
       }
-      float ms = 0.f;
-      CT_TRY(time_fwd(fp, w >= 2 ? ch.tv_blocks : 0, &ms));
-      if (bestw == 0 || ms < best) {
-        best = ms;
-        bestw = w;
-        keep = std::move(own);
-      }
+      walks.push_back(w);
+      tabs.push_back(std::move(own));
     }
-    ch.walk = bestw;
-    if (keep) {
+    int bi = 0;
+    CT_TRY(pick(
+        (int)walks.size(), [](int) { return CT_OK; },
+        [&](int c) {
+          return time_fwd_run(tabs[c] ? tabs[c].get() : p, walks[c] >= 2 ? ch.tv_blocks : 0);
+        },
+        &bi));
+    ch.walk = walks[bi];
+    if (tabs[bi]) {
       if (sv->fwd_alt) {
         free_plan(sv->fwd_alt);
         delete sv->fwd_alt;
       }
-      sv->fwd_alt = keep.release();
-      sv->fwd_alt_walk = bestw;
+      sv->fwd_alt = tabs[bi].release();
+      sv->fwd_alt_walk = ch.walk;
     }
   }
   CT_TRY(solver_set_walk(sv, ch.walk));
   if (cands.size() > 1) {
-    float best = 0.f;
-    Cand bestc = cands[0];
-    for (size_t c = 0; c < cands.size(); ++c) {
-      CT_TRY(solver_set_slices(sv, cands[c].S));
+    // what the iteration runs: with the FFT pair next, R_h^* with its slice
+    // sum deferred into the row pass and the pair itself; else R_h^* and the
+    // slice combine
+    auto run = [&](int c) -> int {
       const int kern = cands[c].kern;
-      // what the iteration runs: with the FFT pair next, R_h^* with its slice
-      // sum deferred into the row pass and the pair itself; else R_h^* and the
-      // slice combine
-      auto run = [&]() -> int {
-        if (!with_fft)
-          return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
-                                  sv->bp_part, sv->bp_S, kern);
-        BpDeferred def{};
-        CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
-                                sv->bp_part, sv->bp_S, kern, nullptr, nullptr, nullptr, &def));
-        return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st,
-                                 sv->nb, sv->spec, def.S > 1 ? &def : nullptr);
-      };
-      float ms = 0.f;
-      CT_TRY(time_it(run, &ms));
-      if (c == 0 || ms < best) {
-        best = ms;
-        bestc = cands[c];
-      }
-    }
-    ch.kern = bestc.kern;
-    ch.S = bestc.S;
+      if (!with_fft)
+        return launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb,
+                                sv->bp_part, sv->bp_S, kern);
+      BpDeferred def{};
+      CT_TRY(launch_radon_adj(p, sv->s1, sv->s2, 1.0f, 0.0f, sv->utmp, st, sv->nb, sv->bp_part,
+                              sv->bp_S, kern, nullptr, nullptr, nullptr, &def));
+      return launch_apply_mult(&sv->pc, sv->pc.d_mult, sv->utmp, sv->u, sv->u_next, st, sv->nb,
+                               sv->spec, def.S > 1 ? &def : nullptr);
+    };
+    int bi = 0;
+    CT_TRY(pick(
+        (int)cands.size(), [&](int c) { return solver_set_slices(sv, cands[c].S); }, run, &bi));
+    ch.kern = cands[bi].kern;
+    ch.S = cands[bi].S;
   }
   if (!tv_fixed && sv->fwd->slots >= 2) {
+    // the backprojection candidates wrote u_next (u + M^{-1} u_tmp, not zero
+    // where the zero state's s1 is not): zero again, so that the update
+    // leaves the state as it is
+    CT_TRY_HIP(hipMemsetAsync(sv->u_next, 0, sizeof(float) * nn, st));
     std::vector<int> blocks;
     for (int b : {64, 128, 256, 512, 1024})
       if (b <= sv->n) blocks.push_back(b);
     if (blocks.empty()) blocks.push_back(sv->n);
     blocks.push_back(0);  // a launch of its own
-    float best = 0.f;
-    int bestb = blocks[0];
-    for (size_t c = 0; c < blocks.size(); ++c) {
-      float ms = 0.f;
-      CT_TRY(time_fwd(sv->fwd, blocks[c], &ms));
-      if (c == 0 || ms < best) {
-        best = ms;
-        bestb = blocks[c];
-      }
-    }
-    ch.tv_blocks = bestb;
+    int bi = 0;
+    CT_TRY(pick(
+        (int)blocks.size(), [](int) { return CT_OK; },
+        [&](int c) { return time_fwd_run(sv->fwd, blocks[c]); }, &bi));
+    ch.tv_blocks = blocks[bi];
   }
   if (!sv->tune_timed) return apply();
   sv->tune_source = 1;

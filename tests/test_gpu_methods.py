@@ -227,9 +227,14 @@ def test_pdrqs3_matches_oracle():
                    c=inf["c"])
     st = pdrq.zero_state(s)
     done = 0
+    # a plan of its own, so that the first PDRQS3 solver times its launch
+    # choices on its own zero state (whose s1 is not zero) and the second
+    # reuses them
+    plan3 = ct.Plan(g.n, g.n_angles, g.n_bins)
     for k, tol in ((1, 1e-5), (60, 1e-4)):
-        sv = ct.Solver(plan, gpu(u0), w.alpha, mb, gpu(bound), beta=inf["beta"], c=inf["c"],
+        sv = ct.Solver(plan3, gpu(u0), w.alpha, mb, gpu(bound), beta=inf["beta"], c=inf["c"],
                        method="pdrqs3")
+        assert sv.tuning()["source"] == ("timed" if k == 1 else "plan")
         sv.step(k)
         while done < k:
             st = pdrq3.step3(s, st)
