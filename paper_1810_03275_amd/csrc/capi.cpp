@@ -1423,9 +1423,40 @@ static int capture_pairs(ct_solver *const *svs, int count, hipStream_t cap, int 
   hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   CT_TRY_HIP(ei);
+  // its first launch then finds it on the device already
+  CT_TRY_HIP(hipGraphUpload(*out, cap));
+  CT_TRY_HIP(hipStreamSynchronize(cap));
   return CT_OK;
 }
 
+
+// Captures every graph multi_step replays: the three kinds at both ping-pong
+// parities (the other parity with u and u_next exchanged for its capture and
+// restored after), so that no later step spends its time capturing.
+static int prepare_graphs(ct_solver *const *svs, int count, hipStream_t *cap,
+                          hipGraphExec_t graphs[kGraphSlots], float *graph_u[kGraphSlots]) {
+  bool all = true;
+  for (int i = 0; i < kGraphSlots; ++i) all = all && graphs[i] != nullptr;
+  if (all) return CT_OK;
+  if (!*cap) CT_TRY_HIP(hipStreamCreateWithFlags(cap, hipStreamNonBlocking));
+  for (int side = 0; side < 2; ++side) {
+    if (side == 1)
+      for (int q = 0; q < count; ++q) std::swap(svs[q]->u, svs[q]->u_next);
+    const int parity = (svs[0]->u < svs[0]->u_next) ? 0 : 1;
+    int rc = CT_OK;
+    for (int kind = 0; kind < 3 && rc == CT_OK; ++kind) {
+      const int idx = parity + 2 * kind;
+      if (graphs[idx]) continue;
+      rc = capture_pairs(svs, count, *cap, kind == 2 ? kLongPairs : 1, kind == 1 ? 2 : 0,
+                         &graphs[idx]);
+      if (rc == CT_OK) graph_u[idx] = svs[0]->u;
+    }
+    if (side == 1)
+      for (int q = 0; q < count; ++q) std::swap(svs[q]->u, svs[q]->u_next);
+    CT_TRY(rc);
+  }
+  return CT_OK;
+}
 
 // k iterations of every solver in svs (same iteration count and parity).
 // With k >= 3 they replay from HIP graphs: an odd k first runs one iteration
@@ -1433,13 +1464,15 @@ static int capture_pairs(ct_solver *const *svs, int count, hipStream_t cap, int 
 // A u for a record; the pairs before it run kLongPairs at a time from the
 // long graph, the rest from the plain two-iteration graph (the same
 // launches in the same order as eager steps).  Smaller k run eagerly, the
-// last in mode 2.  graphs[kGraphSlots] and cap are the caller's cache
-// (captured on first use per parity and kind).
+// last in mode 2.  graphs[kGraphSlots] and cap are the caller's cache, all
+// captured by the first call with k > 0 (prepare_graphs).
 static int multi_step(ct_solver *const *svs, int count, int k, hipStream_t st, hipStream_t *cap,
                       hipGraphExec_t graphs[kGraphSlots], float *graph_u[kGraphSlots]) {
   int left = k;
   bool graphs_ok = true;
   for (int q = 0; q < count; ++q) graphs_ok = graphs_ok && svs[q]->use_graph;
+  // the first step of any length captures them all
+  if (graphs_ok && k > 0) CT_TRY(prepare_graphs(svs, count, cap, graphs, graph_u));
   if (graphs_ok && left >= 3) {
     if (left & 1) {
       for (int q = 0; q < count; ++q) CT_TRY(solver_iter(svs[q], 0, st));
