@@ -424,6 +424,15 @@ def test_tune_cache_file(tmp_path):
     b.step(7)
     for x, y in zip(a.export(), b.export()):
         assert torch.equal(x, y)
+    # an entry without every field (a file of an older format) is not used:
+    # the next solver times its choices and writes a whole entry back
+    text = open(path).read()
+    open(path, "w").write(text.replace(', "fwd_walk": %d' % doc["entries"][0]["fwd_walk"], ""))
+    assert "fwd_walk" not in open(path).read()
+    c = ct.Solver(ct.Plan(n, N, M), *args, beta=500.0, c=2.0,
+                  launch=ct.Launch(tune_cache=path))
+    assert c.tuning()["source"] == "timed" and c.tuning()["saved"]
+    assert json.load(open(path))["entries"][0]["fwd_walk"] == c.layout()["angles_per_walk"]
 
 
 _CHILD = r"""
