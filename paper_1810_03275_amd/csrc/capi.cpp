@@ -992,17 +992,21 @@ static int solver_tune(ct_solver *sv, const ct_params *prm, hipStream_t st) {
   // The index of the fastest of count candidates: each is timed once per
   // round (prepare(c), then run(c) through time_it), rounds interleaved so
   // that clock and thermal drift reach every candidate alike, and its best
-  // round kept; ties go to the earlier candidate.
+  // round kept; after the first round only candidates within 15 % of the
+  // best are timed again.  Ties go to the earlier candidate.
   constexpr int kTuneRounds = 3;
   auto pick = [&](int count, auto &&prepare, auto &&run, int *best) -> int {
     std::vector<float> t(count, 0.f);
-    for (int r = 0; r < kTuneRounds; ++r)
+    for (int r = 0; r < kTuneRounds; ++r) {
+      const float cut = r == 0 ? 0.f : 1.15f * *std::min_element(t.begin(), t.end());
       for (int c = 0; c < count; ++c) {
+        if (r > 0 && t[c] > cut) continue;
         CT_TRY(prepare(c));
         float ms = 0.f;
         CT_TRY(time_it([&]() { return run(c); }, &ms));
         if (r == 0 || ms < t[c]) t[c] = ms;
       }
+    }
     *best = 0;
     for (int c = 1; c < count; ++c)
       if (t[c] < t[*best]) *best = c;
