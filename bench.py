@@ -533,8 +533,8 @@ def main():
                          "its results (for profiling its kernels apart from the others)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "how the path would shard over GPUs is described in the design notes, not run.",
+        print(f"bench.py: the benchmark runs on one GPU (asked for --gpus {args.gpus}); the "
+              "library has no multi-GPU path (sharding by angles is a design, not code).",
               file=sys.stderr)
         sys.exit(2)
 
