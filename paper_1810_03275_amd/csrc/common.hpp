@@ -141,12 +141,16 @@ constexpr int kBpPairChunk = kBpChunk / 4;
 constexpr int kBppPix = 4;                  // pixels per thread of the mirror-pair kernel
 constexpr int kBppTileJ = kBpRowStep * kBppPix;  // its tiles: kBpTileI x kBppTileJ
 
-// FFT plan (mixed radix 2/3/4, Stockham in LDS).
+// FFT plan (mixed radix 8/4/3/2, Stockham in LDS).
 struct FftPlan {
   int32_t L;
   int32_t npass;
   int32_t radix[24];
   uint64_t code;  // radix of pass i in bits [4 i, 4 i + 4) (a scalar the kernels decode)
+  // 1: radix-8 passes spread each butterfly over a quad of lanes (set where a
+  // single problem's row block has fewer butterflies than a workgroup has
+  // threads); fixed per length, so batches compute bitwise as single problems
+  int32_t quad8;
 };
 
 }  // namespace ctpd

@@ -3,7 +3,7 @@
 // x = base + F^{-1}(m * F(y)) for a real image y (n x n, n = 2^a 3^b, even)
 // and a real multiplier m that is even in each frequency.  Three kernels:
 //   row pass     : two real rows packed as one complex row, mixed-radix
-//                  (4/2/3) Stockham FFT in LDS, split into the two half
+//                  (8/4/3/2) Stockham FFT in LDS, split into the two half
 //                  spectra, written column-major: spec[k1][j];
 //   column pass  : per k1, FFT along j, multiply by m[k1][k2], inverse FFT;
 //   inverse rows : rebuild the two Hermitian spectra as one complex row,
@@ -109,6 +109,78 @@ __device__ inline void fft_pass(const float2 *a, float2 *b, int nrows, int L, in
   }
 }
 
+// Value of v in another lane of the same quad, chosen by the DPP quad
+// permutation CTRL (0x4E reads lane ^ 2, 0xB1 lane ^ 1).  All four lanes of
+// the quad must be active.
+template <int CTRL>
+__device__ inline float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// One radix-8 Stockham pass, the same transform as fft_pass<8>, with every
+// butterfly spread over the four lanes of a quad, for power-of-two lengths
+// L = 2^lgL (Ns = 2^lgNs).  Lane q takes inputs q and q + 4 and forms
+// a_q = x_q + x_{q+4} and b_q = (x_q - x_{q+4}) w8^q; the two 4-point DFTs of
+// a and b (the even and the odd outputs) then run across the quad as two
+// radix-2 steps, with partners q ^ 2 and q ^ 1, each one FMA with a lane sign
+// (+1 keeps the sum, -1 the difference).  A pass of L/8 butterflies keeps four
+// times as many lanes busy, with no lane-dependent branches.
+template <bool INV>
+__device__ inline void fft_pass8_quad(const float2 *a, float2 *b, int nrows, int lgL, int lgNs,
+                                      const float2 *tw) {
+  const int lgnbf = lgL - 3;  // L/8 butterflies per row
+  const int lgstep = lgL - lgNs - 3;  // twiddle stride L / (8 Ns)
+  const float sgn = INV ? 1.f : -1.f;
+  const float c = 0.70710678118654752440f;  // sqrt(2)/2
+  // kFftThreads is a multiple of 4, so a quad's lanes share t >> 2 in every
+  // iteration and leave the loop together
+  const int q = threadIdx.x & 3;
+  const float2 w8 = q == 0   ? make_float2(1.f, 0.f)
+                    : q == 1 ? make_float2(c, sgn * c)
+                    : q == 2 ? make_float2(0.f, sgn)
+                             : make_float2(-c, sgn * c);  // exp(sgn i pi q / 4)
+  const float s1 = q < 2 ? 1.f : -1.f, s2 = (q & 1) ? -1.f : 1.f;
+  const bool rot = q == 3;  // the odd difference of the first step times (sgn i)
+  const int p = ((q & 1) << 1) | (q >> 1);  // the 4-point output lane q ends with
+  const int mj = (1 << lgnbf) - 1, mk = (1 << lgNs) - 1;
+  for (int t = threadIdx.x; t < (nrows << (lgnbf + 2)); t += kFftThreads) {
+    const int bf = t >> 2;
+    const int row = bf >> lgnbf, jj = bf & mj;
+    const int jq = jj >> lgNs, k = jj & mk;
+    const float2 *in = a + (row << lgL) + jj;
+    float2 x0 = in[q << lgnbf], x1 = in[(q + 4) << lgnbf];
+    float2 w0 = tw[(k * q) << lgstep], w1 = tw[(k * (q + 4)) << lgstep];  // tw[0] = 1
+    if (INV) {
+      w0.y = -w0.y;
+      w1.y = -w1.y;
+    }
+    x0 = cmul(x0, w0);
+    x1 = cmul(x1, w1);
+    float2 av = make_float2(x0.x + x1.x, x0.y + x1.y);
+    float2 bv = cmul(make_float2(x0.x - x1.x, x0.y - x1.y), w8);
+    {  // partner q ^ 2
+      const float2 ap = make_float2(quad_perm<0x4E>(av.x), quad_perm<0x4E>(av.y));
+      const float2 bp = make_float2(quad_perm<0x4E>(bv.x), quad_perm<0x4E>(bv.y));
+      av = make_float2(fmaf(s1, av.x, ap.x), fmaf(s1, av.y, ap.y));
+      bv = make_float2(fmaf(s1, bv.x, bp.x), fmaf(s1, bv.y, bp.y));
+    }
+    if (rot) {
+      av = make_float2(-sgn * av.y, sgn * av.x);
+      bv = make_float2(-sgn * bv.y, sgn * bv.x);
+    }
+    {  // partner q ^ 1
+      const float2 ap = make_float2(quad_perm<0xB1>(av.x), quad_perm<0xB1>(av.y));
+      const float2 bp = make_float2(quad_perm<0xB1>(bv.x), quad_perm<0xB1>(bv.y));
+      av = make_float2(fmaf(s2, av.x, ap.x), fmaf(s2, av.y, ap.y));
+      bv = make_float2(fmaf(s2, bv.x, bp.x), fmaf(s2, bv.y, bp.y));
+    }
+    // output 2p of the 8-point DFT is the a-DFT's p, output 2p + 1 the b-DFT's
+    float2 *out = b + (row << lgL) + (jq << (lgNs + 3)) + k;
+    out[(2 * p) << lgNs] = av;
+    out[(2 * p + 1) << lgNs] = bv;
+  }
+}
+
 // Stockham FFT of `nrows` rows of length L held in LDS buffer a (row stride
 // L); b is the ping-pong buffer.  Returns the buffer holding the result.
 // INV selects the inverse (conjugate) transform, unnormalized.
@@ -119,7 +191,9 @@ __device__ float2 *fft_rows(float2 *a, float2 *b, int nrows, const FftPlan &pl,
   int Ns = 1;
   for (int ps = 0; ps < pl.npass; ++ps) {
     const int R = (int)((pl.code >> (4 * ps)) & 15u);
-    if (R == 8)
+    if (R == 8 && pl.quad8)
+      fft_pass8_quad<INV>(a, b, nrows, __builtin_ctz(L), __builtin_ctz(Ns), tw);
+    else if (R == 8)
       fft_pass<8, INV>(a, b, nrows, L, Ns, tw);
     else if (R == 4)
       fft_pass<4, INV>(a, b, nrows, L, Ns, tw);
@@ -572,6 +646,9 @@ bool fft_factor(int L, FftPlan *fp) {
   }
   fp->code = 0;
   for (int i = 0; i < fp->npass; ++i) fp->code |= (uint64_t)fp->radix[i] << (4 * i);
+  // quads for power-of-two lengths where one problem's row block leaves
+  // lanes idle in a radix-8 pass (L <= 512)
+  fp->quad8 = (L & (L - 1)) == 0 && rows_per_block(L) * (L / 8) < kFftThreads ? 1 : 0;
   return m == 1 && fp->npass <= 16;
 }
 

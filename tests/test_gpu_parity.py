@@ -252,7 +252,7 @@ def test_grad_div_prox_parity():
         assert rel(got, prox.prox_sino(q, s, u0, bd, np.zeros_like(mask))) <= 1e-6
 
 
-@pytest.mark.parametrize("n", [2, 6, 48, 64, 96, 162, 384, 512, 768, 1024, 2048, 4096])
+@pytest.mark.parametrize("n", [2, 6, 8, 32, 48, 64, 96, 128, 162, 256, 384, 512, 768, 1024, 2048, 4096])
 def test_precond_parity(n):
     print("precond parity", n, flush=True)
     rng = np.random.default_rng(n)
