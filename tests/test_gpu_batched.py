@@ -179,3 +179,26 @@ def test_group_step_equals_separate_steps():
     with pytest.raises(ct.CtpdError):
         grp.step(1)          # the group's solvers are no longer in step
     grp.close()
+
+
+def test_batch_of_eight_512_equals_single():
+    """Eight 512^2 x 720 x 768 problems in one batch solver, where the
+    preconditioner's passes hold four row pairs (and four columns) per
+    workgroup instead of one: each problem's state after two steps is
+    bitwise that of a single solver with the batch's launch choices."""
+    print("batch of eight at 512", flush=True)
+    n, N, M = 512, 720, 768
+    rng = np.random.default_rng(8)
+    plan = ct.Plan(n, N, M)
+    sinos = [gpu(50.0 * np.abs(rng.standard_normal((N, M)))) for _ in range(8)]
+    sb = ct.SolverBatch(plan, sinos, 0.005, beta=600.0, c=2.0, launch=NO_TUNE)
+    sb.step(2)
+    ub, vb1b, vb2b = sb.export()
+    lay, tvb = sb.layout(), sb.tuning()["tv_blocks"]
+    launch = ct.Launch(tune=False, bp_slices=lay["bp_slices"], bp_kernel=lay["bp_kernel"],
+                       tv_blocks=tvb or None, fuse_tv=tvb > 0, fwd_walk=lay["angles_per_walk"])
+    for b in range(8):
+        sv = ct.Solver(plan, sinos[b], 0.005, beta=600.0, c=2.0, launch=launch)
+        sv.step(2)
+        for x, y in zip(sv.export(), (ub[b], vb1b[b], vb2b[b])):
+            assert torch.equal(x, y)
