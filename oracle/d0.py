@@ -12,14 +12,14 @@ here in its order:
 The constraint on D0 is then set from the data, C = c0 u0 (c0 = 0.8 there).
 
 Readings (the passage gives the steps, not their exact rules):
-  * "dilated by r pixels": the Euclidean disk {(a, b) : a^2 + b^2 <= r^2}
+  * the dilation by r pixels: the Euclidean disk {(a, b) : a^2 + b^2 <= r^2}
     of pixel offsets; the image has no pixels outside [0, n)^2.
-  * "back projection to the marked areas ... to obtain areas in the
-    sinogram" maps image to sinogram, i.e. R_h of the indicator image chi of
-    the marked set.  A bin belongs to D0 when (R_h chi)[l, k] > kappa for a
+  * the step that carries the marked image areas over to the sinogram maps
+    image to sinogram, i.e. R_h of the indicator image chi of the marked
+    set.  A bin belongs to D0 when (R_h chi)[l, k] > kappa for a
     small kappa > 0: R_h splits every pixel between two bins with weights
     1 - alpha and alpha that sum to 1, so kappa is the smallest weight with
-    which a marked pixel must reach a bin (a plain "> 0" would make the
+    which a marked pixel must reach a bin (a threshold of zero would make the
     decision depend on the rounding of weights near 0).
 """
 from __future__ import annotations

@@ -1,7 +1,7 @@
 """Power iterations (thesis §4.3, §4.3.1, §5.1).
 
-The thesis finds operator constants "by power iteration" without fixing the
-step count; the reading here is 30 steps, a stated start vector (drawn by the
+The thesis obtains these operator constants with power iterations but does
+not fix the step count; the reading here is 30 steps, a stated start vector (drawn by the
 caller from the seeded input generator and passed in), and the estimate
 ||B x_{29}|| with x_{29} the unit-norm iterate before the last application.
 

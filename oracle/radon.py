@@ -8,8 +8,9 @@ with the same two weights.
 
 Reading of the weights: the printed formula gives weight alpha to bin k and
 1 - alpha to bin k + 1 with alpha = t - floor(t), which is discontinuous in t
-and contradicts the text's "linear interpolation" and the figure caption
-(value split "proportionally to the distance from the bins").  The oracle uses
+and contradicts both the text, which names the scheme linear interpolation,
+and the figure caption, where a value is shared by the two nearest bins in
+proportion to its distance from them.  The oracle uses
 standard linear interpolation: weight 1 - alpha to bin floor(t) and alpha to
 bin floor(t) + 1.
 
