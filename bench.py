@@ -73,16 +73,36 @@ def profile_records(workload: str = "512x720x768"):
     stem = os.path.join(PROFILES, f"pdrqs1_{workload}_")
     return {"sq": load_record(stem + "sq_counters.json"),
             "tcc": load_record(stem + "tcc_counters.json"),
+            "mix": load_record(stem + "valu_mix.json"),
             "traffic": load_record(stem + "traffic.json")}
 
 
-def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, peak, unit):
+def valu_busy_frac(mix, duration_s, rates):
+    """The share of the chip's VALU capacity over a kernel's duration that
+    its VALU instructions occupy, each type priced at the lane rate the
+    probes measured: FP32 adds at the add probe's, FP32 multiplies and FMAs
+    at the FMA probe's, every other VALU instruction (integer, conversion,
+    move, select, compare) at the integer probe's, which makes the figure an
+    upper bound.  Also the FP32 share of the kernel's VALU instructions."""
+    if not mix or not rates:
+        return None, None
+    add = mix["SQ_INSTS_VALU_ADD_F32"]
+    fma = mix["SQ_INSTS_VALU_FMA_F32"] + mix["SQ_INSTS_VALU_MUL_F32"]
+    other = max(mix["SQ_INSTS_VALU"] - add - fma, 0.0)
+    seconds = 64.0 * (add / rates["add_f32"] + fma / rates["fma_f32"] + other / rates["xad_u32"])
+    return round(seconds / duration_s, 4), round((add + fma) / mix["SQ_INSTS_VALU"], 4)
+
+
+def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, peak, unit,
+                    rates=None):
     """The roofline object of one kernel: achieved = algorithmic work per
     launch / its average duration (HIP events), against the published peak;
     with the committed counters: the HBM bytes per launch, the VALU issue
-    fraction (SQ_INSTS_VALU wave-instructions x 64 lanes against the plain
-    issue rate over the same duration) and the L2 hit rate (TCC hits over
-    hits + misses)."""
+    fraction (SQ_INSTS_VALU wave-instructions x 64 lanes against 256 CUs x 4
+    SIMDs x 16 lanes x 2.4 GHz, i.e. 4 cycles per wave-instruction), the VALU
+    busy fraction priced per instruction type at the measured probe rates
+    (`rates`: lane-instructions/s per probe kind) and the L2 hit rate (TCC hits
+    over hits + misses)."""
     from paper_1810_03275_amd.profiling import find_kernel
     if bound == "hbm":
         achieved = alg_bytes / duration_s / 1e9
@@ -101,6 +121,8 @@ def kernel_roofline(recs, prefix, suffix, duration_s, flops, alg_bytes, bound, p
     sq = find_kernel(recs["sq"], prefix, suffix)
     out["valu_issue_frac"] = (round(sq["SQ_INSTS_VALU"] * 64 / duration_s / VALU_LANE_INSTR_PER_S,
                                     4) if sq else None)
+    out["valu_busy_frac"], out["valu_fp32_share"] = valu_busy_frac(
+        find_kernel(recs["mix"], prefix, suffix), duration_s, rates)
     tc = find_kernel(recs["tcc"], prefix, suffix)
     if tc and (tc.get("TCC_HIT_sum", 0) + tc.get("TCC_MISS_sum", 0)) > 0:
         out["l2_hit_rate"] = round(tc["TCC_HIT_sum"] / (tc["TCC_HIT_sum"] + tc["TCC_MISS_sum"]), 4)
@@ -274,7 +296,7 @@ def unrolled_run(ct, torch, K: int = 50, every: int = 10, count: int = 8):
             "dL_dlambda": float(lam.grad), "loss": float(loss.detach())}
 
 
-def large_run(ct, torch, iters: int, tune_cache=None):
+def large_run(ct, torch, iters: int, tune_cache=None, rates=None):
     """The largest single slice: 2048^2, 2880 angles x 3072 bins, 4 metal discs,
     alpha = 0.005; PDRQS1 iterations/s after setup and 10 warm-up iterations,
     per-phase kernel durations (HIP events) and the rooflines of R_h, R_h^*
@@ -320,10 +342,11 @@ def large_run(ct, torch, iters: int, tune_cache=None):
                 recs, fwd_prefix, fwd_suffix, t_fwd, FLOPS_PER_PAIR * pairs,
                 radon_fwd_bytes(w.n, w.n_angles, w.n_bins)
                 + (tv_fused_bytes(w.n) if tun["tv_blocks"] > 0 else 0.0), "alu", PEAK_FP32_TFLOPS,
-                "TFLOP/s"),
+                "TFLOP/s", rates),
             "roofline_radon_adj": kernel_roofline(
                 recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
-                radon_adj_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s"),
+                radon_adj_bytes(w.n, w.n_angles, w.n_bins), "alu", PEAK_FP32_TFLOPS, "TFLOP/s",
+                rates),
             "roofline_fft_pair": fft,
             "solve_1000_iterations_s": round(1000 * dt / iters + setup_s, 2)}
 
@@ -496,6 +519,43 @@ def cpu_baseline(w, budget_s: float):
                       f"given, not timed)"}
 
 
+def device_calibration(ct, torch):
+    """The achievable FP32 VALU issue rate and HBM copy bandwidth, measured
+    with the library's probes (HIP events, median of 5 launches)."""
+    def timed(launch, reps=5):
+        launch()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            launch()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms)[reps // 2] * 1e-3
+
+    blocks, iters = 8192, 4096
+    out = torch.zeros(blocks, device="cuda")
+    valu = {}
+    for kind in ct.VALU_PROBE_KINDS:
+        count = ct.valu_probe(blocks, 1, out, kind)  # count per round x iters below
+        t = timed(lambda: ct.valu_probe(blocks, iters, out, kind))
+        rate = count * iters * 64.0 / t
+        valu[kind] = {"lane_instr_per_s": float(f"{rate:.4g}"),
+                      "cycles_per_wave_instr": round(256 * 4 * 2.4e9 / (rate / 64.0), 3)}
+    nbytes = 2 << 30  # 2 GiB each way: well beyond the 256 MB last-level cache
+    src = torch.ones(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    tc = timed(lambda: ct.copy_probe(src, dst, 8192))
+    del src, dst
+    gbs = 2 * nbytes / tc / 1e9
+    return {"valu": valu, "copy_gbs": round(gbs, 1),
+            "copy_frac_of_peak": round(gbs / PEAK_HBM_GBS, 4),
+            "probes": "16 independent chains per lane of each instruction kind, 8192 x 256 "
+                      "threads x 4096 rounds (cycles per wave-instruction per SIMD at 2.4 GHz); "
+                      "a 2 GiB device copy with 16-byte accesses (read + write bytes)"}
+
+
 def copy_calibration(torch):
     """A plain 64 MiB device copy, three times: the reference dispatch of
     known size that scales the FETCH_SIZE / WRITE_SIZE counters."""
@@ -603,15 +663,17 @@ def main():
     pairs = float(N_IMG * N_IMG * N_ANG)
     lay, tun = sv.layout(), sv.tuning()
     recs = profile_records()
+    cal = device_calibration(ct, torch)
+    rates = {k: v["lane_instr_per_s"] for k, v in cal["valu"].items()}
     fwd_prefix, fwd_suffix = fwd_kernel(lay, tun)
     roof = kernel_roofline(recs, fwd_prefix, fwd_suffix, t_fwd,
                            FLOPS_PER_PAIR * pairs, radon_fwd_bytes(N_IMG, N_ANG, N_BIN)
                            + (tv_fused_bytes(N_IMG) if tun["tv_blocks"] > 0 else 0.0), "alu",
-                           PEAK_FP32_TFLOPS, "TFLOP/s")
+                           PEAK_FP32_TFLOPS, "TFLOP/s", rates)
     adj_prefix, adj_suffix = adj_kernel(lay)
     roof_adj = kernel_roofline(recs, adj_prefix, adj_suffix, t_adj, FLOPS_PER_PAIR * pairs,
                                radon_adj_bytes(N_IMG, N_ANG, N_BIN), "alu", PEAK_FP32_TFLOPS,
-                               "TFLOP/s")
+                               "TFLOP/s", rates)
     fft = {"duration_us": round(t_fft * 1e6, 2), "bound": "hbm", "peak": PEAK_HBM_GBS,
            "unit": "GB/s", "algorithmic_bytes": fft_pair_bytes(N_IMG),
            "achieved": round(fft_pair_bytes(N_IMG) / t_fft / 1e9, 1)}
@@ -653,6 +715,7 @@ def main():
         "roofline_radon_adj": roof_adj,
         "roofline_fft_pair": fft,
         "system": system_info(torch),
+        "device_calibration": cal,
     }
     if args.batched_iters > 0:
         del sv
@@ -665,7 +728,7 @@ def main():
         out["preconditioning"] = precond_comparisons(ct, torch, args.comparison_iters)
     if args.large_iters > 0:
         torch.cuda.empty_cache()
-        out["large"] = large_run(ct, torch, args.large_iters, args.tune_cache)
+        out["large"] = large_run(ct, torch, args.large_iters, args.tune_cache, rates)
     if args.unrolled_iters > 0:
         torch.cuda.empty_cache()
         out["unrolled"] = unrolled_run(ct, torch, args.unrolled_iters)

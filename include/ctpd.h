@@ -506,6 +506,28 @@ int ct_unrolled_backward(ct_tape *t, const float *gbar, float *grad_u0, double *
                          ct_stream s);
 int ct_tape_destroy(ct_tape *t);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement utilities (not steps of the method)                           */
+
+/* A probe of the vector issue rate: `blocks` workgroups of 256 threads whose
+ * lanes each run 16 independent chains for `iters` rounds, i.e.
+ * blocks * 4 * iters * 16 * I wave-instructions of 64 lanes, by kind:
+ * 0 FP32 FMA (I = 1), 1 FP32 add (I = 1), 2 32-bit integer xor-add (I = 1),
+ * 3 integer xor-add and integer-to-float conversion (I = 2).  Timed with
+ * events on s, it gives the achievable VALU rate of each kind, against which
+ * the projectors' issue fractions are read.  out: device buffer of `blocks`
+ * floats, written only if a chain turned negative (never; the store keeps
+ * the work live).  Asynchronous.  Errors: CT_E_INVALID, CT_E_DEVICE. */
+int ct_valu_probe(int32_t blocks, int32_t iters, int32_t kind, float *out, ct_stream s);
+
+/* A streaming copy of `bytes` bytes (a positive multiple of 16) between two
+ * non-overlapping, 16-byte aligned device buffers by `blocks` workgroups of
+ * 256 threads with 16-byte accesses.  Timed with events on s over buffers
+ * larger than the 256 MB last-level cache, it gives the achievable HBM
+ * bandwidth (2 * bytes moved).  Asynchronous.  Errors: CT_E_INVALID,
+ * CT_E_DEVICE. */
+int ct_copy_probe(const void *src, void *dst, int64_t bytes, int32_t blocks, ct_stream s);
+
 #ifdef __cplusplus
 }
 #endif

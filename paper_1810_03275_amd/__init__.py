@@ -332,6 +332,33 @@ def power_norm_noalloc(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] =
     return out.value
 
 
+VALU_PROBE_KINDS = {"fma_f32": (0, 1), "add_f32": (1, 1), "xad_u32": (2, 1),
+                    "xad_u32+cvt_f32_u32": (3, 2)}  # name -> (kind, instructions per round)
+
+
+def valu_probe(blocks: int, iters: int, out: torch.Tensor, kind: str = "fma_f32") -> int:
+    """Launch the vector issue-rate probe (ct_valu_probe) on the current
+    stream and return its wave-instruction count, blocks * 4 * iters * 16 * I
+    (kinds and I in VALU_PROBE_KINDS).  out: float32 device tensor of at least
+    `blocks` elements (it only keeps the work live)."""
+    if out.dtype != torch.float32 or not out.is_cuda or out.numel() < blocks:
+        raise ValueError("out must be a float32 device tensor of at least `blocks` elements")
+    k, per = VALU_PROBE_KINDS[kind]
+    _check(_L.ct_valu_probe(blocks, iters, k, out.data_ptr(), _stream()), "ct_valu_probe")
+    return blocks * 4 * iters * 16 * per
+
+
+def copy_probe(src: torch.Tensor, dst: torch.Tensor, blocks: int) -> None:
+    """Launch the streaming copy probe (ct_copy_probe) of src into dst (device
+    tensors of equal byte size) on the current stream."""
+    nbytes = src.numel() * src.element_size()
+    if (not src.is_cuda or not dst.is_cuda or not src.is_contiguous() or not dst.is_contiguous()
+            or dst.numel() * dst.element_size() != nbytes):
+        raise ValueError("src and dst must be contiguous device tensors of the same byte size")
+    _check(_L.ct_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, blocks, _stream()),
+           "ct_copy_probe")
+
+
 def _params(sigma, tau, eps, c, c_safety, beta, k_max, gap_every, power_iters, validate,
             start_norm, start_precond, n, nonneg=False, method="pdrqs1", precond="invnorm",
             launch=None):

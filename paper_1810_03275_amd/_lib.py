@@ -82,6 +82,8 @@ SIGNATURES = {
     "ct_power_norm": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_double), c_void_p]),
     "ct_power_norm_noalloc": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_double),
                                         c_void_p]),
+    "ct_valu_probe": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "ct_copy_probe": (c_int32, [c_void_p, c_void_p, ctypes.c_int64, c_int32, c_void_p]),
     "ct_params_default": (None, [POINTER(CtParams)]),
     "ct_solver_create": (c_int32, [c_void_p, POINTER(CtProblem), POINTER(CtParams), c_void_p,
                                    POINTER(c_void_p)]),
