@@ -81,15 +81,20 @@ def valu_busy_frac(mix, duration_s, rates):
     """The share of the chip's VALU capacity over a kernel's duration that
     its VALU instructions occupy, each type priced at the lane rate the
     probes measured: FP32 adds at the add probe's, FP32 multiplies and FMAs
-    at the FMA probe's, every other VALU instruction (integer, conversion,
-    move, select, compare) at the integer probe's, which makes the figure an
-    upper bound.  Also the FP32 share of the kernel's VALU instructions."""
+    at the FMA probe's, 64-bit integer instructions at the 64-bit add
+    probe's when that is slower than the 32-bit integer probe, and every other
+    VALU instruction (integer, conversion, move, select, compare) at the
+    32-bit integer probe's, which makes the figure an upper bound.  Also the
+    FP32 share of the kernel's VALU instructions."""
     if not mix or not rates:
         return None, None
     add = mix["SQ_INSTS_VALU_ADD_F32"]
     fma = mix["SQ_INSTS_VALU_FMA_F32"] + mix["SQ_INSTS_VALU_MUL_F32"]
-    other = max(mix["SQ_INSTS_VALU"] - add - fma, 0.0)
-    seconds = 64.0 * (add / rates["add_f32"] + fma / rates["fma_f32"] + other / rates["xad_u32"])
+    i64 = mix["SQ_INSTS_VALU_INT64"]
+    other = max(mix["SQ_INSTS_VALU"] - add - fma - i64, 0.0)
+    slow = rates["xad_u32"]
+    seconds = 64.0 * (add / rates["add_f32"] + fma / rates["fma_f32"]
+                      + i64 / min(rates["add_u64"], slow) + other / slow)
     return round(seconds / duration_s, 4), round((add + fma) / mix["SQ_INSTS_VALU"], 4)
 
 

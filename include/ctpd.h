@@ -513,7 +513,8 @@ int ct_tape_destroy(ct_tape *t);
  * lanes each run 16 independent chains for `iters` rounds, i.e.
  * blocks * 4 * iters * 16 * I wave-instructions of 64 lanes, by kind:
  * 0 FP32 FMA (I = 1), 1 FP32 add (I = 1), 2 32-bit integer xor-add (I = 1),
- * 3 integer xor-add and integer-to-float conversion (I = 2).  Timed with
+ * 3 integer xor-add and integer-to-float conversion (I = 2), 4 64-bit
+ * integer add (I = 1).  Timed with
  * events on s, it gives the achievable VALU rate of each kind, against which
  * the projectors' issue fractions are read.  out: device buffer of `blocks`
  * floats, written only if a chain turned negative (never; the store keeps

@@ -333,7 +333,8 @@ def power_norm_noalloc(plan: Plan, iters: int = 30, x0: Optional[torch.Tensor] =
 
 
 VALU_PROBE_KINDS = {"fma_f32": (0, 1), "add_f32": (1, 1), "xad_u32": (2, 1),
-                    "xad_u32+cvt_f32_u32": (3, 2)}  # name -> (kind, instructions per round)
+                    "xad_u32+cvt_f32_u32": (3, 2), "add_u64": (4, 1)}
+# name -> (kind, instructions per chain and round)
 
 
 def valu_probe(blocks: int, iters: int, out: torch.Tensor, kind: str = "fma_f32") -> int:

@@ -14,8 +14,10 @@ constexpr int kProbeChains = 16;  // independent FMA chains per lane
 // kProbeChains * I wave-instructions of the kind KIND, I per chain and round:
 // 0 FP32 FMA (v_fma_f32, I = 1), 1 FP32 add (v_add_f32, I = 1), 2 32-bit
 // integer xor-add (v_xad_u32, I = 1), 3 xor-add and integer-to-float
-// conversion feeding each other (v_xad_u32 + v_cvt_f32_u32, I = 2).  The
-// chains stay finite and non-negative; the store only keeps them live.
+// conversion feeding each other (v_xad_u32 + v_cvt_f32_u32, I = 2), 4 64-bit
+// integer add (v_lshl_add_u64, I = 1; the step is made opaque to the compiler
+// each round so that the sum stays a chain of adds).  The chains stay finite
+// and non-negative; the store only keeps them live.
 template <int KIND>
 __global__ __launch_bounds__(kProbeThreads) void k_valu_probe(int iters, float seed,
                                                               float *__restrict__ out) {
@@ -23,12 +25,16 @@ __global__ __launch_bounds__(kProbeThreads) void k_valu_probe(int iters, float s
   const uint32_t step = 1u + (threadIdx.x & 7), key = 0x9e3779b9u * (threadIdx.x + 1u);
   float a[kProbeChains];
   uint32_t b[kProbeChains];
+  uint64_t d[kProbeChains];
+  uint64_t step64 = step;
 #pragma unroll
   for (int c = 0; c < kProbeChains; ++c) {
     a[c] = seed * (float)(c + 1);
     b[c] = (uint32_t)c * 977u + threadIdx.x;
+    d[c] = b[c];
   }
   for (int it = 0; it < iters; ++it) {
+    if constexpr (KIND == 4) asm volatile("" : "+v"(step64));
 #pragma unroll
     for (int c = 0; c < kProbeChains; ++c) {
       if constexpr (KIND == 0) {
@@ -37,15 +43,18 @@ __global__ __launch_bounds__(kProbeThreads) void k_valu_probe(int iters, float s
         a[c] = a[c] + m;
       } else if constexpr (KIND == 2) {
         b[c] = (b[c] ^ key) + step;
-      } else {
+      } else if constexpr (KIND == 3) {
         b[c] = (b[c] ^ __float_as_uint(a[c])) + step;
         a[c] = (float)b[c];
+      } else {
+        d[c] = d[c] + step64;
       }
     }
   }
   float s = 0.f;
 #pragma unroll
-  for (int c = 0; c < kProbeChains; ++c) s += (KIND == 2 ? (float)b[c] : a[c]);
+  for (int c = 0; c < kProbeChains; ++c)
+    s += KIND == 2 ? (float)b[c] : KIND == 4 ? (float)(uint32_t)(d[c] >> 8) : a[c];
   if (s < 0.f) out[blockIdx.x] = s;  // every chain stays >= 0: never taken
 }
 
@@ -62,8 +71,8 @@ __global__ __launch_bounds__(kProbeThreads) void k_copy16(const float4 *__restri
 extern "C" int ct_valu_probe(int32_t blocks, int32_t iters, int32_t kind, float *out,
                              ct_stream s) {
   using namespace ctpd;
-  if (blocks < 1 || iters < 1 || kind < 0 || kind > 3 || out == nullptr) {
-    set_error("ct_valu_probe: need blocks >= 1, iters >= 1, kind 0..3 and an output buffer");
+  if (blocks < 1 || iters < 1 || kind < 0 || kind > 4 || out == nullptr) {
+    set_error("ct_valu_probe: need blocks >= 1, iters >= 1, kind 0..4 and an output buffer");
     return CT_E_INVALID;
   }
   const dim3 grid(blocks), block(kProbeThreads);
@@ -74,8 +83,10 @@ extern "C" int ct_valu_probe(int32_t blocks, int32_t iters, int32_t kind, float 
     hipLaunchKernelGGL(k_valu_probe<1>, grid, block, 0, st, iters, 1.0e-3f, out);
   else if (kind == 2)
     hipLaunchKernelGGL(k_valu_probe<2>, grid, block, 0, st, iters, 1.0e-3f, out);
-  else
+  else if (kind == 3)
     hipLaunchKernelGGL(k_valu_probe<3>, grid, block, 0, st, iters, 1.0e-3f, out);
+  else
+    hipLaunchKernelGGL(k_valu_probe<4>, grid, block, 0, st, iters, 1.0e-3f, out);
   CT_TRY_HIP(hipGetLastError());
   return CT_OK;
 }

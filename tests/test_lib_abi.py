@@ -78,7 +78,7 @@ def test_validation_errors_without_device(lib):
     assert lib.ct_precond_create(63, 1.0, 0.3, 1.0, 0.3, ctypes.byref(pc)) == -2  # odd
     assert lib.ct_plan_destroy(None) == 0 and lib.ct_solver_destroy(None) == 0
     assert lib.ct_valu_probe(0, 16, 0, None, None) == -1
-    assert lib.ct_valu_probe(1, 16, 4, None, None) == -1
+    assert lib.ct_valu_probe(1, 16, 5, None, None) == -1
     assert lib.ct_copy_probe(None, None, 16, 1, None) == -1
     assert lib.ct_version() >= 10000
 
