@@ -17,7 +17,7 @@ constexpr int kProbeChains = 16;  // independent FMA chains per lane
 // conversion feeding each other (v_xad_u32 + v_cvt_f32_u32, I = 2), 4 64-bit
 // integer add (v_lshl_add_u64, I = 1; the step is made opaque to the compiler
 // each round so that the sum stays a chain of adds).  The chains stay finite
-// and non-negative; the store only keeps them live.
+// and non-negative; the conditional store only keeps them live.
 template <int KIND>
 __global__ __launch_bounds__(kProbeThreads) void k_valu_probe(int iters, float seed,
                                                               float *__restrict__ out) {
@@ -55,7 +55,9 @@ __global__ __launch_bounds__(kProbeThreads) void k_valu_probe(int iters, float s
 #pragma unroll
   for (int c = 0; c < kProbeChains; ++c)
     s += KIND == 2 ? (float)b[c] : KIND == 4 ? (float)(uint32_t)(d[c] >> 8) : a[c];
-  if (s < 0.f) out[blockIdx.x] = s;  // every chain stays >= 0: never taken
+  // every chain stays >= 0 and the launcher passes seed > 0, so this is
+  // never taken; the compiler cannot know seed's sign and keeps the chains
+  if (s == -seed) out[blockIdx.x] = s;
 }
 
 // dst[i] = src[i] for n16 16-byte elements, grid-strided.
